@@ -1,0 +1,279 @@
+/*
+ * nnp.h -- C ABI of the MI355X (gfx950) engine for ANI-style symmetry-function
+ * neural network potentials: energies, forces, parameter gradients and
+ * velocity-Verlet MD serving.
+ *
+ * The operations are those the OpenMM 8 paper names for machine-learning
+ * potentials: a model maps atomic positions to a potential energy and forces
+ * follow by backpropagation (Methods, "PyTorch Model Support"); the ANI
+ * potentials use one network per element (Methods, "OpenMM-ML": seven elements
+ * for ANI-2x, four for ANI-1ccx); the expensive steps are building neighbor
+ * lists and computing the ANI atom-centered symmetry functions (Methods,
+ * "Optimization Through NNPOps").  The symmetry functions are the published
+ * ANI definition (radial and angular terms with a cosine cutoff); the paper
+ * benchmarks the ANI-2x model inside MD (Results, Table 3).
+ *
+ * Conventions shared by every entry point:
+ *   - Units: A (positions), eV (energies), eV/A (forces), amu, fs.
+ *   - Pointers documented "device" must point to device memory on the current
+ *     HIP device; "host" pointers to ordinary host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Entry points that take a stream only enqueue work; they never
+ *     synchronise unless stated.
+ *   - Host-checkable errors return synchronously and enqueue nothing.
+ *     Errors that only the device can see (species out of range, non-finite
+ *     positions or energies, neighbor-list overflow, malformed molecule
+ *     offsets) set bits of a status word in the workspace; read it with
+ *     nnp_check() after the stream has run.  Outputs are undefined while such
+ *     a bit is set.  Kernels clamp every data-derived index, so a bad input
+ *     never makes them access memory out of bounds.
+ *   - No entry point throws; none aborts.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nnp_handle nnp_handle;
+typedef struct nnp_server nnp_server;
+
+typedef enum {
+  NNP_OK = 0,
+  NNP_E_INVALID = 1,   /* bad argument (null pointer, count, layout, offsets) */
+  NNP_E_SPECIES = 2,   /* species index outside [0, n_species)               */
+  NNP_E_BOX = 3,       /* a box edge is shorter than twice the radial cutoff  */
+  NNP_E_CAPACITY = 4,  /* an atom has more neighbors than the list holds     */
+  NNP_E_OOM = 5,       /* device allocation failed (nnp_create, servers)     */
+  NNP_E_HIP = 6,       /* a HIP runtime call failed                          */
+  NNP_E_NONFINITE = 7, /* non-finite position or energy                      */
+  NNP_E_WORKSPACE = 8, /* workspace missing or smaller than required         */
+  NNP_E_BUSY = 9       /* server: no capacity for the request right now      */
+} nnp_status;
+
+typedef enum {
+  NNP_MLP_FP32 = 0, /* networks in FP32 on MFMA, FP32 accumulation           */
+  NNP_MLP_BF16 = 1  /* network operands BF16 on MFMA, FP32 accumulation      */
+} nnp_precision;
+
+/* Symmetry-function parameters (host memory; copied by nnp_create).
+ * The engine supports the ANI layout: n_shf_r = 16, n_shf_a = 4, n_shf_z = 8,
+ * 1 <= n_species <= 8.  One atom's feature vector G has
+ * F = 16*S + 32*S*(S+1)/2 entries: radial block of neighbor species s at
+ * 16*s + m; angular block of the unordered species pair (p <= q) at
+ * 16*S + 32*P(p,q) + 8*a + z, P(p,q) = p*S - p*(p-1)/2 + (q - p).
+ *   radial  : G[16*s_j + m] += c_R exp(-eta_r (d_ij - shf_r[m])^2) fc(d_ij; rc_rad)
+ *   angular : over unordered neighbor pairs {j,k} within rc_ang,
+ *             theta = acos(kappa cos(angle j-i-k)),
+ *             G[...] += 2^(1-zeta) (1 + cos(theta - shf_z[z]))^zeta
+ *                       exp(-eta_a ((d_ij + d_ik)/2 - shf_a[a])^2)
+ *                       fc(d_ij; rc_ang) fc(d_ik; rc_ang)
+ *   fc(d; R) = cos(pi d / R)/2 + 1/2 for d < R, 0 otherwise.
+ * Neighbor sets use a float32 predicate evaluated without FMA contraction:
+ * dx = fl(x_j - x_i) (minimum image with a box: dx -= L*rint(dx*fl(1/L))),
+ * d2 = fl(fl(fl(dx*dx) + fl(dy*dy)) + fl(dz*dz)), neighbor iff same molecule,
+ * j != i and d2 < fl(R*R). */
+typedef struct {
+  int32_t n_species;
+  float rc_rad;
+  float eta_r;
+  int32_t n_shf_r;
+  const float* shf_r;
+  float rc_ang;
+  float eta_a;
+  float zeta;
+  int32_t n_shf_a;
+  const float* shf_a;
+  int32_t n_shf_z;
+  const float* shf_z;
+  float radial_prefactor; /* c_R; the ANI-2x convention is 0.25 */
+  float angle_cos_scale;  /* kappa in (0, 1); the ANI-2x convention is 0.95 */
+} nnp_aev_params;
+
+/* Per-element networks (host memory; copied and repacked by nnp_create).
+ * Layer l maps width[l] -> width[l+1]; hidden layers apply
+ * CELU_alpha(x) = max(0,x) + min(0, alpha (exp(x/alpha) - 1)); the last layer
+ * is linear with width[n_layers] == 1.  The engine supports n_layers == 4 and
+ * width[0] == F.  `params` is one float32 vector: for species s = 0..S-1, for
+ * layer l = 0..n_layers-1: W_l (width[l+1] x width[l], row-major) then b_l.
+ * The atomic energy is E_i = net_{s_i}(G_i) + self_energy[s_i]. */
+typedef struct {
+  int32_t n_layers;
+  const int32_t* width;      /* n_layers + 1 entries */
+  float celu_alpha;
+  const float* params;       /* nnp_param_count() floats */
+  const double* self_energy; /* n_species entries, or NULL for zeros */
+} nnp_mlp_params;
+
+/* Creates a potential on the current HIP device: validates the parameters,
+ * uploads the symmetry-function constants and packs the weights (FP32 master
+ * copy, BF16 copy and transposed copies for the adjoint).  This is the only
+ * call that copies weights from the host.  Returns NNP_E_INVALID for an
+ * unsupported layout, NNP_E_OOM / NNP_E_HIP on device failures. */
+nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
+                      nnp_precision precision, nnp_handle** out);
+void nnp_destroy(nnp_handle* h);
+
+/* Number of float32 network parameters (the length of `params`). */
+size_t nnp_param_count(const nnp_handle* h);
+
+/* Replaces the network weights from a device vector in the `params` layout
+ * (float32, nnp_param_count() entries); enqueued on `stream`. */
+nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* stream);
+
+/* Neighbor-list capacity per atom (default 128, range 16..1024).  A larger
+ * capacity needs a larger workspace. */
+nnp_status nnp_set_max_neighbors(nnp_handle* h, int32_t max_neighbors);
+
+/* Bytes of workspace an evaluation of this shape needs.  `box` is host memory
+ * (3 floats) or NULL, as for nnp_energy_forces.  Returns 0 for invalid shapes. */
+size_t nnp_workspace_bytes(const nnp_handle* h, int32_t n_atoms, int32_t n_mol,
+                           const float* box);
+
+/* Energies and forces.
+ *   n_atoms >= 0, n_mol >= 1 (n_mol == 1 when a box is given).
+ *   pos         device, float32 [n_atoms][3], A.
+ *   species     device, int32 [n_atoms], element index in [0, n_species).
+ *   mol_offsets device, int32 [n_mol + 1]: molecule m owns atoms
+ *               [mol_offsets[m], mol_offsets[m+1]); non-decreasing, first 0,
+ *               last n_atoms.  There are no pairs across molecules.
+ *   box         host, float32 [3] orthorhombic edge lengths (minimum image,
+ *               every edge >= 2 * rc_rad, else NNP_E_BOX), or NULL.
+ *   E           device, float64 [n_mol]: molecular energies (FP64 sums of the
+ *               FP32 atomic energies and the self energies).
+ *   F           device, float32 [n_atoms][3], or NULL for energy only.
+ *   workspace   device, >= nnp_workspace_bytes(); caller-owned, not retained
+ *               after the call's work completes.  Concurrent calls need
+ *               distinct workspaces.
+ * Allocates nothing; all work is enqueued on `stream`. */
+nnp_status nnp_energy_forces(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
+                             const float* pos, const int32_t* species,
+                             const int32_t* mol_offsets, const float* box,
+                             double* E, float* F, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* Adjoint for L = sum_m dL_dE[m] * E_m.  Recomputes the forward pass (the
+ * symmetry functions are recomputed, not stored between calls), then writes
+ *   dL_dpos    device, float32 [n_atoms][3] = sum_m dL_dE[m] dE_m/dpos, or NULL;
+ *   dL_dparams device, float32 [nnp_param_count()] in the `params` layout
+ *              (overwritten, not accumulated), or NULL;
+ *   E          device, float64 [n_mol], or NULL.
+ * dL_dE is device float64 [n_mol].  Other arguments as nnp_energy_forces. */
+nnp_status nnp_backward(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
+                        const float* pos, const int32_t* species,
+                        const int32_t* mol_offsets, const float* box,
+                        const double* dL_dE, float* dL_dpos, float* dL_dparams,
+                        double* E, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/* Waits for `stream`, then reads and clears the device status word of
+ * `workspace`.  Returns NNP_OK or the first error bit set. */
+nnp_status nnp_check(const nnp_handle* h, void* workspace, void* stream);
+
+const char* nnp_status_string(nnp_status s);
+
+/* Test and debug exports of intermediate results for the last evaluation run
+ * in `workspace` (enqueued on `stream`):
+ *   nnp_debug_neighbors: counts  device int32 [n_atoms][2] (radial, angular)
+ *                        nbr     device int32 [n_atoms][max_neighbors]; row i
+ *                        lists the angular neighbors first, then the rest.
+ *   nnp_debug_aev:       runs staging, neighbor search and the symmetry
+ *                        functions and writes G as float32 [n_atoms][F] in
+ *                        input atom order into `aev` (device). */
+nnp_status nnp_debug_neighbors(nnp_handle* h, int32_t n_atoms, void* workspace,
+                               size_t workspace_bytes, int32_t* counts,
+                               int32_t* nbr, void* stream);
+nnp_status nnp_debug_aev(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
+                         const float* pos, const int32_t* species,
+                         const int32_t* mol_offsets, const float* box, float* aev,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Per-stage device timing with HIP events, for benchmarks.  While enabled,
+ * every evaluation records an event pair around each stage on its stream;
+ * nnp_profile_collect() waits for the stream and adds the elapsed times to
+ * per-stage totals.  Stage i is named by nnp_profile_stage_name(i) for
+ * 0 <= i < nnp_profile_stage_count().  nnp_profile_read() copies the totals
+ * (milliseconds) and launch counts; enabling resets them. */
+nnp_status nnp_profile_enable(nnp_handle* h, int on);
+nnp_status nnp_profile_collect(nnp_handle* h, void* stream);
+int32_t nnp_profile_stage_count(void);
+const char* nnp_profile_stage_name(int32_t i);
+nnp_status nnp_profile_read(const nnp_handle* h, double* total_ms, int64_t* count, int32_t max);
+
+/* ---------------------------------------------------------------------------
+ * Molecular dynamics.  Velocity Verlet in eV, A, amu, fs with FP64 positions
+ * and velocities and FP32 forces evaluated at the FP32 rounding of x:
+ *   v += dt/2 * 9.648533e-3 * F / m;  x += dt * v;  F = F(x);
+ *   v += dt/2 * 9.648533e-3 * F / m;
+ * KE_m = 0.5 * sum m v^2 / 9.648533e-3 (eV, FP64).
+ * ------------------------------------------------------------------------- */
+
+/* n_steps velocity-Verlet steps of a packed batch, all on `stream`.
+ *   x, v   device float64 [n_atoms][3], updated in place.
+ *   F      device float32 [n_atoms][3]: on entry the forces at x (call
+ *          nnp_energy_forces first), on exit the forces at the final x.
+ *   mass   device float64 [n_atoms] (amu).
+ *   E_pot, E_kin  device float64 [n_mol] at the final state (may be NULL).
+ * The workspace must fit nnp_workspace_bytes() for this shape plus
+ * 16 * n_atoms bytes. */
+nnp_status nnp_md_steps(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
+                        double* x, double* v, float* F, const double* mass,
+                        const int32_t* species, const int32_t* mol_offsets,
+                        const float* box, double dt_fs, int32_t n_steps,
+                        double* E_pot, double* E_kin, void* workspace,
+                        size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of MD requests (molecules without a box).
+ * A server owns fixed-capacity device buffers (max_atoms atoms, max_mols
+ * molecules, sized within hbm_budget_bytes), a pending queue, and one
+ * captured HIP graph of a whole velocity-Verlet step over the packed active
+ * set.  Each nnp_server_step():
+ *   1. retires requests that finished their steps (results copied to host),
+ *   2. admits pending requests in arrival order while atoms, slots and the
+ *      HBM budget allow (their x, v, species are copied to the device and the
+ *      batch is repacked on the device),
+ *   3. replays the step graph once over every active request.
+ * Every request's trajectory is independent of the others in the batch.
+ * ------------------------------------------------------------------------- */
+nnp_status nnp_server_create(nnp_handle* h, size_t hbm_budget_bytes,
+                             int32_t max_atoms, int32_t max_mols, double dt_fs,
+                             const double* mass_amu /* host, [n_species] */,
+                             void* stream, nnp_server** out);
+void nnp_server_destroy(nnp_server* s);
+
+/* Queues a request (host arrays are copied).  x, v: float64 [n_atoms][3];
+ * species: int32 [n_atoms]; n_steps >= 1.  NNP_E_BUSY if the request can
+ * never fit the server's capacity. */
+nnp_status nnp_server_submit(nnp_server* s, int64_t req_id, int32_t n_atoms,
+                             const double* x, const double* v,
+                             const int32_t* species, int32_t n_steps);
+
+/* One scheduling round (retire, admit, one MD step).  Returns after the step
+ * has been enqueued; results of requests retired in this round are complete
+ * on return. */
+nnp_status nnp_server_step(nnp_server* s);
+
+/* Number of active and pending requests. */
+int32_t nnp_server_active(const nnp_server* s);
+int32_t nnp_server_pending(const nnp_server* s);
+
+/* Finished request ids (up to `max`), oldest first; each id is reported once. */
+int32_t nnp_server_poll(nnp_server* s, int64_t* done_ids, int32_t max);
+
+/* Result of a finished request: final x, v (host float64 [n][3], may be NULL),
+ * final potential and kinetic energy, and host wall-clock times (seconds,
+ * steady clock) of submission, admission and completion. */
+nnp_status nnp_server_result(nnp_server* s, int64_t req_id, double* x, double* v,
+                             double* e_pot, double* e_kin, double* t_submit,
+                             double* t_admit, double* t_done);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNP_H */

@@ -1,0 +1,144 @@
+// Shared device-side definitions of the NNP engine (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nnp {
+
+constexpr int kWave = 64;
+constexpr int kNR = 16;       // radial shifts per species block
+constexpr int kNA = 4;        // angular radial shifts
+constexpr int kNZ = 8;        // angle shifts
+constexpr int kMaxS = 8;      // species supported
+constexpr int kPad = 128;     // species groups start at multiples of this row count
+constexpr int kLayers = 4;    // Linear layers per element network
+
+// Device status bits (workspace word 0).
+enum : uint32_t {
+  kStSpecies = 1u << 0,
+  kStNonFinite = 1u << 1,
+  kStCapacity = 1u << 2,
+  kStOffsets = 1u << 3,
+};
+
+// Symmetry-function constants, passed by value to the kernels.
+struct AevConst {
+  int S;             // species
+  int F;             // features per atom
+  int Fp;            // row stride of the feature matrix (F rounded up to 64)
+  float rc2_r;       // fl32(rc_r * rc_r): radial predicate
+  float rc2_a;       // fl32(rc_a * rc_a): angular predicate
+  float inv_rc_r;    // 1 / rc_r
+  float inv_rc_a;    // 1 / rc_a
+  float pi_2rc_r;    // pi / (2 rc_r): cutoff derivative scale
+  float pi_2rc_a;
+  float eta_r_l2e;   // eta_r * log2(e)
+  float eta_r2;      // 2 * eta_r
+  float eta_a_l2e;   // eta_a * log2(e)
+  float eta_a;       // eta_a
+  float zeta;
+  float cR;          // radial prefactor
+  float kappa;       // angle cosine scale
+  float shf_r[kNR];
+  float shf_a[kNA];
+  float cos_z[kNZ];
+  float sin_z[kNZ];
+};
+
+// Periodic-box description (orthorhombic).  ncell[d] == 1 means that
+// dimension is not binned (the box is too small for three cells).
+struct BoxConst {
+  int periodic;
+  float L[3];
+  float invL[3];
+  int nc[3];
+  float cell_scale[3];   // nc / L
+};
+
+// Group table written by the species sort (device memory, int32):
+//   cnt[0..7], pstart[0..8], wchunk_start[0..8], total_rows, n_wchunks
+struct GroupTable {
+  int cnt[kMaxS];
+  int pstart[kMaxS + 1];
+  int wchunk[kMaxS + 1];
+  int total_rows;
+  int n_wchunks;
+  int pad[6];
+};
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Orders LDS traffic of the lanes of one wave (no cross-wave effect).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Lanes below this one whose bit is set in m.
+__device__ __forceinline__ int popc_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// ------------------------------------------------------------- bf16 helpers
+
+typedef uint16_t bf16_t;
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  // round to nearest even; NaN kept quiet
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+template <typename T> struct Store;
+template <> struct Store<float> {
+  __device__ __forceinline__ static void put(float* p, float v) { *p = v; }
+  __device__ __forceinline__ static float get(const float* p) { return *p; }
+};
+template <> struct Store<bf16_t> {
+  __device__ __forceinline__ static void put(bf16_t* p, float v) { *p = f2bf(v); }
+  __device__ __forceinline__ static float get(const bf16_t* p) { return bf2f(*p); }
+};
+
+// ------------------------------------------------------------- fp32 predicate
+
+// Displacement component in float32 without contraction (minimum image when
+// periodic), exactly as the neighbor predicate defines it.
+__device__ __forceinline__ float disp(float xi, float xj, float L, float invL, int per) {
+  float d = __fsub_rn(xj, xi);
+  if (per) d = __fsub_rn(d, __fmul_rn(L, rintf(__fmul_rn(d, invL))));
+  return d;
+}
+
+__device__ __forceinline__ float dist2(float dx, float dy, float dz) {
+  return __fadd_rn(__fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)), __fmul_rn(dz, dz));
+}
+
+__device__ __forceinline__ int species_of(float4 p) { return __float_as_int(p.w); }
+
+// Clamp a (possibly corrupt) index into [0, n).
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+}  // namespace nnp

@@ -1,0 +1,736 @@
+// Host side of the NNP engine: the C ABI declared in include/nnp.h.
+//
+// A handle holds the symmetry-function constants and the packed per-element
+// weights on one device.  An evaluation carves the caller's workspace,
+// enqueues the kernels of the path on the caller's stream and returns:
+//   stage + species sort -> neighbor search -> symmetry functions ->
+//   network layers (grouped GEMMs) -> FP64 energy sums ->
+//   adjoint layers -> symmetry-function adjoint + force scatter.
+// Nothing here synchronises except nnp_check and the server's retire step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/nnp.h"
+#include "kernels.h"
+
+using namespace nnp;
+
+struct nnp_handle {
+  int device = 0;
+  nnp_precision prec = NNP_MLP_FP32;
+  AevConst C{};
+  int S = 0, F = 0, Fp = 0;
+  int width[kLayers + 1] = {};
+  float alpha = 0.1f;
+  int max_nbr = 128;
+  size_t n_params = 0;
+  long param_off[kMaxS][kLayers] = {};  // flat offset of W for (species, layer)
+  char* dmem = nullptr;
+  float* flat = nullptr;
+  float* Wf[kLayers] = {};
+  bf16_t* Wb[kLayers] = {};
+  float* WTf[kLayers] = {};
+  bf16_t* WTb[kLayers] = {};
+  float* bias[kLayers] = {};
+  float* wout = nullptr;
+  float* bout = nullptr;
+  double* eself = nullptr;
+  long* param_off_dev = nullptr;  // [kLayers][S]
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;        // reusable events
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  size_t ev_next = 0;
+  double prof_ms[32] = {};
+  long long prof_n[32] = {};
+};
+
+namespace {
+
+constexpr int kWChunk = 1024;  // rows per weight-gradient partial
+
+enum Stage {
+  ST_STAGE = 0, ST_PAIRS, ST_AEV, ST_L1, ST_L2, ST_HEAD, ST_ENERGY, ST_BWD3, ST_BWD2, ST_GRADG,
+  ST_AEVBWD, ST_WGRAD, ST_COUNT
+};
+const char* kStageNames[ST_COUNT] = {
+    "stage+sort", "neighbors", "aev_fwd", "mlp_layer1", "mlp_layer2", "mlp_layer3_head",
+    "energy_sum", "mlp_bwd_layer3", "mlp_bwd_layer2", "mlp_bwd_dEdG", "aev_bwd_forces",
+    "weight_grads"};
+
+hipEvent_t prof_event(nnp_handle* h) {
+  if (h->ev_next == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_next++];
+}
+
+// Records an event pair around one stage when profiling is enabled.
+struct StageTimer {
+  nnp_handle* h;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(nnp_handle* h_, int s, hipStream_t st_) : h(h_), stage(s), st(st_) {
+    if (h->prof && (a = prof_event(h))) (void)hipEventRecord(a, st);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = prof_event(h);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    h->ev_pending.push_back({stage, {a, b}});
+  }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Plan {
+  int n = 0, nmol = 0, rows_cap = 0, cap = 0, nblk = 0, nwchunks = 0;
+  BoxConst B{};
+  int ncell = 0;
+  size_t total = 0;
+  size_t status, dims, gt, xyzs, mol, row, perm, hist, nbr, counts;
+  size_t cell_of, cell_cnt, cell_start, cursor, cell_atoms, cell_xyzs;
+  size_t X, H1, H2, H3, D3, D2, D1, G, erow, uprow, wpart, pos32;
+};
+
+bool make_box(const nnp_handle* h, const float* box, BoxConst& B) {
+  B = BoxConst{};
+  if (!box) {
+    for (int d = 0; d < 3; ++d) {
+      B.L[d] = 1.f;
+      B.invL[d] = 1.f;
+      B.nc[d] = 1;
+      B.cell_scale[d] = 1.f;
+    }
+    return true;
+  }
+  B.periodic = 1;
+  const float rc = 1.f / h->C.inv_rc_r;
+  for (int d = 0; d < 3; ++d) {
+    const float L = box[d];
+    if (!(L >= 2.f * rc) || !std::isfinite(L)) return false;
+    B.L[d] = L;
+    B.invL[d] = 1.0f / L;
+    int nc = (int)std::floor((double)L / ((double)rc + 1e-3));
+    if (nc < 3) nc = 1;
+    if (nc > 128) nc = 128;
+    B.nc[d] = nc;
+    B.cell_scale[d] = (float)nc / L;
+  }
+  return true;
+}
+
+Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B) {
+  Plan P;
+  P.n = n;
+  P.nmol = nmol;
+  P.cap = h->max_nbr;
+  P.B = B;
+  P.ncell = B.periodic ? B.nc[0] * B.nc[1] * B.nc[2] : 0;
+  P.rows_cap = (int)align_up((size_t)std::max(n, 1), kPad) + h->S * kPad;
+  P.nblk = stage_blocks(n);
+  P.nwchunks = (n + kWChunk - 1) / kWChunk + h->S;
+  const size_t esz = h->prec == NNP_MLP_BF16 ? 2 : 4;
+  const size_t R = (size_t)P.rows_cap;
+  const size_t N = (size_t)std::max(n, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + std::max(bytes, (size_t)1), 256);
+    return at;
+  };
+  P.status = take(16);
+  P.dims = take(16);
+  P.gt = take(sizeof(GroupTable));
+  P.xyzs = take(N * 16);
+  P.mol = take(N * 4);
+  P.row = take(N * 4);
+  P.perm = take(R * 4);
+  P.hist = take((size_t)(kMaxS + 1) * P.nblk * 4);
+  P.nbr = take(N * P.cap * 4);
+  P.counts = take(N * 8);
+  if (B.periodic) {
+    P.cell_of = take(N * 4);
+    P.cell_cnt = take((size_t)P.ncell * 4);
+    P.cell_start = take((size_t)(P.ncell + 1) * 4);
+    P.cursor = take((size_t)P.ncell * 4);
+    P.cell_atoms = take(N * 4);
+    P.cell_xyzs = take(N * 16);
+  } else {
+    P.cell_of = P.cell_cnt = P.cell_start = P.cursor = P.cell_atoms = P.cell_xyzs = 0;
+  }
+  const int w1 = h->width[1], w2 = h->width[2], w3 = h->width[3];
+  P.X = take(R * h->Fp * esz);
+  P.H1 = take(R * w1 * esz);
+  P.H2 = take(R * w2 * esz);
+  P.H3 = take(R * w3 * esz);
+  P.D3 = take(R * w3 * esz);
+  P.D2 = take(R * w2 * esz);
+  P.D1 = take(R * w1 * esz);
+  P.G = take(R * h->Fp * 4);
+  P.erow = take(R * 4);
+  P.uprow = take(R * 4);
+  size_t maxlen = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    const size_t in = l == 0 ? h->F : h->width[l];
+    maxlen = std::max(maxlen, (size_t)h->width[l + 1] * in + h->width[l + 1]);
+  }
+  P.wpart = take((size_t)P.nwchunks * maxlen * 4);
+  P.pos32 = take(N * 12);
+  P.total = o;
+  return P;
+}
+
+template <typename T> T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+bool hip_ok(hipError_t e) { return e == hipSuccess; }
+
+// ---------------------------------------------------------------- the path
+
+struct EvalIO {
+  int n_arg, nmol_arg;  // >= 0: counts passed by value; -1: read from the workspace
+  const float* pos;
+  const int* species;
+  const int* off;
+  double* E;            // may be null
+  float* out3;          // forces (sign +1) or dL/dpos (sign -1), may be null
+  float sign;
+  const double* dLdE;   // null: unit upstream
+  float* dparams;       // weight gradients, may be null
+};
+
+template <typename T>
+nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hipStream_t st) {
+  int* dims = at<int>(ws, P.dims);
+  uint32_t* status = at<uint32_t>(ws, P.status);
+  GroupTable* gt = at<GroupTable>(ws, P.gt);
+  float4* xyzs = at<float4>(ws, P.xyzs);
+  int* mol = at<int>(ws, P.mol);
+  int* row = at<int>(ws, P.row);
+  int* perm = at<int>(ws, P.perm);
+  int* hist = at<int>(ws, P.hist);
+  int* nbr = at<int>(ws, P.nbr);
+  int2* counts = at<int2>(ws, P.counts);
+  const int S = h->S, Fp = h->Fp;
+  const int w1 = h->width[1], w2 = h->width[2], w3 = h->width[3];
+  const bool bf = h->prec == NNP_MLP_BF16;
+  const bool need_bwd = io.out3 || io.dparams;
+
+  {
+    StageTimer t(h, ST_STAGE, st);
+    launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.species, io.off, S, xyzs, mol,
+                 io.out3, hist, status, st);
+    launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
+    launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
+  }
+  {
+    StageTimer t(h, ST_PAIRS, st);
+    if (P.B.periodic) {
+      launch_pairs_cell(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.cell_of),
+                        at<int>(ws, P.cell_cnt), at<int>(ws, P.cell_start),
+                        at<int>(ws, P.cursor), at<int>(ws, P.cell_atoms),
+                        at<float4>(ws, P.cell_xyzs), P.cap, nbr, counts, status, st);
+    } else {
+      launch_pairs_mol(dims, P.n, h->C, xyzs, mol, io.off, P.cap, nbr, counts, status, st);
+    }
+  }
+  T* X = at<T>(ws, P.X);
+  {
+    StageTimer t(h, ST_AEV, st);
+    launch_aev_fwd<T>(dims, P.n, h->C, P.B, xyzs, nbr, counts, P.cap, row, X, Fp, st);
+  }
+
+  T* H1 = at<T>(ws, P.H1);
+  T* H2 = at<T>(ws, P.H2);
+  T* H3 = at<T>(ws, P.H3);
+  T* D3 = at<T>(ws, P.D3);
+  T* D2 = at<T>(ws, P.D2);
+  T* D1 = at<T>(ws, P.D1);
+  float* G = at<float>(ws, P.G);
+  float* erow = at<float>(ws, P.erow);
+  const T* W[kLayers];
+  const T* WT[kLayers];
+  for (int l = 0; l < kLayers; ++l) {
+    W[l] = bf ? (const T*)h->Wb[l] : (const T*)h->Wf[l];
+    WT[l] = bf ? (const T*)h->WTb[l] : (const T*)h->WTf[l];
+  }
+  GemmArgs g{};
+  g.gt = gt;
+  g.alpha = h->alpha;
+  g.inv_alpha_l2e = (float)(1.4426950408889634 / h->alpha);
+  bool ok = true;
+  // layer 1: H1 = CELU(X W0^T + b0)
+  g.A = X; g.lda = Fp; g.B = W[0]; g.sB = (long)w1 * Fp; g.ldb = Fp;
+  g.bias = h->bias[0]; g.sBias = w1; g.N = w1; g.K = Fp; g.C = H1; g.ldc = w1;
+  {
+    StageTimer t(h, ST_L1, st);
+    ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
+  }
+  // layer 2: H2 = CELU(H1 W1^T + b1)
+  g.A = H1; g.lda = w1; g.B = W[1]; g.sB = (long)w2 * w1; g.ldb = w1;
+  g.bias = h->bias[1]; g.sBias = w2; g.N = w2; g.K = w1; g.C = H2; g.ldc = w2;
+  {
+    StageTimer t(h, ST_L2, st);
+    ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
+  }
+  // layer 3 + output: E_i, delta3
+  g.A = H2; g.lda = w2; g.B = W[2]; g.sB = (long)w3 * w2; g.ldb = w2;
+  g.bias = h->bias[2]; g.sBias = w3; g.N = w3; g.K = w2;
+  g.C = need_bwd ? (void*)D3 : nullptr; g.ldc = w3;
+  g.w_out = h->wout; g.sWout = w3; g.b_out = h->bout; g.erow = erow;
+  g.H3 = io.dparams ? (void*)H3 : nullptr; g.ldh3 = w3;
+  g.perm = perm; g.mol = mol; g.dLdE = io.dLdE;
+  g.uprow = io.dparams ? at<float>(ws, P.uprow) : nullptr;
+  {
+    StageTimer t(h, ST_HEAD, st);
+    ok &= launch_gemm<T>(EPI_HEAD, g, P.rows_cap, st);
+  }
+  g.H3 = nullptr;
+  g.uprow = nullptr;
+  if (io.E) {
+    StageTimer t(h, ST_ENERGY, st);
+    launch_energy(dims, P.nmol, io.off, xyzs, row, erow, h->eself, io.E, status, st);
+  }
+  if (need_bwd) {
+    // delta2 = (delta3 W2) * CELU'(z2)
+    g.A = D3; g.lda = w3; g.B = WT[2]; g.sB = (long)w2 * w3; g.ldb = w3;
+    g.bias = nullptr; g.N = w2; g.K = w3; g.C = D2; g.ldc = w2; g.H = H2; g.ldh = w2;
+    {
+      StageTimer t(h, ST_BWD3, st);
+      ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+    }
+    // delta1 = (delta2 W1) * CELU'(z1)
+    g.A = D2; g.lda = w2; g.B = WT[1]; g.sB = (long)w1 * w2; g.ldb = w2;
+    g.N = w1; g.K = w2; g.C = D1; g.ldc = w1; g.H = H1; g.ldh = w1;
+    {
+      StageTimer t(h, ST_BWD2, st);
+      ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+    }
+  }
+  if (io.out3) {
+    // g = dE/dG = delta1 W0 (float32)
+    g.A = D1; g.lda = w1; g.B = WT[0]; g.sB = (long)Fp * w1; g.ldb = w1;
+    g.N = Fp; g.K = w1; g.C = G; g.ldc = Fp; g.H = nullptr;
+    {
+      StageTimer t(h, ST_GRADG, st);
+      ok &= launch_gemm<T>(EPI_OUT32, g, P.rows_cap, st);
+    }
+    StageTimer t(h, ST_AEVBWD, st);
+    launch_aev_bwd(dims, P.n, h->C, P.B, xyzs, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
+                   st);
+  }
+  if (io.dparams) {
+    StageTimer t(h, ST_WGRAD, st);
+    float* part = at<float>(ws, P.wpart);
+    const float* up = at<float>(ws, P.uprow);
+    const long* po = h->param_off_dev;
+    // output layer: dW3 = sum up * h3, db3 = sum up
+    launch_wgrad<float, T>(gt, S, P.nwchunks, up, 1, 1, H3, w3, w3, kWChunk, part, io.dparams,
+                           po + 3 * S, st);
+    launch_wgrad<T, T>(gt, S, P.nwchunks, D3, w3, w3, H2, w2, w2, kWChunk, part, io.dparams,
+                       po + 2 * S, st);
+    launch_wgrad<T, T>(gt, S, P.nwchunks, D2, w2, w2, H1, w1, w1, kWChunk, part, io.dparams,
+                       po + 1 * S, st);
+    launch_wgrad<T, T>(gt, S, P.nwchunks, D1, w1, w1, X, Fp, h->F, kWChunk, part, io.dparams,
+                       po, st);
+  }
+  if (!ok) return NNP_E_INVALID;
+  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
+nnp_status run(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hipStream_t st) {
+  if (h->prec == NNP_MLP_BF16) return run_path<bf16_t>(h, P, ws, io, st);
+  return run_path<float>(h, P, ws, io, st);
+}
+
+nnp_status check_common(nnp_handle* h, int n, int nmol, const float* pos, const int* species,
+                        const int* off, const float* box, void* ws, size_t ws_bytes, Plan& P) {
+  if (!h || n < 0 || nmol < 1) return NNP_E_INVALID;
+  if (n > 0 && (!pos || !species)) return NNP_E_INVALID;
+  if (!off) return NNP_E_INVALID;
+  if (n >= (1 << 27)) return NNP_E_INVALID;
+  if (box && nmol != 1) return NNP_E_INVALID;
+  BoxConst B;
+  if (!make_box(h, box, B)) return NNP_E_BOX;
+  P = make_plan(h, n, nmol, B);
+  if (!ws || ws_bytes < P.total) return NNP_E_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return NNP_E_HIP;
+  return NNP_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char* nnp_status_string(nnp_status s) {
+  switch (s) {
+    case NNP_OK: return "ok";
+    case NNP_E_INVALID: return "invalid argument";
+    case NNP_E_SPECIES: return "species index out of range";
+    case NNP_E_BOX: return "box edge shorter than twice the radial cutoff";
+    case NNP_E_CAPACITY: return "neighbor list capacity exceeded";
+    case NNP_E_OOM: return "device out of memory";
+    case NNP_E_HIP: return "HIP runtime error";
+    case NNP_E_NONFINITE: return "non-finite position or energy";
+    case NNP_E_WORKSPACE: return "workspace missing or too small";
+    case NNP_E_BUSY: return "server has no capacity for the request";
+  }
+  return "unknown status";
+}
+
+nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
+                      nnp_precision precision, nnp_handle** out) {
+  if (!aev || !mlp || !out) return NNP_E_INVALID;
+  *out = nullptr;
+  const int S = aev->n_species;
+  if (S < 1 || S > kMaxS) return NNP_E_INVALID;
+  if (aev->n_shf_r != kNR || aev->n_shf_a != kNA || aev->n_shf_z != kNZ) return NNP_E_INVALID;
+  if (!aev->shf_r || !aev->shf_a || !aev->shf_z) return NNP_E_INVALID;
+  if (!(aev->rc_rad > 0.f) || !(aev->rc_ang > 0.f) || aev->rc_ang > aev->rc_rad)
+    return NNP_E_INVALID;
+  if (!(aev->angle_cos_scale > 0.f && aev->angle_cos_scale < 1.f)) return NNP_E_INVALID;
+  if (precision != NNP_MLP_FP32 && precision != NNP_MLP_BF16) return NNP_E_INVALID;
+  if (mlp->n_layers != kLayers || !mlp->width || !mlp->params) return NNP_E_INVALID;
+  const int F = kNR * S + 32 * S * (S + 1) / 2;
+  if (mlp->width[0] != F || mlp->width[kLayers] != 1) return NNP_E_INVALID;
+  for (int l = 1; l < kLayers; ++l)
+    if (mlp->width[l] < 32 || mlp->width[l] > 256 || mlp->width[l] % 32) return NNP_E_INVALID;
+  if (!(mlp->celu_alpha > 0.f)) return NNP_E_INVALID;
+
+  nnp_handle* h = new (std::nothrow) nnp_handle();
+  if (!h) return NNP_E_OOM;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return NNP_E_HIP;
+  }
+  h->prec = precision;
+  h->S = S;
+  h->F = F;
+  h->Fp = (F + 63) / 64 * 64;
+  for (int l = 0; l <= kLayers; ++l) h->width[l] = mlp->width[l];
+  h->alpha = mlp->celu_alpha;
+  AevConst& C = h->C;
+  C.S = S;
+  C.F = F;
+  C.Fp = h->Fp;
+  const float rr = aev->rc_rad, ra = aev->rc_ang;
+  C.rc2_r = rr * rr;
+  C.rc2_a = ra * ra;
+  C.inv_rc_r = 1.0f / rr;
+  C.inv_rc_a = 1.0f / ra;
+  C.pi_2rc_r = (float)(M_PI / (2.0 * rr));
+  C.pi_2rc_a = (float)(M_PI / (2.0 * ra));
+  const double l2e = 1.4426950408889634;
+  C.eta_r_l2e = (float)(aev->eta_r * l2e);
+  C.eta_r2 = 2.f * aev->eta_r;
+  C.eta_a_l2e = (float)(aev->eta_a * l2e);
+  C.eta_a = aev->eta_a;
+  C.zeta = aev->zeta;
+  C.cR = aev->radial_prefactor;
+  C.kappa = aev->angle_cos_scale;
+  for (int m = 0; m < kNR; ++m) C.shf_r[m] = aev->shf_r[m];
+  for (int a = 0; a < kNA; ++a) C.shf_a[a] = aev->shf_a[a];
+  for (int z = 0; z < kNZ; ++z) {
+    C.cos_z[z] = (float)std::cos((double)aev->shf_z[z]);
+    C.sin_z[z] = (float)std::sin((double)aev->shf_z[z]);
+  }
+  // flat parameter offsets
+  size_t o = 0;
+  for (int s = 0; s < S; ++s)
+    for (int l = 0; l < kLayers; ++l) {
+      h->param_off[s][l] = (long)o;
+      o += (size_t)h->width[l + 1] * h->width[l] + h->width[l + 1];
+    }
+  h->n_params = o;
+  // one device allocation for all weight copies
+  size_t bytes = 0;
+  auto take = [&](size_t b) {
+    size_t a = bytes;
+    bytes = align_up(bytes + b, 256);
+    return a;
+  };
+  const size_t o_flat = take(o * 4);
+  size_t o_wf[kLayers], o_wb[kLayers], o_wtf[kLayers], o_wtb[kLayers], o_b[kLayers];
+  for (int l = 0; l < kLayers - 1; ++l) {
+    const size_t inp = l == 0 ? h->Fp : h->width[l];
+    const size_t el = (size_t)S * h->width[l + 1] * inp;
+    o_wf[l] = take(el * 4);
+    o_wb[l] = take(el * 2);
+    o_wtf[l] = take(el * 4);
+    o_wtb[l] = take(el * 2);
+    o_b[l] = take((size_t)S * h->width[l + 1] * 4);
+  }
+  const size_t o_wout = take((size_t)S * h->width[3] * 4);
+  const size_t o_bout = take((size_t)S * 4);
+  const size_t o_eself = take(kMaxS * 8);
+  const size_t o_poff = take((size_t)kLayers * S * 8);
+  if (hipMalloc(&h->dmem, bytes) != hipSuccess) {
+    delete h;
+    return NNP_E_OOM;
+  }
+  h->flat = reinterpret_cast<float*>(h->dmem + o_flat);
+  for (int l = 0; l < kLayers - 1; ++l) {
+    h->Wf[l] = reinterpret_cast<float*>(h->dmem + o_wf[l]);
+    h->Wb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wb[l]);
+    h->WTf[l] = reinterpret_cast<float*>(h->dmem + o_wtf[l]);
+    h->WTb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wtb[l]);
+    h->bias[l] = reinterpret_cast<float*>(h->dmem + o_b[l]);
+  }
+  h->wout = reinterpret_cast<float*>(h->dmem + o_wout);
+  h->bout = reinterpret_cast<float*>(h->dmem + o_bout);
+  h->eself = reinterpret_cast<double*>(h->dmem + o_eself);
+  h->param_off_dev = reinterpret_cast<long*>(h->dmem + o_poff);
+  double es[kMaxS] = {};
+  for (int s = 0; s < S; ++s) es[s] = mlp->self_energy ? mlp->self_energy[s] : 0.0;
+  std::vector<long> po((size_t)kLayers * S);
+  for (int l = 0; l < kLayers; ++l)
+    for (int s = 0; s < S; ++s) po[(size_t)l * S + s] = h->param_off[s][l];
+  bool ok = hip_ok(hipMemcpy(h->flat, mlp->params, o * 4, hipMemcpyHostToDevice)) &&
+            hip_ok(hipMemcpy(h->eself, es, sizeof(es), hipMemcpyHostToDevice)) &&
+            hip_ok(hipMemcpy(h->param_off_dev, po.data(), po.size() * 8, hipMemcpyHostToDevice));
+  if (ok) ok = nnp_set_params_device(h, h->flat, nullptr) == NNP_OK &&
+               hip_ok(hipDeviceSynchronize());
+  if (!ok) {
+    (void)hipFree(h->dmem);
+    delete h;
+    return NNP_E_HIP;
+  }
+  *out = h;
+  return NNP_OK;
+}
+
+void nnp_destroy(nnp_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  for (hipEvent_t ev : h->ev_pool) (void)hipEventDestroy(ev);
+  if (h->dmem) (void)hipFree(h->dmem);
+  delete h;
+}
+
+size_t nnp_param_count(const nnp_handle* h) { return h ? h->n_params : 0; }
+
+nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* stream) {
+  if (!h || !params_dev) return NNP_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (params_dev != h->flat &&
+      hipMemcpyAsync(h->flat, params_dev, h->n_params * 4, hipMemcpyDeviceToDevice, st) !=
+          hipSuccess)
+    return NNP_E_HIP;
+  PackArgs p{};
+  p.flat = h->flat;
+  for (int s = 0; s < h->S; ++s)
+    for (int l = 0; l < kLayers; ++l) p.off[s * kLayers + l] = h->param_off[s][l];
+  for (int l = 0; l <= kLayers; ++l) p.width[l] = h->width[l];
+  p.width[0] = h->F;
+  p.Fp = h->Fp;
+  for (int l = 0; l < kLayers; ++l) {
+    p.Wf[l] = h->Wf[l];
+    p.Wb[l] = h->Wb[l];
+    p.WTf[l] = h->WTf[l];
+    p.WTb[l] = h->WTb[l];
+    p.bias[l] = h->bias[l];
+  }
+  p.wout = h->wout;
+  p.bout = h->bout;
+  launch_pack(p, h->S, st);
+  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
+nnp_status nnp_profile_enable(nnp_handle* h, int on) {
+  if (!h) return NNP_E_INVALID;
+  h->prof = on != 0;
+  h->ev_pending.clear();
+  h->ev_next = 0;
+  for (int i = 0; i < 32; ++i) {
+    h->prof_ms[i] = 0.0;
+    h->prof_n[i] = 0;
+  }
+  return NNP_OK;
+}
+
+nnp_status nnp_profile_collect(nnp_handle* h, void* stream) {
+  if (!h) return NNP_E_INVALID;
+  if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return NNP_E_HIP;
+  for (auto& p : h->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.second.first, p.second.second) != hipSuccess) return NNP_E_HIP;
+    h->prof_ms[p.first] += ms;
+    h->prof_n[p.first] += 1;
+  }
+  h->ev_pending.clear();
+  h->ev_next = 0;
+  return NNP_OK;
+}
+
+int32_t nnp_profile_stage_count(void) { return ST_COUNT; }
+
+const char* nnp_profile_stage_name(int32_t i) {
+  return (i >= 0 && i < ST_COUNT) ? kStageNames[i] : "";
+}
+
+nnp_status nnp_profile_read(const nnp_handle* h, double* total_ms, int64_t* count, int32_t max) {
+  if (!h) return NNP_E_INVALID;
+  for (int i = 0; i < max && i < ST_COUNT; ++i) {
+    if (total_ms) total_ms[i] = h->prof_ms[i];
+    if (count) count[i] = h->prof_n[i];
+  }
+  return NNP_OK;
+}
+
+nnp_status nnp_set_max_neighbors(nnp_handle* h, int32_t m) {
+  if (!h || m < 16 || m > 1024) return NNP_E_INVALID;
+  h->max_nbr = m;
+  return NNP_OK;
+}
+
+size_t nnp_workspace_bytes(const nnp_handle* h, int32_t n, int32_t nmol, const float* box) {
+  if (!h || n < 0 || nmol < 1) return 0;
+  BoxConst B;
+  if (!make_box(h, box, B)) return 0;
+  return make_plan(h, n, nmol, B).total;
+}
+
+nnp_status nnp_energy_forces(nnp_handle* h, int32_t n, int32_t nmol, const float* pos,
+                             const int32_t* species, const int32_t* off, const float* box,
+                             double* E, float* F, void* ws, size_t ws_bytes, void* stream) {
+  Plan P;
+  nnp_status s = check_common(h, n, nmol, pos, species, off, box, ws, ws_bytes, P);
+  if (s != NNP_OK) return s;
+  if (!E) return NNP_E_INVALID;
+  EvalIO io{n, nmol, pos, species, off, E, F, 1.f, nullptr, nullptr};
+  return run(h, P, ws, io, static_cast<hipStream_t>(stream));
+}
+
+nnp_status nnp_backward(nnp_handle* h, int32_t n, int32_t nmol, const float* pos,
+                        const int32_t* species, const int32_t* off, const float* box,
+                        const double* dLdE, float* dL_dpos, float* dL_dparams, double* E,
+                        void* ws, size_t ws_bytes, void* stream) {
+  Plan P;
+  nnp_status s = check_common(h, n, nmol, pos, species, off, box, ws, ws_bytes, P);
+  if (s != NNP_OK) return s;
+  if (!dLdE) return NNP_E_INVALID;
+  EvalIO io{n, nmol, pos, species, off, E, dL_dpos, -1.f, dLdE, dL_dparams};
+  return run(h, P, ws, io, static_cast<hipStream_t>(stream));
+}
+
+nnp_status nnp_check(const nnp_handle* h, void* ws, void* stream) {
+  if (!h || !ws) return NNP_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess) return NNP_E_HIP;
+  uint32_t word = 0;
+  if (hipMemcpy(&word, ws, 4, hipMemcpyDeviceToHost) != hipSuccess) return NNP_E_HIP;
+  if (word & kStOffsets) return NNP_E_INVALID;
+  if (word & kStSpecies) return NNP_E_SPECIES;
+  if (word & kStNonFinite) return NNP_E_NONFINITE;
+  if (word & kStCapacity) return NNP_E_CAPACITY;
+  return NNP_OK;
+}
+
+nnp_status nnp_debug_neighbors(nnp_handle* h, int32_t n, void* ws, size_t ws_bytes,
+                               int32_t* counts, int32_t* nbr, void* stream) {
+  if (!h || !ws || n < 0) return NNP_E_INVALID;
+  BoxConst B;
+  make_box(h, nullptr, B);
+  // the neighbor and count arrays sit at the same offsets with and without a box
+  Plan P = make_plan(h, n, 1, B);
+  if (ws_bytes < P.total) return NNP_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (counts && hipMemcpyAsync(counts, at<char>(ws, P.counts), (size_t)n * 8,
+                               hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return NNP_E_HIP;
+  if (nbr && hipMemcpyAsync(nbr, at<char>(ws, P.nbr), (size_t)n * P.cap * 4,
+                            hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return NNP_E_HIP;
+  return NNP_OK;
+}
+
+nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* pos,
+                         const int32_t* species, const int32_t* off, const float* box, float* aev,
+                         void* ws, size_t ws_bytes, void* stream) {
+  Plan P;
+  nnp_status s = check_common(h, n, nmol, pos, species, off, box, ws, ws_bytes, P);
+  if (s != NNP_OK) return s;
+  if (!aev) return NNP_E_INVALID;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int* dims = at<int>(ws, P.dims);
+  uint32_t* status = at<uint32_t>(ws, P.status);
+  float4* xyzs = at<float4>(ws, P.xyzs);
+  launch_stage(n, nmol, P.n, dims, pos, species, off, h->S, xyzs, at<int>(ws, P.mol), nullptr,
+               at<int>(ws, P.hist), status, st);
+  launch_groups(dims, P.n, h->S, at<int>(ws, P.hist), at<GroupTable>(ws, P.gt),
+                at<int>(ws, P.perm), P.rows_cap, off, kWChunk, status, st);
+  if (P.B.periodic)
+    launch_pairs_cell(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.cell_of), at<int>(ws, P.cell_cnt),
+                      at<int>(ws, P.cell_start), at<int>(ws, P.cursor), at<int>(ws, P.cell_atoms),
+                      at<float4>(ws, P.cell_xyzs), P.cap, at<int>(ws, P.nbr),
+                      at<int2>(ws, P.counts), status, st);
+  else
+    launch_pairs_mol(dims, P.n, h->C, xyzs, at<int>(ws, P.mol), off, P.cap, at<int>(ws, P.nbr),
+                     at<int2>(ws, P.counts), status, st);
+  launch_aev_fwd<float>(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.nbr), at<int2>(ws, P.counts),
+                        P.cap, nullptr, aev, h->F, st);
+  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
+// ------------------------------------------------------------------------- MD
+
+nnp_status nnp_md_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, double* v, float* F,
+                        const double* mass, const int32_t* species, const int32_t* off,
+                        const float* box, double dt, int32_t n_steps, double* E_pot,
+                        double* E_kin, void* ws, size_t ws_bytes, void* stream) {
+  if (!x || !v || !F || !mass || n_steps < 0 || !(dt > 0.0)) return NNP_E_INVALID;
+  Plan P;
+  float* pos32 = nullptr;
+  {
+    // positions are staged inside the workspace: validate with a dummy non-null pointer
+    nnp_status s = check_common(h, n, nmol, reinterpret_cast<const float*>(x), species, off, box,
+                                ws, ws_bytes, P);
+    if (s != NNP_OK) return s;
+    pos32 = at<float>(ws, P.pos32);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int* dims = at<int>(ws, P.dims);
+  // dims are written by the first force evaluation; integration kernels read them
+  double* Etmp = E_pot;
+  std::vector<double> dummy;
+  nnp_status s = NNP_OK;
+  for (int k = 0; k < n_steps && s == NNP_OK; ++k) {
+    if (k == 0) {
+      // the staging kernel of the first evaluation has not run yet: use counts by value
+      launch_fill_i32(dims, n, 1, st);
+      launch_fill_i32(dims + 1, nmol, 1, st);
+    }
+    launch_vv_kick_drift(dims, n, x, v, F, mass, dt, pos32, st);
+    EvalIO io{n, nmol, pos32, species, off, Etmp, F, 1.f, nullptr, nullptr};
+    s = run(h, P, ws, io, st);
+    if (s != NNP_OK) break;
+    launch_vv_kick(dims, n, v, F, mass, dt, st);
+  }
+  if (s == NNP_OK && E_kin) {
+    if (n_steps == 0) {
+      launch_fill_i32(dims, n, 1, st);
+      launch_fill_i32(dims + 1, nmol, 1, st);
+    }
+    launch_kinetic(dims, nmol, off, v, mass, E_kin, st);
+  }
+  if (s != NNP_OK) return s;
+  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
+}  // extern "C"

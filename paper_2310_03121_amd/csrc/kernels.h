@@ -1,0 +1,120 @@
+// Kernel entry points and launch helpers of the NNP engine.
+#pragma once
+
+#include "common.h"
+
+namespace nnp {
+
+enum { EPI_CELU = 0, EPI_HEAD = 1, EPI_BWD = 2, EPI_OUT32 = 3 };
+
+struct GemmArgs {
+  const void* A;
+  int lda;
+  const void* B;   // element s uses B + s * sB, row-major [N][K]
+  long sB;
+  int ldb;
+  const float* bias;
+  int sBias;
+  int N, K;
+  const GroupTable* gt;
+  void* C;
+  int ldc;
+  const void* H;   // EPI_BWD: activation whose CELU derivative scales acc
+  int ldh;
+  const float* w_out;  // EPI_HEAD: output-layer weights [S][N]
+  int sWout;
+  const float* b_out;  // [S]
+  float* erow;         // [rows] atomic energies (EPI_HEAD)
+  void* H3;            // optional store of the last hidden activation
+  int ldh3;
+  const int* perm;     // sorted row -> atom
+  const int* mol;      // atom -> molecule
+  const double* dLdE;  // per-molecule upstream gradient, or null for ones
+  float* uprow;        // optional store of the per-row upstream gradient (EPI_HEAD)
+  float alpha;
+  float inv_alpha_l2e; // log2(e) / alpha
+};
+
+struct PackArgs {
+  const float* flat;
+  long off[kMaxS * kLayers];  // flat offset of W for (species, layer)
+  int width[kLayers + 1];
+  int Fp;
+  float* Wf[kLayers];
+  bf16_t* Wb[kLayers];
+  float* WTf[kLayers];
+  bf16_t* WTb[kLayers];
+  float* bias[kLayers];
+  float* wout;
+  float* bout;
+};
+
+// stage.hip
+inline int stage_blocks(int n_cap) { return n_cap > 0 ? (n_cap + 255) / 256 : 1; }
+__global__ void k_fill_i32(int* p, int v, int n);
+__global__ void k_fill_f32(float* p, float v, long n);
+__global__ void k_fill_f64(double* p, double v, int n);
+void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
+                  const int* species, const int* off, int S, float4* xyzs, int* mol, float* Fzero,
+                  int* hist, uint32_t* status, hipStream_t st);
+void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
+                   int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
+                   hipStream_t st);
+void launch_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const int* hist,
+                    int* row, int* perm, hipStream_t st);
+void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* xyzs,
+                   const int* row, const float* erow, const double* eself, double* E,
+                   uint32_t* status, hipStream_t st);
+void launch_fill_i32(int* p, int v, int n, hipStream_t st);
+void launch_fill_f32(float* p, float v, long n, hipStream_t st);
+void launch_fill_f64(double* p, double v, int n, hipStream_t st);
+
+// neighbors.hip
+void launch_pairs_mol(const int* dims, int n_cap, const AevConst& C, const float4* xyzs,
+                      const int* mol, const int* off, int cap, int* nbr, int2* counts,
+                      uint32_t* status, hipStream_t st);
+void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
+                       const float4* xyzs, int* cell_of, int* cell_cnt, int* cell_start,
+                       int* cursor, int* cell_atoms, float4* cell_xyzs, int cap, int* nbr,
+                       int2* counts, uint32_t* status, hipStream_t st);
+
+// aev.hip
+template <typename OutT>
+void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
+                    const float4* xyzs, const int* nbr, const int2* counts, int cap,
+                    const int* row_of, OutT* out, int ld, hipStream_t st);
+void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
+                    const float4* xyzs, const int* nbr, const int2* counts, int cap,
+                    const int* row_of, const float* g, int ldg, float* out, float sign,
+                    hipStream_t st);
+
+// mlp.hip
+int gemm_pick_bn(int N, int epi);
+template <typename T>
+bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st);
+template <typename TD, typename TH>
+void launch_wgrad(const GroupTable* gt, int S, int n_chunks_cap, const TD* D, int ldd, int Nout,
+                  const TH* H, int ldh, int Nin, int chunk, float* partial, float* dparams,
+                  const long* param_off_dev, hipStream_t st);
+void launch_pack(const PackArgs& p, int S, hipStream_t st);
+
+// md.hip
+void launch_vv_kick_drift(const int* dims, int n_cap, double* x, double* v, const float* F,
+                          const double* mass, double dt, float* pos32, hipStream_t st);
+void launch_vv_kick(const int* dims, int n_cap, double* v, const float* F, const double* mass,
+                    double dt, hipStream_t st);
+void launch_kinetic(const int* dims, int nmol_cap, const int* off, const double* v,
+                    const double* mass, double* ke, hipStream_t st);
+void launch_gather_rows(const int* src, int n, const double* x_old, const double* v_old,
+                        const int* sp_old, const double* m_old, const float* f_old,
+                        const double* x_new_in, const double* v_new_in, const int* sp_new_in,
+                        const double* m_new_in, double* x, double* v, int* sp, double* m, float* f,
+                        hipStream_t st);
+void launch_serve_integrate(const int* dims, int n_cap, const int* mol, const int* kdone,
+                            const int* nsteps, double* x, double* v, const float* F,
+                            const double* mass, double dt, hipStream_t st);
+void launch_serve_advance(const int* dims, int nmol_cap, int* kdone, hipStream_t st);
+void launch_cast_pos(const int* dims, int n_cap, const double* x, float* pos32, hipStream_t st);
+void launch_copy_bytes(const void* a, void* b, size_t bytes, hipStream_t st);
+
+}  // namespace nnp

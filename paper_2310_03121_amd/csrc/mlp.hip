@@ -1,0 +1,416 @@
+// Per-element atomic networks as grouped GEMMs on MFMA.
+//
+// ANI potentials give each element its own network and sum the atomic
+// outputs (Methods, "OpenMM-ML").  Atoms are sorted by element into groups
+// that start at multiples of kPad rows, so one GEMM launch serves every
+// element: a tile of BM rows belongs to one group and uses that element's
+// weights.  Layers are C = A * B^T with A the row-major activations and B a
+// row-major [N][K] weight matrix (W for the forward pass, W^T copies for the
+// adjoint).  Epilogues are fused:
+//   CELU : h = CELU(acc + b)                                  (hidden layers)
+//   HEAD : h3 = CELU(acc + b); E_i = w_out . h3 + b_out;
+//          delta3 = upstream_i * w_out * CELU'(z3)             (last hidden layer)
+//   BWD  : delta = acc * CELU'(z) with CELU'(z) = 1 + h/alpha for h <= 0
+//   OUT32: plain float32 output (dE/dG)
+// BF16 operands use v_mfma_f32_16x16x32_bf16 and FP32 operands
+// v_mfma_f32_16x16x4f32; both accumulate in FP32.  Tiles stream through a
+// double-buffered LDS ring with one barrier per K step.
+#include "kernels.h"
+
+namespace nnp {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<bf16_t> {
+  static constexpr int BK = 32;    // K elements per LDS stage (64 bytes per row)
+  static constexpr int RS = 40;    // LDS row stride in elements (80 bytes)
+  __device__ __forceinline__ static void step(const bf16_t* a, const bf16_t* b, floatx4_t& acc) {
+    const uint4 ua = *reinterpret_cast<const uint4*>(a);
+    const uint4 ub = *reinterpret_cast<const uint4*>(b);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ua),
+                                                  __builtin_bit_cast(bf16x8_t, ub), acc, 0, 0, 0);
+  }
+  // lane's K offset inside a stage for the A/B fragment
+  __device__ __forceinline__ static int koff(int lane) { return (lane >> 4) * 8; }
+};
+template <> struct Mfma<float> {
+  static constexpr int BK = 16;
+  static constexpr int RS = 20;
+  __device__ __forceinline__ static void step(const float* a, const float* b, floatx4_t& acc) {
+    const float4 va = *reinterpret_cast<const float4*>(a);
+    const float4 vb = *reinterpret_cast<const float4*>(b);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.z, vb.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.w, vb.w, acc, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int koff(int lane) { return (lane >> 4) * 4; }
+};
+
+__device__ __forceinline__ float celu_f(float v, float alpha, float inv_alpha_l2e) {
+  return v > 0.f ? v : alpha * (__builtin_amdgcn_exp2f(v * inv_alpha_l2e) - 1.f);
+}
+
+template <typename T, int BM, int BN, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  constexpr int BK = Mfma<T>::BK, RS = Mfma<T>::RS;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int VPR = 4;                       // 16-byte vectors per stage row
+  constexpr int EPV = 16 / sizeof(T);          // elements per vector
+  constexpr int NVA = (BM * VPR + 255) / 256;  // vectors per thread, A
+  constexpr int NVB = (BN * VPR + 255) / 256;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  T* As = reinterpret_cast<T*>(smem);
+  T* Bs = As + 2 * BM * RS;
+
+  const GroupTable* gt = a.gt;
+  const int row0 = blockIdx.x * BM;
+  if (row0 >= gt->total_rows) return;
+  int s = 0;
+#pragma unroll
+  for (int q = 1; q < kMaxS; ++q) s = (row0 >= gt->pstart[q]) ? q : s;
+  const int row_end = gt->pstart[s] + gt->cnt[s];
+  if (row0 >= row_end) return;  // a tile of pad rows only
+  const int n0 = blockIdx.y * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+
+  const T* A = reinterpret_cast<const T*>(a.A);
+  const T* B = reinterpret_cast<const T*>(a.B) + (size_t)s * a.sB;
+  const int nk = a.K / BK;
+
+  uint4 ra[NVA], rb[NVB];
+  auto gload = [&](int kt) {
+    const int k0 = kt * BK;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * 256;
+      const int r = idx >> 2, sg = idx & 3;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (idx < BM * VPR && row0 + r < row_end)
+        val = *reinterpret_cast<const uint4*>(A + (size_t)(row0 + r) * a.lda + k0 + sg * EPV);
+      ra[v] = val;
+    }
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = tid + v * 256;
+      const int r = idx >> 2, sg = idx & 3;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (idx < BN * VPR && n0 + r < a.N)
+        val = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + r) * a.ldb + k0 + sg * EPV);
+      rb[v] = val;
+    }
+  };
+  auto lstore = [&](int buf) {
+    T* as = As + buf * BM * RS;
+    T* bs = Bs + buf * BN * RS;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * 256;
+      if (idx < BM * VPR) *reinterpret_cast<uint4*>(as + (idx >> 2) * RS + (idx & 3) * EPV) = ra[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NVB; ++v) {
+      const int idx = tid + v * 256;
+      if (idx < BN * VPR) *reinterpret_cast<uint4*>(bs + (idx >> 2) * RS + (idx & 3) * EPV) = rb[v];
+    }
+  };
+
+  floatx4_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int ko = Mfma<T>::koff(lane);
+  const int rl = lane & 15;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+    const T* as = As + buf * BM * RS + (wm * WTM + rl) * RS + ko;
+    const T* bs = Bs + buf * BN * RS + (wn * WTN + rl) * RS + ko;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) Mfma<T>::step(as + i * 16 * RS, bs + j * 16 * RS, acc[i][j]);
+    if (kt + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ------------------------------------------------------------- epilogue
+  const float* bias = a.bias ? a.bias + (size_t)s * a.sBias : nullptr;
+  const int rq = (lane >> 4) * 4;  // first of this lane's 4 rows inside a 16x16 tile
+  float epart[TM][4];
+  if constexpr (EPI == EPI_HEAD) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) epart[i][e] = 0.f;
+  }
+  const float* wout = (EPI == EPI_HEAD) ? a.w_out + (size_t)s * a.sWout : nullptr;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int rloc = wm * WTM + i * 16 + rq + e;
+      const int row = row0 + rloc;
+      const bool rv = row < row_end;
+      float up = 1.f;
+      if constexpr (EPI == EPI_HEAD) {
+        up = 0.f;
+        if (rv) {
+          up = 1.f;
+          if (a.dLdE) up = (float)a.dLdE[a.mol[a.perm[row]]];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = n0 + wn * WTN + j * 16 + rl;
+        if (col >= a.N) continue;
+        const float v = acc[i][j][e];
+        if constexpr (EPI == EPI_CELU) {
+          const float h = rv ? celu_f(v + bias[col], a.alpha, a.inv_alpha_l2e) : 0.f;
+          Store<T>::put(reinterpret_cast<T*>(a.C) + (size_t)row * a.ldc + col, h);
+        } else if constexpr (EPI == EPI_HEAD) {
+          const float z = v + bias[col];
+          const float ex = __builtin_amdgcn_exp2f(fminf(z, 0.f) * a.inv_alpha_l2e);
+          const float h = z > 0.f ? z : a.alpha * (ex - 1.f);
+          const float dh = z > 0.f ? 1.f : ex;
+          if (rv) epart[i][e] += wout[col] * h;
+          if (a.C)
+            Store<T>::put(reinterpret_cast<T*>(a.C) + (size_t)row * a.ldc + col,
+                          rv ? up * wout[col] * dh : 0.f);
+          if (a.H3)
+            Store<T>::put(reinterpret_cast<T*>(a.H3) + (size_t)row * a.ldh3 + col, rv ? h : 0.f);
+        } else if constexpr (EPI == EPI_BWD) {
+          float d = 0.f;
+          if (rv) {
+            const float hp = Store<T>::get(reinterpret_cast<const T*>(a.H) + (size_t)row * a.ldh + col);
+            d = v * (hp > 0.f ? 1.f : 1.f + hp / a.alpha);
+          }
+          Store<T>::put(reinterpret_cast<T*>(a.C) + (size_t)row * a.ldc + col, d);
+        } else {  // EPI_OUT32
+          reinterpret_cast<float*>(a.C)[(size_t)row * a.ldc + col] = rv ? v : 0.f;
+        }
+      }
+    }
+  }
+  if constexpr (EPI == EPI_HEAD) {
+    // sum the 16 column lanes of each row, then the two column halves (waves)
+    float* part = reinterpret_cast<float*>(smem);  // [2][BM], LDS reused after the K loop
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float v = epart[i][e];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        if (rl == 0) part[wn * BM + wm * WTM + i * 16 + rq + e] = v;
+      }
+    __syncthreads();
+    for (int t = tid; t < BM; t += 256) {
+      const int row = row0 + t;
+      if (row < row_end) a.erow[row] = part[t] + part[BM + t] + a.b_out[s];
+      if (a.uprow) {
+        float up = 0.f;
+        if (row < row_end) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
+        a.uprow[row] = up;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ launch helpers
+
+template <typename T, int BM, int BN, int EPI>
+static void launch_tile(const GemmArgs& a, int rows_cap, hipStream_t st) {
+  const size_t lds = (size_t)2 * (BM + BN) * Mfma<T>::RS * sizeof(T);
+  dim3 grid((rows_cap + BM - 1) / BM, (a.N + BN - 1) / BN);
+  hipLaunchKernelGGL((k_gemm<T, BM, BN, EPI>), grid, dim3(256), lds, st, a);
+}
+
+template <typename T, int EPI>
+static bool launch_bn(const GemmArgs& a, int rows_cap, int BN, hipStream_t st) {
+  switch (BN) {
+    case 64: launch_tile<T, 128, 64, EPI>(a, rows_cap, st); return true;
+    case 96: launch_tile<T, 128, 96, EPI>(a, rows_cap, st); return true;
+    case 128: launch_tile<T, 128, 128, EPI>(a, rows_cap, st); return true;
+    case 160: launch_tile<T, 128, 160, EPI>(a, rows_cap, st); return true;
+    case 192: launch_tile<T, 128, 192, EPI>(a, rows_cap, st); return true;
+    case 256: launch_tile<T, 128, 256, EPI>(a, rows_cap, st); return true;
+    default: return false;
+  }
+}
+
+int gemm_pick_bn(int N, int epi) {
+  if (epi == EPI_HEAD) return N;
+  if (N <= 256) return N;
+  if (N % 256 == 0) return 256;
+  if (N % 192 == 0) return 192;
+  if (N % 128 == 0) return 128;
+  return 64;
+}
+
+template <typename T>
+bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st) {
+  const int BN = gemm_pick_bn(a.N, epi);
+  switch (epi) {
+    case EPI_CELU: return launch_bn<T, EPI_CELU>(a, rows_cap, BN, st);
+    case EPI_HEAD: return launch_bn<T, EPI_HEAD>(a, rows_cap, BN, st);
+    case EPI_BWD: return launch_bn<T, EPI_BWD>(a, rows_cap, BN, st);
+    case EPI_OUT32: return launch_bn<T, EPI_OUT32>(a, rows_cap, BN, st);
+  }
+  return false;
+}
+template bool launch_gemm<float>(int, const GemmArgs&, int, hipStream_t);
+template bool launch_gemm<bf16_t>(int, const GemmArgs&, int, hipStream_t);
+
+// ------------------------------------------------------------ weight gradients
+//
+// dW[o][i] = sum over the element's rows of D[r][o] * H[r][i];  db[o] = sum D[r][o].
+// The rows of each element are cut into chunks of `chunk` rows; block
+// (chunk, o-tile, i-tile) writes its partial sums, and a second kernel adds
+// the partials of each element in chunk order (deterministic).
+
+template <typename TD, typename TH>
+__global__ __launch_bounds__(256) void k_wgrad(const GroupTable* __restrict__ gt, int S,
+                                               const TD* __restrict__ D, int ldd, int Nout,
+                                               const TH* __restrict__ H, int ldh, int Nin,
+                                               int chunk, float* __restrict__ partial) {
+  __shared__ float sd[32][65];
+  __shared__ float sh[32][65];
+  const int c = blockIdx.x;
+  if (c >= gt->n_wchunks) return;
+  int s = 0;
+  for (int q = 1; q < S; ++q) s = (c >= gt->wchunk[q]) ? q : s;
+  const int r0 = gt->pstart[s] + (c - gt->wchunk[s]) * chunk;
+  int r1 = r0 + chunk;
+  const int rend = gt->pstart[s] + gt->cnt[s];
+  r1 = r1 < rend ? r1 : rend;
+  const int o0 = blockIdx.y * 64, i0 = blockIdx.z * 64;
+  const int tid = threadIdx.x;
+  const int to = (tid >> 4) * 4, ti = (tid & 15) * 4;
+  float acc[4][4] = {};
+  float bacc = 0.f;
+  for (int r = r0; r < r1; r += 32) {
+    for (int v = tid; v < 32 * 64; v += 256) {
+      const int rr = v >> 6, cc = v & 63;
+      const int row = r + rr;
+      const bool ok = row < r1;
+      sd[rr][cc] = (ok && o0 + cc < Nout) ? Store<TD>::get(D + (size_t)row * ldd + o0 + cc) : 0.f;
+      sh[rr][cc] = (ok && i0 + cc < Nin) ? Store<TH>::get(H + (size_t)row * ldh + i0 + cc) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int rr = 0; rr < 32; ++rr) {
+      float dv[4], hv[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        dv[x] = sd[rr][to + x];
+        hv[x] = sh[rr][ti + x];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += dv[x] * hv[y];
+    }
+    if (blockIdx.z == 0 && tid < 64) {
+      for (int rr = 0; rr < 32; ++rr) bacc += sd[rr][tid];
+    }
+    __syncthreads();
+  }
+  float* out = partial + (size_t)c * ((size_t)Nout * Nin + Nout);
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int o = o0 + to + x, i = i0 + ti + y;
+      if (o < Nout && i < Nin) out[(size_t)o * Nin + i] = acc[x][y];
+    }
+  if (blockIdx.z == 0 && tid < 64 && o0 + tid < Nout) out[(size_t)Nout * Nin + o0 + tid] = bacc;
+}
+
+// out[s] (W then b, Nout*Nin + Nout floats at param_off[s]) = sum of partials.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const GroupTable* __restrict__ gt, int S,
+                                                      const float* __restrict__ partial, int len,
+                                                      float* __restrict__ dparams,
+                                                      const long* __restrict__ param_off) {
+  const int s = blockIdx.y;
+  if (s >= S) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  float v = 0.f;
+  for (int c = gt->wchunk[s]; c < gt->wchunk[s + 1]; ++c) v += partial[(size_t)c * len + e];
+  dparams[param_off[s] + e] = v;
+}
+
+template <typename TD, typename TH>
+void launch_wgrad(const GroupTable* gt, int S, int n_chunks_cap, const TD* D, int ldd, int Nout,
+                  const TH* H, int ldh, int Nin, int chunk, float* partial, float* dparams,
+                  const long* param_off_dev, hipStream_t st) {
+  dim3 grid(n_chunks_cap, (Nout + 63) / 64, (Nin + 63) / 64);
+  hipLaunchKernelGGL((k_wgrad<TD, TH>), grid, dim3(256), 0, st, gt, S, D, ldd, Nout, H, ldh, Nin,
+                     chunk, partial);
+  const int len = Nout * Nin + Nout;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((len + 255) / 256, S), dim3(256), 0, st, gt, S, partial,
+                     len, dparams, param_off_dev);
+}
+template void launch_wgrad<float, float>(const GroupTable*, int, int, const float*, int, int,
+                                         const float*, int, int, int, float*, float*, const long*,
+                                         hipStream_t);
+template void launch_wgrad<bf16_t, bf16_t>(const GroupTable*, int, int, const bf16_t*, int, int,
+                                           const bf16_t*, int, int, int, float*, float*,
+                                           const long*, hipStream_t);
+template void launch_wgrad<float, bf16_t>(const GroupTable*, int, int, const float*, int, int,
+                                          const bf16_t*, int, int, int, float*, float*,
+                                          const long*, hipStream_t);
+
+// ------------------------------------------------------------ weight packing
+//
+// From the flat parameter vector (per species, per layer: W row-major
+// out x in, then b) to: W_l [S][out][in_pad] (float and bf16), W_l^T
+// [S][in_pad][out] (float and bf16), biases [S][out], output weights [S][w3]
+// and output biases [S].  One thread per (species, layer, out, in_pad).
+__global__ __launch_bounds__(256) void k_pack(PackArgs p) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = blockIdx.y, s = blockIdx.z;
+  const int in = p.width[l], out = p.width[l + 1];
+  const int inp = l == 0 ? p.Fp : in;
+  const float* src = p.flat + p.off[s * kLayers + l];
+  if (l < kLayers - 1) {
+    if (t >= (long)out * inp) return;
+    const int o = (int)(t / inp), i = (int)(t % inp);
+    const float v = i < in ? src[(size_t)o * in + i] : 0.f;
+    const size_t ws = (size_t)s * out * inp;
+    p.Wf[l][ws + (size_t)o * inp + i] = v;
+    p.Wb[l][ws + (size_t)o * inp + i] = f2bf(v);
+    p.WTf[l][ws + (size_t)i * out + o] = v;
+    p.WTb[l][ws + (size_t)i * out + o] = f2bf(v);
+    if (i == 0) p.bias[l][(size_t)s * out + o] = src[(size_t)out * in + o];
+  } else {
+    if (t >= in) return;
+    p.wout[(size_t)s * in + t] = src[t];
+    if (t == 0) p.bout[s] = src[in];
+  }
+}
+
+void launch_pack(const PackArgs& p, int S, hipStream_t st) {
+  long maxel = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    const long inp = l == 0 ? p.Fp : p.width[l];
+    const long el = (long)p.width[l + 1] * inp;
+    maxel = el > maxel ? el : maxel;
+  }
+  dim3 grid((unsigned)((maxel + 255) / 256), kLayers, S);
+  hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, st, p);
+}
+
+}  // namespace nnp

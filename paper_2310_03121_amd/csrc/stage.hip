@@ -1,0 +1,262 @@
+// Staging, species sort and energy reduction.
+//
+// Staging turns the caller's AoS float32 positions into float4 records
+// (x, y, z, species bits), finds each atom's molecule from the offsets, zeroes
+// the force output, validates species and positions, and histograms species
+// per block.  The species sort is a stable counting sort: every species group
+// starts at a multiple of kPad rows, so the per-element network GEMMs can tile
+// rows without a tile straddling two elements (one network per element,
+// Methods "OpenMM-ML").  The molecular energy is the FP64 sum of the FP32
+// atomic energies plus self energies.
+#include "kernels.h"
+
+namespace nnp {
+
+__global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __restrict__ dims,
+                                               const float* __restrict__ pos,
+                                               const int* __restrict__ species,
+                                               const int* __restrict__ off, int S,
+                                               float4* __restrict__ xyzs, int* __restrict__ mol,
+                                               float* __restrict__ Fzero, int* __restrict__ hist,
+                                               uint32_t* __restrict__ status) {
+  __shared__ int h[kMaxS];
+  __shared__ uint32_t bits;
+  const int n = n_arg >= 0 ? n_arg : dims[0];
+  const int nmol = nmol_arg >= 0 ? nmol_arg : dims[1];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n_arg >= 0) {
+    dims[0] = n;
+    dims[1] = nmol;
+  }
+  if (threadIdx.x < kMaxS) h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) bits = 0;
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    int s = species[i];
+    uint32_t st = 0;
+    if (s < 0 || s >= S) {
+      st |= kStSpecies;
+      s = clampi(s, S);
+    }
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+      st |= kStNonFinite;
+      x = y = z = 0.f;
+    }
+    // molecule: the last m with off[m] <= i (off is non-decreasing when valid)
+    int lo = 0, hi = nmol;
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    mol[i] = lo;
+    xyzs[i] = make_float4(x, y, z, __int_as_float(s));
+    if (Fzero) {
+      Fzero[3 * i] = 0.f;
+      Fzero[3 * i + 1] = 0.f;
+      Fzero[3 * i + 2] = 0.f;
+    }
+    atomicAdd(&h[s], 1);
+    if (st) atomicOr(&bits, st);
+  }
+  __syncthreads();
+  if (threadIdx.x < S) hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+  // this block's error bits; the group kernel folds them into the status word
+  if (threadIdx.x == 0) hist[kMaxS * gridDim.x + blockIdx.x] = (int)bits;
+}
+
+// One block: species totals, padded group starts, per-block bases of the
+// stable scatter, pad-row markers, molecule-offset validation, the chunk
+// table of the weight-gradient reduction, and the evaluation's status word
+// (overwritten here; kernels that run later only add bits).
+__global__ __launch_bounds__(1024) void k_groups(const int* __restrict__ dims, int nblk, int S,
+                                                 int* __restrict__ hist, GroupTable* __restrict__ gt,
+                                                 int* __restrict__ perm, int rows_cap,
+                                                 const int* __restrict__ off, int wchunk_rows,
+                                                 uint32_t* __restrict__ status) {
+  __shared__ int tot[kMaxS];
+  __shared__ int pst[kMaxS + 1];
+  __shared__ int scan[1024];
+  const int n = dims[0], nmol = dims[1];
+  const int t = threadIdx.x;
+  if (t < kMaxS) tot[t] = 0;
+  __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    int acc = 0;
+    for (int b = t; b < nblk; b += blockDim.x) acc += hist[s * nblk + b];
+    atomicAdd(&tot[s], acc);
+  }
+  __syncthreads();
+  if (t == 0) {
+    int p = 0, c = 0;
+    for (int s = 0; s < kMaxS; ++s) {
+      int cnt = s < S ? tot[s] : 0;
+      pst[s] = p;
+      gt->cnt[s] = cnt;
+      gt->pstart[s] = p;
+      gt->wchunk[s] = c;
+      p += (cnt + kPad - 1) / kPad * kPad;
+      c += (cnt + wchunk_rows - 1) / wchunk_rows;
+    }
+    pst[kMaxS] = p;
+    gt->pstart[kMaxS] = p;
+    gt->wchunk[kMaxS] = c;
+    gt->total_rows = p;
+    gt->n_wchunks = c;
+  }
+  __syncthreads();
+  // exclusive scan of each species' block counts, offset by the group start
+  for (int s = 0; s < S; ++s) {
+    int carry = pst[s];
+    for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
+      int b = b0 + t;
+      int v = b < nblk ? hist[s * nblk + b] : 0;
+      scan[t] = v;
+      __syncthreads();
+      for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        int u = t >= o ? scan[t - o] : 0;
+        __syncthreads();
+        scan[t] += u;
+        __syncthreads();
+      }
+      if (b < nblk) hist[s * nblk + b] = carry + scan[t] - v;
+      int last = scan[blockDim.x - 1];
+      __syncthreads();
+      carry += last;
+    }
+  }
+  // pad rows: inside each group after its atoms, and after the last group
+  for (int s = 0; s < kMaxS; ++s) {
+    int a = pst[s] + (s < S ? tot[s] : 0), b = pst[s + 1];
+    for (int r = a + t; r < b; r += blockDim.x) perm[r] = -1;
+  }
+  for (int r = pst[kMaxS] + t; r < rows_cap; r += blockDim.x) perm[r] = -1;
+  // offsets: off[0] == 0, non-decreasing, off[nmol] == n
+  bool bad = false;
+  for (int m = t; m < nmol; m += blockDim.x) bad |= off[m] > off[m + 1];
+  if (t == 0) bad |= off[0] != 0 || off[nmol] != n;
+  // status word of this evaluation: staging bits of every block + offsets
+  uint32_t bits = bad ? kStOffsets : 0u;
+  for (int b = t; b < nblk; b += blockDim.x) bits |= (uint32_t)hist[kMaxS * nblk + b];
+  scan[t] = (int)bits;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t all = 0;
+    for (int k = 0; k < (int)blockDim.x; ++k) all |= (uint32_t)scan[k];
+    *status = all;
+  }
+}
+
+// Stable scatter into species-sorted rows: rank = block base + earlier waves
+// of the block + earlier lanes of the wave with the same species.
+__global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ dims, int S,
+                                                 const float4* __restrict__ xyzs,
+                                                 const int* __restrict__ hist, int* __restrict__ row,
+                                                 int* __restrict__ perm) {
+  __shared__ int wcnt[4][kMaxS];
+  const int n = dims[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = threadIdx.x >> 6;
+  const int s = i < n ? species_of(xyzs[i]) : -1;
+  int rank = 0;
+  for (int q = 0; q < S; ++q) {
+    uint64_t m = ballot(s == q);
+    if (s == q) rank = popc_below(m);
+    if (lane_id() == 0) wcnt[w][q] = __popcll(m);
+  }
+  __syncthreads();
+  if (i < n) {
+    int base = hist[s * gridDim.x + blockIdx.x];
+    for (int v = 0; v < w; ++v) base += wcnt[v][s];
+    int r = base + rank;
+    row[i] = r;
+    perm[r] = i;
+  }
+}
+
+// One wave per molecule: E_m = sum_i (double)E_row[row[i]] + e_self[s_i].
+__global__ __launch_bounds__(256) void k_energy(const int* __restrict__ dims,
+                                                const int* __restrict__ off,
+                                                const float4* __restrict__ xyzs,
+                                                const int* __restrict__ row,
+                                                const float* __restrict__ erow,
+                                                const double* __restrict__ eself,
+                                                double* __restrict__ E, uint32_t* __restrict__ status) {
+  const int n = dims[0], nmol = dims[1];
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= nmol) return;
+  int a = off[m], b = off[m + 1];
+  a = a < 0 ? 0 : (a > n ? n : a);
+  b = b < a ? a : (b > n ? n : b);
+  double acc = 0.0;
+  for (int i = a + lane_id(); i < b; i += kWave)
+    acc += (double)erow[row[i]] + eself[species_of(xyzs[i])];
+  acc = wave_sum_d(acc);
+  if (lane_id() == 0) {
+    E[m] = acc;
+    if (!isfinite(acc)) atomicOr(status, kStNonFinite);
+  }
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, int v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, float v, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, double v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ----------------------------------------------------------------- launchers
+
+void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
+                  const int* species, const int* off, int S, float4* xyzs, int* mol, float* Fzero,
+                  int* hist, uint32_t* status, hipStream_t st) {
+  const int nblk = stage_blocks(n_cap);
+  hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, dims, pos, species,
+                     off, S, xyzs, mol, Fzero, hist, status);
+}
+
+void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
+                   int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_groups, dim3(1), dim3(1024), 0, st, dims, stage_blocks(n_cap), S, hist, gt,
+                     perm, rows_cap, off, wchunk_rows, status);
+}
+
+void launch_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const int* hist,
+                    int* row, int* perm, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3(stage_blocks(n_cap)), dim3(256), 0, st, dims, S, xyzs, hist,
+                     row, perm);
+}
+
+void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* xyzs,
+                   const int* row, const float* erow, const double* eself, double* E,
+                   uint32_t* status, hipStream_t st) {
+  if (nmol_cap <= 0) return;
+  hipLaunchKernelGGL(k_energy, dim3((nmol_cap + 3) / 4), dim3(256), 0, st, dims, off, xyzs, row,
+                     erow, eself, E, status);
+}
+
+void launch_fill_i32(int* p, int v, int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+}
+
+void launch_fill_f32(float* p, float v, long n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
+}
+
+void launch_fill_f64(double* p, double v, int n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+}
+
+}  // namespace nnp
