@@ -125,8 +125,8 @@ size_t nnp_param_count(const nnp_handle* h);
  * (float32, nnp_param_count() entries); enqueued on `stream`. */
 nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* stream);
 
-/* Neighbor-list capacity per atom (default 128, range 16..1024).  A larger
- * capacity needs a larger workspace. */
+/* Neighbor-list capacity per atom (default 128, range 16..512, rounded up to
+ * a multiple of 16).  A larger capacity needs a larger workspace. */
 nnp_status nnp_set_max_neighbors(nnp_handle* h, int32_t max_neighbors);
 
 /* Bytes of workspace an evaluation of this shape needs.  `box` is host memory

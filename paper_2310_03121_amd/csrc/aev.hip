@@ -7,16 +7,15 @@
 // are the negative gradient of the energy (Methods, "PyTorch Model Support").
 //
 // Per atom the wave first loads its neighbor records into LDS (displacement,
-// distance, cutoff values, species).  Radial terms use lanes (g, m): four
-// neighbors at a time, one radial shift m per lane; per-species sums stay in
-// registers and are combined across the four neighbor slots by lane shuffles.
-// Angular terms are enumerated per unordered species-pair block: the neighbor
-// list is grouped by species, so the triples of block (p, q) are the products
-// of two species segments (or the pairs inside one).  Lanes (t, z) take eight
-// triples at a time, one angle shift z per lane, and keep the four radial
-// shifts in registers; the block's 32 sums are combined across triple slots
-// by shuffles and written once, so every output element is written by one
-// store in a fixed summation order.  The angle term uses the identity
+// distance, cutoff values, species) and clears an LDS copy of its feature
+// row.  Radial terms use lanes (g, m): four neighbors at a time, one radial
+// shift m per lane; per-species sums stay in registers and are combined
+// across the four neighbor slots by lane shuffles.  Angular terms run over
+// the unordered pairs {j, k} of angular neighbors directly: lanes (t, z) take
+// eight pairs at a time, one angle shift z per lane, and add their four
+// radial-shift terms to the LDS row at the pair's species block (LDS atomic
+// adds).  The finished row is written to global memory once, four features
+// per lane, so the output is coalesced.  The angle term uses the identity
 // cos(theta - theta_z) = kappa c cos(theta_z) + sqrt(1 - kappa^2 c^2) sin(theta_z)
 // for theta = acos(kappa c); (1 + cos)/2 raised to zeta is exp2(zeta log2(.)).
 //
@@ -28,12 +27,6 @@
 
 namespace nnp {
 
-struct NbrLds {
-  float4* d;    // dx, dy, dz, r
-  float4* fc;   // fc_rad, fc_ang, dfc_rad, dfc_ang
-  int* sp;
-};
-
 __device__ __forceinline__ float cutoff_val(float r, float inv_rc, float& dfc, float pi_2rc) {
   float s, c;
   sincospif(r * inv_rc, &s, &c);
@@ -41,80 +34,40 @@ __device__ __forceinline__ float cutoff_val(float r, float inv_rc, float& dfc, f
   return 0.5f * c + 0.5f;
 }
 
-// Loads neighbor records of atom i into LDS; returns (nr, na).
-__device__ __forceinline__ int2 load_neighbors(const AevConst& C, const BoxConst& B, int i,
-                                               const float4* __restrict__ xyzs,
-                                               const int* __restrict__ nbr,
-                                               const int2* __restrict__ counts, int cap, int n,
-                                               NbrLds L) {
-  const int lane = lane_id();
-  const int2 cn = counts[i];
-  const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
-  const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
-  const float4 pi = xyzs[i];
-  for (int e = lane; e < nr; e += kWave) {
-    const int j = clampi(nbr[(size_t)i * cap + e], n);
-    const float4 pj = xyzs[j];
-    const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], B.periodic);
-    const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], B.periodic);
-    const float dz = disp(pi.z, pj.z, B.L[2], B.invL[2], B.periodic);
-    const float r = sqrtf(dist2(dx, dy, dz));
-    float dfr, dfa = 0.f;
-    const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
-    float fa = 0.f;
-    if (e < na) fa = cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a);
-    L.d[e] = make_float4(dx, dy, dz, r);
-    L.fc[e] = make_float4(fr, fa, dfr, dfa);
-    L.sp[e] = species_of(pj);
-  }
-  return make_int2(nr, na);
-}
-
-// Start of each species segment among the angular entries [0, na) (the list
-// is grouped by species there).  Lane q < 9 returns the first index whose
-// species is >= q.
-__device__ __forceinline__ int segment_start(const int* sp, int na, int q) {
-  int lo = 0, hi = na;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (sp[mid] < q) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-// Triple t of block (p, q) -> entries (ej, ek) of the neighbor list.
-__device__ __forceinline__ void decode_triple(int t, bool same, int sp0, int cp, int sq0, int cq,
-                                              int& ej, int& ek) {
-  if (!same) {
-    const int a = t / cq;
-    ej = sp0 + a;
-    ek = sq0 + (t - a * cq);
-    return;
-  }
-  // pairs a < b of one segment, row-major: start(a) = a*cp - a*(a+1)/2
-  const float c2 = (float)(2 * cp - 1);
-  int a = (int)((c2 - sqrtf(fmaxf(c2 * c2 - 8.f * (float)t, 0.f))) * 0.5f);
-  a = a < 0 ? 0 : (a > cp - 2 ? cp - 2 : a);
-  while (a > 0 && a * cp - a * (a + 1) / 2 > t) --a;
-  while (a + 1 <= cp - 2 && (a + 1) * cp - (a + 1) * (a + 2) / 2 <= t) ++a;
-  const int b = t - (a * cp - a * (a + 1) / 2) + a + 1;
-  ej = sp0 + a;
-  ek = sp0 + b;
-}
-
-__device__ __forceinline__ float sel8(const float (&v)[kMaxS], int q) {
-  float r = v[0];
+// Per-lane entry of a table held in the (uniform) kernel arguments, by
+// unrolled selects: indexing the argument struct with a lane-dependent index
+// would copy it to scratch memory.
+template <int N>
+__device__ __forceinline__ float pick(const float (&tab)[N], int idx) {
+  float r = tab[0];
 #pragma unroll
-  for (int k = 1; k < kMaxS; ++k) r = (q == k) ? v[k] : r;
+  for (int k = 1; k < N; ++k) r = (idx == k) ? tab[k] : r;
   return r;
-}
-
-__device__ __forceinline__ float sel4(float a0, float a1, float a2, float a3, int q) {
-  return q == 0 ? a0 : (q == 1 ? a1 : (q == 2 ? a2 : a3));
 }
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+// Unordered pair t of the list prefix [0, na) -> entries a < b (row-major:
+// pairs before row a number a*na - a*(a+1)/2).
+__device__ __forceinline__ void decode_pair(int t, int na, int& a, int& b) {
+  const float c2 = (float)(2 * na - 1);
+  int r = (int)((c2 - sqrtf(fmaxf(c2 * c2 - 8.f * (float)t, 0.f))) * 0.5f);
+  r = r < 0 ? 0 : (r > na - 2 ? na - 2 : r);
+  while (r > 0 && r * na - r * (r + 1) / 2 > t) --r;
+  while (r + 1 <= na - 2 && (r + 1) * na - (r + 1) * (r + 2) / 2 <= t) ++r;
+  a = r;
+  b = t - (r * na - r * (r + 1) / 2) + r + 1;
+}
+
+__device__ __forceinline__ int pair_block(int p, int q, int S) {
+  const int lo = p < q ? p : q, hi = p < q ? q : p;
+  return lo * S - lo * (lo - 1) / 2 + (hi - lo);
+}
+
+// LDS per wave (forward): feature row [Fp] float, then per neighbor
+// float4 (dx, dy, dz, r), float2 (fc_rad, fc_ang), int species.
+constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
 
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, AevConst C, BoxConst B,
@@ -129,29 +82,48 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   const int lane = lane_id();
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
-  NbrLds L;
-  L.d = lds4 + (size_t)w * cap * 2;
-  L.fc = L.d + cap;
-  L.sp = reinterpret_cast<int*>(lds4 + (size_t)4 * cap * 2) + w * cap;
-  const int2 cnt = load_neighbors(C, B, i, xyzs, nbr, counts, cap, n, L);
-  const int nr = cnt.x, na = cnt.y;
+  const int Fp = C.Fp;
+  char* base = reinterpret_cast<char*>(lds4) + (size_t)w * (Fp * 4 + cap * kFwdBytesPerNbr);
+  float* rowl = reinterpret_cast<float*>(base);
+  float4* nd = reinterpret_cast<float4*>(rowl + Fp);
+  float2* nf = reinterpret_cast<float2*>(nd + cap);
+  int* nsp = reinterpret_cast<int*>(nf + cap);
+
+  const int2 cn = counts[i];
+  const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
+  const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
+  const float4 pi = xyzs[i];
+  for (int e = lane; e < nr; e += kWave) {
+    const int j = clampi(nbr[(size_t)i * cap + e], n);
+    const float4 pj = xyzs[j];
+    const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], B.periodic);
+    const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], B.periodic);
+    const float dz = disp(pi.z, pj.z, B.L[2], B.invL[2], B.periodic);
+    const float r = sqrtf(dist2(dx, dy, dz));
+    float dfr, dfa;
+    const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
+    const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
+    nd[e] = make_float4(dx, dy, dz, r);
+    nf[e] = make_float2(fr, fa);
+    nsp[e] = species_of(pj);
+  }
+  for (int c = lane * 4; c < Fp; c += 4 * kWave)
+    *reinterpret_cast<float4*>(rowl + c) = make_float4(0.f, 0.f, 0.f, 0.f);
   wave_lds_sync();
-  OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
   const int S = C.S;
 
-  // ---- radial
+  // ---- radial: lanes (g, m), four neighbors per pass, per-species registers
   {
     const int g = lane >> 4, m = lane & 15;
-    const float Rm = C.shf_r[m];
+    const float Rm = pick(C.shf_r, m);
     float acc[kMaxS];
 #pragma unroll
     for (int q = 0; q < kMaxS; ++q) acc[q] = 0.f;
     for (int e = g; e < nr; e += 4) {
-      const float r = L.d[e].w;
-      const float fr = L.fc[e].x;
-      const int s = L.sp[e];
+      const float r = nd[e].w;
       const float u = r - Rm;
-      const float term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * fr;
+      const float term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x;
+      const int s = nsp[e];
 #pragma unroll
       for (int q = 0; q < kMaxS; ++q) acc[q] += (s == q) ? term : 0.f;
     }
@@ -159,64 +131,54 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
     for (int q = 0; q < kMaxS; ++q) {
       acc[q] += __shfl_xor(acc[q], 16, 64);
       acc[q] += __shfl_xor(acc[q], 32, 64);
+      if ((q & 3) == g && q < S) rowl[q * kNR + m] = acc[q];
     }
-    const float v0 = sel8(acc, g), v1 = sel8(acc, g + 4);
-    if (g < S) Store<OutT>::put(orow + g * kNR + m, v0);
-    if (g + 4 < S) Store<OutT>::put(orow + (g + 4) * kNR + m, v1);
   }
 
-  // ---- angular
-  const int seg_mine = lane <= kMaxS ? segment_start(L.sp, na, lane) : na;
-  const int tz = lane & 7, tg = lane >> 3;
-  const float cz = C.cos_z[tz], sz = C.sin_z[tz];
-  const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
-  int blk = 0;
-  for (int p = 0; p < S; ++p) {
-    const int sp0 = __shfl(seg_mine, p, 64);
-    const int cp = __shfl(seg_mine, p + 1, 64) - sp0;
-    for (int q = p; q < S; ++q, ++blk) {
-      const int sq0 = __shfl(seg_mine, q, 64);
-      const int cq = __shfl(seg_mine, q + 1, 64) - sq0;
-      const bool same = p == q;
-      const int T = same ? cp * (cp - 1) / 2 : cp * cq;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-      for (int t0 = 0; t0 < T; t0 += 8) {
-        const int t = t0 + tg;
-        if (t < T) {
-          int ej, ek;
-          decode_triple(t, same, sp0, cp, sq0, cq, ej, ek);
-          const float4 vj = L.d[ej], vk = L.d[ek];
-          const float fj = L.fc[ej].y, fk = L.fc[ek].y;
-          const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) / (vj.w * vk.w);
-          const float kc = C.kappa * cs;
-          const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
-          const float cd = kc * cz + sn * sz;
-          const float base = 0.5f + 0.5f * cd;
-          const float f1 = 2.f * fast_exp2(C.zeta * fast_log2(base));
-          const float dbar = 0.5f * (vj.w + vk.w);
-          const float wgt = f1 * fj * fk;
-          float u;
-          u = dbar - ra0; a0 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-          u = dbar - ra1; a1 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-          u = dbar - ra2; a2 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-          u = dbar - ra3; a3 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-        }
-      }
-#pragma unroll
-      for (int o = 8; o <= 32; o <<= 1) {
-        a0 += __shfl_xor(a0, o, 64);
-        a1 += __shfl_xor(a1, o, 64);
-        a2 += __shfl_xor(a2, o, 64);
-        a3 += __shfl_xor(a3, o, 64);
-      }
-      if (lane < 32) {
-        const float v = sel4(a0, a1, a2, a3, lane >> 3);
-        Store<OutT>::put(orow + S * kNR + blk * 32 + lane, v);
+  // ---- angular: lanes (t, z), eight unordered neighbor pairs per pass
+  {
+    const int tz = lane & 7, tg = lane >> 3;
+    const float cz = pick(C.cos_z, tz), sz = pick(C.sin_z, tz);
+    const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
+    const int T = na * (na - 1) / 2;
+    float* ang = rowl + S * kNR + tz;
+    for (int t0 = 0; t0 < T; t0 += 8) {
+      const int t = t0 + tg;
+      if (t < T) {
+        int ej, ek;
+        decode_pair(t, na, ej, ek);
+        const float4 vj = nd[ej], vk = nd[ek];
+        const float fj = nf[ej].y, fk = nf[ek].y;
+        const int blk = pair_block(nsp[ej], nsp[ek], S);
+        const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) / (vj.w * vk.w);
+        const float kc = C.kappa * cs;
+        const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
+        const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
+        const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fj * fk;
+        const float dbar = 0.5f * (vj.w + vk.w);
+        float* dst = ang + blk * 32;
+        float u;
+        u = dbar - ra0; atomicAdd(dst, wgt * fast_exp2(-C.eta_a_l2e * u * u));
+        u = dbar - ra1; atomicAdd(dst + 8, wgt * fast_exp2(-C.eta_a_l2e * u * u));
+        u = dbar - ra2; atomicAdd(dst + 16, wgt * fast_exp2(-C.eta_a_l2e * u * u));
+        u = dbar - ra3; atomicAdd(dst + 24, wgt * fast_exp2(-C.eta_a_l2e * u * u));
       }
     }
   }
-  for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
+  wave_lds_sync();
+
+  // ---- write the row (coalesced, 4 features per lane and pass)
+  OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
+  for (int c = lane * 4; c < ld; c += 4 * kWave) {
+    const float4 v = *reinterpret_cast<const float4*>(rowl + c);
+    Store<OutT>::put4(orow + c, v);
+  }
 }
+
+// LDS per wave (adjoint): dE/dG row [Fp] float, then per neighbor float4
+// (dx, dy, dz, r), float4 (fc_rad, fc_ang, dfc_rad, dfc_ang), float4
+// accumulated dE/d(displacement), int species.
+constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 
 // Adjoint: g (float32 rows, stride ldg) -> scatter into out (float32 [n][3]).
 // sign = +1 writes forces (-dE/dr); sign = -1 writes the gradient dE/dr.
@@ -233,32 +195,52 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   const int lane = lane_id();
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
-  NbrLds L;
-  L.d = lds4 + (size_t)w * cap * 3;
-  L.fc = L.d + cap;
-  float4* grad = L.fc + cap;
-  L.sp = reinterpret_cast<int*>(lds4 + (size_t)4 * cap * 3) + w * cap;
-  const int2 cnt = load_neighbors(C, B, i, xyzs, nbr, counts, cap, n, L);
-  const int nr = cnt.x, na = cnt.y;
-  const float* grow = g + (size_t)row_of[i] * ldg;
+  const int Fp = C.Fp;
+  char* base = reinterpret_cast<char*>(lds4) + (size_t)w * (Fp * 4 + cap * kBwdBytesPerNbr);
+  float* grow = reinterpret_cast<float*>(base);
+  float4* nd = reinterpret_cast<float4*>(grow + Fp);
+  float4* nf = nd + cap;
+  float4* grad = nf + cap;
+  int* nsp = reinterpret_cast<int*>(grad + cap);
+
+  const int2 cn = counts[i];
+  const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
+  const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
+  const float4 pi = xyzs[i];
+  const float* gsrc = g + (size_t)row_of[i] * ldg;
+  for (int c = lane * 4; c < Fp; c += 4 * kWave)
+    *reinterpret_cast<float4*>(grow + c) = *reinterpret_cast<const float4*>(gsrc + c);
+  for (int e = lane; e < nr; e += kWave) {
+    const int j = clampi(nbr[(size_t)i * cap + e], n);
+    const float4 pj = xyzs[j];
+    const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], B.periodic);
+    const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], B.periodic);
+    const float dz = disp(pi.z, pj.z, B.L[2], B.invL[2], B.periodic);
+    const float r = sqrtf(dist2(dx, dy, dz));
+    float dfr, dfa = 0.f;
+    const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
+    const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
+    nd[e] = make_float4(dx, dy, dz, r);
+    nf[e] = make_float4(fr, fa, dfr, dfa);
+    nsp[e] = species_of(pj);
+  }
+  wave_lds_sync();
   const int S = C.S;
 
   // ---- radial: dE/dr_ij per neighbor, reduced over the 16 shift lanes
   {
     const int gq = lane >> 4, m = lane & 15;
-    const float Rm = C.shf_r[m];
-    wave_lds_sync();
+    const float Rm = pick(C.shf_r, m);
     for (int e0 = 0; e0 < nr; e0 += 4) {
       const int e = e0 + gq;
       float contrib = 0.f;
       float4 v = make_float4(0.f, 0.f, 0.f, 1.f);
       if (e < nr) {
-        v = L.d[e];
-        const float4 f = L.fc[e];
-        const int s = L.sp[e];
+        v = nd[e];
+        const float4 f = nf[e];
         const float u = v.w - Rm;
         const float ex = C.cR * fast_exp2(-C.eta_r_l2e * u * u);
-        contrib = grow[s * kNR + m] * ex * (f.z - C.eta_r2 * u * f.x);
+        contrib = grow[nsp[e] * kNR + m] * ex * (f.z - C.eta_r2 * u * f.x);
       }
 #pragma unroll
       for (int o = 1; o < 16; o <<= 1) contrib += __shfl_xor(contrib, o, 64);
@@ -267,81 +249,69 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
         grad[e] = make_float4(v.x * sc, v.y * sc, v.z * sc, 0.f);
       }
     }
-    wave_lds_sync();
   }
+  wave_lds_sync();
 
-  // ---- angular
-  const int seg_mine = lane <= kMaxS ? segment_start(L.sp, na, lane) : na;
-  const int tz = lane & 7, tg = lane >> 3;
-  const float cz = C.cos_z[tz], sz = C.sin_z[tz];
-  const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
-  int blk = 0;
-  for (int p = 0; p < S; ++p) {
-    const int sp0 = __shfl(seg_mine, p, 64);
-    const int cp = __shfl(seg_mine, p + 1, 64) - sp0;
-    for (int q = p; q < S; ++q, ++blk) {
-      const int sq0 = __shfl(seg_mine, q, 64);
-      const int cq = __shfl(seg_mine, q + 1, 64) - sq0;
-      const bool same = p == q;
-      const int T = same ? cp * (cp - 1) / 2 : cp * cq;
-      if (T == 0) continue;
-      const float* gb = grow + S * kNR + blk * 32 + tz;
-      const float g0 = gb[0], g1 = gb[8], g2 = gb[16], g3 = gb[24];
-      for (int t0 = 0; t0 < T; t0 += 8) {
-        const int t = t0 + tg;
-        float X0 = 0.f, X1 = 0.f, Xc = 0.f;
-        int ej = 0, ek = 0;
-        float4 vj = make_float4(0.f, 0.f, 0.f, 1.f), vk = vj;
-        float fj = 0.f, fk = 0.f, dfj = 0.f, dfk = 0.f, cs = 0.f;
-        if (t < T) {
-          decode_triple(t, same, sp0, cp, sq0, cq, ej, ek);
-          vj = L.d[ej];
-          vk = L.d[ek];
-          const float4 cj = L.fc[ej], ck = L.fc[ek];
-          fj = cj.y; fk = ck.y; dfj = cj.w; dfk = ck.w;
-          cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) / (vj.w * vk.w);
-          const float kc = C.kappa * cs;
-          const float sn = sqrtf(fmaxf(1.f - kc * kc, 1e-12f));
-          const float cd = kc * cz + sn * sz;
-          const float base = 0.5f + 0.5f * cd;
-          const float pw = fast_exp2(C.zeta * fast_log2(base));
-          const float f1 = 2.f * pw;
-          // d f1 / d c = 2 zeta base^(zeta-1) * 0.5 * d cd / d c
-          const float dcd = C.kappa * (cz - kc * sz / sn);
-          const float df1 = C.zeta * pw / base * dcd;
-          const float dbar = 0.5f * (vj.w + vk.w);
-          float u, e2, A0 = 0.f, A1 = 0.f;
-          u = dbar - ra0; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g0 * e2; A1 -= g0 * C.eta_a * u * e2;
-          u = dbar - ra1; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g1 * e2; A1 -= g1 * C.eta_a * u * e2;
-          u = dbar - ra2; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g2 * e2; A1 -= g2 * C.eta_a * u * e2;
-          u = dbar - ra3; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g3 * e2; A1 -= g3 * C.eta_a * u * e2;
-          X0 = f1 * A0;
-          X1 = f1 * A1;
-          Xc = df1 * A0;
-        }
+  // ---- angular: lanes (t, z), eight unordered pairs per pass
+  {
+    const int tz = lane & 7, tg = lane >> 3;
+    const float cz = pick(C.cos_z, tz), sz = pick(C.sin_z, tz);
+    const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
+    const int T = na * (na - 1) / 2;
+    const float* gang = grow + S * kNR + tz;
+    for (int t0 = 0; t0 < T; t0 += 8) {
+      const int t = t0 + tg;
+      float X0 = 0.f, X1 = 0.f, Xc = 0.f;
+      int ej = 0, ek = 0;
+      float4 vj = make_float4(0.f, 0.f, 0.f, 1.f), vk = vj;
+      float fj = 0.f, fk = 0.f, dfj = 0.f, dfk = 0.f, cs = 0.f;
+      if (t < T) {
+        decode_pair(t, na, ej, ek);
+        vj = nd[ej];
+        vk = nd[ek];
+        const float4 cj = nf[ej], ck = nf[ek];
+        fj = cj.y; fk = ck.y; dfj = cj.w; dfk = ck.w;
+        const float* gb = gang + pair_block(nsp[ej], nsp[ek], S) * 32;
+        const float g0 = gb[0], g1 = gb[8], g2 = gb[16], g3 = gb[24];
+        cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) / (vj.w * vk.w);
+        const float kc = C.kappa * cs;
+        const float sn = sqrtf(fmaxf(1.f - kc * kc, 1e-12f));
+        const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
+        const float pw = fast_exp2(C.zeta * fast_log2(base_));
+        const float f1 = 2.f * pw;
+        // d f1 / d c = zeta base^(zeta-1) d(kappa c cos_z + sqrt(1-kappa^2 c^2) sin_z)/dc
+        const float df1 = C.zeta * pw / base_ * (C.kappa * (cz - kc * sz / sn));
+        const float dbar = 0.5f * (vj.w + vk.w);
+        float u, e2, A0 = 0.f, A1 = 0.f;
+        u = dbar - ra0; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g0 * e2; A1 -= g0 * u * e2;
+        u = dbar - ra1; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g1 * e2; A1 -= g1 * u * e2;
+        u = dbar - ra2; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g2 * e2; A1 -= g2 * u * e2;
+        u = dbar - ra3; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g3 * e2; A1 -= g3 * u * e2;
+        X0 = f1 * A0;
+        X1 = f1 * A1 * C.eta_a;
+        Xc = df1 * A0;
+      }
 #pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-          X0 += __shfl_xor(X0, o, 64);
-          X1 += __shfl_xor(X1, o, 64);
-          Xc += __shfl_xor(Xc, o, 64);
-        }
-        if (t < T && tz == 0) {
-          const float fcc = fj * fk;
-          const float dEdc = Xc * fcc;
-          const float dEdj = X1 * fcc + X0 * dfj * fk;
-          const float dEdk = X1 * fcc + X0 * fj * dfk;
-          const float ijk = 1.f / (vj.w * vk.w);
-          const float ij2 = 1.f / (vj.w * vj.w), ik2 = 1.f / (vk.w * vk.w);
-          const float aj = dEdj / vj.w - dEdc * cs * ij2;
-          const float ak = dEdk / vk.w - dEdc * cs * ik2;
-          const float b = dEdc * ijk;
-          atomicAdd(&grad[ej].x, aj * vj.x + b * vk.x);
-          atomicAdd(&grad[ej].y, aj * vj.y + b * vk.y);
-          atomicAdd(&grad[ej].z, aj * vj.z + b * vk.z);
-          atomicAdd(&grad[ek].x, ak * vk.x + b * vj.x);
-          atomicAdd(&grad[ek].y, ak * vk.y + b * vj.y);
-          atomicAdd(&grad[ek].z, ak * vk.z + b * vj.z);
-        }
+      for (int o = 1; o < 8; o <<= 1) {
+        X0 += __shfl_xor(X0, o, 64);
+        X1 += __shfl_xor(X1, o, 64);
+        Xc += __shfl_xor(Xc, o, 64);
+      }
+      if (t < T && tz == 0) {
+        const float fcc = fj * fk;
+        const float dEdc = Xc * fcc;
+        const float dEdj = X1 * fcc + X0 * dfj * fk;
+        const float dEdk = X1 * fcc + X0 * fj * dfk;
+        const float ijk = 1.f / (vj.w * vk.w);
+        const float aj = dEdj / vj.w - dEdc * cs / (vj.w * vj.w);
+        const float ak = dEdk / vk.w - dEdc * cs / (vk.w * vk.w);
+        const float bb = dEdc * ijk;
+        atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
+        atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
+        atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
+        atomicAdd(&grad[ek].x, ak * vk.x + bb * vj.x);
+        atomicAdd(&grad[ek].y, ak * vk.y + bb * vj.y);
+        atomicAdd(&grad[ek].z, ak * vk.z + bb * vj.z);
       }
     }
   }
@@ -376,7 +346,9 @@ void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const BoxCons
                     const float4* xyzs, const int* nbr, const int2* counts, int cap,
                     const int* row_of, OutT* out, int ld, hipStream_t st) {
   if (n_cap <= 0) return;
-  const size_t lds = (size_t)4 * cap * (2 * sizeof(float4) + sizeof(int));
+  const size_t lds = (size_t)4 * (C.Fp * 4 + cap * kFwdBytesPerNbr);
+  static const bool attr = (ensure_lds(k_aev_fwd<OutT>), true);
+  (void)attr;
   hipLaunchKernelGGL(k_aev_fwd<OutT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, B,
                      xyzs, nbr, counts, cap, row_of, out, ld);
 }
@@ -393,7 +365,9 @@ void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const BoxCons
                     const int* row_of, const float* g, int ldg, float* out, float sign,
                     hipStream_t st) {
   if (n_cap <= 0) return;
-  const size_t lds = (size_t)4 * cap * (3 * sizeof(float4) + sizeof(int));
+  const size_t lds = (size_t)4 * (C.Fp * 4 + cap * kBwdBytesPerNbr);
+  static const bool attr = (ensure_lds(k_aev_bwd), true);
+  (void)attr;
   hipLaunchKernelGGL(k_aev_bwd, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, B, xyzs, nbr,
                      counts, cap, row_of, g, ldg, out, sign);
 }

@@ -116,10 +116,18 @@ template <typename T> struct Store;
 template <> struct Store<float> {
   __device__ __forceinline__ static void put(float* p, float v) { *p = v; }
   __device__ __forceinline__ static float get(const float* p) { return *p; }
+  __device__ __forceinline__ static void put4(float* p, float4 v) {
+    *reinterpret_cast<float4*>(p) = v;
+  }
 };
 template <> struct Store<bf16_t> {
   __device__ __forceinline__ static void put(bf16_t* p, float v) { *p = f2bf(v); }
   __device__ __forceinline__ static float get(const bf16_t* p) { return bf2f(*p); }
+  __device__ __forceinline__ static void put4(bf16_t* p, float4 v) {
+    const uint32_t lo = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+    const uint32_t hi = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+    *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
+  }
 };
 
 // ------------------------------------------------------------- fp32 predicate
@@ -137,6 +145,15 @@ __device__ __forceinline__ float dist2(float dx, float dy, float dz) {
 }
 
 __device__ __forceinline__ int species_of(float4 p) { return __float_as_int(p.w); }
+
+// Raises a kernel's dynamic LDS limit to the gfx950 maximum (160 KB per
+// workgroup; the default is 64 KB), once per kernel, before its first launch
+// (so never while a stream is being captured into a graph).
+template <typename K>
+inline void ensure_lds(K* kernel) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
 
 // Clamp a (possibly corrupt) index into [0, n).
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }

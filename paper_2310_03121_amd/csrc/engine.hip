@@ -594,8 +594,8 @@ nnp_status nnp_profile_read(const nnp_handle* h, double* total_ms, int64_t* coun
 }
 
 nnp_status nnp_set_max_neighbors(nnp_handle* h, int32_t m) {
-  if (!h || m < 16 || m > 1024) return NNP_E_INVALID;
-  h->max_nbr = m;
+  if (!h || m < 16 || m > 512) return NNP_E_INVALID;
+  h->max_nbr = (m + 15) / 16 * 16;  // keeps the per-wave LDS regions 16-byte aligned
   return NNP_OK;
 }
 
@@ -731,6 +731,453 @@ nnp_status nnp_md_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, doubl
   }
   if (s != NNP_OK) return s;
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
+}  // extern "C"
+
+// =================================================================== serving
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+  int64_t id = 0;
+  int n = 0;
+  int n_steps = 0;
+  int k = 0;  // steps issued (host mirror of the device counter)
+  std::vector<double> x, v;
+  std::vector<int> sp;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  double e_pot = 0, e_kin = 0;
+};
+
+}  // namespace
+
+struct nnp_server {
+  nnp_handle* h = nullptr;
+  hipStream_t st = nullptr;
+  double dt = 0.5;
+  double mass_tab[kMaxS] = {};
+  int max_atoms = 0, max_mols = 0;
+  size_t bytes = 0;
+  char* dmem = nullptr;
+  // active state (fixed addresses: the step graph refers to them)
+  double *x = nullptr, *v = nullptr, *m = nullptr;
+  int* sp = nullptr;
+  float* F = nullptr;
+  float* pos32 = nullptr;
+  int *off = nullptr, *kdone = nullptr, *nsteps = nullptr;
+  double *epot = nullptr, *ekin = nullptr;
+  // repack scratch and staging of admitted atoms
+  double *x2 = nullptr, *v2 = nullptr, *m2 = nullptr;
+  int* sp2 = nullptr;
+  float* F2 = nullptr;
+  int* src = nullptr;
+  double *in_x = nullptr, *in_v = nullptr, *in_m = nullptr;
+  int* in_sp = nullptr;
+  void* ws = nullptr;
+  Plan P;
+  // pinned host mirrors
+  char* hmem = nullptr;
+  int *h_src = nullptr, *h_off = nullptr, *h_kdone = nullptr, *h_nsteps = nullptr,
+      *h_dims = nullptr, *h_in_sp = nullptr;
+  double *h_in_x = nullptr, *h_in_v = nullptr, *h_in_m = nullptr, *h_out = nullptr;
+  hipEvent_t ev_upload = nullptr;
+  // graph of one step
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool warmed = false;
+  // requests
+  std::deque<Req*> pending;
+  std::vector<Req*> active;
+  std::map<int64_t, Req*> finished;
+  std::deque<int64_t> done_q;
+  int active_atoms = 0;
+  ~nnp_server() {
+    for (Req* r : pending) delete r;
+    for (Req* r : active) delete r;
+    for (auto& kv : finished) delete kv.second;
+  }
+};
+
+namespace {
+
+size_t server_state_bytes(int A, int M) {
+  size_t b = 0;
+  auto add = [&](size_t x) { b = align_up(b + x, 256); };
+  add((size_t)A * 24); add((size_t)A * 24); add((size_t)A * 8); add((size_t)A * 4);
+  add((size_t)A * 12); add((size_t)A * 12);
+  add((size_t)(M + 1) * 4); add((size_t)M * 4); add((size_t)M * 4); add((size_t)M * 8);
+  add((size_t)M * 8);
+  add((size_t)A * 24); add((size_t)A * 24); add((size_t)A * 8); add((size_t)A * 4);
+  add((size_t)A * 12); add((size_t)A * 4);
+  add((size_t)A * 24); add((size_t)A * 24); add((size_t)A * 8); add((size_t)A * 4);
+  return b;
+}
+
+// One MD step of the packed batch: forces at x, integration by per-molecule
+// phase, kinetic energies, counters.  Every kernel reads the live atom and
+// molecule counts from the workspace, so the same launches (or their graph)
+// serve any batch up to the capacity.
+nnp_status server_enqueue_step(nnp_server* s) {
+  nnp_handle* h = s->h;
+  const Plan& P = s->P;
+  int* dims = at<int>(s->ws, P.dims);
+  launch_cast_pos(dims, s->max_atoms, s->x, s->pos32, s->st);
+  EvalIO io{-1, -1, s->pos32, s->sp, s->off, s->epot, s->F, 1.f, nullptr, nullptr};
+  nnp_status r = run(h, P, s->ws, io, s->st);
+  if (r != NNP_OK) return r;
+  launch_serve_integrate(dims, s->max_atoms, at<int>(s->ws, P.mol), s->kdone, s->nsteps, s->x,
+                         s->v, s->F, s->m, s->dt, s->st);
+  launch_kinetic(dims, s->max_mols, s->off, s->v, s->m, s->ekin, s->st);
+  launch_serve_advance(dims, s->max_mols, s->kdone, s->st);
+  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+nnp_status nnp_server_create(nnp_handle* h, size_t budget, int32_t max_atoms, int32_t max_mols,
+                             double dt_fs, const double* mass_amu, void* stream,
+                             nnp_server** out) {
+  (void)stream;
+  if (!h || !out || !mass_amu || max_atoms < 1 || max_mols < 1 || !(dt_fs > 0.0))
+    return NNP_E_INVALID;
+  *out = nullptr;
+  if (hipSetDevice(h->device) != hipSuccess) return NNP_E_HIP;
+  // fit the capacity to the HBM budget: state + workspace at capacity
+  BoxConst B;
+  make_box(h, nullptr, B);
+  int A = max_atoms;
+  for (;;) {
+    const size_t need = server_state_bytes(A, max_mols) + make_plan(h, A, max_mols, B).total;
+    if (need <= budget) break;
+    const int A2 = (int)((double)A * (double)budget / (double)need * 0.98);
+    if (A2 < 1 || A2 >= A) return NNP_E_OOM;
+    A = A2;
+  }
+  nnp_server* s = new (std::nothrow) nnp_server();
+  if (!s) return NNP_E_OOM;
+  s->h = h;
+  s->dt = dt_fs;
+  for (int q = 0; q < h->S; ++q) s->mass_tab[q] = mass_amu[q];
+  s->max_atoms = A;
+  s->max_mols = max_mols;
+  s->P = make_plan(h, A, max_mols, B);
+  const size_t sb = server_state_bytes(A, max_mols);
+  s->bytes = sb + s->P.total;
+  if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc(&s->dmem, s->bytes) != hipSuccess) {
+    if (s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+    return NNP_E_OOM;
+  }
+  size_t o = 0;
+  auto take = [&](size_t x) {
+    char* p = s->dmem + o;
+    o = align_up(o + x, 256);
+    return p;
+  };
+  s->x = (double*)take((size_t)A * 24);
+  s->v = (double*)take((size_t)A * 24);
+  s->m = (double*)take((size_t)A * 8);
+  s->sp = (int*)take((size_t)A * 4);
+  s->F = (float*)take((size_t)A * 12);
+  s->pos32 = (float*)take((size_t)A * 12);
+  s->off = (int*)take((size_t)(max_mols + 1) * 4);
+  s->kdone = (int*)take((size_t)max_mols * 4);
+  s->nsteps = (int*)take((size_t)max_mols * 4);
+  s->epot = (double*)take((size_t)max_mols * 8);
+  s->ekin = (double*)take((size_t)max_mols * 8);
+  s->x2 = (double*)take((size_t)A * 24);
+  s->v2 = (double*)take((size_t)A * 24);
+  s->m2 = (double*)take((size_t)A * 8);
+  s->sp2 = (int*)take((size_t)A * 4);
+  s->F2 = (float*)take((size_t)A * 12);
+  s->src = (int*)take((size_t)A * 4);
+  s->in_x = (double*)take((size_t)A * 24);
+  s->in_v = (double*)take((size_t)A * 24);
+  s->in_m = (double*)take((size_t)A * 8);
+  s->in_sp = (int*)take((size_t)A * 4);
+  s->ws = s->dmem + align_up(sb, 256);
+  // pinned host mirrors
+  // src, in_sp | off, kdone, nsteps | dims | in_x, in_v, in_m | out (x, v, energies)
+  const size_t hb = (size_t)A * 8 + (size_t)(max_mols + 1) * 12 + 64 + (size_t)A * 56 +
+                    (size_t)A * 48 + (size_t)max_mols * 16 + 4096;
+  if (hipHostMalloc((void**)&s->hmem, hb) != hipSuccess) {
+    (void)hipFree(s->dmem);
+    (void)hipStreamDestroy(s->st);
+    delete s;
+    return NNP_E_OOM;
+  }
+  size_t ho = 0;
+  auto htake = [&](size_t x) {
+    char* p = s->hmem + ho;
+    ho = align_up(ho + x, 64);
+    return p;
+  };
+  s->h_src = (int*)htake((size_t)A * 4);
+  s->h_in_sp = (int*)htake((size_t)A * 4);
+  s->h_off = (int*)htake((size_t)(max_mols + 1) * 4);
+  s->h_kdone = (int*)htake((size_t)max_mols * 4);
+  s->h_nsteps = (int*)htake((size_t)max_mols * 4);
+  s->h_dims = (int*)htake(16);
+  s->h_in_x = (double*)htake((size_t)A * 24);
+  s->h_in_v = (double*)htake((size_t)A * 24);
+  s->h_in_m = (double*)htake((size_t)A * 8);
+  s->h_out = (double*)htake((size_t)A * 48 + (size_t)max_mols * 16);
+  (void)hipEventCreateWithFlags(&s->ev_upload, hipEventDisableTiming);
+  // empty batch: counts 0, offsets {0}
+  s->h_dims[0] = 0;
+  s->h_dims[1] = 0;
+  s->h_off[0] = 0;
+  bool ok = hip_ok(hipMemcpyAsync(at<int>(s->ws, s->P.dims), s->h_dims, 8, hipMemcpyHostToDevice,
+                                  s->st)) &&
+            hip_ok(hipMemcpyAsync(s->off, s->h_off, 4, hipMemcpyHostToDevice, s->st)) &&
+            hip_ok(hipStreamSynchronize(s->st));
+  if (!ok) {
+    nnp_server_destroy(s);
+    return NNP_E_HIP;
+  }
+  *out = s;
+  return NNP_OK;
+}
+
+void nnp_server_destroy(nnp_server* s) {
+  if (!s) return;
+  (void)hipSetDevice(s->h->device);
+  if (s->st) (void)hipStreamSynchronize(s->st);
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->ev_upload) (void)hipEventDestroy(s->ev_upload);
+  if (s->hmem) (void)hipHostFree(s->hmem);
+  if (s->dmem) (void)hipFree(s->dmem);
+  if (s->st) (void)hipStreamDestroy(s->st);
+  delete s;
+}
+
+nnp_status nnp_server_submit(nnp_server* s, int64_t id, int32_t n, const double* x,
+                             const double* v, const int32_t* species, int32_t n_steps) {
+  if (!s || n < 1 || !x || !v || !species || n_steps < 1) return NNP_E_INVALID;
+  if (n > s->max_atoms) return NNP_E_BUSY;
+  for (int i = 0; i < n; ++i)
+    if (species[i] < 0 || species[i] >= s->h->S) return NNP_E_SPECIES;
+  Req* r = new (std::nothrow) Req();
+  if (!r) return NNP_E_OOM;
+  r->id = id;
+  r->n = n;
+  r->n_steps = n_steps;
+  r->x.assign(x, x + 3 * (size_t)n);
+  r->v.assign(v, v + 3 * (size_t)n);
+  r->sp.assign(species, species + n);
+  r->t_submit = now_s();
+  s->pending.push_back(r);
+  return NNP_OK;
+}
+
+int32_t nnp_server_active(const nnp_server* s) { return s ? (int32_t)s->active.size() : 0; }
+int32_t nnp_server_pending(const nnp_server* s) { return s ? (int32_t)s->pending.size() : 0; }
+
+nnp_status nnp_server_step(nnp_server* s) {
+  if (!s) return NNP_E_INVALID;
+  if (hipSetDevice(s->h->device) != hipSuccess) return NNP_E_HIP;
+  // 1. drop requests whose final step ran in the previous round
+  std::vector<Req*> keep;
+  bool changed = false;
+  for (Req* r : s->active) {
+    if (r->k > r->n_steps) {
+      changed = true;
+      s->active_atoms -= r->n;
+    } else {
+      keep.push_back(r);
+    }
+  }
+  // 2. admit in arrival order while atoms and molecule slots allow
+  std::vector<Req*> admit;
+  int atoms = s->active_atoms;
+  int mols = (int)keep.size();
+  while (!s->pending.empty()) {
+    Req* r = s->pending.front();
+    if (atoms + r->n > s->max_atoms || mols + 1 > s->max_mols) break;
+    s->pending.pop_front();
+    admit.push_back(r);
+    atoms += r->n;
+    ++mols;
+  }
+  if (!admit.empty()) changed = true;
+  // 3. repack on the device: survivors keep their state, admitted atoms come
+  //    from staging
+  if (changed) {
+    if (hipEventSynchronize(s->ev_upload) != hipSuccess) return NNP_E_HIP;
+    std::vector<int> old_start(s->active.size());
+    {
+      int o = 0;
+      for (size_t q = 0; q < s->active.size(); ++q) {
+        old_start[q] = o;
+        o += s->active[q]->n;
+      }
+    }
+    int t = 0, mcount = 0, staged = 0;
+    s->h_off[0] = 0;
+    size_t aq = 0;
+    for (size_t q = 0; q < s->active.size(); ++q) {
+      Req* r = s->active[q];
+      if (r->k > r->n_steps) continue;
+      for (int i = 0; i < r->n; ++i) s->h_src[t++] = old_start[q] + i;
+      s->h_kdone[mcount] = r->k;
+      s->h_nsteps[mcount] = r->n_steps;
+      s->h_off[++mcount] = t;
+      ++aq;
+    }
+    const double now = now_s();
+    for (Req* r : admit) {
+      for (int i = 0; i < r->n; ++i) {
+        s->h_src[t++] = -(staged + i) - 1;
+        for (int c = 0; c < 3; ++c) {
+          s->h_in_x[3 * (staged + i) + c] = r->x[3 * i + c];
+          s->h_in_v[3 * (staged + i) + c] = r->v[3 * i + c];
+        }
+        s->h_in_sp[staged + i] = r->sp[i];
+        s->h_in_m[staged + i] = s->mass_tab[r->sp[i]];
+      }
+      staged += r->n;
+      r->k = 0;
+      r->t_admit = now;
+      s->h_kdone[mcount] = 0;
+      s->h_nsteps[mcount] = r->n_steps;
+      s->h_off[++mcount] = t;
+    }
+    s->h_dims[0] = t;
+    s->h_dims[1] = mcount;
+    hipStream_t st = s->st;
+    bool ok = true;
+    if (staged) {
+      ok &= hip_ok(hipMemcpyAsync(s->in_x, s->h_in_x, (size_t)staged * 24, hipMemcpyHostToDevice, st));
+      ok &= hip_ok(hipMemcpyAsync(s->in_v, s->h_in_v, (size_t)staged * 24, hipMemcpyHostToDevice, st));
+      ok &= hip_ok(hipMemcpyAsync(s->in_m, s->h_in_m, (size_t)staged * 8, hipMemcpyHostToDevice, st));
+      ok &= hip_ok(hipMemcpyAsync(s->in_sp, s->h_in_sp, (size_t)staged * 4, hipMemcpyHostToDevice, st));
+    }
+    if (t) ok &= hip_ok(hipMemcpyAsync(s->src, s->h_src, (size_t)t * 4, hipMemcpyHostToDevice, st));
+    ok &= hip_ok(hipMemcpyAsync(s->off, s->h_off, (size_t)(mcount + 1) * 4, hipMemcpyHostToDevice, st));
+    if (mcount) {
+      ok &= hip_ok(hipMemcpyAsync(s->kdone, s->h_kdone, (size_t)mcount * 4, hipMemcpyHostToDevice, st));
+      ok &= hip_ok(hipMemcpyAsync(s->nsteps, s->h_nsteps, (size_t)mcount * 4, hipMemcpyHostToDevice, st));
+    }
+    ok &= hip_ok(hipMemcpyAsync(at<int>(s->ws, s->P.dims), s->h_dims, 8, hipMemcpyHostToDevice, st));
+    ok &= hip_ok(hipEventRecord(s->ev_upload, st));
+    if (!ok) return NNP_E_HIP;
+    launch_gather_rows(s->src, t, s->x, s->v, s->sp, s->m, s->F, s->in_x, s->in_v, s->in_sp,
+                       s->in_m, s->x2, s->v2, s->sp2, s->m2, s->F2, st);
+    ok &= hip_ok(hipMemcpyAsync(s->x, s->x2, (size_t)t * 24, hipMemcpyDeviceToDevice, st));
+    ok &= hip_ok(hipMemcpyAsync(s->v, s->v2, (size_t)t * 24, hipMemcpyDeviceToDevice, st));
+    ok &= hip_ok(hipMemcpyAsync(s->m, s->m2, (size_t)t * 8, hipMemcpyDeviceToDevice, st));
+    ok &= hip_ok(hipMemcpyAsync(s->sp, s->sp2, (size_t)t * 4, hipMemcpyDeviceToDevice, st));
+    if (!ok) return NNP_E_HIP;
+    std::vector<Req*> next;
+    for (Req* r : keep) next.push_back(r);
+    for (Req* r : admit) next.push_back(r);
+    s->active.swap(next);
+    s->active_atoms = atoms;
+  }
+  if (s->active.empty()) return NNP_OK;
+  // 4. one step over the whole batch (graph replay after a first eager step)
+  nnp_status r;
+  if (!s->warmed) {
+    r = server_enqueue_step(s);
+    if (r != NNP_OK) return r;
+    s->warmed = true;
+  } else {
+    if (!s->exec) {
+      if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return NNP_E_HIP;
+      r = server_enqueue_step(s);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(s->st, &g);
+      if (r != NNP_OK || ec != hipSuccess) return r != NNP_OK ? r : NNP_E_HIP;
+      s->graph = g;
+      if (hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0) != hipSuccess) return NNP_E_HIP;
+    }
+    if (hipGraphLaunch(s->exec, s->st) != hipSuccess) return NNP_E_HIP;
+  }
+  for (Req* q : s->active) q->k += 1;
+  // 5. requests whose closing half kick ran: copy results out
+  std::vector<std::pair<Req*, int>> fin;
+  {
+    int o = 0, mi = 0;
+    for (Req* q : s->active) {
+      if (q->k > q->n_steps) fin.push_back({q, o});
+      o += q->n;
+      ++mi;
+    }
+  }
+  if (!fin.empty()) {
+    size_t ho = 0;
+    std::vector<size_t> at_h;
+    bool ok = true;
+    for (auto& f : fin) {
+      at_h.push_back(ho);
+      const size_t nb = (size_t)f.first->n * 24;
+      ok &= hip_ok(hipMemcpyAsync(s->h_out + ho, s->x + 3 * (size_t)f.second, nb,
+                                  hipMemcpyDeviceToHost, s->st));
+      ok &= hip_ok(hipMemcpyAsync(s->h_out + ho + 3 * f.first->n, s->v + 3 * (size_t)f.second,
+                                  nb, hipMemcpyDeviceToHost, s->st));
+      ho += 6 * (size_t)f.first->n;
+    }
+    // molecule energies: index of each finishing molecule in the batch
+    const size_t eo = ho;
+    ok &= hip_ok(hipMemcpyAsync(s->h_out + eo, s->epot, s->active.size() * 8,
+                                hipMemcpyDeviceToHost, s->st));
+    ok &= hip_ok(hipMemcpyAsync(s->h_out + eo + s->active.size(), s->ekin,
+                                s->active.size() * 8, hipMemcpyDeviceToHost, s->st));
+    ok &= hip_ok(hipStreamSynchronize(s->st));
+    if (!ok) return NNP_E_HIP;
+    const double now = now_s();
+    for (size_t q = 0; q < fin.size(); ++q) {
+      Req* r = fin[q].first;
+      const double* hx = s->h_out + at_h[q];
+      r->x.assign(hx, hx + 3 * (size_t)r->n);
+      r->v.assign(hx + 3 * r->n, hx + 6 * (size_t)r->n);
+      size_t mi = 0;
+      while (s->active[mi] != r) ++mi;
+      r->e_pot = s->h_out[eo + mi];
+      r->e_kin = s->h_out[eo + s->active.size() + mi];
+      r->t_done = now;
+      s->finished[r->id] = r;
+      s->done_q.push_back(r->id);
+    }
+  }
+  return NNP_OK;
+}
+
+int32_t nnp_server_poll(nnp_server* s, int64_t* ids, int32_t max) {
+  if (!s || !ids || max < 1) return 0;
+  int32_t k = 0;
+  while (k < max && !s->done_q.empty()) {
+    ids[k++] = s->done_q.front();
+    s->done_q.pop_front();
+  }
+  return k;
+}
+
+nnp_status nnp_server_result(nnp_server* s, int64_t id, double* x, double* v, double* e_pot,
+                             double* e_kin, double* t_submit, double* t_admit, double* t_done) {
+  if (!s) return NNP_E_INVALID;
+  auto it = s->finished.find(id);
+  if (it == s->finished.end()) return NNP_E_INVALID;
+  Req* r = it->second;
+  if (x) std::memcpy(x, r->x.data(), r->x.size() * 8);
+  if (v) std::memcpy(v, r->v.data(), r->v.size() * 8);
+  if (e_pot) *e_pot = r->e_pot;
+  if (e_kin) *e_kin = r->e_kin;
+  if (t_submit) *t_submit = r->t_submit;
+  if (t_admit) *t_admit = r->t_admit;
+  if (t_done) *t_done = r->t_done;
+  return NNP_OK;
 }
 
 }  // extern "C"

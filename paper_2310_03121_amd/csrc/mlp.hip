@@ -13,8 +13,9 @@
 //   BWD  : delta = acc * CELU'(z) with CELU'(z) = 1 + h/alpha for h <= 0
 //   OUT32: plain float32 output (dE/dG)
 // BF16 operands use v_mfma_f32_16x16x32_bf16 and FP32 operands
-// v_mfma_f32_16x16x4f32; both accumulate in FP32.  Tiles stream through a
-// double-buffered LDS ring with one barrier per K step.
+// v_mfma_f32_16x16x4f32; both accumulate in FP32.  Each K stage moves 128
+// bytes of every tile row through a double-buffered LDS ring (rows padded to
+// 144 bytes), with one barrier per stage; a K tail is zero-filled.
 #include "kernels.h"
 
 namespace nnp {
@@ -24,41 +25,51 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Mfma;
 template <> struct Mfma<bf16_t> {
-  static constexpr int BK = 32;    // K elements per LDS stage (64 bytes per row)
-  static constexpr int RS = 40;    // LDS row stride in elements (80 bytes)
-  __device__ __forceinline__ static void step(const bf16_t* a, const bf16_t* b, floatx4_t& acc) {
-    const uint4 ua = *reinterpret_cast<const uint4*>(a);
-    const uint4 ub = *reinterpret_cast<const uint4*>(b);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ua),
-                                                  __builtin_bit_cast(bf16x8_t, ub), acc, 0, 0, 0);
+  static constexpr int BK = 64;    // K elements per LDS stage (128 bytes per row)
+  static constexpr int RS = 72;    // LDS row stride in elements (144 bytes)
+  static constexpr int KSUB = 2;   // fragment reads per stage
+  // lane's element offset inside a stage for fragment read kk
+  __device__ __forceinline__ static int koff(int lane, int kk) { return kk * 32 + (lane >> 4) * 8; }
+  __device__ __forceinline__ static void mma(const uint4& a, const uint4& b, floatx4_t& acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                  __builtin_bit_cast(bf16x8_t, b), acc, 0, 0, 0);
   }
-  // lane's K offset inside a stage for the A/B fragment
-  __device__ __forceinline__ static int koff(int lane) { return (lane >> 4) * 8; }
 };
 template <> struct Mfma<float> {
-  static constexpr int BK = 16;
-  static constexpr int RS = 20;
-  __device__ __forceinline__ static void step(const float* a, const float* b, floatx4_t& acc) {
-    const float4 va = *reinterpret_cast<const float4*>(a);
-    const float4 vb = *reinterpret_cast<const float4*>(b);
+  static constexpr int BK = 32;
+  static constexpr int RS = 36;
+  static constexpr int KSUB = 2;
+  // float4 read kk covers k = kk*16 + (lane>>4)*4 + {0..3}; component c feeds
+  // MFMA c, whose four k slots (lane groups) are {c, 4+c, 8+c, 12+c} + kk*16
+  __device__ __forceinline__ static int koff(int lane, int kk) { return kk * 16 + (lane >> 4) * 4; }
+  __device__ __forceinline__ static void mma(const uint4& a, const uint4& b, floatx4_t& acc) {
+    const float4 va = __builtin_bit_cast(float4, a);
+    const float4 vb = __builtin_bit_cast(float4, b);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.z, vb.z, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.w, vb.w, acc, 0, 0, 0);
   }
-  __device__ __forceinline__ static int koff(int lane) { return (lane >> 4) * 4; }
 };
 
 __device__ __forceinline__ float celu_f(float v, float alpha, float inv_alpha_l2e) {
   return v > 0.f ? v : alpha * (__builtin_amdgcn_exp2f(v * inv_alpha_l2e) - 1.f);
 }
 
-template <typename T, int BM, int BN, int EPI>
+template <typename T, int BM, int BN>
+constexpr size_t gemm_lds_bytes() {
+  return (size_t)2 * (BM + BN) * Mfma<T>::RS * sizeof(T);
+}
+
+// 256 threads = WM x WN waves; wave tile (BM/WM) x (BN/WN) of 16x16 MFMA tiles.
+template <typename T, int BM, int BN, int WM, int WN, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  static_assert(WM * WN == 4, "four waves");
   constexpr int BK = Mfma<T>::BK, RS = Mfma<T>::RS;
-  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int TM = WTM / 16, TN = WTN / 16;
-  constexpr int VPR = 4;                       // 16-byte vectors per stage row
+  static_assert(TM * 16 == WTM && TN * 16 == WTN, "wave tile must be whole 16x16 tiles");
+  constexpr int VPR = BK * sizeof(T) / 16;     // 16-byte vectors per stage row (8)
   constexpr int EPV = 16 / sizeof(T);          // elements per vector
   constexpr int NVA = (BM * VPR + 255) / 256;  // vectors per thread, A
   constexpr int NVB = (BN * VPR + 255) / 256;
@@ -76,11 +87,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   if (row0 >= row_end) return;  // a tile of pad rows only
   const int n0 = blockIdx.y * BN;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
+  const int wm = wv / WN, wn = wv % WN;
 
   const T* A = reinterpret_cast<const T*>(a.A);
   const T* B = reinterpret_cast<const T*>(a.B) + (size_t)s * a.sB;
-  const int nk = a.K / BK;
+  const int K = a.K;
+  const int nk = (K + BK - 1) / BK;
 
   uint4 ra[NVA], rb[NVB];
   auto gload = [&](int kt) {
@@ -88,18 +100,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
-      const int r = idx >> 2, sg = idx & 3;
+      const int r = idx / VPR, sg = idx % VPR;
       uint4 val = make_uint4(0, 0, 0, 0);
-      if (idx < BM * VPR && row0 + r < row_end)
+      if (idx < BM * VPR && row0 + r < row_end && k0 + sg * EPV < K)
         val = *reinterpret_cast<const uint4*>(A + (size_t)(row0 + r) * a.lda + k0 + sg * EPV);
       ra[v] = val;
     }
 #pragma unroll
     for (int v = 0; v < NVB; ++v) {
       const int idx = tid + v * 256;
-      const int r = idx >> 2, sg = idx & 3;
+      const int r = idx / VPR, sg = idx % VPR;
       uint4 val = make_uint4(0, 0, 0, 0);
-      if (idx < BN * VPR && n0 + r < a.N)
+      if (idx < BN * VPR && n0 + r < a.N && k0 + sg * EPV < K)
         val = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + r) * a.ldb + k0 + sg * EPV);
       rb[v] = val;
     }
@@ -110,12 +122,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
-      if (idx < BM * VPR) *reinterpret_cast<uint4*>(as + (idx >> 2) * RS + (idx & 3) * EPV) = ra[v];
+      if (idx < BM * VPR)
+        *reinterpret_cast<uint4*>(as + (idx / VPR) * RS + (idx % VPR) * EPV) = ra[v];
     }
 #pragma unroll
     for (int v = 0; v < NVB; ++v) {
       const int idx = tid + v * 256;
-      if (idx < BN * VPR) *reinterpret_cast<uint4*>(bs + (idx >> 2) * RS + (idx & 3) * EPV) = rb[v];
+      if (idx < BN * VPR)
+        *reinterpret_cast<uint4*>(bs + (idx / VPR) * RS + (idx % VPR) * EPV) = rb[v];
     }
   };
 
@@ -128,17 +142,25 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   gload(0);
   lstore(0);
   __syncthreads();
-  const int ko = Mfma<T>::koff(lane);
   const int rl = lane & 15;
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) gload(kt + 1);
-    const T* as = As + buf * BM * RS + (wm * WTM + rl) * RS + ko;
-    const T* bs = Bs + buf * BN * RS + (wn * WTN + rl) * RS + ko;
+    const T* as = As + buf * BM * RS + (wm * WTM + rl) * RS;
+    const T* bs = Bs + buf * BN * RS + (wn * WTN + rl) * RS;
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int kk = 0; kk < Mfma<T>::KSUB; ++kk) {
+      const int ko = Mfma<T>::koff(lane, kk);
+      uint4 fa[TM], fb[TN];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) Mfma<T>::step(as + i * 16 * RS, bs + j * 16 * RS, acc[i][j]);
+      for (int i = 0; i < TM; ++i) fa[i] = *reinterpret_cast<const uint4*>(as + i * 16 * RS + ko);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) fb[j] = *reinterpret_cast<const uint4*>(bs + j * 16 * RS + ko);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) Mfma<T>::mma(fa[i], fb[j], acc[i][j]);
+    }
     if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
   }
@@ -202,8 +224,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     }
   }
   if constexpr (EPI == EPI_HEAD) {
-    // sum the 16 column lanes of each row, then the two column halves (waves)
-    float* part = reinterpret_cast<float*>(smem);  // [2][BM], LDS reused after the K loop
+    // sum the 16 column lanes of each row, then the WN column slices (waves)
+    float* part = reinterpret_cast<float*>(smem);  // [WN][BM], LDS reused after the K loop
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -218,7 +240,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     __syncthreads();
     for (int t = tid; t < BM; t += 256) {
       const int row = row0 + t;
-      if (row < row_end) a.erow[row] = part[t] + part[BM + t] + a.b_out[s];
+      float e = a.b_out[s];
+#pragma unroll
+      for (int q = 0; q < WN; ++q) e += part[q * BM + t];
+      if (row < row_end) a.erow[row] = e;
       if (a.uprow) {
         float up = 0.f;
         if (row < row_end) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
@@ -230,43 +255,60 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 
 // ------------------------------------------------------------ launch helpers
 
-template <typename T, int BM, int BN, int EPI>
+template <typename T, int BM, int BN, int WM, int WN, int EPI>
 static void launch_tile(const GemmArgs& a, int rows_cap, hipStream_t st) {
-  const size_t lds = (size_t)2 * (BM + BN) * Mfma<T>::RS * sizeof(T);
+  constexpr size_t lds = gemm_lds_bytes<T, BM, BN>();
+  static const bool attr = (ensure_lds(k_gemm<T, BM, BN, WM, WN, EPI>), true);
+  (void)attr;
   dim3 grid((rows_cap + BM - 1) / BM, (a.N + BN - 1) / BN);
-  hipLaunchKernelGGL((k_gemm<T, BM, BN, EPI>), grid, dim3(256), lds, st, a);
+  hipLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN, EPI>), grid, dim3(256), lds, st, a);
+}
+
+// Column tile for the non-head layers: the largest of 128, 96, 80, 64, 32
+// dividing N (all widths are multiples of 32).
+int gemm_pick_bn(int N, int epi) {
+  if (epi == EPI_HEAD) return N;
+  for (int bn : {128, 96, 80, 64, 32})
+    if (N % bn == 0) return bn;
+  return 0;
 }
 
 template <typename T, int EPI>
-static bool launch_bn(const GemmArgs& a, int rows_cap, int BN, hipStream_t st) {
-  switch (BN) {
-    case 64: launch_tile<T, 128, 64, EPI>(a, rows_cap, st); return true;
-    case 96: launch_tile<T, 128, 96, EPI>(a, rows_cap, st); return true;
-    case 128: launch_tile<T, 128, 128, EPI>(a, rows_cap, st); return true;
-    case 160: launch_tile<T, 128, 160, EPI>(a, rows_cap, st); return true;
-    case 192: launch_tile<T, 128, 192, EPI>(a, rows_cap, st); return true;
-    case 256: launch_tile<T, 128, 256, EPI>(a, rows_cap, st); return true;
+static bool launch_body(const GemmArgs& a, int rows_cap, hipStream_t st) {
+  switch (gemm_pick_bn(a.N, EPI)) {
+    case 128: launch_tile<T, 128, 128, 2, 2, EPI>(a, rows_cap, st); return true;
+    case 96: launch_tile<T, 128, 96, 2, 2, EPI>(a, rows_cap, st); return true;
+    case 80: launch_tile<T, 128, 80, 4, 1, EPI>(a, rows_cap, st); return true;
+    case 64: launch_tile<T, 128, 64, 2, 2, EPI>(a, rows_cap, st); return true;
+    case 32: launch_tile<T, 128, 32, 2, 2, EPI>(a, rows_cap, st); return true;
     default: return false;
   }
 }
 
-int gemm_pick_bn(int N, int epi) {
-  if (epi == EPI_HEAD) return N;
-  if (N <= 256) return N;
-  if (N % 256 == 0) return 256;
-  if (N % 192 == 0) return 192;
-  if (N % 128 == 0) return 128;
-  return 64;
+// The head layer keeps every column of a row in one workgroup (the energy is
+// a dot product over them): BN = N, 64-row tiles.
+template <typename T>
+static bool launch_head(const GemmArgs& a, int rows_cap, hipStream_t st) {
+  switch (a.N) {
+    case 96: launch_tile<T, 64, 96, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    case 128: launch_tile<T, 64, 128, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    case 160: launch_tile<T, 64, 160, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    case 192: launch_tile<T, 64, 192, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    case 224: launch_tile<T, 64, 224, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    case 256: launch_tile<T, 64, 256, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    case 32: launch_tile<T, 64, 32, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    case 64: launch_tile<T, 64, 64, 2, 2, EPI_HEAD>(a, rows_cap, st); return true;
+    default: return false;
+  }
 }
 
 template <typename T>
 bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st) {
-  const int BN = gemm_pick_bn(a.N, epi);
   switch (epi) {
-    case EPI_CELU: return launch_bn<T, EPI_CELU>(a, rows_cap, BN, st);
-    case EPI_HEAD: return launch_bn<T, EPI_HEAD>(a, rows_cap, BN, st);
-    case EPI_BWD: return launch_bn<T, EPI_BWD>(a, rows_cap, BN, st);
-    case EPI_OUT32: return launch_bn<T, EPI_OUT32>(a, rows_cap, BN, st);
+    case EPI_CELU: return launch_body<T, EPI_CELU>(a, rows_cap, st);
+    case EPI_HEAD: return launch_head<T>(a, rows_cap, st);
+    case EPI_BWD: return launch_body<T, EPI_BWD>(a, rows_cap, st);
+    case EPI_OUT32: return launch_body<T, EPI_OUT32>(a, rows_cap, st);
   }
   return false;
 }

@@ -84,7 +84,9 @@ __global__ __launch_bounds__(1024) void k_groups(const int* __restrict__ dims, i
   for (int s = 0; s < S; ++s) {
     int acc = 0;
     for (int b = t; b < nblk; b += blockDim.x) acc += hist[s * nblk + b];
-    atomicAdd(&tot[s], acc);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((t & 63) == 0) atomicAdd(&tot[s], acc);
   }
   __syncthreads();
   if (t == 0) {
@@ -138,13 +140,13 @@ __global__ __launch_bounds__(1024) void k_groups(const int* __restrict__ dims, i
   // status word of this evaluation: staging bits of every block + offsets
   uint32_t bits = bad ? kStOffsets : 0u;
   for (int b = t; b < nblk; b += blockDim.x) bits |= (uint32_t)hist[kMaxS * nblk + b];
-  scan[t] = (int)bits;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, o, 64);
+  if (t == 0) scan[0] = 0;
   __syncthreads();
-  if (t == 0) {
-    uint32_t all = 0;
-    for (int k = 0; k < (int)blockDim.x; ++k) all |= (uint32_t)scan[k];
-    *status = all;
-  }
+  if ((t & 63) == 0 && bits) atomicOr(reinterpret_cast<unsigned int*>(&scan[0]), bits);
+  __syncthreads();
+  if (t == 0) *status = (uint32_t)scan[0];
 }
 
 // Stable scatter into species-sorted rows: rank = block base + earlier waves

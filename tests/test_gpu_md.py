@@ -1,0 +1,157 @@
+"""GPU molecular dynamics and serving against the oracle integrator.
+
+Bars: velocity Verlet on the GPU tracks the FP64 oracle integrator to
+|dx| <= 1e-6 A over 20 steps (FP32 forces at FP32-rounded positions on both
+sides); time reversal returns within 1e-5 A; a served request equals the same
+molecule integrated alone to |dx| <= 1e-4 A and relative energy 1e-5 after
+its steps (the only difference is the order of atomic force additions).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as o
+import workloads as w
+from gpu_util import potential, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def _md_gpu(pot, s, v0, dt, n_steps):
+    pos, sp, off = to_dev(s)
+    x = torch.from_numpy(s.pos.astype(np.float64)).cuda()
+    v = torch.from_numpy(v0).cuda()
+    m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+    _, F = pot.energy_forces(pos, sp, off, s.box)
+    Ep, Ek = pot.md_steps(x, v, F, m, sp, off, dt, n_steps, s.box)
+    pot.check()
+    return x.cpu().numpy(), v.cpu().numpy(), Ep.cpu().numpy(), Ek.cpu().numpy()
+
+
+def test_velocity_verlet_matches_oracle():
+    s = w.single_molecule(24, seed=5, n_species=4)
+    announce("md vs oracle integrator, 24 atoms, 20 steps")
+    pot, at, mt = potential(4, "fp32")
+    v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(1))
+    x, v, Ep, Ek = _md_gpu(pot, s, v0, 0.5, 20)
+
+    def ff(x32):
+        r = o.energy_forces(x32, s.species, s.mol_offsets, None, aev_table=at, mlp_table=mt)
+        return r.E, r.F
+
+    xo, vo, rec = o.velocity_verlet(s.pos.astype(np.float64), v0, w.MASS_AMU[s.species], ff, 0.5, 20)
+    print(f"max|dx| {np.abs(x - xo).max():.2e}  max|dv| {np.abs(v - vo).max():.2e}")
+    assert np.abs(x - xo).max() <= 1e-6
+    assert np.abs(v - vo).max() <= 1e-7
+    assert abs(Ek[0] - rec[-1][2]) <= 1e-6 * abs(rec[-1][2])
+    assert abs(Ep[0] - rec[-1][1]) <= 1e-5 * max(1.0, abs(rec[-1][1]))
+
+
+def test_time_reversibility():
+    s = w.single_molecule(40, seed=6, n_species=7)
+    announce("md time reversal, 40 atoms")
+    pot, at, mt = potential(7, "fp32")
+    v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(2))
+    x1, v1, _, _ = _md_gpu(pot, s, v0, 0.5, 50)
+    s1 = w.System(x1.astype(np.float32), s.species, s.mol_offsets, None, 7)
+    # continue from the FP64 state, reversed
+    pos, sp, off = to_dev(s1)
+    x = torch.from_numpy(x1).cuda()
+    v = torch.from_numpy(-v1).cuda()
+    m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+    _, F = pot.energy_forces(x.float(), sp, off, None)
+    pot.md_steps(x, v, F, m, sp, off, 0.5, 50)
+    pot.check()
+    err = np.abs(x.cpu().numpy() - s.pos.astype(np.float64)).max()
+    print(f"reversal max|dx| {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_nve_energy_drift_water_box():
+    s = w.water_box(300, 20.9, seed=12, n_species=7)  # ~0.1 atoms/A^3, 900 atoms
+    announce(f"NVE drift, {s.n_atoms}-atom water box, 400 steps at 0.5 fs")
+    pot, at, mt = potential(7, "fp32")
+    v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(3))
+    pos, sp, off = to_dev(s)
+    x = torch.from_numpy(s.pos.astype(np.float64)).cuda()
+    v = torch.from_numpy(v0).cuda()
+    m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+    E0, F = pot.energy_forces(pos, sp, off, s.box)
+    ke0 = o.kinetic_energy(v0, w.MASS_AMU[s.species])
+    tot = [E0.item() + ke0]
+    for _ in range(8):
+        Ep, Ek = pot.md_steps(x, v, F, m, sp, off, 0.5, 50, s.box)
+        tot.append(Ep.item() + Ek.item())
+    pot.check()
+    tot = np.array(tot)
+    drift = np.abs(tot - tot[0]).max() / s.n_atoms
+    print(f"max |E_tot - E_0| / atom = {drift:.2e} eV over 200 fs")
+    assert drift <= 2e-4
+
+
+def _requests(n, seed=3):
+    return w.poisson_requests(n, rate=1000.0, seed=seed, n_steps=30)
+
+
+def test_serving_alone_equals_mix():
+    from paper_2310_03121_amd import Server
+    announce("server: continuous batching vs each request alone")
+    pot, at, mt = potential(7, "fp32")
+    reqs = _requests(24)
+    srv = Server(pot, hbm_budget_bytes=8 << 30, max_atoms=900, max_mols=12, dt_fs=0.5,
+                 mass_amu=w.MASS_AMU)
+    for r in reqs:
+        assert srv.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
+                          r.n_steps) == 0
+    done = {}
+    steps = 0
+    max_active = 0
+    while len(done) < len(reqs):
+        srv.step()
+        steps += 1
+        max_active = max(max_active, srv.active)
+        for i in srv.poll():
+            done[i] = srv.result(i, reqs[i].system.n_atoms)
+        assert steps < 5000
+    print(f"{steps} scheduling rounds, up to {max_active} requests in flight")
+    assert max_active > 1
+    worst = 0.0
+    for r in reqs[:10]:
+        x, v, Ep, Ek = _md_gpu(pot, r.system, r.vel, 0.5, r.n_steps)
+        d = done[r.req_id]
+        dx = np.abs(d["x"] - x).max()
+        worst = max(worst, dx)
+        assert dx <= 1e-4, (r.req_id, dx)
+        assert abs(d["e_pot"] - Ep[0]) <= 1e-5 * max(1.0, abs(Ep[0]))
+        assert abs(d["e_kin"] - Ek[0]) <= 1e-5 * max(1.0, abs(Ek[0]))
+        assert d["t_submit"] <= d["t_admit"] <= d["t_done"]
+    print(f"alone vs mix: worst max|dx| {worst:.2e} A")
+
+
+def test_serving_respects_capacity_and_budget():
+    from paper_2310_03121_amd import Server
+    announce("server: tiny HBM budget admits fewer atoms at once")
+    pot, at, mt = potential(7, "fp32")
+    reqs = _requests(8, seed=9)
+    small = Server(pot, hbm_budget_bytes=24 << 20, max_atoms=4096, max_mols=64, dt_fs=0.5,
+                   mass_amu=w.MASS_AMU)
+    big = max(r.system.n_atoms for r in reqs)
+    ids = []
+    for r in reqs:
+        code = small.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
+                            r.n_steps)
+        assert code in (0, 9)
+        if code == 0:
+            ids.append(r.req_id)
+    got = set()
+    rounds = 0
+    while len(got) < len(ids):
+        small.step()
+        rounds += 1
+        got.update(small.poll())
+        assert rounds < 20000
+    print(f"{len(ids)} requests served under a 24 MiB budget in {rounds} rounds (largest {big} atoms)")
