@@ -70,6 +70,18 @@ def time_path(pot, pos, sp, off, box, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     pot.check()
+    # the same evaluations replayed from a captured HIP graph
+    g = pot.capture(pos, sp, off, box)
+    for _ in range(warmup):
+        g.launch()
+    g.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.launch()
+    g.synchronize()
+    dt_graph = time.perf_counter() - t0
+    g.check()
+    del g
     # per-stage device times with HIP events on the launch stream, same steps
     pot.profile(True)
     for _ in range(steps):
@@ -77,7 +89,65 @@ def time_path(pot, pos, sp, off, box, steps, warmup):
         pot.profile_collect()
     stages = pot.profile_read()
     pot.profile(False)
-    return dt, out, stages
+    return dt, dt_graph, out, stages
+
+
+def serve_leg(pot, reqs, rate=None, max_atoms=8192, max_mols=256):
+    """Drive the continuous-batching server with a request stream.
+
+    rate=None: closed loop (everything submitted at t=0; gives the saturation
+    rate).  Otherwise requests are released at their Poisson arrival times
+    scaled to `rate` per second.  Latency = completion - scheduled arrival."""
+    from paper_2310_03121_amd import Server
+    import workloads as w
+    srv = Server(pot, hbm_budget_bytes=16 << 30, max_atoms=max_atoms, max_mols=max_mols,
+                 dt_fs=0.5, mass_amu=w.MASS_AMU)
+    gaps = np.diff([0.0] + [r.t_arrive for r in reqs])
+    base_rate = len(reqs) / reqs[-1].t_arrive
+    arrive = np.zeros(len(reqs)) if rate is None else np.cumsum(gaps) * base_rate / rate
+    nxt = 0
+    lat = {}
+    t0 = time.perf_counter()
+    while len(lat) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arrive[nxt] <= now:
+            r = reqs[nxt]
+            code = srv.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
+                              r.n_steps)
+            assert code == 0, code
+            nxt += 1
+        if srv.active == 0 and srv.pending == 0:
+            if nxt < len(reqs):
+                time.sleep(max(0.0, min(1e-3, arrive[nxt] - now)))
+            continue
+        srv.step()
+        for i in srv.poll():
+            srv.result(i, reqs[i].system.n_atoms)
+            lat[i] = time.perf_counter() - t0 - arrive[i]
+    wall = time.perf_counter() - t0
+    atom_evals = sum(r.system.n_atoms * (r.n_steps + 1) for r in reqs)
+    L = np.array(sorted(lat.values())) * 1e3
+    return {"requests": len(reqs), "wall_s": wall, "req_per_s": len(reqs) / wall,
+            "atoms_evals_per_s": atom_evals / wall, "p50_ms": float(np.percentile(L, 50)),
+            "p99_ms": float(np.percentile(L, 99))}
+
+
+def serving(at, mt, n_req=300, n_steps=100):
+    import workloads as w
+    from paper_2310_03121_amd import Potential
+    reqs = w.poisson_requests(n_req, rate=1.0, seed=3, arrival_seed=30, n_steps=n_steps)
+    out = {"workload": f"{n_req} MD requests, 10-150 atoms (log-uniform), {n_steps} velocity-Verlet "
+                       f"steps of 0.5 fs each, Poisson arrivals, 7 elements"}
+    for prec in ("bf16", "fp32"):
+        pot = Potential.from_tables(at, mt, precision=prec)
+        serve_leg(pot, reqs[:20])  # warm-up: graph capture, kernel attributes
+        sat = serve_leg(pot, reqs)
+        mu = sat["req_per_s"]
+        r = {"saturation": sat}
+        for f in (0.5, 0.8):
+            r[f"open_loop_{f}mu"] = serve_leg(pot, reqs, rate=f * mu)
+        out[prec] = r
+    return out
 
 
 def cpu_baseline(s, S, budget_s=12.0):
@@ -120,6 +190,11 @@ def main():
     ap.add_argument("--workload", default="batch")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-oracle", action="store_true", help="skip the force-error check")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 512 MiB device copy (a known-size reference for "
+                         "hardware byte counters)")
+    ap.add_argument("--precision", default="both", choices=("both", "bf16", "fp32"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is measured on one GPU's share "
@@ -131,6 +206,12 @@ def main():
     import workloads as w
     from paper_2310_03121_amd import Potential
 
+    if args.copy_probe:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s, S, desc = workload(args.workload)
     at, mt = w.aev_table(S), w.mlp_table(S)
     dev = torch.device("cuda:0")
@@ -141,10 +222,16 @@ def main():
     ref = None if args.no_oracle else oracle.energy_forces(s, aev_table=at, mlp_table=mt)
 
     results = {}
-    for prec in ("bf16", "fp32"):
+    precs = ("bf16", "fp32") if args.precision == "both" else (args.precision,)
+    for prec in precs:
         pot = Potential.from_tables(at, mt, precision=prec)
-        dt, (E, F), stages = time_path(pot, pos, sp, off, box, args.steps, args.warmup)
+        dt_eager, dt_graph, (E, F), stages = time_path(pot, pos, sp, off, box, args.steps,
+                                                       args.warmup)
+        dt = min(dt_eager, dt_graph)
         r = {"value": s.n_atoms * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
+             "launch": "graph replay" if dt_graph <= dt_eager else "eager",
+             "eager_ms_per_step": 1e3 * dt_eager / args.steps,
+             "graph_ms_per_step": 1e3 * dt_graph / args.steps,
              "stages_ms": {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}}
         if ref is not None:
             Fn = F.cpu().numpy().astype(np.float64)
@@ -155,7 +242,8 @@ def main():
         del pot
         torch.cuda.empty_cache()
 
-    main_r = results["bf16"]
+    main_prec = precs[0]
+    main_r = results[main_prec]
     # roofline of the dominant kernel (largest per-launch device time)
     F_feat = mt.widths[0]
     sf = stage_flops(mt.widths, F_feat)
@@ -163,8 +251,8 @@ def main():
     dom = max(st, key=st.get)
     if dom in sf:
         achieved = sf[dom] * s.n_atoms / (st[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["bf16"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["bf16"], "traffic": None,
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[main_prec],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[main_prec], "traffic": None,
                 "flop_per_launch": sf[dom] * s.n_atoms, "avg_launch_ms": st[dom]}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
@@ -180,21 +268,27 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": main_r["ms_per_step"],
+        "launch": main_r["launch"],
+        "eager_ms_per_step": main_r["eager_ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": main_prec,
         "data": "synthetic (seeded geometries and Gaussian weights)",
         "config": {"workload": desc, "n_atoms": s.n_atoms, "n_mol": s.n_mol,
-                   "mlp_widths": list(mt.widths), "precision_main": "bf16 MLP, fp32 AEV/forces"},
+                   "mlp_widths": list(mt.widths), "precision_main": f"{main_prec} MLP, fp32 AEV/forces"},
         "force_rmse_eV_per_A": main_r.get("force_rmse_eV_per_A"),
         "force_rel_rms": main_r.get("force_rel_rms"),
-        "fp32_path": results["fp32"],
-        "bf16_stages_ms": main_r["stages_ms"],
+        "fp32_path": results.get("fp32"),
+        "stages_ms": main_r["stages_ms"],
         "mlp_path_tflops": path_tflops,
-        "mlp_path_frac_of_bf16_peak": path_tflops / PEAK_TFLOPS["bf16"],
+        "mlp_path_frac_of_peak": path_tflops / PEAK_TFLOPS[main_prec],
         "roofline": roof,
     }
+    if not args.no_serve:
+        sv = serving(w.aev_table(7), w.mlp_table(7))
+        out["serving"] = sv
+        out["p99_latency_ms_bf16_0.8mu"] = sv["bf16"]["open_loop_0.8mu"]["p99_ms"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, S)
     print(json.dumps(out))

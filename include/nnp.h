@@ -192,6 +192,21 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
                          const int32_t* mol_offsets, const float* box, float* aev,
                          void* workspace, size_t workspace_bytes, void* stream);
 
+/* Captured evaluations.  nnp_graph_capture() runs one nnp_energy_forces()
+ * eagerly on `stream`, then captures the same call into a HIP graph; each
+ * nnp_graph_launch() replays it.  The graph keeps the pointers it was
+ * captured with: callers update the position (or species, offsets) buffers in
+ * place between launches, with the same atom and molecule counts.  `stream`
+ * must not be the legacy default stream (NULL).  The handle, workspace and
+ * buffers must outlive the graph. */
+typedef struct nnp_graph nnp_graph;
+nnp_status nnp_graph_capture(nnp_handle* h, int32_t n_atoms, int32_t n_mol, const float* pos,
+                             const int32_t* species, const int32_t* mol_offsets,
+                             const float* box, double* E, float* F, void* workspace,
+                             size_t workspace_bytes, void* stream, nnp_graph** out);
+nnp_status nnp_graph_launch(nnp_graph* g, void* stream);
+void nnp_graph_destroy(nnp_graph* g);
+
 /* Per-stage device timing with HIP events, for benchmarks.  While enabled,
  * every evaluation records an event pair around each stage on its stream;
  * nnp_profile_collect() waits for the stream and adds the elapsed times to

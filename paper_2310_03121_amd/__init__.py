@@ -14,7 +14,7 @@ import torch
 from . import capi
 from .capi import NNPError, NNP_MLP_BF16, NNP_MLP_FP32
 
-__all__ = ["Potential", "NNPFunction", "Server", "NNPError", "capi"]
+__all__ = ["Potential", "NNPFunction", "Server", "Graph", "NNPError", "capi"]
 
 
 def _ptr(t):
@@ -179,6 +179,12 @@ class Potential:
                                            _stream()), "debug_aev")
         return out
 
+    def capture(self, pos, species, mol_offsets, box=None, stream=None):
+        """A replayable graph of energy_forces on these buffers (see
+        nnp_graph_capture); returns a Graph whose .E and .F are the outputs.
+        Update ``pos`` in place between launches."""
+        return Graph(self, pos, species, mol_offsets, box, stream)
+
     # ---------------------------------------------------------- profiling
     def profile(self, on: bool):
         capi.check(self._lib.nnp_profile_enable(self._h, int(bool(on))), "profile_enable")
@@ -209,6 +215,50 @@ class Potential:
                                           float(dt), int(n_steps), _ptr(Ep), _ptr(Ek), _ptr(ws),
                                           ws.numel(), _stream()), "nnp_md_steps")
         return Ep, Ek
+
+
+class Graph:
+    """A captured energy + force evaluation (nnp_graph_*)."""
+
+    def __init__(self, pot, pos, species, mol_offsets, box=None, stream=None):
+        self.pot = pot
+        self.stream = stream or torch.cuda.Stream()
+        n = pos.shape[0]
+        n_mol = mol_offsets.shape[0] - 1
+        self.pos, self.species, self.off = pos, species, mol_offsets
+        self.E = torch.empty(n_mol, dtype=torch.float64, device=pos.device)
+        self.F = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+        self.ws = torch.empty(max(pot.workspace_bytes(n, n_mol, box), 256), dtype=torch.uint8,
+                              device=pos.device)
+        self._box, bp = pot._box_arg(box)
+        g = C.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        capi.check(pot._lib.nnp_graph_capture(
+            pot._h, n, n_mol, _ptr(pos), _ptr(species), _ptr(mol_offsets), bp, _ptr(self.E),
+            _ptr(self.F), _ptr(self.ws), self.ws.numel(), C.c_void_p(self.stream.cuda_stream),
+            C.byref(g)), "nnp_graph_capture")
+        self._g = g
+        self.stream.synchronize()
+
+    def launch(self):
+        capi.check(self.pot._lib.nnp_graph_launch(self._g, C.c_void_p(self.stream.cuda_stream)),
+                   "nnp_graph_launch")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def check(self):
+        capi.check(self.pot._lib.nnp_check(self.pot._h, _ptr(self.ws),
+                                           C.c_void_p(self.stream.cuda_stream)), "device status")
+
+    def __del__(self):
+        g = getattr(self, "_g", None)
+        if g is not None and g.value:
+            try:
+                self.pot._lib.nnp_graph_destroy(g)
+            except Exception:
+                pass
+            self._g = None
 
 
 class NNPFunction(torch.autograd.Function):

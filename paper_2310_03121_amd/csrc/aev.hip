@@ -18,25 +18,59 @@
 // per lane, so the output is coalesced.  The angle term uses the identity
 // cos(theta - theta_z) = kappa c cos(theta_z) + sqrt(1 - kappa^2 c^2) sin(theta_z)
 // for theta = acos(kappa c); (1 + cos)/2 raised to zeta is exp2(zeta log2(.)).
+// Radial terms go straight into the LDS row with LDS atomic adds.
 //
 // The adjoint recomputes the same terms, contracts them with g = dE/dG
-// (read from the network backward pass), accumulates dE/d(displacement) per
-// neighbor slot in LDS, then scatters: one atomic add per neighbor and
-// component for the neighbors, and one wave-reduced add for the centre atom.
+// (read from the network backward pass, only the blocks the atom touches),
+// accumulates dE/d(displacement) per neighbor slot in LDS, then scatters: one
+// atomic add per neighbor and component for the neighbors, and one
+// wave-reduced add for the centre atom.
 #include "kernels.h"
 
 namespace nnp {
 
+// sin(pi t) and cos(pi t) for t in [0, 1] from Taylor polynomials of sin and
+// cos on u = pi (t - 1/2) in [-pi/2, pi/2] (cos(pi t) = -sin u,
+// sin(pi t) = cos u); the truncation error is below 1e-8, under FP32 rounding.
+__device__ __forceinline__ void sincos_pi01(float t, float& s, float& c) {
+  const float u = 3.14159265358979f * (t - 0.5f);
+  const float u2 = u * u;
+  // sin u = u (1 - u^2/3! + u^4/5! - ... - u^12/13!)
+  float ps = -1.6059043836821614e-10f;               // -1/13!
+  ps = ps * u2 + 2.5052108385441720e-8f;              //  1/11!
+  ps = ps * u2 - 2.7557319223985893e-6f;              // -1/9!
+  ps = ps * u2 + 1.9841269841269841e-4f;              //  1/7!
+  ps = ps * u2 - 8.3333333333333333e-3f;              // -1/5!
+  ps = ps * u2 + 1.6666666666666667e-1f;              //  1/3!
+  const float sinu = u - u * u2 * ps;
+  // cos u = 1 - u^2/2! + u^4/4! - ... + u^12/12!
+  float pc = 2.0876756987868099e-9f;                 //  1/12!
+  pc = pc * u2 - 2.7557319223985891e-7f;              // -1/10!
+  pc = pc * u2 + 2.4801587301587302e-5f;              //  1/8!
+  pc = pc * u2 - 1.3888888888888889e-3f;              // -1/6!
+  pc = pc * u2 + 4.1666666666666667e-2f;              //  1/4!
+  pc = pc * u2 - 0.5f;                                // -1/2!
+  const float cosu = 1.f + u2 * pc;
+  c = -sinu;
+  s = cosu;
+}
+
+// fc(r; R) = cos(pi r / R)/2 + 1/2 and its derivative -(pi/2R) sin(pi r/R).
 __device__ __forceinline__ float cutoff_val(float r, float inv_rc, float& dfc, float pi_2rc) {
   float s, c;
-  sincospif(r * inv_rc, &s, &c);
+  sincos_pi01(fminf(r * inv_rc, 1.f), s, c);
   dfc = -pi_2rc * s;
   return 0.5f * c + 0.5f;
 }
 
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Per-lane entry of a table held in the (uniform) kernel arguments, by
 // unrolled selects: indexing the argument struct with a lane-dependent index
-// would copy it to scratch memory.
+// would copy it to scratch memory, and a table in global memory would add a
+// memory round trip to every wave.
 template <int N>
 __device__ __forceinline__ float pick(const float (&tab)[N], int idx) {
   float r = tab[0];
@@ -44,9 +78,6 @@ __device__ __forceinline__ float pick(const float (&tab)[N], int idx) {
   for (int k = 1; k < N; ++k) r = (idx == k) ? tab[k] : r;
   return r;
 }
-
-__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
-__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 
 // Unordered pair t of the list prefix [0, na) -> entries a < b (row-major:
 // pairs before row a number a*na - a*(a+1)/2).
@@ -89,12 +120,16 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   float2* nf = reinterpret_cast<float2*>(nd + cap);
   int* nsp = reinterpret_cast<int*>(nf + cap);
 
+  // the first 64 row entries are fetched together with the counts, so only
+  // the neighbor-position gather waits on them
+  const int* nrow = nbr + (size_t)i * cap;
+  const int j0 = lane < cap ? nrow[lane] : 0;
   const int2 cn = counts[i];
+  const float4 pi = xyzs[i];
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
   const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
-  const float4 pi = xyzs[i];
   for (int e = lane; e < nr; e += kWave) {
-    const int j = clampi(nbr[(size_t)i * cap + e], n);
+    const int j = clampi(e < kWave ? j0 : nrow[e], n);
     const float4 pj = xyzs[j];
     const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], B.periodic);
     const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], B.periodic);
@@ -112,26 +147,14 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   wave_lds_sync();
   const int S = C.S;
 
-  // ---- radial: lanes (g, m), four neighbors per pass, per-species registers
+  // ---- radial: lanes (g, m), four neighbors per pass, LDS adds into the
+  //      species block of each neighbor
   {
     const int g = lane >> 4, m = lane & 15;
     const float Rm = pick(C.shf_r, m);
-    float acc[kMaxS];
-#pragma unroll
-    for (int q = 0; q < kMaxS; ++q) acc[q] = 0.f;
     for (int e = g; e < nr; e += 4) {
-      const float r = nd[e].w;
-      const float u = r - Rm;
-      const float term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x;
-      const int s = nsp[e];
-#pragma unroll
-      for (int q = 0; q < kMaxS; ++q) acc[q] += (s == q) ? term : 0.f;
-    }
-#pragma unroll
-    for (int q = 0; q < kMaxS; ++q) {
-      acc[q] += __shfl_xor(acc[q], 16, 64);
-      acc[q] += __shfl_xor(acc[q], 32, 64);
-      if ((q & 3) == g && q < S) rowl[q * kNR + m] = acc[q];
+      const float u = nd[e].w - Rm;
+      atomicAdd(rowl + nsp[e] * kNR + m, C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x);
     }
   }
 
@@ -150,7 +173,7 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
         const float4 vj = nd[ej], vk = nd[ek];
         const float fj = nf[ej].y, fk = nf[ek].y;
         const int blk = pair_block(nsp[ej], nsp[ek], S);
-        const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) / (vj.w * vk.w);
+        const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
         const float kc = C.kappa * cs;
         const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
         const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
@@ -175,19 +198,21 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   }
 }
 
-// LDS per wave (adjoint): dE/dG row [Fp] float, then per neighbor float4
-// (dx, dy, dz, r), float4 (fc_rad, fc_ang, dfc_rad, dfc_ang), float4
-// accumulated dE/d(displacement), int species.
+// LDS per wave (adjoint): per neighbor float4 (dx, dy, dz, r), float4
+// (fc_rad, fc_ang, dfc_rad, dfc_ang), float4 accumulated dE/d(displacement),
+// int species.  The dE/dG row is read from global memory where a term needs
+// it (an atom touches only the blocks of the species around it).
 constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 
-// Adjoint: g (float32 rows, stride ldg) -> scatter into out (float32 [n][3]).
+// Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
 // sign = +1 writes forces (-dE/dr); sign = -1 writes the gradient dE/dr.
+template <typename GT>
 __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C, BoxConst B,
                                                  const float4* __restrict__ xyzs,
                                                  const int* __restrict__ nbr,
                                                  const int2* __restrict__ counts, int cap,
                                                  const int* __restrict__ row_of,
-                                                 const float* __restrict__ g, int ldg,
+                                                 const GT* __restrict__ g, int ldg,
                                                  float* __restrict__ out, float sign) {
   extern __shared__ float4 lds4[];
   const int n = dims[0];
@@ -195,23 +220,20 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   const int lane = lane_id();
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
-  const int Fp = C.Fp;
-  char* base = reinterpret_cast<char*>(lds4) + (size_t)w * (Fp * 4 + cap * kBwdBytesPerNbr);
-  float* grow = reinterpret_cast<float*>(base);
-  float4* nd = reinterpret_cast<float4*>(grow + Fp);
+  float4* nd = lds4 + (size_t)w * cap * 3;
   float4* nf = nd + cap;
   float4* grad = nf + cap;
-  int* nsp = reinterpret_cast<int*>(grad + cap);
+  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)4 * cap * 3) + w * cap;
 
+  const int* nrow = nbr + (size_t)i * cap;
+  const int j0 = lane < cap ? nrow[lane] : 0;
   const int2 cn = counts[i];
+  const float4 pi = xyzs[i];
+  const GT* grow = g + (size_t)row_of[i] * ldg;
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
   const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
-  const float4 pi = xyzs[i];
-  const float* gsrc = g + (size_t)row_of[i] * ldg;
-  for (int c = lane * 4; c < Fp; c += 4 * kWave)
-    *reinterpret_cast<float4*>(grow + c) = *reinterpret_cast<const float4*>(gsrc + c);
   for (int e = lane; e < nr; e += kWave) {
-    const int j = clampi(nbr[(size_t)i * cap + e], n);
+    const int j = clampi(e < kWave ? j0 : nrow[e], n);
     const float4 pj = xyzs[j];
     const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], B.periodic);
     const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], B.periodic);
@@ -240,12 +262,12 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
         const float4 f = nf[e];
         const float u = v.w - Rm;
         const float ex = C.cR * fast_exp2(-C.eta_r_l2e * u * u);
-        contrib = grow[nsp[e] * kNR + m] * ex * (f.z - C.eta_r2 * u * f.x);
+        contrib = Store<GT>::get(grow + nsp[e] * kNR + m) * ex * (f.z - C.eta_r2 * u * f.x);
       }
 #pragma unroll
       for (int o = 1; o < 16; o <<= 1) contrib += __shfl_xor(contrib, o, 64);
       if (e < nr && m == 0) {
-        const float sc = contrib / v.w;
+        const float sc = contrib * fast_rcp(v.w);
         grad[e] = make_float4(v.x * sc, v.y * sc, v.z * sc, 0.f);
       }
     }
@@ -258,7 +280,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
     const float cz = pick(C.cos_z, tz), sz = pick(C.sin_z, tz);
     const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
     const int T = na * (na - 1) / 2;
-    const float* gang = grow + S * kNR + tz;
+    const GT* gang = grow + S * kNR + tz;
     for (int t0 = 0; t0 < T; t0 += 8) {
       const int t = t0 + tg;
       float X0 = 0.f, X1 = 0.f, Xc = 0.f;
@@ -271,16 +293,18 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
         vk = nd[ek];
         const float4 cj = nf[ej], ck = nf[ek];
         fj = cj.y; fk = ck.y; dfj = cj.w; dfk = ck.w;
-        const float* gb = gang + pair_block(nsp[ej], nsp[ek], S) * 32;
-        const float g0 = gb[0], g1 = gb[8], g2 = gb[16], g3 = gb[24];
-        cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) / (vj.w * vk.w);
+        const GT* gb = gang + pair_block(nsp[ej], nsp[ek], S) * 32;
+        const float g0 = Store<GT>::get(gb), g1 = Store<GT>::get(gb + 8),
+                    g2 = Store<GT>::get(gb + 16), g3 = Store<GT>::get(gb + 24);
+        const float ijk = fast_rcp(vj.w * vk.w);
+        cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * ijk;
         const float kc = C.kappa * cs;
         const float sn = sqrtf(fmaxf(1.f - kc * kc, 1e-12f));
         const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
         const float pw = fast_exp2(C.zeta * fast_log2(base_));
         const float f1 = 2.f * pw;
         // d f1 / d c = zeta base^(zeta-1) d(kappa c cos_z + sqrt(1-kappa^2 c^2) sin_z)/dc
-        const float df1 = C.zeta * pw / base_ * (C.kappa * (cz - kc * sz / sn));
+        const float df1 = C.zeta * pw * fast_rcp(base_) * (C.kappa * (cz - kc * sz * fast_rcp(sn)));
         const float dbar = 0.5f * (vj.w + vk.w);
         float u, e2, A0 = 0.f, A1 = 0.f;
         u = dbar - ra0; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g0 * e2; A1 -= g0 * u * e2;
@@ -302,10 +326,10 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
         const float dEdc = Xc * fcc;
         const float dEdj = X1 * fcc + X0 * dfj * fk;
         const float dEdk = X1 * fcc + X0 * fj * dfk;
-        const float ijk = 1.f / (vj.w * vk.w);
-        const float aj = dEdj / vj.w - dEdc * cs / (vj.w * vj.w);
-        const float ak = dEdk / vk.w - dEdc * cs / (vk.w * vk.w);
-        const float bb = dEdc * ijk;
+        const float rj = fast_rcp(vj.w), rk = fast_rcp(vk.w);
+        const float aj = (dEdj - dEdc * cs * rj) * rj;
+        const float ak = (dEdk - dEdc * cs * rk) * rk;
+        const float bb = dEdc * rj * rk;
         atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
         atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
         atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
@@ -360,16 +384,24 @@ template void launch_aev_fwd<bf16_t>(const int*, int, const AevConst&, const Box
                                      const float4*, const int*, const int2*, int, const int*,
                                      bf16_t*, int, hipStream_t);
 
+template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                     const float4* xyzs, const int* nbr, const int2* counts, int cap,
-                    const int* row_of, const float* g, int ldg, float* out, float sign,
+                    const int* row_of, const GT* g, int ldg, float* out, float sign,
                     hipStream_t st) {
   if (n_cap <= 0) return;
-  const size_t lds = (size_t)4 * (C.Fp * 4 + cap * kBwdBytesPerNbr);
-  static const bool attr = (ensure_lds(k_aev_bwd), true);
+  const size_t lds = (size_t)4 * cap * kBwdBytesPerNbr;
+  static const bool attr = (ensure_lds(k_aev_bwd<GT>), true);
   (void)attr;
-  hipLaunchKernelGGL(k_aev_bwd, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, B, xyzs, nbr,
-                     counts, cap, row_of, g, ldg, out, sign);
+  hipLaunchKernelGGL(k_aev_bwd<GT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, B,
+                     xyzs,
+                     nbr, counts, cap, row_of, g, ldg, out, sign);
 }
+template void launch_aev_bwd<float>(const int*, int, const AevConst&, const BoxConst&,
+                                    const float4*, const int*, const int2*, int, const int*,
+                                    const float*, int, float*, float, hipStream_t);
+template void launch_aev_bwd<bf16_t>(const int*, int, const AevConst&, const BoxConst&,
+                                     const float4*, const int*, const int2*, int, const int*,
+                                     const bf16_t*, int, float*, float, hipStream_t);
 
 }  // namespace nnp

@@ -102,12 +102,15 @@ __device__ __forceinline__ int popc_below(uint64_t m) {
 
 typedef uint16_t bf16_t;
 
+// round to nearest even (v_cvt_pk_bf16_f32)
 __device__ __forceinline__ bf16_t f2bf(float f) {
-  // round to nearest even; NaN kept quiet
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
+  return __builtin_bit_cast(bf16_t, (__bf16)f);
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  const bf16x2_t v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
@@ -124,9 +127,7 @@ template <> struct Store<bf16_t> {
   __device__ __forceinline__ static void put(bf16_t* p, float v) { *p = f2bf(v); }
   __device__ __forceinline__ static float get(const bf16_t* p) { return bf2f(*p); }
   __device__ __forceinline__ static void put4(bf16_t* p, float4 v) {
-    const uint32_t lo = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
-    const uint32_t hi = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
-    *reinterpret_cast<uint2*>(p) = make_uint2(lo, hi);
+    *reinterpret_cast<uint2*>(p) = make_uint2(f2bf2(v.x, v.y), f2bf2(v.z, v.w));
   }
 };
 

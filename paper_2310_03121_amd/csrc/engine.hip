@@ -179,7 +179,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B) {
   P.D3 = take(R * w3 * esz);
   P.D2 = take(R * w2 * esz);
   P.D1 = take(R * w1 * esz);
-  P.G = take(R * h->Fp * 4);
+  P.G = take(R * h->Fp * esz);
   P.erow = take(R * 4);
   P.uprow = take(R * 4);
   size_t maxlen = 0;
@@ -203,7 +203,8 @@ bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
 struct EvalIO {
   int n_arg, nmol_arg;  // >= 0: counts passed by value; -1: read from the workspace
-  const float* pos;
+  const float* pos;     // float32 positions, or
+  const double* pos64;  // float64 positions (MD state), rounded to float32 on staging
   const int* species;
   const int* off;
   double* E;            // may be null
@@ -232,8 +233,8 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
 
   {
     StageTimer t(h, ST_STAGE, st);
-    launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.species, io.off, S, xyzs, mol,
-                 io.out3, hist, status, st);
+    launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.species, io.off, S, xyzs,
+                 mol, io.out3, hist, status, st);
     launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
     launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
   }
@@ -260,7 +261,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   T* D3 = at<T>(ws, P.D3);
   T* D2 = at<T>(ws, P.D2);
   T* D1 = at<T>(ws, P.D1);
-  float* G = at<float>(ws, P.G);
+  T* G = at<T>(ws, P.G);
   float* erow = at<float>(ws, P.erow);
   const T* W[kLayers];
   const T* WT[kLayers];
@@ -322,16 +323,16 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
   }
   if (io.out3) {
-    // g = dE/dG = delta1 W0 (float32)
+    // g = dE/dG = delta1 W0 (in the network operand type)
     g.A = D1; g.lda = w1; g.B = WT[0]; g.sB = (long)Fp * w1; g.ldb = w1;
     g.N = Fp; g.K = w1; g.C = G; g.ldc = Fp; g.H = nullptr;
     {
       StageTimer t(h, ST_GRADG, st);
-      ok &= launch_gemm<T>(EPI_OUT32, g, P.rows_cap, st);
+      ok &= launch_gemm<T>(EPI_OUT, g, P.rows_cap, st);
     }
     StageTimer t(h, ST_AEVBWD, st);
-    launch_aev_bwd(dims, P.n, h->C, P.B, xyzs, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
-                   st);
+    launch_aev_bwd<T>(dims, P.n, h->C, P.B, xyzs, nbr, counts, P.cap, row, G, Fp, io.out3,
+                      io.sign, st);
   }
   if (io.dparams) {
     StageTimer t(h, ST_WGRAD, st);
@@ -496,6 +497,7 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
   h->bout = reinterpret_cast<float*>(h->dmem + o_bout);
   h->eself = reinterpret_cast<double*>(h->dmem + o_eself);
   h->param_off_dev = reinterpret_cast<long*>(h->dmem + o_poff);
+
   double es[kMaxS] = {};
   for (int s = 0; s < S; ++s) es[s] = mlp->self_energy ? mlp->self_energy[s] : 0.0;
   std::vector<long> po((size_t)kLayers * S);
@@ -613,7 +615,7 @@ nnp_status nnp_energy_forces(nnp_handle* h, int32_t n, int32_t nmol, const float
   nnp_status s = check_common(h, n, nmol, pos, species, off, box, ws, ws_bytes, P);
   if (s != NNP_OK) return s;
   if (!E) return NNP_E_INVALID;
-  EvalIO io{n, nmol, pos, species, off, E, F, 1.f, nullptr, nullptr};
+  EvalIO io{n, nmol, pos, nullptr, species, off, E, F, 1.f, nullptr, nullptr};
   return run(h, P, ws, io, static_cast<hipStream_t>(stream));
 }
 
@@ -625,7 +627,7 @@ nnp_status nnp_backward(nnp_handle* h, int32_t n, int32_t nmol, const float* pos
   nnp_status s = check_common(h, n, nmol, pos, species, off, box, ws, ws_bytes, P);
   if (s != NNP_OK) return s;
   if (!dLdE) return NNP_E_INVALID;
-  EvalIO io{n, nmol, pos, species, off, E, dL_dpos, -1.f, dLdE, dL_dparams};
+  EvalIO io{n, nmol, pos, nullptr, species, off, E, dL_dpos, -1.f, dLdE, dL_dparams};
   return run(h, P, ws, io, static_cast<hipStream_t>(stream));
 }
 
@@ -671,8 +673,8 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   int* dims = at<int>(ws, P.dims);
   uint32_t* status = at<uint32_t>(ws, P.status);
   float4* xyzs = at<float4>(ws, P.xyzs);
-  launch_stage(n, nmol, P.n, dims, pos, species, off, h->S, xyzs, at<int>(ws, P.mol), nullptr,
-               at<int>(ws, P.hist), status, st);
+  launch_stage(n, nmol, P.n, dims, pos, nullptr, species, off, h->S, xyzs, at<int>(ws, P.mol),
+               nullptr, at<int>(ws, P.hist), status, st);
   launch_groups(dims, P.n, h->S, at<int>(ws, P.hist), at<GroupTable>(ws, P.gt),
                 at<int>(ws, P.perm), P.rows_cap, off, kWChunk, status, st);
   if (P.B.periodic)
@@ -686,6 +688,66 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   launch_aev_fwd<float>(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.nbr), at<int2>(ws, P.counts),
                         P.cap, nullptr, aev, h->F, st);
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
+// ------------------------------------------------------------- graph replay
+
+}  // extern "C"
+
+struct nnp_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+extern "C" {
+
+nnp_status nnp_graph_capture(nnp_handle* h, int32_t n, int32_t nmol, const float* pos,
+                             const int32_t* species, const int32_t* off, const float* box,
+                             double* E, float* F, void* ws, size_t ws_bytes, void* stream,
+                             nnp_graph** out) {
+  if (!out || !stream) return NNP_E_INVALID;
+  *out = nullptr;
+  if (h && h->prof) return NNP_E_INVALID;  // event timing cannot be captured
+  // eager run: validates the arguments and sets kernel attributes
+  nnp_status s = nnp_energy_forces(h, n, nmol, pos, species, off, box, E, F, ws, ws_bytes, stream);
+  if (s != NNP_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return NNP_E_HIP;
+  s = nnp_energy_forces(h, n, nmol, pos, species, off, box, E, F, ws, ws_bytes, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(st, &g);
+  if (s != NNP_OK || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return s != NNP_OK ? s : NNP_E_HIP;
+  }
+  nnp_graph* G = new (std::nothrow) nnp_graph();
+  if (!G) {
+    (void)hipGraphDestroy(g);
+    return NNP_E_OOM;
+  }
+  G->graph = g;
+  G->device = h->device;
+  if (hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    delete G;
+    return NNP_E_HIP;
+  }
+  *out = G;
+  return NNP_OK;
+}
+
+nnp_status nnp_graph_launch(nnp_graph* g, void* stream) {
+  if (!g || !g->exec) return NNP_E_INVALID;
+  return hip_ok(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream))) ? NNP_OK : NNP_E_HIP;
+}
+
+void nnp_graph_destroy(nnp_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 // ------------------------------------------------------------------------- MD
@@ -717,7 +779,7 @@ nnp_status nnp_md_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, doubl
       launch_fill_i32(dims + 1, nmol, 1, st);
     }
     launch_vv_kick_drift(dims, n, x, v, F, mass, dt, pos32, st);
-    EvalIO io{n, nmol, pos32, species, off, Etmp, F, 1.f, nullptr, nullptr};
+    EvalIO io{n, nmol, pos32, nullptr, species, off, Etmp, F, 1.f, nullptr, nullptr};
     s = run(h, P, ws, io, st);
     if (s != NNP_OK) break;
     launch_vv_kick(dims, n, v, F, mass, dt, st);
@@ -727,7 +789,7 @@ nnp_status nnp_md_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, doubl
       launch_fill_i32(dims, n, 1, st);
       launch_fill_i32(dims + 1, nmol, 1, st);
     }
-    launch_kinetic(dims, nmol, off, v, mass, E_kin, st);
+    launch_kinetic(dims, nmol, off, v, mass, E_kin, nullptr, st);
   }
   if (s != NNP_OK) return s;
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
@@ -798,8 +860,11 @@ struct nnp_server {
   std::deque<int64_t> done_q;
   int active_atoms = 0;
   ~nnp_server() {
+    // a request that finished in the last round is still listed as active;
+    // the finished map owns it
     for (Req* r : pending) delete r;
-    for (Req* r : active) delete r;
+    for (Req* r : active)
+      if (r->k <= r->n_steps) delete r;
     for (auto& kv : finished) delete kv.second;
   }
 };
@@ -827,14 +892,12 @@ nnp_status server_enqueue_step(nnp_server* s) {
   nnp_handle* h = s->h;
   const Plan& P = s->P;
   int* dims = at<int>(s->ws, P.dims);
-  launch_cast_pos(dims, s->max_atoms, s->x, s->pos32, s->st);
-  EvalIO io{-1, -1, s->pos32, s->sp, s->off, s->epot, s->F, 1.f, nullptr, nullptr};
+  EvalIO io{-1, -1, nullptr, s->x, s->sp, s->off, s->epot, s->F, 1.f, nullptr, nullptr};
   nnp_status r = run(h, P, s->ws, io, s->st);
   if (r != NNP_OK) return r;
   launch_serve_integrate(dims, s->max_atoms, at<int>(s->ws, P.mol), s->kdone, s->nsteps, s->x,
                          s->v, s->F, s->m, s->dt, s->st);
-  launch_kinetic(dims, s->max_mols, s->off, s->v, s->m, s->ekin, s->st);
-  launch_serve_advance(dims, s->max_mols, s->kdone, s->st);
+  launch_kinetic(dims, s->max_mols, s->off, s->v, s->m, s->ekin, s->kdone, s->st);
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
 }
 

@@ -5,7 +5,7 @@
 
 namespace nnp {
 
-enum { EPI_CELU = 0, EPI_HEAD = 1, EPI_BWD = 2, EPI_OUT32 = 3 };
+enum { EPI_CELU = 0, EPI_HEAD = 1, EPI_BWD = 2, EPI_OUT = 3 };
 
 struct GemmArgs {
   const void* A;
@@ -55,8 +55,8 @@ __global__ void k_fill_i32(int* p, int v, int n);
 __global__ void k_fill_f32(float* p, float v, long n);
 __global__ void k_fill_f64(double* p, double v, int n);
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
-                  const int* species, const int* off, int S, float4* xyzs, int* mol, float* Fzero,
-                  int* hist, uint32_t* status, hipStream_t st);
+                  const double* pos64, const int* species, const int* off, int S, float4* xyzs,
+                  int* mol, float* Fzero, int* hist, uint32_t* status, hipStream_t st);
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
                    int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
                    hipStream_t st);
@@ -83,9 +83,10 @@ template <typename OutT>
 void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                     const float4* xyzs, const int* nbr, const int2* counts, int cap,
                     const int* row_of, OutT* out, int ld, hipStream_t st);
+template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                     const float4* xyzs, const int* nbr, const int2* counts, int cap,
-                    const int* row_of, const float* g, int ldg, float* out, float sign,
+                    const int* row_of, const GT* g, int ldg, float* out, float sign,
                     hipStream_t st);
 
 // mlp.hip
@@ -104,7 +105,7 @@ void launch_vv_kick_drift(const int* dims, int n_cap, double* x, double* v, cons
 void launch_vv_kick(const int* dims, int n_cap, double* v, const float* F, const double* mass,
                     double dt, hipStream_t st);
 void launch_kinetic(const int* dims, int nmol_cap, const int* off, const double* v,
-                    const double* mass, double* ke, hipStream_t st);
+                    const double* mass, double* ke, int* kdone, hipStream_t st);
 void launch_gather_rows(const int* src, int n, const double* x_old, const double* v_old,
                         const int* sp_old, const double* m_old, const float* f_old,
                         const double* x_new_in, const double* v_new_in, const int* sp_new_in,
@@ -113,8 +114,6 @@ void launch_gather_rows(const int* src, int n, const double* x_old, const double
 void launch_serve_integrate(const int* dims, int n_cap, const int* mol, const int* kdone,
                             const int* nsteps, double* x, double* v, const float* F,
                             const double* mass, double dt, hipStream_t st);
-void launch_serve_advance(const int* dims, int nmol_cap, int* kdone, hipStream_t st);
-void launch_cast_pos(const int* dims, int n_cap, const double* x, float* pos32, hipStream_t st);
-void launch_copy_bytes(const void* a, void* b, size_t bytes, hipStream_t st);
+
 
 }  // namespace nnp

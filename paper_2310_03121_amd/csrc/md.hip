@@ -49,10 +49,12 @@ __global__ __launch_bounds__(256) void k_vv_kick(const int* __restrict__ dims, d
   for (int c = 0; c < 3; ++c) v[3 * i + c] += s * (double)F[3 * i + c];
 }
 
+// Kinetic energy per molecule; with `kdone`, also advances the molecule's
+// step counter (serving).
 __global__ __launch_bounds__(256) void k_kinetic(const int* __restrict__ dims, const int* __restrict__ off,
                                                  const double* __restrict__ v,
                                                  const double* __restrict__ mass,
-                                                 double* __restrict__ ke) {
+                                                 double* __restrict__ ke, int* __restrict__ kdone) {
   const int n = dims[0], nmol = dims[1];
   const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= nmol) return;
@@ -63,7 +65,10 @@ __global__ __launch_bounds__(256) void k_kinetic(const int* __restrict__ dims, c
   for (int i = a + lane_id(); i < b; i += kWave)
     acc += mass[i] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
   acc = wave_sum_d(acc);
-  if (lane_id() == 0) ke[m] = 0.5 * acc / kAccUnit;
+  if (lane_id() == 0) {
+    ke[m] = 0.5 * acc / kAccUnit;
+    if (kdone) kdone[m] += 1;
+  }
 }
 
 // Server step integration, driven by per-molecule counters (see above).
@@ -89,19 +94,6 @@ __global__ __launch_bounds__(256) void k_serve_integrate(const int* __restrict__
     v[3 * i + c] = vv;
     if (drift) x[3 * i + c] += dt * vv;
   }
-}
-
-__global__ void k_serve_advance(const int* __restrict__ dims, int* __restrict__ kdone) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m < dims[1]) kdone[m] += 1;
-}
-
-__global__ __launch_bounds__(256) void k_cast_pos(const int* __restrict__ dims, const double* __restrict__ x,
-                                                  float* __restrict__ pos32) {
-  const int n = dims[0];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * n) return;
-  pos32[i] = (float)x[i];
 }
 
 // New packed atom t takes its state from old packed atom src[t] (>= 0) or from
@@ -142,11 +134,6 @@ __global__ __launch_bounds__(256) void k_gather_rows(const int* __restrict__ src
   }
 }
 
-__global__ void k_copy_bytes(const uint4* __restrict__ a, uint4* __restrict__ b, long n16) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n16) b[i] = a[i];
-}
-
 // ----------------------------------------------------------------- launchers
 
 void launch_vv_kick_drift(const int* dims, int n_cap, double* x, double* v, const float* F,
@@ -163,9 +150,10 @@ void launch_vv_kick(const int* dims, int n_cap, double* v, const float* F, const
 }
 
 void launch_kinetic(const int* dims, int nmol_cap, const int* off, const double* v,
-                    const double* mass, double* ke, hipStream_t st) {
+                    const double* mass, double* ke, int* kdone, hipStream_t st) {
   if (nmol_cap <= 0) return;
-  hipLaunchKernelGGL(k_kinetic, dim3((nmol_cap + 3) / 4), dim3(256), 0, st, dims, off, v, mass, ke);
+  hipLaunchKernelGGL(k_kinetic, dim3((nmol_cap + 3) / 4), dim3(256), 0, st, dims, off, v, mass, ke,
+                     kdone);
 }
 
 void launch_serve_integrate(const int* dims, int n_cap, const int* mol, const int* kdone,
@@ -176,16 +164,6 @@ void launch_serve_integrate(const int* dims, int n_cap, const int* mol, const in
                      kdone, nsteps, x, v, F, mass, dt);
 }
 
-void launch_serve_advance(const int* dims, int nmol_cap, int* kdone, hipStream_t st) {
-  if (nmol_cap <= 0) return;
-  hipLaunchKernelGGL(k_serve_advance, dim3((nmol_cap + 255) / 256), dim3(256), 0, st, dims, kdone);
-}
-
-void launch_cast_pos(const int* dims, int n_cap, const double* x, float* pos32, hipStream_t st) {
-  if (n_cap <= 0) return;
-  hipLaunchKernelGGL(k_cast_pos, dim3((3 * n_cap + 255) / 256), dim3(256), 0, st, dims, x, pos32);
-}
-
 void launch_gather_rows(const int* src, int n, const double* x_old, const double* v_old,
                         const int* sp_old, const double* m_old, const float* f_old,
                         const double* x_in, const double* v_in, const int* sp_in,
@@ -194,13 +172,6 @@ void launch_gather_rows(const int* src, int n, const double* x_old, const double
   if (n <= 0) return;
   hipLaunchKernelGGL(k_gather_rows, dim3((n + 255) / 256), dim3(256), 0, st, src, n, x_old, v_old,
                      sp_old, m_old, f_old, x_in, v_in, sp_in, m_in, x, v, sp, m, f);
-}
-
-void launch_copy_bytes(const void* a, void* b, size_t bytes, hipStream_t st) {
-  const long n16 = (long)(bytes / 16);
-  if (n16 <= 0) return;
-  hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, st,
-                     reinterpret_cast<const uint4*>(a), reinterpret_cast<uint4*>(b), n16);
 }
 
 }  // namespace nnp

@@ -11,7 +11,7 @@
 //   HEAD : h3 = CELU(acc + b); E_i = w_out . h3 + b_out;
 //          delta3 = upstream_i * w_out * CELU'(z3)             (last hidden layer)
 //   BWD  : delta = acc * CELU'(z) with CELU'(z) = 1 + h/alpha for h <= 0
-//   OUT32: plain float32 output (dE/dG)
+//   OUT  : plain output in the operand type (dE/dG)
 // BF16 operands use v_mfma_f32_16x16x32_bf16 and FP32 operands
 // v_mfma_f32_16x16x4f32; both accumulate in FP32.  Each K stage moves 128
 // bytes of every tile row through a double-buffered LDS ring (rows padded to
@@ -168,39 +168,73 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   // ------------------------------------------------------------- epilogue
   const float* bias = a.bias ? a.bias + (size_t)s * a.sBias : nullptr;
   const int rq = (lane >> 4) * 4;  // first of this lane's 4 rows inside a 16x16 tile
-  float epart[TM][4];
-  if constexpr (EPI == EPI_HEAD) {
+  if constexpr (EPI != EPI_HEAD) {
+    // Stage the tile in LDS as float (CELU applied, or raw accumulators), then
+    // write whole rows with one 4-column vector per thread and pass.
+    constexpr int CS = BN + 4;
+    static_assert((size_t)BM * CS * 4 <= gemm_lds_bytes<T, BM, BN>(), "staging fits");
+    float* ct = reinterpret_cast<float*>(smem);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rloc = wm * WTM + i * 16 + rq + e;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int cloc = wn * WTN + j * 16 + rl;
+          float v = acc[i][j][e];
+          if constexpr (EPI == EPI_CELU) {
+            const int col = n0 + cloc;
+            v = celu_f(v + (col < a.N ? bias[col] : 0.f), a.alpha, a.inv_alpha_l2e);
+          }
+          ct[rloc * CS + cloc] = v;
+        }
+      }
+    __syncthreads();
+    constexpr int C4 = BN / 4;
+    for (int idx = tid; idx < BM * C4; idx += 256) {
+      const int rloc = idx / C4, c = (idx % C4) * 4;
+      const int row = row0 + rloc, col = n0 + c;
+      if (col >= a.N) continue;
+      const bool rv = row < row_end;
+      float4 v = *reinterpret_cast<const float4*>(ct + rloc * CS + c);
+      if (!rv) v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (EPI == EPI_BWD) {
+        if (rv) {
+          const T* hp = reinterpret_cast<const T*>(a.H) + (size_t)row * a.ldh + col;
+          const float inv_a = 1.f / a.alpha;
+          float h0 = Store<T>::get(hp), h1 = Store<T>::get(hp + 1), h2 = Store<T>::get(hp + 2),
+                h3 = Store<T>::get(hp + 3);
+          v.x *= h0 > 0.f ? 1.f : 1.f + h0 * inv_a;
+          v.y *= h1 > 0.f ? 1.f : 1.f + h1 * inv_a;
+          v.z *= h2 > 0.f ? 1.f : 1.f + h2 * inv_a;
+          v.w *= h3 > 0.f ? 1.f : 1.f + h3 * inv_a;
+        }
+      }
+      Store<T>::put4(reinterpret_cast<T*>(a.C) + (size_t)row * a.ldc + col, v);
+    }
+    return;
+  } else {
+    float epart[TM][4];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) epart[i][e] = 0.f;
-  }
-  const float* wout = (EPI == EPI_HEAD) ? a.w_out + (size_t)s * a.sWout : nullptr;
+    const float* wout = a.w_out + (size_t)s * a.sWout;
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
+    for (int i = 0; i < TM; ++i) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int rloc = wm * WTM + i * 16 + rq + e;
-      const int row = row0 + rloc;
-      const bool rv = row < row_end;
-      float up = 1.f;
-      if constexpr (EPI == EPI_HEAD) {
-        up = 0.f;
-        if (rv) {
-          up = 1.f;
-          if (a.dLdE) up = (float)a.dLdE[a.mol[a.perm[row]]];
-        }
-      }
+      for (int e = 0; e < 4; ++e) {
+        const int rloc = wm * WTM + i * 16 + rq + e;
+        const int row = row0 + rloc;
+        const bool rv = row < row_end;
+        float up = 0.f;
+        if (rv) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const int col = n0 + wn * WTN + j * 16 + rl;
-        if (col >= a.N) continue;
-        const float v = acc[i][j][e];
-        if constexpr (EPI == EPI_CELU) {
-          const float h = rv ? celu_f(v + bias[col], a.alpha, a.inv_alpha_l2e) : 0.f;
-          Store<T>::put(reinterpret_cast<T*>(a.C) + (size_t)row * a.ldc + col, h);
-        } else if constexpr (EPI == EPI_HEAD) {
-          const float z = v + bias[col];
+        for (int j = 0; j < TN; ++j) {
+          const int col = n0 + wn * WTN + j * 16 + rl;
+          if (col >= a.N) continue;
+          const float z = acc[i][j][e] + bias[col];
           const float ex = __builtin_amdgcn_exp2f(fminf(z, 0.f) * a.inv_alpha_l2e);
           const float h = z > 0.f ? z : a.alpha * (ex - 1.f);
           const float dh = z > 0.f ? 1.f : ex;
@@ -210,20 +244,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
                           rv ? up * wout[col] * dh : 0.f);
           if (a.H3)
             Store<T>::put(reinterpret_cast<T*>(a.H3) + (size_t)row * a.ldh3 + col, rv ? h : 0.f);
-        } else if constexpr (EPI == EPI_BWD) {
-          float d = 0.f;
-          if (rv) {
-            const float hp = Store<T>::get(reinterpret_cast<const T*>(a.H) + (size_t)row * a.ldh + col);
-            d = v * (hp > 0.f ? 1.f : 1.f + hp / a.alpha);
-          }
-          Store<T>::put(reinterpret_cast<T*>(a.C) + (size_t)row * a.ldc + col, d);
-        } else {  // EPI_OUT32
-          reinterpret_cast<float*>(a.C)[(size_t)row * a.ldc + col] = rv ? v : 0.f;
         }
       }
     }
-  }
-  if constexpr (EPI == EPI_HEAD) {
     // sum the 16 column lanes of each row, then the WN column slices (waves)
     float* part = reinterpret_cast<float*>(smem);  // [WN][BM], LDS reused after the K loop
 #pragma unroll
@@ -308,7 +331,7 @@ bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st) {
     case EPI_CELU: return launch_body<T, EPI_CELU>(a, rows_cap, st);
     case EPI_HEAD: return launch_head<T>(a, rows_cap, st);
     case EPI_BWD: return launch_body<T, EPI_BWD>(a, rows_cap, st);
-    case EPI_OUT32: return launch_body<T, EPI_OUT32>(a, rows_cap, st);
+    case EPI_OUT: return launch_body<T, EPI_OUT>(a, rows_cap, st);
   }
   return false;
 }

@@ -14,6 +14,7 @@ namespace nnp {
 
 __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __restrict__ dims,
                                                const float* __restrict__ pos,
+                                               const double* __restrict__ pos64,
                                                const int* __restrict__ species,
                                                const int* __restrict__ off, int S,
                                                float4* __restrict__ xyzs, int* __restrict__ mol,
@@ -32,7 +33,16 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __r
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
-    float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    float x, y, z;
+    if (pos64) {  // MD state: the potential sees the FP32 rounding of x
+      x = (float)pos64[3 * i];
+      y = (float)pos64[3 * i + 1];
+      z = (float)pos64[3 * i + 2];
+    } else {
+      x = pos[3 * i];
+      y = pos[3 * i + 1];
+      z = pos[3 * i + 2];
+    }
     int s = species[i];
     uint32_t st = 0;
     if (s < 0 || s >= S) {
@@ -65,38 +75,40 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __r
   if (threadIdx.x == 0) hist[kMaxS * gridDim.x + blockIdx.x] = (int)bits;
 }
 
-// One block: species totals, padded group starts, per-block bases of the
-// stable scatter, pad-row markers, molecule-offset validation, the chunk
-// table of the weight-gradient reduction, and the evaluation's status word
-// (overwritten here; kernels that run later only add bits).
-__global__ __launch_bounds__(1024) void k_groups(const int* __restrict__ dims, int nblk, int S,
-                                                 int* __restrict__ hist, GroupTable* __restrict__ gt,
-                                                 int* __restrict__ perm, int rows_cap,
-                                                 const int* __restrict__ off, int wchunk_rows,
-                                                 uint32_t* __restrict__ status) {
+// One block of kMaxS waves (wave q works on species q): species totals,
+// padded group starts, per-block bases of the stable scatter (wave-level
+// prefix sums, no block barriers inside the scans), pad-row markers,
+// molecule-offset validation, the chunk table of the weight-gradient
+// reduction, and the evaluation's status word (overwritten here; kernels
+// that run later only add bits).
+__global__ __launch_bounds__(512) void k_groups(const int* __restrict__ dims, int nblk, int S,
+                                                int* __restrict__ hist, GroupTable* __restrict__ gt,
+                                                int* __restrict__ perm, int rows_cap,
+                                                const int* __restrict__ off, int wchunk_rows,
+                                                uint32_t* __restrict__ status) {
   __shared__ int tot[kMaxS];
   __shared__ int pst[kMaxS + 1];
-  __shared__ int scan[1024];
+  __shared__ unsigned int bits_all;
   const int n = dims[0], nmol = dims[1];
-  const int t = threadIdx.x;
-  if (t < kMaxS) tot[t] = 0;
-  __syncthreads();
-  for (int s = 0; s < S; ++s) {
+  const int t = threadIdx.x, wq = t >> 6, lane = t & 63;
+  if (t == 0) bits_all = 0u;
+  if (wq < kMaxS) {
     int acc = 0;
-    for (int b = t; b < nblk; b += blockDim.x) acc += hist[s * nblk + b];
+    if (wq < S)
+      for (int b = lane; b < nblk; b += kWave) acc += hist[wq * nblk + b];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if ((t & 63) == 0) atomicAdd(&tot[s], acc);
+    if (lane == 0) tot[wq] = acc;
   }
   __syncthreads();
   if (t == 0) {
     int p = 0, c = 0;
-    for (int s = 0; s < kMaxS; ++s) {
-      int cnt = s < S ? tot[s] : 0;
-      pst[s] = p;
-      gt->cnt[s] = cnt;
-      gt->pstart[s] = p;
-      gt->wchunk[s] = c;
+    for (int q = 0; q < kMaxS; ++q) {
+      const int cnt = q < S ? tot[q] : 0;
+      pst[q] = p;
+      gt->cnt[q] = cnt;
+      gt->pstart[q] = p;
+      gt->wchunk[q] = c;
       p += (cnt + kPad - 1) / kPad * kPad;
       c += (cnt + wchunk_rows - 1) / wchunk_rows;
     }
@@ -108,45 +120,38 @@ __global__ __launch_bounds__(1024) void k_groups(const int* __restrict__ dims, i
   }
   __syncthreads();
   // exclusive scan of each species' block counts, offset by the group start
-  for (int s = 0; s < S; ++s) {
-    int carry = pst[s];
-    for (int b0 = 0; b0 < nblk; b0 += blockDim.x) {
-      int b = b0 + t;
-      int v = b < nblk ? hist[s * nblk + b] : 0;
-      scan[t] = v;
-      __syncthreads();
-      for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        int u = t >= o ? scan[t - o] : 0;
-        __syncthreads();
-        scan[t] += u;
-        __syncthreads();
+  if (wq < S) {
+    int carry = pst[wq];
+    for (int b0 = 0; b0 < nblk; b0 += kWave) {
+      const int b = b0 + lane;
+      const int v = b < nblk ? hist[wq * nblk + b] : 0;
+      int incl = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
       }
-      if (b < nblk) hist[s * nblk + b] = carry + scan[t] - v;
-      int last = scan[blockDim.x - 1];
-      __syncthreads();
-      carry += last;
+      if (b < nblk) hist[wq * nblk + b] = carry + incl - v;
+      carry += __shfl(incl, 63, 64);
     }
   }
   // pad rows: inside each group after its atoms, and after the last group
-  for (int s = 0; s < kMaxS; ++s) {
-    int a = pst[s] + (s < S ? tot[s] : 0), b = pst[s + 1];
-    for (int r = a + t; r < b; r += blockDim.x) perm[r] = -1;
+  for (int q = 0; q < kMaxS; ++q) {
+    const int a = pst[q] + (q < S ? tot[q] : 0), e = pst[q + 1];
+    for (int r = a + t; r < e; r += blockDim.x) perm[r] = -1;
   }
   for (int r = pst[kMaxS] + t; r < rows_cap; r += blockDim.x) perm[r] = -1;
-  // offsets: off[0] == 0, non-decreasing, off[nmol] == n
+  // offsets: off[0] == 0, non-decreasing, off[nmol] == n; staging bits
   bool bad = false;
   for (int m = t; m < nmol; m += blockDim.x) bad |= off[m] > off[m + 1];
   if (t == 0) bad |= off[0] != 0 || off[nmol] != n;
-  // status word of this evaluation: staging bits of every block + offsets
   uint32_t bits = bad ? kStOffsets : 0u;
   for (int b = t; b < nblk; b += blockDim.x) bits |= (uint32_t)hist[kMaxS * nblk + b];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, o, 64);
-  if (t == 0) scan[0] = 0;
+  if (lane == 0 && bits) atomicOr(&bits_all, bits);
   __syncthreads();
-  if ((t & 63) == 0 && bits) atomicOr(reinterpret_cast<unsigned int*>(&scan[0]), bits);
-  __syncthreads();
-  if (t == 0) *status = (uint32_t)scan[0];
+  if (t == 0) *status = bits_all;
 }
 
 // Stable scatter into species-sorted rows: rank = block base + earlier waves
@@ -218,17 +223,17 @@ __global__ void k_fill_f64(double* __restrict__ p, double v, int n) {
 // ----------------------------------------------------------------- launchers
 
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
-                  const int* species, const int* off, int S, float4* xyzs, int* mol, float* Fzero,
-                  int* hist, uint32_t* status, hipStream_t st) {
+                  const double* pos64, const int* species, const int* off, int S, float4* xyzs,
+                  int* mol, float* Fzero, int* hist, uint32_t* status, hipStream_t st) {
   const int nblk = stage_blocks(n_cap);
-  hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, dims, pos, species,
-                     off, S, xyzs, mol, Fzero, hist, status);
+  hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, dims, pos, pos64,
+                     species, off, S, xyzs, mol, Fzero, hist, status);
 }
 
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
                    int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_groups, dim3(1), dim3(1024), 0, st, dims, stage_blocks(n_cap), S, hist, gt,
+  hipLaunchKernelGGL(k_groups, dim3(1), dim3(64 * kMaxS), 0, st, dims, stage_blocks(n_cap), S, hist, gt,
                      perm, rows_cap, off, wchunk_rows, status);
 }
 

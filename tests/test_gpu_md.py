@@ -71,9 +71,14 @@ def test_time_reversibility():
     assert err <= 1e-5
 
 
-def test_nve_energy_drift_water_box():
-    s = w.water_box(300, 20.9, seed=12, n_species=7)  # ~0.1 atoms/A^3, 900 atoms
-    announce(f"NVE drift, {s.n_atoms}-atom water box, 400 steps at 0.5 fs")
+def test_nve_energy_error_matches_oracle_integrator():
+    # The random-weight potential heats a water box quickly (kinetic energy
+    # grows ~20x in 100 fs), so energy conservation is judged against the FP64
+    # oracle integrator on the same system and step: the GPU path's
+    # max |E_tot - E_0| must be no worse than the oracle's, up to a small
+    # FP32 allowance.
+    s = w.water_box(60, 12.0, seed=12, n_species=7)
+    announce(f"NVE energy error vs oracle, {s.n_atoms}-atom water box, 160 steps at 0.25 fs")
     pot, at, mt = potential(7, "fp32")
     v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(3))
     pos, sp, off = to_dev(s)
@@ -81,16 +86,23 @@ def test_nve_energy_drift_water_box():
     v = torch.from_numpy(v0).cuda()
     m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
     E0, F = pot.energy_forces(pos, sp, off, s.box)
-    ke0 = o.kinetic_energy(v0, w.MASS_AMU[s.species])
-    tot = [E0.item() + ke0]
-    for _ in range(8):
-        Ep, Ek = pot.md_steps(x, v, F, m, sp, off, 0.5, 50, s.box)
+    tot = [E0.item() + o.kinetic_energy(v0, w.MASS_AMU[s.species])]
+    for _ in range(16):
+        Ep, Ek = pot.md_steps(x, v, F, m, sp, off, 0.25, 10, s.box)
         tot.append(Ep.item() + Ek.item())
     pot.check()
-    tot = np.array(tot)
-    drift = np.abs(tot - tot[0]).max() / s.n_atoms
-    print(f"max |E_tot - E_0| / atom = {drift:.2e} eV over 200 fs")
-    assert drift <= 2e-4
+    gpu_err = np.abs(np.array(tot) - tot[0]).max() / s.n_atoms
+
+    def ff(x32):
+        r = o.energy_forces(x32, s.species, s.mol_offsets, s.box, aev_table=at, mlp_table=mt)
+        return r.E, r.F
+
+    _, _, rec = o.velocity_verlet(s.pos.astype(np.float64), v0, w.MASS_AMU[s.species], ff, 0.25,
+                                  160, record_every=10)
+    e = np.array([r[1] + r[2] for r in rec])
+    ora_err = np.abs(e - e[0]).max() / s.n_atoms
+    print(f"max |E_tot - E_0| / atom: GPU {gpu_err:.3e} eV, oracle {ora_err:.3e} eV")
+    assert gpu_err <= 1.2 * ora_err + 1e-5
 
 
 def _requests(n, seed=3):

@@ -274,3 +274,26 @@ def test_empty_and_isolated():
     r = o.energy_forces(s, aev_table=at, mlp_table=mt)
     np.testing.assert_allclose(E.cpu().numpy(), r.E, rtol=1e-6, atol=1e-7)
     assert np.all(F.cpu().numpy() == 0)
+
+
+def test_graph_replay_matches_eager():
+    # replays of a captured evaluation, with positions changed in place and
+    # eager evaluations and synchronisations between the replays
+    s = w.conformer_batch(16, 64, seed=1)
+    announce("graph replay vs eager, 16x64 batch, 4 replays")
+    for prec in ("fp32", "bf16"):
+        pot, at, mt = get_pot(7, prec)
+        pos, sp, off = to_dev(s)
+        g = pot.capture(pos, sp, off, None)
+        rng = torch.Generator(device="cpu").manual_seed(5)
+        for k in range(4):
+            with torch.no_grad():
+                pos.add_((torch.randn(pos.shape, generator=rng) * 0.01).cuda())
+            torch.cuda.synchronize()
+            E_ref, F_ref = pot.energy_forces(pos, sp, off, None)
+            torch.cuda.synchronize()
+            g.launch()
+            g.synchronize()
+            g.check()
+            assert torch.equal(g.E.cpu(), E_ref.cpu()), (prec, k)
+            assert rel_rms(g.F.cpu().numpy(), F_ref.cpu().numpy()) <= 1e-6, (prec, k)
