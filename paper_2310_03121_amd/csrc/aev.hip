@@ -7,18 +7,18 @@
 // are the negative gradient of the energy (Methods, "PyTorch Model Support").
 //
 // Per atom the wave first loads its neighbor records into LDS (displacement,
-// distance, cutoff values, species) and clears an LDS copy of its feature
-// row.  Radial terms use lanes (g, m): four neighbors at a time, one radial
-// shift m per lane; per-species sums stay in registers and are combined
-// across the four neighbor slots by lane shuffles.  Angular terms run over
-// the unordered pairs {j, k} of angular neighbors directly: lanes (t, z) take
-// eight pairs at a time, one angle shift z per lane, and add their four
-// radial-shift terms to the LDS row at the pair's species block (LDS atomic
-// adds).  The finished row is written to global memory once, four features
-// per lane, so the output is coalesced.  The angle term uses the identity
+// distance, cutoff values, species).  Radial terms use lanes (g, m): four
+// neighbors at a time, one radial shift m per lane; per-species sums stay in
+// registers and are combined across the four neighbor slots by lane
+// shuffles.  Angular terms walk the species-pair blocks in layout order: the
+// angular neighbors are grouped by species, so a block's pairs are the
+// products of two species segments (or the pairs inside one); empty blocks
+// cost a single store of zeros.  Lanes (t, z) take eight pairs at a time, one
+// angle shift z per lane, keep the four radial shifts in registers, and the
+// block's 32 sums are combined across pair slots by shuffles and stored once,
+// in a fixed order.  The angle term uses the identity
 // cos(theta - theta_z) = kappa c cos(theta_z) + sqrt(1 - kappa^2 c^2) sin(theta_z)
 // for theta = acos(kappa c); (1 + cos)/2 raised to zeta is exp2(zeta log2(.)).
-// Radial terms go straight into the LDS row with LDS atomic adds.
 //
 // The adjoint recomputes the same terms, contracts them with g = dE/dG
 // (read from the network backward pass, only the blocks the atom touches),
@@ -96,8 +96,9 @@ __device__ __forceinline__ int pair_block(int p, int q, int S) {
   return lo * S - lo * (lo - 1) / 2 + (hi - lo);
 }
 
-// LDS per wave (forward): feature row [Fp] float, then per neighbor
-// float4 (dx, dy, dz, r), float2 (fc_rad, fc_ang), int species.
+// LDS per wave (forward): per neighbor float4 (dx, dy, dz, r), float2
+// (fc_rad, fc_ang), int species.  The feature row is accumulated in
+// registers and stored block by block, so no LDS row is needed.
 constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
 
 template <typename OutT>
@@ -113,12 +114,10 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   const int lane = lane_id();
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
-  const int Fp = C.Fp;
-  char* base = reinterpret_cast<char*>(lds4) + (size_t)w * (Fp * 4 + cap * kFwdBytesPerNbr);
-  float* rowl = reinterpret_cast<float*>(base);
-  float4* nd = reinterpret_cast<float4*>(rowl + Fp);
-  float2* nf = reinterpret_cast<float2*>(nd + cap);
-  int* nsp = reinterpret_cast<int*>(nf + cap);
+  float4* nd = lds4 + (size_t)w * cap;
+  float2* nf = reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) + (size_t)w * cap;
+  int* nsp = reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
+                                    (size_t)4 * cap) + w * cap;
 
   // the first 64 row entries are fetched together with the counts, so only
   // the neighbor-position gather waits on them
@@ -142,60 +141,106 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
     nf[e] = make_float2(fr, fa);
     nsp[e] = species_of(pj);
   }
-  for (int c = lane * 4; c < Fp; c += 4 * kWave)
-    *reinterpret_cast<float4*>(rowl + c) = make_float4(0.f, 0.f, 0.f, 0.f);
   wave_lds_sync();
   const int S = C.S;
+  OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
 
-  // ---- radial: lanes (g, m), four neighbors per pass, LDS adds into the
-  //      species block of each neighbor
+  // ---- radial: lanes (g, m), four neighbors per pass, per-species registers
   {
     const int g = lane >> 4, m = lane & 15;
     const float Rm = pick(C.shf_r, m);
+    float acc[kMaxS];
+#pragma unroll
+    for (int q = 0; q < kMaxS; ++q) acc[q] = 0.f;
     for (int e = g; e < nr; e += 4) {
       const float u = nd[e].w - Rm;
-      atomicAdd(rowl + nsp[e] * kNR + m, C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x);
+      const float term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x;
+      const int s = nsp[e];
+#pragma unroll
+      for (int q = 0; q < kMaxS; ++q) acc[q] += (s == q) ? term : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxS; ++q) {
+      acc[q] += __shfl_xor(acc[q], 16, 64);
+      acc[q] += __shfl_xor(acc[q], 32, 64);
+      if ((q & 3) == g && q < S) Store<OutT>::put(orow + q * kNR + m, acc[q]);
     }
   }
 
-  // ---- angular: lanes (t, z), eight unordered neighbor pairs per pass
+  // ---- angular: species-pair blocks in layout order.  The angular entries
+  // [0, na) are grouped by species; each species' segment comes from a ballot.
+  // Lanes (t, z): eight neighbor pairs per pass, one angle shift per lane, the
+  // four radial shifts in registers; sums over pairs by shuffles.
   {
+    int seg[kMaxS + 1];
+#pragma unroll
+    for (int q = 0; q <= kMaxS; ++q) seg[q] = 0;
+    for (int e0 = 0; e0 < na; e0 += kWave) {
+      const int sp_l = e0 + lane < na ? nsp[e0 + lane] : -1;
+#pragma unroll
+      for (int q = 0; q < kMaxS; ++q) seg[q + 1] += __popcll(ballot(sp_l == q));
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxS; ++q) seg[q + 1] += seg[q];
     const int tz = lane & 7, tg = lane >> 3;
     const float cz = pick(C.cos_z, tz), sz = pick(C.sin_z, tz);
     const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
-    const int T = na * (na - 1) / 2;
-    float* ang = rowl + S * kNR + tz;
-    for (int t0 = 0; t0 < T; t0 += 8) {
-      const int t = t0 + tg;
-      if (t < T) {
-        int ej, ek;
-        decode_pair(t, na, ej, ek);
-        const float4 vj = nd[ej], vk = nd[ek];
-        const float fj = nf[ej].y, fk = nf[ek].y;
-        const int blk = pair_block(nsp[ej], nsp[ek], S);
-        const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
-        const float kc = C.kappa * cs;
-        const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
-        const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
-        const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fj * fk;
-        const float dbar = 0.5f * (vj.w + vk.w);
-        float* dst = ang + blk * 32;
-        float u;
-        u = dbar - ra0; atomicAdd(dst, wgt * fast_exp2(-C.eta_a_l2e * u * u));
-        u = dbar - ra1; atomicAdd(dst + 8, wgt * fast_exp2(-C.eta_a_l2e * u * u));
-        u = dbar - ra2; atomicAdd(dst + 16, wgt * fast_exp2(-C.eta_a_l2e * u * u));
-        u = dbar - ra3; atomicAdd(dst + 24, wgt * fast_exp2(-C.eta_a_l2e * u * u));
+    OutT* ang = orow + S * kNR;
+    int blk = 0;
+    for (int p = 0; p < S; ++p) {
+      const int p0 = seg[p], cp = seg[p + 1] - seg[p];
+      for (int q = p; q < S; ++q, ++blk) {
+        const int q0 = seg[q], cq = seg[q + 1] - seg[q];
+        const bool same = p == q;
+        const int T = same ? cp * (cp - 1) / 2 : cp * cq;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int t0 = 0; t0 < T; t0 += 8) {
+          const int t = t0 + tg;
+          if (t < T) {
+            int ej, ek;
+            if (same) {
+              decode_pair(t, cp, ej, ek);
+              ej += p0;
+              ek += p0;
+            } else {
+              const int x = t / cq;
+              ej = p0 + x;
+              ek = q0 + (t - x * cq);
+            }
+            const float4 vj = nd[ej], vk = nd[ek];
+            const float fj = nf[ej].y, fk = nf[ek].y;
+            const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
+            const float kc = C.kappa * cs;
+            const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
+            const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
+            const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fj * fk;
+            const float dbar = 0.5f * (vj.w + vk.w);
+            float u;
+            u = dbar - ra0; a0 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
+            u = dbar - ra1; a1 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
+            u = dbar - ra2; a2 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
+            u = dbar - ra3; a3 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
+          }
+        }
+        if (T > 0) {
+#pragma unroll
+          for (int o = 8; o <= 32; o <<= 1) {
+            a0 += __shfl_xor(a0, o, 64);
+            a1 += __shfl_xor(a1, o, 64);
+            a2 += __shfl_xor(a2, o, 64);
+            a3 += __shfl_xor(a3, o, 64);
+          }
+        }
+        // lane l < 32 holds (a = l / 8, z = l % 8): feature blk*32 + l
+        if (lane < 32) {
+          const int sel = lane >> 3;
+          const float v = sel == 0 ? a0 : (sel == 1 ? a1 : (sel == 2 ? a2 : a3));
+          Store<OutT>::put(ang + blk * 32 + lane, v);
+        }
       }
     }
   }
-  wave_lds_sync();
-
-  // ---- write the row (coalesced, 4 features per lane and pass)
-  OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
-  for (int c = lane * 4; c < ld; c += 4 * kWave) {
-    const float4 v = *reinterpret_cast<const float4*>(rowl + c);
-    Store<OutT>::put4(orow + c, v);
-  }
+  for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
 }
 
 // LDS per wave (adjoint): per neighbor float4 (dx, dy, dz, r), float4
@@ -370,7 +415,7 @@ void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const BoxCons
                     const float4* xyzs, const int* nbr, const int2* counts, int cap,
                     const int* row_of, OutT* out, int ld, hipStream_t st) {
   if (n_cap <= 0) return;
-  const size_t lds = (size_t)4 * (C.Fp * 4 + cap * kFwdBytesPerNbr);
+  const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr;
   static const bool attr = (ensure_lds(k_aev_fwd<OutT>), true);
   (void)attr;
   hipLaunchKernelGGL(k_aev_fwd<OutT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, B,

@@ -59,12 +59,12 @@ constexpr int kWChunk = 1024;  // rows per weight-gradient partial
 
 enum Stage {
   ST_STAGE = 0, ST_PAIRS, ST_AEV, ST_L1, ST_L2, ST_HEAD, ST_ENERGY, ST_BWD3, ST_BWD2, ST_GRADG,
-  ST_AEVBWD, ST_WGRAD, ST_COUNT
+  ST_AEVBWD, ST_WGRAD, ST_MID, ST_COUNT
 };
 const char* kStageNames[ST_COUNT] = {
     "stage+sort", "neighbors", "aev_fwd", "mlp_layer1", "mlp_layer2", "mlp_layer3_head",
     "energy_sum", "mlp_bwd_layer3", "mlp_bwd_layer2", "mlp_bwd_dEdG", "aev_bwd_forces",
-    "weight_grads"};
+    "weight_grads", "mlp_mid_fused"};
 
 hipEvent_t prof_event(nnp_handle* h) {
   if (h->ev_next == h->ev_pool.size()) {
@@ -281,45 +281,84 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     StageTimer t(h, ST_L1, st);
     ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
   }
-  // layer 2: H2 = CELU(H1 W1^T + b1)
-  g.A = H1; g.lda = w1; g.B = W[1]; g.sB = (long)w2 * w1; g.ldb = w1;
-  g.bias = h->bias[1]; g.sBias = w2; g.N = w2; g.K = w1; g.C = H2; g.ldc = w2;
-  {
-    StageTimer t(h, ST_L2, st);
-    ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
-  }
-  // layer 3 + output: E_i, delta3
-  g.A = H2; g.lda = w2; g.B = W[2]; g.sB = (long)w3 * w2; g.ldb = w2;
-  g.bias = h->bias[2]; g.sBias = w3; g.N = w3; g.K = w2;
-  g.C = need_bwd ? (void*)D3 : nullptr; g.ldc = w3;
-  g.w_out = h->wout; g.sWout = w3; g.b_out = h->bout; g.erow = erow;
-  g.H3 = io.dparams ? (void*)H3 : nullptr; g.ldh3 = w3;
-  g.perm = perm; g.mol = mol; g.dLdE = io.dLdE;
-  g.uprow = io.dparams ? at<float>(ws, P.uprow) : nullptr;
-  {
-    StageTimer t(h, ST_HEAD, st);
-    ok &= launch_gemm<T>(EPI_HEAD, g, P.rows_cap, st);
-  }
-  g.H3 = nullptr;
-  g.uprow = nullptr;
-  if (io.E) {
-    StageTimer t(h, ST_ENERGY, st);
-    launch_energy(dims, P.nmol, io.off, xyzs, row, erow, h->eself, io.E, status, st);
-  }
-  if (need_bwd) {
-    // delta2 = (delta3 W2) * CELU'(z2)
-    g.A = D3; g.lda = w3; g.B = WT[2]; g.sB = (long)w2 * w3; g.ldb = w3;
-    g.bias = nullptr; g.N = w2; g.K = w3; g.C = D2; g.ldc = w2; g.H = H2; g.ldh = w2;
-    {
-      StageTimer t(h, ST_BWD3, st);
-      ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+  // BF16 with gradients: one fused launch for layer 2, the energy head and the
+  // adjoint of layers 3 and 2 (intermediates stay in LDS)
+  bool fused = false;
+  if (bf && need_bwd) {
+    MidArgs ma{};
+    ma.gt = gt;
+    ma.H1 = reinterpret_cast<const bf16_t*>(H1);
+    ma.W1 = h->Wb[1];
+    ma.W2 = h->Wb[2];
+    ma.W2T = h->WTb[2];
+    ma.W1T = h->WTb[1];
+    ma.b1 = h->bias[1];
+    ma.b2 = h->bias[2];
+    ma.wout = h->wout;
+    ma.bout = h->bout;
+    ma.erow = erow;
+    ma.D1 = reinterpret_cast<bf16_t*>(D1);
+    if (io.dparams) {
+      ma.H2 = reinterpret_cast<bf16_t*>(H2);
+      ma.H3 = reinterpret_cast<bf16_t*>(H3);
+      ma.D3 = reinterpret_cast<bf16_t*>(D3);
+      ma.D2 = reinterpret_cast<bf16_t*>(D2);
+      ma.uprow = at<float>(ws, P.uprow);
     }
-    // delta1 = (delta2 W1) * CELU'(z1)
-    g.A = D2; g.lda = w2; g.B = WT[1]; g.sB = (long)w1 * w2; g.ldb = w2;
-    g.N = w1; g.K = w2; g.C = D1; g.ldc = w1; g.H = H1; g.ldh = w1;
+    ma.perm = perm;
+    ma.mol = mol;
+    ma.dLdE = io.dLdE;
+    ma.alpha = h->alpha;
+    ma.inv_alpha_l2e = g.inv_alpha_l2e;
+    StageTimer t(h, ST_MID, st);
+    fused = launch_mlp_mid(h->width, ma, P.rows_cap, st);
+  }
+  if (fused) {
+    if (io.E) {
+      StageTimer t(h, ST_ENERGY, st);
+      launch_energy(dims, P.nmol, io.off, xyzs, row, erow, h->eself, io.E, status, st);
+    }
+  } else {
+    // layer 2: H2 = CELU(H1 W1^T + b1)
+    g.A = H1; g.lda = w1; g.B = W[1]; g.sB = (long)w2 * w1; g.ldb = w1;
+    g.bias = h->bias[1]; g.sBias = w2; g.N = w2; g.K = w1; g.C = H2; g.ldc = w2;
     {
-      StageTimer t(h, ST_BWD2, st);
-      ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+      StageTimer t(h, ST_L2, st);
+      ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
+    }
+    // layer 3 + output: E_i, delta3
+    g.A = H2; g.lda = w2; g.B = W[2]; g.sB = (long)w3 * w2; g.ldb = w2;
+    g.bias = h->bias[2]; g.sBias = w3; g.N = w3; g.K = w2;
+    g.C = need_bwd ? (void*)D3 : nullptr; g.ldc = w3;
+    g.w_out = h->wout; g.sWout = w3; g.b_out = h->bout; g.erow = erow;
+    g.H3 = io.dparams ? (void*)H3 : nullptr; g.ldh3 = w3;
+    g.perm = perm; g.mol = mol; g.dLdE = io.dLdE;
+    g.uprow = io.dparams ? at<float>(ws, P.uprow) : nullptr;
+    {
+      StageTimer t(h, ST_HEAD, st);
+      ok &= launch_gemm<T>(EPI_HEAD, g, P.rows_cap, st);
+    }
+    g.H3 = nullptr;
+    g.uprow = nullptr;
+    if (io.E) {
+      StageTimer t(h, ST_ENERGY, st);
+      launch_energy(dims, P.nmol, io.off, xyzs, row, erow, h->eself, io.E, status, st);
+    }
+    if (need_bwd) {
+      // delta2 = (delta3 W2) * CELU'(z2)
+      g.A = D3; g.lda = w3; g.B = WT[2]; g.sB = (long)w2 * w3; g.ldb = w3;
+      g.bias = nullptr; g.N = w2; g.K = w3; g.C = D2; g.ldc = w2; g.H = H2; g.ldh = w2;
+      {
+        StageTimer t(h, ST_BWD3, st);
+        ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+      }
+      // delta1 = (delta2 W1) * CELU'(z1)
+      g.A = D2; g.lda = w2; g.B = WT[1]; g.sB = (long)w1 * w2; g.ldb = w2;
+      g.N = w1; g.K = w2; g.C = D1; g.ldc = w1; g.H = H1; g.ldh = w1;
+      {
+        StageTimer t(h, ST_BWD2, st);
+        ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+      }
     }
   }
   if (io.out3) {

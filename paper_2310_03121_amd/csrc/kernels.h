@@ -35,6 +35,31 @@ struct GemmArgs {
   float inv_alpha_l2e; // log2(e) / alpha
 };
 
+struct MidArgs {
+  const GroupTable* gt;
+  const bf16_t* H1;               // [rows][W1]
+  const bf16_t* W1;               // [S][W2][W1]
+  const bf16_t* W2;               // [S][W3][W2]
+  const bf16_t* W2T;              // [S][W2][W3]
+  const bf16_t* W1T;              // [S][W1][W2]
+  const float* b1;                // [S][W2]
+  const float* b2;                // [S][W3]
+  const float* wout;              // [S][W3]
+  const float* bout;              // [S]
+  float* erow;                    // [rows]
+  bf16_t* D1;                     // [rows][W1]
+  bf16_t* H2;                     // optional [rows][W2]
+  bf16_t* H3;                     // optional [rows][W3]
+  bf16_t* D3;                     // optional [rows][W3]
+  bf16_t* D2;                     // optional [rows][W2]
+  float* uprow;                   // optional [rows]
+  const int* perm;
+  const int* mol;
+  const double* dLdE;
+  float alpha;
+  float inv_alpha_l2e;
+};
+
 struct PackArgs {
   const float* flat;
   long off[kMaxS * kLayers];  // flat offset of W for (species, layer)
@@ -98,6 +123,9 @@ void launch_wgrad(const GroupTable* gt, int S, int n_chunks_cap, const TD* D, in
                   const TH* H, int ldh, int Nin, int chunk, float* partial, float* dparams,
                   const long* param_off_dev, hipStream_t st);
 void launch_pack(const PackArgs& p, int S, hipStream_t st);
+
+// mlp_mid.hip
+bool launch_mlp_mid(const int* width, const MidArgs& a, int rows_cap, hipStream_t st);
 
 // md.hip
 void launch_vv_kick_drift(const int* dims, int n_cap, double* x, double* v, const float* F,
