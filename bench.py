@@ -39,10 +39,70 @@ def mlp_flops_per_atom(widths, F):
 def stage_flops(widths, F):
     """Algorithmic FLOPs per atom of each network stage."""
     w1, w2, w3 = widths[1], widths[2], widths[3]
-    return {
+    d = {
         "mlp_layer1": 2 * F * w1, "mlp_layer2": 2 * w1 * w2, "mlp_layer3_head": 2 * w2 * w3 + 2 * w3,
         "mlp_bwd_layer3": 2 * w3 * w2, "mlp_bwd_layer2": 2 * w2 * w1, "mlp_bwd_dEdG": 2 * w1 * F,
     }
+    d["mlp_mid_fused"] = (d["mlp_layer2"] + d["mlp_layer3_head"] + d["mlp_bwd_layer3"]
+                          + d["mlp_bwd_layer2"])
+    return d
+
+
+# Algorithmic fp32 operations of the symmetry-function kernels (add, mul and
+# each transcendental counted as one), from the radial and angular terms as
+# defined: per radial neighbor pair 16 shifts x 6 (difference, square, scale,
+# exp, cutoff product, sum) + 11 (distance, cutoff); per angular triple 151
+# (cosine 7, kappa and sine 4, 8 angle shifts x 7, 4 distance shifts x 4 + 2,
+# 32 products and sums, cutoff product 2).  The adjoint recomputes the forward
+# terms and adds their derivatives and the scatter: 199 per radial pair, 280
+# per angular triple.
+AEV_OPS = {"aev_fwd": (107, 151), "aev_bwd_forces": (199, 280)}
+PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, unpacked fp32
+
+
+def pair_counts(pot, n_atoms):
+    """Directed radial pairs and angular triples of the last evaluation."""
+    counts, _ = pot.debug_neighbors(n_atoms)
+    c = counts.cpu().numpy().astype(np.int64)
+    return int(c[:, 0].sum()), int((c[:, 1] * (c[:, 1] - 1) // 2).sum())
+
+
+def source_digest():
+    """sha256 over the HIP sources and headers of the library."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2310_03121_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(stage, workload_key):
+    """HBM bytes per launch of `stage` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled against a copy of known size), or None
+    when the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_key}.md")
+    if not os.path.exists(path):
+        return None
+    digest, rows = None, {}
+    for line in open(path):
+        if line.startswith("source_digest:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("|") and not line.startswith("|--"):
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 6 and cells[0] != "stage":
+                try:
+                    rows[cells[0]] = float(cells[5])
+                except ValueError:
+                    pass
+    if digest != source_digest() or stage not in rows:
+        return None
+    return rows[stage]
+
+
+WORKLOAD_KEYS = {"batch": "batch512x64", "water1500": "water1500", "water7667": "water7667"}
 
 
 def workload(name):
@@ -238,6 +298,8 @@ def main():
             r["force_rmse_eV_per_A"] = float(np.sqrt(np.mean((Fn - ref.F) ** 2)))
             r["force_rel_rms"] = float(np.linalg.norm(Fn - ref.F) / np.linalg.norm(ref.F))
             r["energy_max_abs_err_eV"] = float(np.max(np.abs(E.cpu().numpy() - ref.E)))
+        if prec == precs[0]:
+            r["pairs"], r["triples"] = pair_counts(pot, s.n_atoms)
         results[prec] = r
         del pot
         torch.cuda.empty_cache()
@@ -249,14 +311,23 @@ def main():
     sf = stage_flops(mt.widths, F_feat)
     st = main_r["stages_ms"]
     dom = max(st, key=st.get)
+    traffic = profiled_traffic(dom, WORKLOAD_KEYS[args.workload] + "_" + main_prec)
     if dom in sf:
         achieved = sf[dom] * s.n_atoms / (st[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[main_prec],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[main_prec], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[main_prec], "traffic": traffic,
                 "flop_per_launch": sf[dom] * s.n_atoms, "avg_launch_ms": st[dom]}
+    elif dom in AEV_OPS:
+        op_pair, op_trip = AEV_OPS[dom]
+        ops = op_pair * main_r["pairs"] + op_trip * main_r["triples"]
+        achieved = ops / (st[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
+                "flop_per_launch": ops, "avg_launch_ms": st[dom],
+                "pairs": main_r["pairs"], "triples": main_r["triples"]}
     else:
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None,
-                "frac": None, "traffic": None, "avg_launch_ms": st[dom]}
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": st[dom]}
     fwd, bwd = mlp_flops_per_atom(mt.widths, F_feat)
     path_tflops = (fwd + bwd) * s.n_atoms / (main_r["ms_per_step"] * 1e-3) / 1e12
 

@@ -35,10 +35,11 @@ struct nnp_handle {
   long param_off[kMaxS][kLayers] = {};  // flat offset of W for (species, layer)
   char* dmem = nullptr;
   float* flat = nullptr;
-  float* Wf[kLayers] = {};
+  float* Wf[kLayers] = {};     // row-major W and W^T (LDS-staged kernels)
   bf16_t* Wb[kLayers] = {};
   float* WTf[kLayers] = {};
-  bf16_t* WTb[kLayers] = {};
+  bf16_t* Wqb[kLayers] = {};   // fragment order, W and W^T (BF16 body kernels)
+  bf16_t* WTqb[kLayers] = {};
   float* bias[kLayers] = {};
   float* wout = nullptr;
   float* bout = nullptr;
@@ -266,8 +267,8 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   const T* W[kLayers];
   const T* WT[kLayers];
   for (int l = 0; l < kLayers; ++l) {
-    W[l] = bf ? (const T*)h->Wb[l] : (const T*)h->Wf[l];
-    WT[l] = bf ? (const T*)h->WTb[l] : (const T*)h->WTf[l];
+    W[l] = bf ? (const T*)h->Wqb[l] : (const T*)h->Wf[l];
+    WT[l] = bf ? (const T*)h->WTqb[l] : (const T*)h->WTf[l];
   }
   GemmArgs g{};
   g.gt = gt;
@@ -288,10 +289,10 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     MidArgs ma{};
     ma.gt = gt;
     ma.H1 = reinterpret_cast<const bf16_t*>(H1);
-    ma.W1 = h->Wb[1];
-    ma.W2 = h->Wb[2];
-    ma.W2T = h->WTb[2];
-    ma.W1T = h->WTb[1];
+    ma.W1 = h->Wqb[1];
+    ma.W2 = h->Wqb[2];
+    ma.W2T = h->WTqb[2];
+    ma.W1T = h->WTqb[1];
     ma.b1 = h->bias[1];
     ma.b2 = h->bias[2];
     ma.wout = h->wout;
@@ -327,7 +328,8 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
     }
     // layer 3 + output: E_i, delta3
-    g.A = H2; g.lda = w2; g.B = W[2]; g.sB = (long)w3 * w2; g.ldb = w2;
+    g.A = H2; g.lda = w2; g.sB = (long)w3 * w2; g.ldb = w2;
+    g.B = bf ? (const void*)h->Wb[2] : (const void*)h->Wf[2];  // row-major for the head
     g.bias = h->bias[2]; g.sBias = w3; g.N = w3; g.K = w2;
     g.C = need_bwd ? (void*)D3 : nullptr; g.ldc = w3;
     g.w_out = h->wout; g.sWout = w3; g.b_out = h->bout; g.erow = erow;
@@ -506,14 +508,16 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
     return a;
   };
   const size_t o_flat = take(o * 4);
-  size_t o_wf[kLayers], o_wb[kLayers], o_wtf[kLayers], o_wtb[kLayers], o_b[kLayers];
+  size_t o_wf[kLayers], o_wb[kLayers], o_wtf[kLayers], o_wqb[kLayers], o_wtqb[kLayers],
+      o_b[kLayers];
   for (int l = 0; l < kLayers - 1; ++l) {
     const size_t inp = l == 0 ? h->Fp : h->width[l];
     const size_t el = (size_t)S * h->width[l + 1] * inp;
     o_wf[l] = take(el * 4);
     o_wb[l] = take(el * 2);
     o_wtf[l] = take(el * 4);
-    o_wtb[l] = take(el * 2);
+    o_wqb[l] = take(el * 2);
+    o_wtqb[l] = take(el * 2);
     o_b[l] = take((size_t)S * h->width[l + 1] * 4);
   }
   const size_t o_wout = take((size_t)S * h->width[3] * 4);
@@ -529,7 +533,8 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
     h->Wf[l] = reinterpret_cast<float*>(h->dmem + o_wf[l]);
     h->Wb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wb[l]);
     h->WTf[l] = reinterpret_cast<float*>(h->dmem + o_wtf[l]);
-    h->WTb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wtb[l]);
+    h->Wqb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wqb[l]);
+    h->WTqb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wtqb[l]);
     h->bias[l] = reinterpret_cast<float*>(h->dmem + o_b[l]);
   }
   h->wout = reinterpret_cast<float*>(h->dmem + o_wout);
@@ -584,7 +589,8 @@ nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* s
     p.Wf[l] = h->Wf[l];
     p.Wb[l] = h->Wb[l];
     p.WTf[l] = h->WTf[l];
-    p.WTb[l] = h->WTb[l];
+    p.Wqb[l] = h->Wqb[l];
+    p.WTqb[l] = h->WTqb[l];
     p.bias[l] = h->bias[l];
   }
   p.wout = h->wout;

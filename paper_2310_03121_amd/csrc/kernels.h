@@ -10,7 +10,8 @@ enum { EPI_CELU = 0, EPI_HEAD = 1, EPI_BWD = 2, EPI_OUT = 3 };
 struct GemmArgs {
   const void* A;
   int lda;
-  const void* B;   // element s uses B + s * sB, row-major [N][K]
+  const void* B;   // element s uses B + s * sB: [N][K], BF16 body layers in fragment
+                   // order, otherwise row-major with stride ldb
   long sB;
   int ldb;
   const float* bias;
@@ -38,10 +39,10 @@ struct GemmArgs {
 struct MidArgs {
   const GroupTable* gt;
   const bf16_t* H1;               // [rows][W1]
-  const bf16_t* W1;               // [S][W2][W1]
-  const bf16_t* W2;               // [S][W3][W2]
-  const bf16_t* W2T;              // [S][W2][W3]
-  const bf16_t* W1T;              // [S][W1][W2]
+  const bf16_t* W1;               // [S][W2][W1], fragment order
+  const bf16_t* W2;               // [S][W3][W2], fragment order
+  const bf16_t* W2T;              // [S][W2][W3], fragment order
+  const bf16_t* W1T;              // [S][W1][W2], fragment order
   const float* b1;                // [S][W2]
   const float* b2;                // [S][W3]
   const float* wout;              // [S][W3]
@@ -65,10 +66,11 @@ struct PackArgs {
   long off[kMaxS * kLayers];  // flat offset of W for (species, layer)
   int width[kLayers + 1];
   int Fp;
-  float* Wf[kLayers];
+  float* Wf[kLayers];     // W [S][out][in_pad], row-major
   bf16_t* Wb[kLayers];
-  float* WTf[kLayers];
-  bf16_t* WTb[kLayers];
+  float* WTf[kLayers];    // W^T [S][in_pad][out], row-major
+  bf16_t* Wqb[kLayers];   // W in MFMA fragment order (N = out, K = in_pad)
+  bf16_t* WTqb[kLayers];  // W^T in MFMA fragment order (N = in_pad, K = out)
   float* bias[kLayers];
   float* wout;
   float* bout;
@@ -115,7 +117,6 @@ void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const BoxCons
                     hipStream_t st);
 
 // mlp.hip
-int gemm_pick_bn(int N, int epi);
 template <typename T>
 bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st);
 template <typename TD, typename TH>

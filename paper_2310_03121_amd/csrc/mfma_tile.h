@@ -1,0 +1,171 @@
+// MFMA building blocks shared by the network kernels.
+//
+// A wave owns a (TM*16) x (TN*16) block of C = A * B^T.  The activations A
+// sit in LDS (row-major, a byte stride per row); the weights B ([N][K]
+// row-major, the same for every row tile of an element and therefore L2
+// resident) are read from global memory straight into MFMA operand registers,
+// P k-steps ahead of their use, so weights need neither LDS space nor
+// barriers.  The MFMA is issued with the operands swapped (B as the first
+// source), which leaves each lane holding four consecutive columns of one row
+// of C: lane l has row l % 16 and columns 4 * (l / 16) + {0, 1, 2, 3} of each
+// 16 x 16 tile, so epilogues store 4-column vectors.
+//
+// Fragment of a k-step (16 bytes per lane, BF16): lane l holds row l % 16 of
+// its 16-row slice, elements [8 * (l / 16), +8) of the k-step's 32 (one
+// v_mfma_f32_16x16x32_bf16).  A is read that way from row-major LDS; B is
+// pre-packed so that the 64 lanes' fragments are contiguous.
+#pragma once
+#include "kernels.h"
+
+namespace nnp {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Frag;
+template <> struct Frag<bf16_t> {
+  static constexpr int KS = 32;  // K per k-step
+  static constexpr int EL = 8;   // elements per lane per fragment
+  __device__ __forceinline__ static void mma(const uint4& b, const uint4& a, f32x4_t& acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, b),
+                                                  __builtin_bit_cast(bf16x8_t, a), acc, 0, 0, 0);
+  }
+};
+
+// Register ring of weight fragments: slot u holds the TN fragments of every
+// k-step s with s % P == u.  Loads are unconditional (a step past the end
+// re-reads the last step, which keeps every access inside B), so the wait
+// before a step's MFMAs is an exact count of the loads issued after it.
+// B is stored in fragment order (see k_pack): tile nt, k-step ks, lane l at
+// ((nt * (K/KS) + ks) * 64 + l) * EL, so each fragment load is one contiguous
+// 1 KB block per wave.  Steps are counted per pass over [0, nsp), nsp = ns
+// rounded up to the ring depth: steps in [ns, nsp) re-read the last step
+// (their A columns are zero), and steps from nsp on read the next pass's
+// steps, so a pass's first fragments arrive while the previous one ends.
+template <typename T, int TN, int P>
+struct BRing {
+  static constexpr int FE = 64 * Frag<T>::EL;  // elements per fragment
+  uint4 r[P][TN];
+  const T* base;       // this pass: fragment (n_first / 16, 0) + this lane
+  const T* base_next;  // next pass (or this one again after the last)
+  size_t tile;         // elements per 16-row tile (all k-steps)
+  int ns, nsp;
+  __device__ __forceinline__ const T* at(const T* B, int n_first, int lane) const {
+    return B + (size_t)(n_first / 16) * tile + lane * Frag<T>::EL;
+  }
+  __device__ __forceinline__ void init(const T* B, int n_first, int n_next, int lane, int K) {
+    ns = K / Frag<T>::KS;
+    nsp = (ns + P - 1) / P * P;
+    tile = (size_t)ns * FE;
+    base = at(B, n_first, lane);
+    base_next = n_next >= 0 ? at(B, n_next, lane) : base;
+  }
+  __device__ __forceinline__ void next_pass(const T* B, int n_next, int lane) {
+    base = base_next;
+    base_next = n_next >= 0 ? at(B, n_next, lane) : base;
+  }
+  template <int U>
+  __device__ __forceinline__ void load(int s) {
+    const T* p = s < ns ? base + (size_t)s * FE
+                        : (s < nsp ? base + (size_t)(ns - 1) * FE : base_next + (size_t)(s - nsp) * FE);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) r[U][j] = *reinterpret_cast<const uint4*>(p + j * tile);
+  }
+  __device__ __forceinline__ void prologue() {
+    load<0>(0);
+    if constexpr (P > 1) load<1>(1);
+    if constexpr (P > 2) load<2>(2);
+    if constexpr (P > 3) load<3>(3);
+  }
+};
+
+// One k-step: TM A fragments from LDS (`arow` points at this lane's row and
+// k-group in the step's first column), TM x TN MFMAs against ring slot U,
+// then (if REFILL) the slot is refilled with step s_next.  The scheduling
+// barrier keeps the refill right behind the step: left alone, the compiler
+// sinks all refills of a group to its end, which removes the prefetch.
+template <typename T, int TM, int TN, int P, int U, bool REFILL>
+__device__ __forceinline__ void kstep(const unsigned char* arow, int astride16, BRing<T, TN, P>& br,
+                                      int s_next, f32x4_t (&acc)[TM][TN]) {
+  uint4 fa[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) fa[i] = *reinterpret_cast<const uint4*>(arow + i * astride16);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) Frag<T>::mma(br.r[U][j], fa[i], acc[i][j]);
+  if constexpr (REFILL) br.template load<U>(s_next);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// A group of P consecutive k-steps s0 .. s0+P-1 (s0 a multiple of P), A
+// starting at `ap` for step s0; every step refills its slot with step + P.
+template <typename T, int TM, int TN, int P>
+__device__ __forceinline__ void kgroup(const unsigned char* ap, int astride16, BRing<T, TN, P>& br,
+                                       int s0, f32x4_t (&acc)[TM][TN]) {
+  constexpr int SB = Frag<T>::KS * sizeof(T);
+  kstep<T, TM, TN, P, 0, true>(ap, astride16, br, s0 + P, acc);
+  if constexpr (P > 1) kstep<T, TM, TN, P, 1, true>(ap + SB, astride16, br, s0 + 1 + P, acc);
+  if constexpr (P > 2) kstep<T, TM, TN, P, 2, true>(ap + 2 * SB, astride16, br, s0 + 2 + P, acc);
+  if constexpr (P > 3) kstep<T, TM, TN, P, 3, true>(ap + 3 * SB, astride16, br, s0 + 3 + P, acc);
+}
+
+// All NS k-steps of a product with compile-time K, fully unrolled: slot
+// refills stop at the last step, so no load is wasted.
+template <typename T, int TM, int TN, int P, int NS, int S = 0>
+__device__ __forceinline__ void ksteps_ct(const unsigned char* a0, int astride16,
+                                          BRing<T, TN, P>& br, f32x4_t (&acc)[TM][TN]) {
+  if constexpr (S < NS) {
+    constexpr int SB = Frag<T>::KS * sizeof(T);
+    kstep<T, TM, TN, P, S % P, (S + P < NS)>(a0 + S * SB, astride16, br, S + P, acc);
+    ksteps_ct<T, TM, TN, P, NS, S + 1>(a0, astride16, br, acc);
+  }
+}
+
+template <int TM, int TN>
+__device__ __forceinline__ void zero_acc(f32x4_t (&acc)[TM][TN]) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+}
+
+// Workgroup b of nb -> row tile, so that the tiles of one XCD (dispatch goes
+// round-robin over the eight XCDs) are consecutive: neighbouring tiles share
+// an element and hence the weights their XCD's L2 holds.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Species of the tile starting at row0 (groups start at multiples of kPad).
+__device__ __forceinline__ int tile_species(const GroupTable* gt, int row0) {
+  int s = 0;
+#pragma unroll
+  for (int q = 1; q < kMaxS; ++q) s = (row0 >= gt->pstart[q]) ? q : s;
+  return s;
+}
+
+__device__ __forceinline__ float celu_fwd(float z, float alpha, float inv_alpha_l2e) {
+  return z > 0.f ? z : alpha * (__builtin_amdgcn_exp2f(z * inv_alpha_l2e) - 1.f);
+}
+
+__device__ __forceinline__ float celu_slope(float h, float inv_alpha) {
+  return h > 0.f ? 1.f : 1.f + h * inv_alpha;
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> {
+  __device__ __forceinline__ static float4 get(const float* p) {
+    return *reinterpret_cast<const float4*>(p);
+  }
+};
+template <> struct Vec4<bf16_t> {
+  __device__ __forceinline__ static float4 get(const bf16_t* p) {
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                       __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+  }
+};
+
+}  // namespace nnp

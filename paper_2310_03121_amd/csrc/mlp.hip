@@ -3,7 +3,7 @@
 // ANI potentials give each element its own network and sum the atomic
 // outputs (Methods, "OpenMM-ML").  Atoms are sorted by element into groups
 // that start at multiples of kPad rows, so one GEMM launch serves every
-// element: a tile of BM rows belongs to one group and uses that element's
+// element: a 128-row tile belongs to one group and uses that element's
 // weights.  Layers are C = A * B^T with A the row-major activations and B a
 // row-major [N][K] weight matrix (W for the forward pass, W^T copies for the
 // adjoint).  Epilogues are fused:
@@ -13,16 +13,235 @@
 //   BWD  : delta = acc * CELU'(z) with CELU'(z) = 1 + h/alpha for h <= 0
 //   OUT  : plain output in the operand type (dE/dG)
 // BF16 operands use v_mfma_f32_16x16x32_bf16 and FP32 operands
-// v_mfma_f32_16x16x4f32; both accumulate in FP32.  Each K stage moves 128
-// bytes of every tile row through a double-buffered LDS ring (rows padded to
-// 144 bytes), with one barrier per stage; a K tail is zero-filled.
-#include "kernels.h"
+// v_mfma_f32_16x16x4f32; both accumulate in FP32.
+#include "mfma_tile.h"
 
 namespace nnp {
 
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
+// ------------------------------------------------------------- body layers
+//
+// One workgroup per 128-row tile (8 waves, WM x WN of TM x TN 16x16 tiles)
+// covers all N columns in passes of NP = WN * TN * 16, so the activations
+// are read from HBM once.  A moves through LDS in chunks of 256 bytes per
+// row: up to three chunks (K <= 384 BF16 or 192 FP32) stay resident across
+// the passes; longer K streams through two chunk buffers with two chunks in
+// flight in registers.  Weights stream into registers P k-steps ahead, and
+// across pass boundaries.  Each wave writes its results through a small LDS
+// stage, 16 rows at a time, so that every store instruction writes whole
+// 128-byte (BF16) or 256-byte (FP32) row segments.
+constexpr int kChunkBytes = 256;
+constexpr int kChunkStride = kChunkBytes + 16;  // LDS row stride (bytes)
+constexpr int kMaxResident = 3;
 
+template <typename T, int TN>
+constexpr int stage_stride() { return TN * 16 * (int)sizeof(T) + 16; }
+
+template <typename T, int WM, int WN, int TM, int TN, int EPI, bool RESIDENT>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int BM = WM * TM * 16;
+  static_assert(BM == kPad, "a row tile is one padding unit of a species group");
+  constexpr int NP = WN * TN * 16;
+  constexpr int KC = kChunkBytes / sizeof(T);
+  constexpr int SPC = KC / Frag<T>::KS;  // k-steps per chunk
+  constexpr int P = 4;
+  static_assert(SPC == P, "one ring cycle per chunk");
+  constexpr int VPR = kChunkBytes / 16;
+  constexpr int NVA = BM * VPR / NT;
+  constexpr int SS = stage_stride<T, TN>();
+  constexpr int WCOLB = TN * 16 * sizeof(T);  // bytes of a wave's tile row
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+
+  const GroupTable* gt = a.gt;
+  const int row0 = xcd_tile(blockIdx.x, gridDim.x) * BM;
+  if (row0 >= gt->total_rows) return;
+  const int s = tile_species(gt, row0);
+  const int row_end = gt->pstart[s] + gt->cnt[s];
+  if (row0 >= row_end) return;  // a tile of pad rows only
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv / WN, wn = wv % WN;
+  const int K = a.K;
+  const T* A = reinterpret_cast<const T*>(a.A);
+  const T* B = reinterpret_cast<const T*>(a.B) + (size_t)s * a.sB;
+
+  auto aload = [&](int c, uint4 (&ra)[NVA]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * NT;
+      const int r = idx / VPR, k = c * KC + (idx % VPR) * (16 / (int)sizeof(T));
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (row0 + r < row_end && k < K)
+        val = *reinterpret_cast<const uint4*>(A + (size_t)(row0 + r) * a.lda + k);
+      ra[v] = val;
+    }
+  };
+  auto astore = [&](int buf, const uint4 (&ra)[NVA]) __attribute__((always_inline)) {
+    unsigned char* base = smem + buf * BM * kChunkStride;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int idx = tid + v * NT;
+      *reinterpret_cast<uint4*>(base + (idx / VPR) * kChunkStride + (idx % VPR) * 16) = ra[v];
+    }
+  };
+
+  const int ns = K / Frag<T>::KS;
+  const int nchunks = (ns + SPC - 1) / SPC;  // RESIDENT: nchunks <= kMaxResident
+  const int npass = a.N / NP;
+  const int arow = (wm * TM * 16 + (lane & 15)) * kChunkStride + (lane >> 4) * 16;
+  const int rl = lane & 15, cq = (lane >> 4) * 4;
+  const float* bias = a.bias ? a.bias + (size_t)s * a.sBias : nullptr;
+  const float ia = 1.f / a.alpha;
+  unsigned char* stg = smem + (RESIDENT ? nchunks : 2) * BM * kChunkStride + wv * 16 * SS;
+  const int col_w = wn * TN * 16;  // this wave's first column inside a pass
+
+  f32x4_t acc[TM][TN];
+  zero_acc(acc);
+  BRing<T, TN, P> br;
+  br.init(B, col_w, npass > 1 ? NP + col_w : -1, lane, K);
+  br.prologue();
+
+  // Epilogue of pass p: finish each 16x16 tile in registers (lane holds row
+  // rl, columns cq..cq+3), stage 16 rows of the wave tile in LDS, then write
+  // them as whole row segments.
+  auto epilogue = [&](int p) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int rloc = wm * TM * 16 + i * 16;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int row = row0 + rloc + rl;
+        const bool rv = row < row_end;
+        const int col = p * NP + col_w + j * 16 + cq;
+        float4 v = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        if constexpr (EPI == EPI_CELU) {
+          const float4 b = *reinterpret_cast<const float4*>(bias + col);
+          v = make_float4(celu_fwd(v.x + b.x, a.alpha, a.inv_alpha_l2e),
+                          celu_fwd(v.y + b.y, a.alpha, a.inv_alpha_l2e),
+                          celu_fwd(v.z + b.z, a.alpha, a.inv_alpha_l2e),
+                          celu_fwd(v.w + b.w, a.alpha, a.inv_alpha_l2e));
+        } else if constexpr (EPI == EPI_BWD) {
+          if (rv) {
+            const float4 h = Vec4<T>::get(reinterpret_cast<const T*>(a.H) + (size_t)row * a.ldh + col);
+            v.x *= celu_slope(h.x, ia);
+            v.y *= celu_slope(h.y, ia);
+            v.z *= celu_slope(h.z, ia);
+            v.w *= celu_slope(h.w, ia);
+          }
+        }
+        if (!rv) v = make_float4(0.f, 0.f, 0.f, 0.f);
+        Store<T>::put4(reinterpret_cast<T*>(stg + rl * SS + (j * 16 + cq) * sizeof(T)), v);
+      }
+      wave_lds_sync();
+      // 16 rows x WCOLB bytes, 16 bytes per lane per store
+      constexpr int VR = WCOLB / 16;  // vectors per row
+#pragma unroll
+      for (int q = 0; q < (16 * VR + 63) / 64; ++q) {
+        const int idx = lane + q * 64;
+        if (16 * VR % 64 == 0 || idx < 16 * VR) {
+          const int r = idx / VR, cv = idx % VR;
+          const uint4 val = *reinterpret_cast<const uint4*>(stg + r * SS + cv * 16);
+          unsigned char* dst = reinterpret_cast<unsigned char*>(a.C) +
+                               ((size_t)(row0 + rloc + r) * a.ldc + p * NP + col_w) * sizeof(T) +
+                               cv * 16;
+          *reinterpret_cast<uint4*>(dst) = val;
+        }
+      }
+      wave_lds_sync();
+    }
+  };
+
+  if constexpr (RESIDENT) {
+    uint4 ra[NVA];
+    for (int c = 0; c < nchunks; ++c) {
+      aload(c, ra);
+      astore(c, ra);
+    }
+    __syncthreads();
+    for (int p = 0; p < npass; ++p) {
+      for (int c = 0; c < nchunks; ++c)
+        kgroup<T, TM, TN, P>(smem + c * BM * kChunkStride + arow, 16 * kChunkStride, br, c * SPC,
+                             acc);
+      br.next_pass(B, p + 2 < npass ? (p + 2) * NP + col_w : -1, lane);
+      epilogue(p);
+      zero_acc(acc);
+    }
+  } else {
+    // flat sequence of (pass, chunk) units u = p * nchunks + c; unit u + 1 is
+    // in LDS-bound registers while unit u computes, unit u + 2 in flight
+    const int nu = npass * nchunks;
+    uint4 ra0[NVA], ra1[NVA];
+    aload(0, ra0);
+    astore(0, ra0);
+    aload(1 % nchunks, ra1);
+    __syncthreads();
+    auto unit = [&](int u, uint4 (&r_next2)[NVA], const uint4 (&r_next1)[NVA])
+                    __attribute__((always_inline)) {
+      const int c = u % nchunks;
+      aload((u + 2 < nu ? u + 2 : nu - 1) % nchunks, r_next2);
+      kgroup<T, TM, TN, P>(smem + (u & 1) * BM * kChunkStride + arow, 16 * kChunkStride, br,
+                           c * SPC, acc);
+      astore((u + 1) & 1, r_next1);
+      __syncthreads();
+      if (c == nchunks - 1) {
+        const int p = u / nchunks;
+        br.next_pass(B, p + 2 < npass ? (p + 2) * NP + col_w : -1, lane);
+        epilogue(p);
+        zero_acc(acc);
+      }
+    };
+    for (int u = 0; u < nu; u += 2) {
+      unit(u, ra0, ra1);
+      if (u + 1 < nu) unit(u + 1, ra1, ra0);
+    }
+  }
+}
+
+template <typename T, int WM, int WN, int TM, int TN, int EPI, bool RES>
+static void launch_rb_t(const GemmArgs& a, int nchunks, int rows_cap, hipStream_t st) {
+  const size_t lds = (size_t)(RES ? nchunks : 2) * kPad * kChunkStride +
+                     (size_t)WM * WN * 16 * stage_stride<T, TN>();
+  static const bool attr = (ensure_lds(k_gemm_rb<T, WM, WN, TM, TN, EPI, RES>), true);
+  (void)attr;
+  hipLaunchKernelGGL((k_gemm_rb<T, WM, WN, TM, TN, EPI, RES>), dim3(rows_cap / kPad),
+                     dim3(64 * WM * WN), lds, st, a);
+}
+
+template <typename T, int WM, int WN, int TM, int TN, int EPI>
+static void launch_rb(const GemmArgs& a, int rows_cap, hipStream_t st) {
+  const int nchunks = (int)((a.K * sizeof(T) + kChunkBytes - 1) / kChunkBytes);
+  if (nchunks <= kMaxResident)
+    launch_rb_t<T, WM, WN, TM, TN, EPI, true>(a, nchunks, rows_cap, st);
+  else
+    launch_rb_t<T, WM, WN, TM, TN, EPI, false>(a, nchunks, rows_cap, st);
+}
+
+// Column layout for N: 2 x 4 waves of 64-row x TN*16-column tiles when N is a
+// multiple of 64 (passes of 64*TN, TN the largest of 4, 3, 2, 1 dividing
+// N/64), else 4 x 2 waves of 32-row tiles with TN in 5, 3, 1.
+template <typename T, int EPI>
+static bool launch_body(const GemmArgs& a, int rows_cap, hipStream_t st) {
+  if (a.K % Frag<T>::KS != 0) return false;
+  if (a.N % 64 == 0) {
+    if (a.N % 256 == 0) { launch_rb<T, 2, 4, 4, 4, EPI>(a, rows_cap, st); return true; }
+    if (a.N % 192 == 0) { launch_rb<T, 2, 4, 4, 3, EPI>(a, rows_cap, st); return true; }
+    if (a.N % 128 == 0) { launch_rb<T, 2, 4, 4, 2, EPI>(a, rows_cap, st); return true; }
+    launch_rb<T, 2, 4, 4, 1, EPI>(a, rows_cap, st);
+    return true;
+  }
+  if (a.N % 32 != 0) return false;
+  if (a.N % 160 == 0) { launch_rb<T, 4, 2, 2, 5, EPI>(a, rows_cap, st); return true; }
+  if (a.N % 96 == 0) { launch_rb<T, 4, 2, 2, 3, EPI>(a, rows_cap, st); return true; }
+  launch_rb<T, 4, 2, 2, 1, EPI>(a, rows_cap, st);
+  return true;
+}
+
+// ------------------------------------------------------- LDS-staged products
+//
+// The energy head (every column of a row in one workgroup: the energy is a
+// dot product over them) and the FP32 layers, whose MFMA rate rather than
+// latency bounds them: both operands are staged through a double-buffered
+// LDS ring (128 bytes of K per row and stage, rows padded to 144 bytes), one
+// barrier per stage, zero-filled K tail.  B is row-major [N][K] (ldb).
 template <typename T> struct Mfma;
 template <> struct Mfma<bf16_t> {
   static constexpr int BK = 64;    // K elements per LDS stage (128 bytes per row)
@@ -30,7 +249,7 @@ template <> struct Mfma<bf16_t> {
   static constexpr int KSUB = 2;   // fragment reads per stage
   // lane's element offset inside a stage for fragment read kk
   __device__ __forceinline__ static int koff(int lane, int kk) { return kk * 32 + (lane >> 4) * 8; }
-  __device__ __forceinline__ static void mma(const uint4& a, const uint4& b, floatx4_t& acc) {
+  __device__ __forceinline__ static void mma(const uint4& a, const uint4& b, f32x4_t& acc) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
                                                   __builtin_bit_cast(bf16x8_t, b), acc, 0, 0, 0);
   }
@@ -42,7 +261,7 @@ template <> struct Mfma<float> {
   // float4 read kk covers k = kk*16 + (lane>>4)*4 + {0..3}; component c feeds
   // MFMA c, whose four k slots (lane groups) are {c, 4+c, 8+c, 12+c} + kk*16
   __device__ __forceinline__ static int koff(int lane, int kk) { return kk * 16 + (lane >> 4) * 4; }
-  __device__ __forceinline__ static void mma(const uint4& a, const uint4& b, floatx4_t& acc) {
+  __device__ __forceinline__ static void mma(const uint4& a, const uint4& b, f32x4_t& acc) {
     const float4 va = __builtin_bit_cast(float4, a);
     const float4 vb = __builtin_bit_cast(float4, b);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb.x, acc, 0, 0, 0);
@@ -52,10 +271,6 @@ template <> struct Mfma<float> {
   }
 };
 
-__device__ __forceinline__ float celu_f(float v, float alpha, float inv_alpha_l2e) {
-  return v > 0.f ? v : alpha * (__builtin_amdgcn_exp2f(v * inv_alpha_l2e) - 1.f);
-}
-
 template <typename T, int BM, int BN>
 constexpr size_t gemm_lds_bytes() {
   return (size_t)2 * (BM + BN) * Mfma<T>::RS * sizeof(T);
@@ -63,7 +278,7 @@ constexpr size_t gemm_lds_bytes() {
 
 // 256 threads = WM x WN waves; wave tile (BM/WM) x (BN/WN) of 16x16 MFMA tiles.
 template <typename T, int BM, int BN, int WM, int WN, int EPI>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+__global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
   static_assert(WM * WN == 4, "four waves");
   constexpr int BK = Mfma<T>::BK, RS = Mfma<T>::RS;
   constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -133,11 +348,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     }
   };
 
-  floatx4_t acc[TM][TN];
+  f32x4_t acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
   gload(0);
   lstore(0);
@@ -185,7 +400,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
           float v = acc[i][j][e];
           if constexpr (EPI == EPI_CELU) {
             const int col = n0 + cloc;
-            v = celu_f(v + (col < a.N ? bias[col] : 0.f), a.alpha, a.inv_alpha_l2e);
+            v = celu_fwd(v + (col < a.N ? bias[col] : 0.f), a.alpha, a.inv_alpha_l2e);
           }
           ct[rloc * CS + cloc] = v;
         }
@@ -281,15 +496,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 template <typename T, int BM, int BN, int WM, int WN, int EPI>
 static void launch_tile(const GemmArgs& a, int rows_cap, hipStream_t st) {
   constexpr size_t lds = gemm_lds_bytes<T, BM, BN>();
-  static const bool attr = (ensure_lds(k_gemm<T, BM, BN, WM, WN, EPI>), true);
+  static const bool attr = (ensure_lds(k_gemm_lds<T, BM, BN, WM, WN, EPI>), true);
   (void)attr;
   dim3 grid((rows_cap + BM - 1) / BM, (a.N + BN - 1) / BN);
-  hipLaunchKernelGGL((k_gemm<T, BM, BN, WM, WN, EPI>), grid, dim3(256), lds, st, a);
+  hipLaunchKernelGGL((k_gemm_lds<T, BM, BN, WM, WN, EPI>), grid, dim3(256), lds, st, a);
 }
 
 // Column tile for the non-head layers: the largest of 128, 96, 80, 64, 32
 // dividing N (all widths are multiples of 32).
-int gemm_pick_bn(int N, int epi) {
+static int gemm_pick_bn(int N, int epi) {
   if (epi == EPI_HEAD) return N;
   for (int bn : {128, 96, 80, 64, 32})
     if (N % bn == 0) return bn;
@@ -297,7 +512,7 @@ int gemm_pick_bn(int N, int epi) {
 }
 
 template <typename T, int EPI>
-static bool launch_body(const GemmArgs& a, int rows_cap, hipStream_t st) {
+static bool launch_lds_body(const GemmArgs& a, int rows_cap, hipStream_t st) {
   switch (gemm_pick_bn(a.N, EPI)) {
     case 128: launch_tile<T, 128, 128, 2, 2, EPI>(a, rows_cap, st); return true;
     case 96: launch_tile<T, 128, 96, 2, 2, EPI>(a, rows_cap, st); return true;
@@ -325,18 +540,30 @@ static bool launch_head(const GemmArgs& a, int rows_cap, hipStream_t st) {
   }
 }
 
+// BF16 body layers use the register-streamed kernel (B in fragment order);
+// FP32 body layers and the head use the LDS-staged kernel (B row-major).
 template <typename T>
-bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st) {
+bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st);
+template <>
+bool launch_gemm<bf16_t>(int epi, const GemmArgs& a, int rows_cap, hipStream_t st) {
   switch (epi) {
-    case EPI_CELU: return launch_body<T, EPI_CELU>(a, rows_cap, st);
-    case EPI_HEAD: return launch_head<T>(a, rows_cap, st);
-    case EPI_BWD: return launch_body<T, EPI_BWD>(a, rows_cap, st);
-    case EPI_OUT: return launch_body<T, EPI_OUT>(a, rows_cap, st);
+    case EPI_CELU: return launch_body<bf16_t, EPI_CELU>(a, rows_cap, st);
+    case EPI_HEAD: return launch_head<bf16_t>(a, rows_cap, st);
+    case EPI_BWD: return launch_body<bf16_t, EPI_BWD>(a, rows_cap, st);
+    case EPI_OUT: return launch_body<bf16_t, EPI_OUT>(a, rows_cap, st);
   }
   return false;
 }
-template bool launch_gemm<float>(int, const GemmArgs&, int, hipStream_t);
-template bool launch_gemm<bf16_t>(int, const GemmArgs&, int, hipStream_t);
+template <>
+bool launch_gemm<float>(int epi, const GemmArgs& a, int rows_cap, hipStream_t st) {
+  switch (epi) {
+    case EPI_CELU: return launch_lds_body<float, EPI_CELU>(a, rows_cap, st);
+    case EPI_HEAD: return launch_head<float>(a, rows_cap, st);
+    case EPI_BWD: return launch_lds_body<float, EPI_BWD>(a, rows_cap, st);
+    case EPI_OUT: return launch_lds_body<float, EPI_OUT>(a, rows_cap, st);
+  }
+  return false;
+}
 
 // ------------------------------------------------------------ weight gradients
 //
@@ -441,9 +668,24 @@ template void launch_wgrad<float, bf16_t>(const GroupTable*, int, int, const flo
 // ------------------------------------------------------------ weight packing
 //
 // From the flat parameter vector (per species, per layer: W row-major
-// out x in, then b) to: W_l [S][out][in_pad] (float and bf16), W_l^T
-// [S][in_pad][out] (float and bf16), biases [S][out], output weights [S][w3]
-// and output biases [S].  One thread per (species, layer, out, in_pad).
+// out x in, then b) to: W_l [S][out][in_pad] row-major (float and bf16) and
+// W_l^T [S][in_pad][out] row-major (float), the LDS-staged kernels' operands;
+// W_l and W_l^T in MFMA fragment order (bf16), the register-streamed
+// kernels' operands; biases [S][out], output weights [S][w3] and output
+// biases [S].  One thread per (species, layer, out, in_pad).
+//
+// Fragment order of a [N][K] operand: 16-row tiles, then k-steps of KS, then
+// the 64 lanes of the wave, then the EL elements of a lane; lane l of k-step
+// ks in tile nt holds row nt*16 + l % 16, columns ks*KS + (l / 16)*EL + e.
+// A wave's fragment is then one contiguous 1 KB block.
+template <typename T>
+__device__ __forceinline__ size_t frag_off(int n, int k, int K) {
+  constexpr int KS = Frag<T>::KS, EL = Frag<T>::EL;
+  const int kk = k % KS;
+  const int lane = (kk / EL) * 16 + n % 16;
+  return (((size_t)(n / 16) * (K / KS) + k / KS) * 64 + lane) * EL + kk % EL;
+}
+
 __global__ __launch_bounds__(256) void k_pack(PackArgs p) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int l = blockIdx.y, s = blockIdx.z;
@@ -458,7 +700,8 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs p) {
     p.Wf[l][ws + (size_t)o * inp + i] = v;
     p.Wb[l][ws + (size_t)o * inp + i] = f2bf(v);
     p.WTf[l][ws + (size_t)i * out + o] = v;
-    p.WTb[l][ws + (size_t)i * out + o] = f2bf(v);
+    p.Wqb[l][ws + frag_off<bf16_t>(o, i, inp)] = f2bf(v);
+    p.WTqb[l][ws + frag_off<bf16_t>(i, o, out)] = f2bf(v);
     if (i == 0) p.bias[l][(size_t)s * out + o] = src[(size_t)out * in + o];
   } else {
     if (t >= in) return;

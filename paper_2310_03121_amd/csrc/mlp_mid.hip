@@ -1,208 +1,170 @@
 // Fused middle of the per-element networks (BF16 operands, FP32 accumulate):
 // layer 2, the energy head, and the adjoint of layers 3 and 2, for one tile of
-// 64 species-sorted rows per workgroup.
+// 128 species-sorted rows per workgroup.
 //
 //   H2 = CELU(H1 W1^T + b1)                       (kept in LDS)
 //   z3 = H2 W2^T + b2;  E_i = w_out . CELU(z3) + b_out
-//   D3 = up_i * w_out * CELU'(z3)                 (kept in LDS)
+//   D3 = up_i * w_out * CELU'(z3)                 (kept in LDS, over H1)
 //   D2 = (D3 W2) * CELU'(z2)                      (written over H2 in LDS)
 //   D1 = (D2 W1) * CELU'(z1)                      (to global)
 //
 // CELU'(z) is recovered from the stored activation: 1 for h > 0, else
-// 1 + h/alpha.  The four products are MFMA GEMMs with the A operand resident
-// in LDS and the weight operand streamed through a double-buffered LDS stage
-// of 64 K-columns.  This removes three launches and the HBM round trips of
-// H2, D3 and D2 that separate layer kernels would need.  Optional pointers
-// also store H2, H3, D3 and D2 for the parameter gradients.
-#include "kernels.h"
+// 1 + h/alpha (for D1 from H1 in global memory, which the tile loaded at the
+// start and which is still L2 resident).  The four products are MFMA GEMMs
+// with the A operand resident in LDS and the weights streamed into registers
+// (mfma_tile.h); 8 waves per workgroup.  This removes three launches and the
+// HBM round trips of H2, D3 and D2 that separate layer kernels would need.
+// Optional pointers also store H2, H3, D3 and D2 for the parameter gradients.
+#include "mfma_tile.h"
 
 namespace nnp {
 
-typedef __bf16 bf16x8_mid __attribute__((ext_vector_type(8)));
-typedef float floatx4_mid __attribute__((ext_vector_type(4)));
+constexpr int kMidBM = 128;
 
-constexpr int kMidBM = 64;
-constexpr int kMidBK = 64;
-constexpr int kMidBS = kMidBK + 8;  // LDS stride of a staged weight row (elements)
+// Wave layout of a product with N columns in one pass: 2 x 4 waves of
+// 64 x (N/4) when N is a multiple of 64, else 4 x 2 waves of 32 x (N/2).
+template <int N>
+struct MidCfg {
+  static constexpr bool wide = N % 64 == 0;
+  static constexpr int WM = wide ? 2 : 4;
+  static constexpr int WN = wide ? 4 : 2;
+  static constexpr int TM = wide ? 4 : 2;
+  static constexpr int TN = wide ? N / 64 : N / 32;
+  static constexpr int P = 4;  // weight ring depth (k-steps)
+  static_assert(WM * TM * 16 == kMidBM && WN * TN * 16 == N, "one pass covers N");
+};
 
-__device__ __forceinline__ int rup64(int x) { return (x + 63) / 64 * 64; }
-
-// C[64 x N] = A[64 x K] (LDS, stride sa) * B[N x K]^T (global, stride ldb).
-// Waves 2 x 2: wave (wm, wn) owns rows wm*32 .. +31 and columns wn*16*TN .. .
-template <int TN>
-__device__ __forceinline__ void mid_gemm(const bf16_t* As, int sa, const bf16_t* __restrict__ Bg,
-                                         int ldb, int N, int K, bf16_t* Bs,
-                                         floatx4_mid (&acc)[2][TN], int tid, int lane, int wm,
-                                         int wn) {
-  constexpr int NVB = (2 * 16 * TN * 8 + 255) / 256;  // 16-byte vectors per thread per stage
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4_mid{0.f, 0.f, 0.f, 0.f};
-  const int nk = (K + kMidBK - 1) / kMidBK;
-  uint4 rb[NVB];
-  auto gload = [&](int kt) {
-#pragma unroll
-    for (int v = 0; v < NVB; ++v) {
-      const int idx = tid + v * 256;
-      const int r = idx >> 3, sg = idx & 7;
-      const int k = kt * kMidBK + sg * 8;
-      uint4 val = make_uint4(0, 0, 0, 0);
-      if (r < N && k < K) val = *reinterpret_cast<const uint4*>(Bg + (size_t)r * ldb + k);
-      rb[v] = val;
-    }
-  };
-  auto lstore = [&](int buf) {
-    bf16_t* bs = Bs + buf * 256 * kMidBS;
-#pragma unroll
-    for (int v = 0; v < NVB; ++v) {
-      const int idx = tid + v * 256;
-      const int r = idx >> 3, sg = idx & 7;
-      if (r < N) *reinterpret_cast<uint4*>(bs + r * kMidBS + sg * 8) = rb[v];
-    }
-  };
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  const int rl = lane & 15, kq = (lane >> 4) * 8;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
-    const bf16_t* bs = Bs + buf * 256 * kMidBS + (wn * 16 * TN + rl) * kMidBS + kq;
-    const bf16_t* as = As + (wm * 32 + rl) * sa + kt * kMidBK + kq;
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      uint4 fa[2], fb[TN];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        fa[i] = *reinterpret_cast<const uint4*>(as + i * 16 * sa + kk * 32);
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        fb[j] = *reinterpret_cast<const uint4*>(bs + j * 16 * kMidBS + kk * 32);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf16x8_mid, fa[i]), __builtin_bit_cast(bf16x8_mid, fb[j]),
-              acc[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
-  }
+// acc = A (LDS, row stride sa bytes, K columns) * B^T (global [N][K]).
+template <int N, int K>
+__device__ __forceinline__ void mid_product(const unsigned char* As, int sa, const bf16_t* B,
+                                            int lane, int wv,
+                                            f32x4_t (&acc)[MidCfg<N>::TM][MidCfg<N>::TN]) {
+  using C = MidCfg<N>;
+  static_assert(K % Frag<bf16_t>::KS == 0, "whole k-steps");
+  const int wm = wv / C::WN, wn = wv % C::WN;
+  zero_acc(acc);
+  BRing<bf16_t, C::TN, C::P> br;
+  br.init(B, wn * C::TN * 16, -1, lane, K);
+  br.prologue();
+  const unsigned char* a0 = As + (wm * C::TM * 16 + (lane & 15)) * sa + (lane >> 4) * 16;
+  ksteps_ct<bf16_t, C::TM, C::TN, C::P, K / Frag<bf16_t>::KS>(a0, 16 * sa, br, acc);
 }
 
-__device__ __forceinline__ float celu_mid(float z, float alpha, float inv_alpha_l2e) {
-  return z > 0.f ? z : alpha * (__builtin_amdgcn_exp2f(z * inv_alpha_l2e) - 1.f);
+__device__ __forceinline__ void lds_put4(unsigned char* p, float4 v) {
+  *reinterpret_cast<uint2*>(p) = make_uint2(f2bf2(v.x, v.y), f2bf2(v.z, v.w));
 }
 
-__device__ __forceinline__ float dcelu_from_h(float h, float inv_alpha) {
-  return h > 0.f ? 1.f : 1.f + h * inv_alpha;
+__device__ __forceinline__ float4 lds_get4(const unsigned char* p) {
+  const uint2 u = *reinterpret_cast<const uint2*>(p);
+  return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                     __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
 }
 
 template <int W1, int W2, int W3>
-__global__ __launch_bounds__(256) void k_mlp_mid(MidArgs a) {
-  constexpr int TA = W2 / 32, TB = W3 / 32, TC = W2 / 32, TD = W1 / 32;
-  constexpr int S1 = (W1 + 63) / 64 * 64 + 8;  // LDS strides (elements)
-  constexpr int S2 = (W2 + 63) / 64 * 64 + 8;
-  constexpr int S3 = (W3 + 63) / 64 * 64 + 8;
+__global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
+  static_assert(W3 <= W1, "D3 is stored over H1");
+  constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;  // LDS row strides (bytes)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  bf16_t* L1 = reinterpret_cast<bf16_t*>(smem);  // H1 tile
-  bf16_t* L2 = L1 + kMidBM * S1;                  // H2, then D2
-  bf16_t* L3 = L2 + kMidBM * S2;                  // D3
-  bf16_t* Bs = L3 + kMidBM * S3;                  // weight stages
-  float* epart = reinterpret_cast<float*>(Bs + 2 * 256 * kMidBS);  // [2][64]
+  unsigned char* X1 = smem;                          // H1, then D3
+  unsigned char* X2 = X1 + kMidBM * S1;              // H2, then D2
+  float* epart = reinterpret_cast<float*>(X2 + kMidBM * S2);  // [WN][128]
 
   const GroupTable* gt = a.gt;
-  const int row0 = blockIdx.x * kMidBM;
+  const int row0 = xcd_tile(blockIdx.x, gridDim.x) * kMidBM;
   if (row0 >= gt->total_rows) return;
-  int s = 0;
-#pragma unroll
-  for (int q = 1; q < kMaxS; ++q) s = (row0 >= gt->pstart[q]) ? q : s;
+  const int s = tile_species(gt, row0);
   const int row_end = gt->pstart[s] + gt->cnt[s];
   if (row0 >= row_end) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  const int rl = lane & 15, rq = (lane >> 4) * 4;
+  const int rl = lane & 15, cq = (lane >> 4) * 4;
   const float alpha = a.alpha, ia = 1.f / a.alpha, ial2e = a.inv_alpha_l2e;
 
-  // H1 tile -> LDS (zero rows past the group, zero K padding)
-  for (int idx = tid; idx < kMidBM * (S1 - 8) / 8; idx += 256) {
-    const int r = idx / ((S1 - 8) / 8), c = (idx % ((S1 - 8) / 8)) * 8;
+  // H1 tile -> LDS (zero rows past the group)
+  constexpr int V1 = W1 / 8;  // 16-byte vectors per row
+  for (int idx = tid; idx < kMidBM * V1; idx += 512) {
+    const int r = idx / V1, c = idx % V1;
     uint4 v = make_uint4(0, 0, 0, 0);
-    if (row0 + r < row_end && c < W1)
-      v = *reinterpret_cast<const uint4*>(a.H1 + (size_t)(row0 + r) * W1 + c);
-    *reinterpret_cast<uint4*>(L1 + r * S1 + c) = v;
+    if (row0 + r < row_end)
+      v = *reinterpret_cast<const uint4*>(a.H1 + (size_t)(row0 + r) * W1 + c * 8);
+    *reinterpret_cast<uint4*>(X1 + r * S1 + c * 16) = v;
   }
-  // zero the K padding of the H2/D2 and D3 regions (read as A operands)
-  constexpr int P2 = (S2 - 8) - W2, P3 = (S3 - 8) - W3;
-  if constexpr (P3 > 0)
-    for (int idx = tid; idx < kMidBM * P3; idx += 256) L3[(idx / P3) * S3 + W3 + idx % P3] = 0;
-  if constexpr (P2 > 0)
-    for (int idx = tid; idx < kMidBM * P2; idx += 256) L2[(idx / P2) * S2 + W2 + idx % P2] = 0;
   __syncthreads();
 
   // ---- H2 = CELU(H1 W1^T + b1)
   {
-    floatx4_mid acc[2][TA];
-    mid_gemm<TA>(L1, S1, a.W1 + (size_t)s * W2 * W1, W1, W2, W1, Bs, acc, tid, lane, wm, wn);
+    using C = MidCfg<W2>;
+    f32x4_t acc[C::TM][C::TN];
+    mid_product<W2, W1>(X1, S1, a.W1 + (size_t)s * W2 * W1, lane, wv, acc);
+    const int wm = wv / C::WN, wn = wv % C::WN;
     const float* b1 = a.b1 + (size_t)s * W2;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < C::TM; ++i) {
+      const int r = wm * C::TM * 16 + i * 16 + rl;
+      const bool rv = row0 + r < row_end;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wm * 32 + i * 16 + rq + e;
-        const bool rv = row0 + r < row_end;
-#pragma unroll
-        for (int j = 0; j < TA; ++j) {
-          const int c = wn * 16 * TA + j * 16 + rl;
-          const float h = rv ? celu_mid(acc[i][j][e] + b1[c], alpha, ial2e) : 0.f;
-          L2[r * S2 + c] = f2bf(h);
-          if (a.H2) a.H2[(size_t)(row0 + r) * W2 + c] = f2bf(h);
-        }
+      for (int j = 0; j < C::TN; ++j) {
+        const int c = wn * C::TN * 16 + j * 16 + cq;
+        const float4 b = *reinterpret_cast<const float4*>(b1 + c);
+        float4 h = make_float4(celu_fwd(acc[i][j][0] + b.x, alpha, ial2e),
+                               celu_fwd(acc[i][j][1] + b.y, alpha, ial2e),
+                               celu_fwd(acc[i][j][2] + b.z, alpha, ial2e),
+                               celu_fwd(acc[i][j][3] + b.w, alpha, ial2e));
+        if (!rv) h = make_float4(0.f, 0.f, 0.f, 0.f);
+        lds_put4(X2 + r * S2 + c * 2, h);
+        if (a.H2) Store<bf16_t>::put4(a.H2 + (size_t)(row0 + r) * W2 + c, h);
       }
+    }
   }
   __syncthreads();
 
-  // ---- z3 = H2 W2^T + b2: energies and D3
+  // ---- z3 = H2 W2^T + b2: energies and D3 (over H1)
   {
-    floatx4_mid acc[2][TB];
-    mid_gemm<TB>(L2, S2, a.W2 + (size_t)s * W3 * W2, W2, W3, W2, Bs, acc, tid, lane, wm, wn);
+    using C = MidCfg<W3>;
+    f32x4_t acc[C::TM][C::TN];
+    mid_product<W3, W2>(X2, S2, a.W2 + (size_t)s * W3 * W2, lane, wv, acc);
+    const int wm = wv / C::WN, wn = wv % C::WN;
     const float* b2 = a.b2 + (size_t)s * W3;
     const float* wo = a.wout + (size_t)s * W3;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < C::TM; ++i) {
+      const int r = wm * C::TM * 16 + i * 16 + rl;
+      const int row = row0 + r;
+      const bool rv = row < row_end;
+      float up = 0.f;
+      if (rv) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
+      float ep = 0.f;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wm * 32 + i * 16 + rq + e;
-        const int row = row0 + r;
-        const bool rv = row < row_end;
-        float up = 0.f;
-        if (rv) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
-        float ep = 0.f;
+      for (int j = 0; j < C::TN; ++j) {
+        const int c = wn * C::TN * 16 + j * 16 + cq;
+        const float4 b = *reinterpret_cast<const float4*>(b2 + c);
+        const float4 w = *reinterpret_cast<const float4*>(wo + c);
+        float h[4], d[4];
+        const float bb[4] = {b.x, b.y, b.z, b.w}, ww[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int j = 0; j < TB; ++j) {
-          const int c = wn * 16 * TB + j * 16 + rl;
-          const float z = acc[i][j][e] + b2[c];
+        for (int e = 0; e < 4; ++e) {
+          const float z = acc[i][j][e] + bb[e];
           const float ex = __builtin_amdgcn_exp2f(fminf(z, 0.f) * ial2e);
-          const float h = z > 0.f ? z : alpha * (ex - 1.f);
-          const float d = rv ? up * wo[c] * (z > 0.f ? 1.f : ex) : 0.f;
-          ep += rv ? wo[c] * h : 0.f;
-          L3[r * S3 + c] = f2bf(d);
-          if (a.H3) a.H3[(size_t)row * W3 + c] = f2bf(rv ? h : 0.f);
-          if (a.D3) a.D3[(size_t)row * W3 + c] = f2bf(d);
+          h[e] = rv ? (z > 0.f ? z : alpha * (ex - 1.f)) : 0.f;
+          d[e] = rv ? up * ww[e] * (z > 0.f ? 1.f : ex) : 0.f;
+          ep += ww[e] * h[e];
         }
-        ep += __shfl_xor(ep, 1, 64);
-        ep += __shfl_xor(ep, 2, 64);
-        ep += __shfl_xor(ep, 4, 64);
-        ep += __shfl_xor(ep, 8, 64);
-        if (rl == 0) epart[wn * kMidBM + r] = ep;
+        const float4 d4 = make_float4(d[0], d[1], d[2], d[3]);
+        lds_put4(X1 + r * S1 + c * 2, d4);
+        if (a.H3) Store<bf16_t>::put4(a.H3 + (size_t)row * W3 + c, make_float4(h[0], h[1], h[2], h[3]));
+        if (a.D3) Store<bf16_t>::put4(a.D3 + (size_t)row * W3 + c, d4);
       }
+      ep += __shfl_xor(ep, 16, 64);
+      ep += __shfl_xor(ep, 32, 64);
+      if (lane < 16) epart[wn * kMidBM + r] = ep;
+    }
   }
   __syncthreads();
   if (tid < kMidBM) {
     const int row = row0 + tid;
-    if (row < row_end) a.erow[row] = epart[tid] + epart[kMidBM + tid] + a.bout[s];
+    float e = a.bout[s];
+#pragma unroll
+    for (int q = 0; q < MidCfg<W3>::WN; ++q) e += epart[q * kMidBM + tid];
+    if (row < row_end) a.erow[row] = e;
     if (a.uprow) {
       float up = 0.f;
       if (row < row_end) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
@@ -212,52 +174,57 @@ __global__ __launch_bounds__(256) void k_mlp_mid(MidArgs a) {
 
   // ---- D2 = (D3 W2) * CELU'(z2), written over H2
   {
-    floatx4_mid acc[2][TC];
-    mid_gemm<TC>(L3, S3, a.W2T + (size_t)s * W2 * W3, W3, W2, W3, Bs, acc, tid, lane, wm, wn);
+    using C = MidCfg<W2>;
+    f32x4_t acc[C::TM][C::TN];
+    mid_product<W2, W3>(X1, S1, a.W2T + (size_t)s * W2 * W3, lane, wv, acc);
+    const int wm = wv / C::WN, wn = wv % C::WN;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < C::TM; ++i) {
+      const int r = wm * C::TM * 16 + i * 16 + rl;
+      const bool rv = row0 + r < row_end;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wm * 32 + i * 16 + rq + e;
-        const bool rv = row0 + r < row_end;
-#pragma unroll
-        for (int j = 0; j < TC; ++j) {
-          const int c = wn * 16 * TC + j * 16 + rl;
-          const float h = bf2f(L2[r * S2 + c]);
-          const float d = rv ? acc[i][j][e] * dcelu_from_h(h, ia) : 0.f;
-          L2[r * S2 + c] = f2bf(d);
-          if (a.D2) a.D2[(size_t)(row0 + r) * W2 + c] = f2bf(d);
-        }
+      for (int j = 0; j < C::TN; ++j) {
+        const int c = wn * C::TN * 16 + j * 16 + cq;
+        const float4 h = lds_get4(X2 + r * S2 + c * 2);
+        float4 d = make_float4(acc[i][j][0] * celu_slope(h.x, ia), acc[i][j][1] * celu_slope(h.y, ia),
+                               acc[i][j][2] * celu_slope(h.z, ia), acc[i][j][3] * celu_slope(h.w, ia));
+        if (!rv) d = make_float4(0.f, 0.f, 0.f, 0.f);
+        lds_put4(X2 + r * S2 + c * 2, d);
+        if (a.D2) Store<bf16_t>::put4(a.D2 + (size_t)(row0 + r) * W2 + c, d);
       }
+    }
   }
   __syncthreads();
 
   // ---- D1 = (D2 W1) * CELU'(z1) -> global
   {
-    floatx4_mid acc[2][TD];
-    mid_gemm<TD>(L2, S2, a.W1T + (size_t)s * W1 * W2, W2, W1, W2, Bs, acc, tid, lane, wm, wn);
+    using C = MidCfg<W1>;
+    f32x4_t acc[C::TM][C::TN];
+    mid_product<W1, W2>(X2, S2, a.W1T + (size_t)s * W1 * W2, lane, wv, acc);
+    const int wm = wv / C::WN, wn = wv % C::WN;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < C::TM; ++i) {
+      const int r = wm * C::TM * 16 + i * 16 + rl;
+      const int row = row0 + r;
+      const bool rv = row < row_end;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = wm * 32 + i * 16 + rq + e;
-        const bool rv = row0 + r < row_end;
-#pragma unroll
-        for (int j = 0; j < TD; ++j) {
-          const int c = wn * 16 * TD + j * 16 + rl;
-          const float h = bf2f(L1[r * S1 + c]);
-          const float d = rv ? acc[i][j][e] * dcelu_from_h(h, ia) : 0.f;
-          a.D1[(size_t)(row0 + r) * W1 + c] = f2bf(d);
+      for (int j = 0; j < C::TN; ++j) {
+        const int c = wn * C::TN * 16 + j * 16 + cq;
+        float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (rv) {
+          const float4 h = Vec4<bf16_t>::get(a.H1 + (size_t)row * W1 + c);
+          d = make_float4(acc[i][j][0] * celu_slope(h.x, ia), acc[i][j][1] * celu_slope(h.y, ia),
+                          acc[i][j][2] * celu_slope(h.z, ia), acc[i][j][3] * celu_slope(h.w, ia));
         }
+        Store<bf16_t>::put4(a.D1 + (size_t)row * W1 + c, d);
       }
+    }
   }
 }
 
 template <int W1, int W2, int W3>
 static size_t mid_lds() {
-  constexpr int S1 = (W1 + 63) / 64 * 64 + 8, S2 = (W2 + 63) / 64 * 64 + 8,
-                S3 = (W3 + 63) / 64 * 64 + 8;
-  return (size_t)2 * (kMidBM * (S1 + S2 + S3) + 2 * 256 * kMidBS) + 2 * kMidBM * 4;
+  return (size_t)kMidBM * ((W1 * 2 + 16) + (W2 * 2 + 16)) + 4 * kMidBM * sizeof(float);
 }
 
 template <int W1, int W2, int W3>
@@ -265,8 +232,7 @@ static void launch_mid_t(const MidArgs& a, int rows_cap, hipStream_t st) {
   const size_t lds = mid_lds<W1, W2, W3>();
   static const bool attr = (ensure_lds(k_mlp_mid<W1, W2, W3>), true);
   (void)attr;
-  hipLaunchKernelGGL((k_mlp_mid<W1, W2, W3>), dim3((rows_cap + kMidBM - 1) / kMidBM), dim3(256),
-                     lds, st, a);
+  hipLaunchKernelGGL((k_mlp_mid<W1, W2, W3>), dim3(rows_cap / kMidBM), dim3(512), lds, st, a);
 }
 
 // Widths with a fused kernel: 1008-256-192-160 (seven elements) and
