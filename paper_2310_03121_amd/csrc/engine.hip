@@ -264,11 +264,17 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   T* D1 = at<T>(ws, P.D1);
   T* G = at<T>(ws, P.G);
   float* erow = at<float>(ws, P.erow);
-  const T* W[kLayers];
-  const T* WT[kLayers];
+  // B operands: row-major W (both precisions) and W^T (FP32), and the BF16
+  // fragment-order copies of W and W^T
+  const void* W[kLayers];
+  const void* WT[kLayers];
+  const void* Wq[kLayers];
+  const void* WTq[kLayers];
   for (int l = 0; l < kLayers; ++l) {
-    W[l] = bf ? (const T*)h->Wqb[l] : (const T*)h->Wf[l];
-    WT[l] = bf ? (const T*)h->WTqb[l] : (const T*)h->WTf[l];
+    W[l] = bf ? (const void*)h->Wb[l] : (const void*)h->Wf[l];
+    WT[l] = bf ? nullptr : (const void*)h->WTf[l];
+    Wq[l] = bf ? (const void*)h->Wqb[l] : nullptr;
+    WTq[l] = bf ? (const void*)h->WTqb[l] : nullptr;
   }
   GemmArgs g{};
   g.gt = gt;
@@ -276,7 +282,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   g.inv_alpha_l2e = (float)(1.4426950408889634 / h->alpha);
   bool ok = true;
   // layer 1: H1 = CELU(X W0^T + b0)
-  g.A = X; g.lda = Fp; g.B = W[0]; g.sB = (long)w1 * Fp; g.ldb = Fp;
+  g.A = X; g.lda = Fp; g.B = W[0]; g.Bq = Wq[0]; g.sB = (long)w1 * Fp; g.ldb = Fp;
   g.bias = h->bias[0]; g.sBias = w1; g.N = w1; g.K = Fp; g.C = H1; g.ldc = w1;
   {
     StageTimer t(h, ST_L1, st);
@@ -321,15 +327,14 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
   } else {
     // layer 2: H2 = CELU(H1 W1^T + b1)
-    g.A = H1; g.lda = w1; g.B = W[1]; g.sB = (long)w2 * w1; g.ldb = w1;
+    g.A = H1; g.lda = w1; g.B = W[1]; g.Bq = Wq[1]; g.sB = (long)w2 * w1; g.ldb = w1;
     g.bias = h->bias[1]; g.sBias = w2; g.N = w2; g.K = w1; g.C = H2; g.ldc = w2;
     {
       StageTimer t(h, ST_L2, st);
       ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
     }
     // layer 3 + output: E_i, delta3
-    g.A = H2; g.lda = w2; g.sB = (long)w3 * w2; g.ldb = w2;
-    g.B = bf ? (const void*)h->Wb[2] : (const void*)h->Wf[2];  // row-major for the head
+    g.A = H2; g.lda = w2; g.B = W[2]; g.Bq = nullptr; g.sB = (long)w3 * w2; g.ldb = w2;
     g.bias = h->bias[2]; g.sBias = w3; g.N = w3; g.K = w2;
     g.C = need_bwd ? (void*)D3 : nullptr; g.ldc = w3;
     g.w_out = h->wout; g.sWout = w3; g.b_out = h->bout; g.erow = erow;
@@ -348,14 +353,14 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
     if (need_bwd) {
       // delta2 = (delta3 W2) * CELU'(z2)
-      g.A = D3; g.lda = w3; g.B = WT[2]; g.sB = (long)w2 * w3; g.ldb = w3;
+      g.A = D3; g.lda = w3; g.B = WT[2]; g.Bq = WTq[2]; g.sB = (long)w2 * w3; g.ldb = w3;
       g.bias = nullptr; g.N = w2; g.K = w3; g.C = D2; g.ldc = w2; g.H = H2; g.ldh = w2;
       {
         StageTimer t(h, ST_BWD3, st);
         ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
       }
       // delta1 = (delta2 W1) * CELU'(z1)
-      g.A = D2; g.lda = w2; g.B = WT[1]; g.sB = (long)w1 * w2; g.ldb = w2;
+      g.A = D2; g.lda = w2; g.B = WT[1]; g.Bq = WTq[1]; g.sB = (long)w1 * w2; g.ldb = w2;
       g.N = w1; g.K = w2; g.C = D1; g.ldc = w1; g.H = H1; g.ldh = w1;
       {
         StageTimer t(h, ST_BWD2, st);
@@ -365,7 +370,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   }
   if (io.out3) {
     // g = dE/dG = delta1 W0 (in the network operand type)
-    g.A = D1; g.lda = w1; g.B = WT[0]; g.sB = (long)Fp * w1; g.ldb = w1;
+    g.A = D1; g.lda = w1; g.B = WT[0]; g.Bq = WTq[0]; g.sB = (long)Fp * w1; g.ldb = w1;
     g.N = Fp; g.K = w1; g.C = G; g.ldc = Fp; g.H = nullptr;
     {
       StageTimer t(h, ST_GRADG, st);

@@ -10,8 +10,8 @@ enum { EPI_CELU = 0, EPI_HEAD = 1, EPI_BWD = 2, EPI_OUT = 3 };
 struct GemmArgs {
   const void* A;
   int lda;
-  const void* B;   // element s uses B + s * sB: [N][K], BF16 body layers in fragment
-                   // order, otherwise row-major with stride ldb
+  const void* B;   // element s uses B + s * sB: [N][K] row-major, stride ldb
+  const void* Bq;  // the same in MFMA fragment order (BF16; nullptr if absent)
   long sB;
   int ldb;
   const float* bias;
