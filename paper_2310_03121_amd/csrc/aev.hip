@@ -7,16 +7,16 @@
 // are the negative gradient of the energy (Methods, "PyTorch Model Support").
 //
 // Per atom the wave first loads its neighbor records into LDS (displacement,
-// distance, cutoff values, species).  Radial terms use lanes (g, m): four
-// neighbors at a time, one radial shift m per lane; per-species sums stay in
-// registers and are combined across the four neighbor slots by lane
-// shuffles.  Angular terms walk the species-pair blocks in layout order: the
-// angular neighbors are grouped by species, so a block's pairs are the
-// products of two species segments (or the pairs inside one); empty blocks
-// cost a single store of zeros.  Lanes (t, z) take eight pairs at a time, one
-// angle shift z per lane, keep the four radial shifts in registers, and the
-// block's 32 sums are combined across pair slots by shuffles and stored once,
-// in a fixed order.  The angle term uses the identity
+// distance, cutoff values, species).  Both sums of the forward pass are
+// products with a one-hot matrix, which the FP32 MFMA computes exactly (its
+// products are a term times 1 or 0): the radial row G[s][m] is
+// onehot(species x neighbors) * terms(neighbors x 16 shifts), four neighbors
+// per v_mfma_f32_16x16x4f32, and the angular rows G[block][a z] are
+// onehot(blocks x pairs) * terms(pairs x 32), four neighbor pairs per pass.
+// Each lane computes one term per product; there are no per-block loops or
+// cross-lane reductions, and the accumulator layout is the feature layout,
+// so the results are stored straight from registers.  The angle term uses
+// the identity
 // cos(theta - theta_z) = kappa c cos(theta_z) + sqrt(1 - kappa^2 c^2) sin(theta_z)
 // for theta = acos(kappa c); (1 + cos)/2 raised to zeta is exp2(zeta log2(.)).
 //
@@ -101,6 +101,14 @@ __device__ __forceinline__ int pair_block(int p, int q, int S) {
 // registers and stored block by block, so no LDS row is needed.
 constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
 
+typedef float aev_f32x4 __attribute__((ext_vector_type(4)));
+
+// acc += A * B for one 16 x 16 x 4 FP32 MFMA: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and holds C[4 * (l / 16) + r][l % 16], r = 0..3.
+__device__ __forceinline__ aev_f32x4 mfma4(float a, float b, aev_f32x4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, AevConst C, BoxConst B,
                                                  const float4* __restrict__ xyzs,
@@ -144,99 +152,83 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   wave_lds_sync();
   const int S = C.S;
   OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
+  const int l16 = lane & 15, kq = lane >> 4;
 
-  // ---- radial: lanes (g, m), four neighbors per pass, per-species registers
+  // ---- radial: G[s][m] = sum over neighbors e of [species(e) == s] * term(e, m)
+  // as MFMA products of a one-hot (species x 4 neighbors) with the terms
+  // (4 neighbors x 16 shifts); lane (kq, l16) computes neighbor kq, shift l16.
   {
-    const int g = lane >> 4, m = lane & 15;
-    const float Rm = pick(C.shf_r, m);
-    float acc[kMaxS];
-#pragma unroll
-    for (int q = 0; q < kMaxS; ++q) acc[q] = 0.f;
-    for (int e = g; e < nr; e += 4) {
-      const float u = nd[e].w - Rm;
-      const float term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x;
-      const int s = nsp[e];
-#pragma unroll
-      for (int q = 0; q < kMaxS; ++q) acc[q] += (s == q) ? term : 0.f;
+    const float Rm = pick(C.shf_r, l16);
+    aev_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int e0 = 0; e0 < nr; e0 += 4) {
+      const int e = e0 + kq;
+      float term = 0.f, hot = 0.f;
+      if (e < nr) {
+        const float u = nd[e].w - Rm;
+        term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x;
+        hot = nsp[e] == l16 ? 1.f : 0.f;
+      }
+      acc = mfma4(hot, term, acc);
     }
 #pragma unroll
-    for (int q = 0; q < kMaxS; ++q) {
-      acc[q] += __shfl_xor(acc[q], 16, 64);
-      acc[q] += __shfl_xor(acc[q], 32, 64);
-      if ((q & 3) == g && q < S) Store<OutT>::put(orow + q * kNR + m, acc[q]);
+    for (int r = 0; r < 4; ++r) {
+      const int s = kq * 4 + r;
+      if (s < S) Store<OutT>::put(orow + s * kNR + l16, acc[r]);
     }
   }
 
-  // ---- angular: species-pair blocks in layout order.  The angular entries
-  // [0, na) are grouped by species; each species' segment comes from a ballot.
-  // Lanes (t, z): eight neighbor pairs per pass, one angle shift per lane, the
-  // four radial shifts in registers; sums over pairs by shuffles.
+  // ---- angular: G[blk][a z] = sum over unordered pairs of angular neighbors
+  // of [block(pair) == blk] * term(pair, a, z), four pairs per pass.  Lane
+  // (kq, l16) takes pair kq and column l16 of each of the two 16-column
+  // halves: angle shift z = l16 % 8 and radial shifts a = l16 / 8 and
+  // l16 / 8 + 2.  Blocks 16.. (seven or more elements) use a second tile.
   {
-    int seg[kMaxS + 1];
-#pragma unroll
-    for (int q = 0; q <= kMaxS; ++q) seg[q] = 0;
-    for (int e0 = 0; e0 < na; e0 += kWave) {
-      const int sp_l = e0 + lane < na ? nsp[e0 + lane] : -1;
-#pragma unroll
-      for (int q = 0; q < kMaxS; ++q) seg[q + 1] += __popcll(ballot(sp_l == q));
+    const int T = na * (na - 1) / 2;
+    const int nblk = S * (S + 1) / 2;
+    const int z = l16 & 7, ah = l16 >> 3;
+    const float cz = pick(C.cos_z, z), sz = pick(C.sin_z, z);
+    const float ra_lo = ah ? C.shf_a[1] : C.shf_a[0];
+    const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
+    aev_f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
+    for (int t0 = 0; t0 < T; t0 += 4) {
+      const int t = t0 + kq;
+      float b0 = 0.f, b1 = 0.f, h0 = 0.f, h1 = 0.f;
+      if (t < T) {
+        int ej, ek;
+        decode_pair(t, na, ej, ek);
+        const float4 vj = nd[ej], vk = nd[ek];
+        const float fj = nf[ej].y, fk = nf[ek].y;
+        const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
+        const float kc = C.kappa * cs;
+        const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
+        const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
+        const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fj * fk;
+        const float dbar = 0.5f * (vj.w + vk.w);
+        const float u0 = dbar - ra_lo, u1 = dbar - ra_hi;
+        b0 = wgt * fast_exp2(-C.eta_a_l2e * u0 * u0);
+        b1 = wgt * fast_exp2(-C.eta_a_l2e * u1 * u1);
+        const int blk = pair_block(nsp[ej], nsp[ek], S);
+        h0 = blk == l16 ? 1.f : 0.f;
+        h1 = blk == l16 + 16 ? 1.f : 0.f;
+      }
+      c00 = mfma4(h0, b0, c00);
+      c01 = mfma4(h0, b1, c01);
+      if (nblk > 16) {
+        c10 = mfma4(h1, b0, c10);
+        c11 = mfma4(h1, b1, c11);
+      }
     }
-#pragma unroll
-    for (int q = 0; q < kMaxS; ++q) seg[q + 1] += seg[q];
-    const int tz = lane & 7, tg = lane >> 3;
-    const float cz = pick(C.cos_z, tz), sz = pick(C.sin_z, tz);
-    const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
     OutT* ang = orow + S * kNR;
-    int blk = 0;
-    for (int p = 0; p < S; ++p) {
-      const int p0 = seg[p], cp = seg[p + 1] - seg[p];
-      for (int q = p; q < S; ++q, ++blk) {
-        const int q0 = seg[q], cq = seg[q + 1] - seg[q];
-        const bool same = p == q;
-        const int T = same ? cp * (cp - 1) / 2 : cp * cq;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-        for (int t0 = 0; t0 < T; t0 += 8) {
-          const int t = t0 + tg;
-          if (t < T) {
-            int ej, ek;
-            if (same) {
-              decode_pair(t, cp, ej, ek);
-              ej += p0;
-              ek += p0;
-            } else {
-              const int x = t / cq;
-              ej = p0 + x;
-              ek = q0 + (t - x * cq);
-            }
-            const float4 vj = nd[ej], vk = nd[ek];
-            const float fj = nf[ej].y, fk = nf[ek].y;
-            const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
-            const float kc = C.kappa * cs;
-            const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
-            const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
-            const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fj * fk;
-            const float dbar = 0.5f * (vj.w + vk.w);
-            float u;
-            u = dbar - ra0; a0 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-            u = dbar - ra1; a1 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-            u = dbar - ra2; a2 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-            u = dbar - ra3; a3 += wgt * fast_exp2(-C.eta_a_l2e * u * u);
-          }
-        }
-        if (T > 0) {
 #pragma unroll
-          for (int o = 8; o <= 32; o <<= 1) {
-            a0 += __shfl_xor(a0, o, 64);
-            a1 += __shfl_xor(a1, o, 64);
-            a2 += __shfl_xor(a2, o, 64);
-            a3 += __shfl_xor(a3, o, 64);
-          }
-        }
-        // lane l < 32 holds (a = l / 8, z = l % 8): feature blk*32 + l
-        if (lane < 32) {
-          const int sel = lane >> 3;
-          const float v = sel == 0 ? a0 : (sel == 1 ? a1 : (sel == 2 ? a2 : a3));
-          Store<OutT>::put(ang + blk * 32 + lane, v);
-        }
+    for (int r = 0; r < 4; ++r) {
+      const int b = kq * 4 + r;
+      if (b < nblk) {
+        Store<OutT>::put(ang + b * 32 + l16, c00[r]);
+        Store<OutT>::put(ang + b * 32 + 16 + l16, c01[r]);
+      }
+      if (b + 16 < nblk) {
+        Store<OutT>::put(ang + (b + 16) * 32 + l16, c10[r]);
+        Store<OutT>::put(ang + (b + 16) * 32 + 16 + l16, c11[r]);
       }
     }
   }
