@@ -110,9 +110,8 @@ __device__ __forceinline__ aev_f32x4 mfma4(float a, float b, aev_f32x4 acc) {
 }
 
 template <typename OutT>
-__global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, AevConst C, BoxConst B,
-                                                 const float4* __restrict__ xyzs,
-                                                 const int* __restrict__ nbr,
+__global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, AevConst C,
+                                                 const float4* __restrict__ rec,
                                                  const int2* __restrict__ counts, int cap,
                                                  const int* __restrict__ row_of,
                                                  OutT* __restrict__ out, int ld) {
@@ -127,27 +126,21 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   int* nsp = reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
                                     (size_t)4 * cap) + w * cap;
 
-  // the first 64 row entries are fetched together with the counts, so only
-  // the neighbor-position gather waits on them
-  const int* nrow = nbr + (size_t)i * cap;
-  const int j0 = lane < cap ? nrow[lane] : 0;
+  // the first 64 records are fetched together with the counts
+  const float4* nrec = rec + (size_t)i * cap;
+  const float4 q0 = lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
   const int2 cn = counts[i];
-  const float4 pi = xyzs[i];
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
   const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
   for (int e = lane; e < nr; e += kWave) {
-    const int j = clampi(e < kWave ? j0 : nrow[e], n);
-    const float4 pj = xyzs[j];
-    const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], B.periodic);
-    const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], B.periodic);
-    const float dz = disp(pi.z, pj.z, B.L[2], B.invL[2], B.periodic);
-    const float r = sqrtf(dist2(dx, dy, dz));
+    const float4 q = e < kWave ? q0 : nrec[e];
+    const float r = sqrtf(dist2(q.x, q.y, q.z));
     float dfr, dfa;
     const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
     const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
-    nd[e] = make_float4(dx, dy, dz, r);
+    nd[e] = make_float4(q.x, q.y, q.z, r);
     nf[e] = make_float2(fr, fa);
-    nsp[e] = species_of(pj);
+    nsp[e] = species_of(q);
   }
   wave_lds_sync();
   const int S = C.S;
@@ -244,8 +237,8 @@ constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 // Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
 // sign = +1 writes forces (-dE/dr); sign = -1 writes the gradient dE/dr.
 template <typename GT>
-__global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C, BoxConst B,
-                                                 const float4* __restrict__ xyzs,
+__global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C,
+                                                 const float4* __restrict__ rec,
                                                  const int* __restrict__ nbr,
                                                  const int2* __restrict__ counts, int cap,
                                                  const int* __restrict__ row_of,
@@ -262,26 +255,25 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   float4* grad = nf + cap;
   int* nsp = reinterpret_cast<int*>(lds4 + (size_t)4 * cap * 3) + w * cap;
 
+  // records, counts, the dE/dG row and the neighbor indices of the scatter
+  // are all first-level loads
   const int* nrow = nbr + (size_t)i * cap;
+  const float4* nrec = rec + (size_t)i * cap;
+  const float4 q0 = lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
   const int j0 = lane < cap ? nrow[lane] : 0;
   const int2 cn = counts[i];
-  const float4 pi = xyzs[i];
   const GT* grow = g + (size_t)row_of[i] * ldg;
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
   const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
   for (int e = lane; e < nr; e += kWave) {
-    const int j = clampi(e < kWave ? j0 : nrow[e], n);
-    const float4 pj = xyzs[j];
-    const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], B.periodic);
-    const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], B.periodic);
-    const float dz = disp(pi.z, pj.z, B.L[2], B.invL[2], B.periodic);
-    const float r = sqrtf(dist2(dx, dy, dz));
+    const float4 q = e < kWave ? q0 : nrec[e];
+    const float r = sqrtf(dist2(q.x, q.y, q.z));
     float dfr, dfa = 0.f;
     const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
     const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
-    nd[e] = make_float4(dx, dy, dz, r);
+    nd[e] = make_float4(q.x, q.y, q.z, r);
     nf[e] = make_float4(fr, fa, dfr, dfa);
-    nsp[e] = species_of(pj);
+    nsp[e] = species_of(q);
   }
   wave_lds_sync();
   const int S = C.S;
@@ -382,7 +374,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   float sx = 0.f, sy = 0.f, sz2 = 0.f;
   for (int e = lane; e < nr; e += kWave) {
     const float4 gv = grad[e];
-    const int j = clampi(nbr[(size_t)i * cap + e], n);
+    const int j = clampi(e < kWave ? j0 : nrow[e], n);
     unsafeAtomicAdd(out + 3 * j, -sign * gv.x);
     unsafeAtomicAdd(out + 3 * j + 1, -sign * gv.y);
     unsafeAtomicAdd(out + 3 * j + 2, -sign * gv.z);
@@ -390,9 +382,9 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
     sy += gv.y;
     sz2 += gv.z;
   }
-  sx = wave_sum(sx);
-  sy = wave_sum(sy);
-  sz2 = wave_sum(sz2);
+  sx = wave_sum_rows(sx);
+  sy = wave_sum_rows(sy);
+  sz2 = wave_sum_rows(sz2);
   if (lane == 0) {
     unsafeAtomicAdd(out + 3 * i, sign * sx);
     unsafeAtomicAdd(out + 3 * i + 1, sign * sy);
@@ -403,42 +395,37 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
 // ----------------------------------------------------------------- launchers
 
 template <typename OutT>
-void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
-                    const float4* xyzs, const int* nbr, const int2* counts, int cap,
-                    const int* row_of, OutT* out, int ld, hipStream_t st) {
+void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
+                    const int2* counts, int cap, const int* row_of, OutT* out, int ld,
+                    hipStream_t st) {
   if (n_cap <= 0) return;
   const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr;
   static const bool attr = (ensure_lds(k_aev_fwd<OutT>), true);
   (void)attr;
-  hipLaunchKernelGGL(k_aev_fwd<OutT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, B,
-                     xyzs, nbr, counts, cap, row_of, out, ld);
+  hipLaunchKernelGGL(k_aev_fwd<OutT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec,
+                     counts, cap, row_of, out, ld);
 }
-
-template void launch_aev_fwd<float>(const int*, int, const AevConst&, const BoxConst&,
-                                    const float4*, const int*, const int2*, int, const int*,
-                                    float*, int, hipStream_t);
-template void launch_aev_fwd<bf16_t>(const int*, int, const AevConst&, const BoxConst&,
-                                     const float4*, const int*, const int2*, int, const int*,
-                                     bf16_t*, int, hipStream_t);
+template void launch_aev_fwd<float>(const int*, int, const AevConst&, const float4*, const int2*,
+                                    int, const int*, float*, int, hipStream_t);
+template void launch_aev_fwd<bf16_t>(const int*, int, const AevConst&, const float4*,
+                                     const int2*, int, const int*, bf16_t*, int, hipStream_t);
 
 template <typename GT>
-void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
-                    const float4* xyzs, const int* nbr, const int2* counts, int cap,
-                    const int* row_of, const GT* g, int ldg, float* out, float sign,
-                    hipStream_t st) {
+void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
+                    const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
+                    int ldg, float* out, float sign, hipStream_t st) {
   if (n_cap <= 0) return;
   const size_t lds = (size_t)4 * cap * kBwdBytesPerNbr;
   static const bool attr = (ensure_lds(k_aev_bwd<GT>), true);
   (void)attr;
-  hipLaunchKernelGGL(k_aev_bwd<GT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, B,
-                     xyzs,
-                     nbr, counts, cap, row_of, g, ldg, out, sign);
+  hipLaunchKernelGGL(k_aev_bwd<GT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec, nbr,
+                     counts, cap, row_of, g, ldg, out, sign);
 }
-template void launch_aev_bwd<float>(const int*, int, const AevConst&, const BoxConst&,
-                                    const float4*, const int*, const int2*, int, const int*,
-                                    const float*, int, float*, float, hipStream_t);
-template void launch_aev_bwd<bf16_t>(const int*, int, const AevConst&, const BoxConst&,
-                                     const float4*, const int*, const int2*, int, const int*,
-                                     const bf16_t*, int, float*, float, hipStream_t);
+template void launch_aev_bwd<float>(const int*, int, const AevConst&, const float4*, const int*,
+                                    const int2*, int, const int*, const float*, int, float*, float,
+                                    hipStream_t);
+template void launch_aev_bwd<bf16_t>(const int*, int, const AevConst&, const float4*, const int*,
+                                     const int2*, int, const int*, const bf16_t*, int, float*,
+                                     float, hipStream_t);
 
 }  // namespace nnp

@@ -77,6 +77,21 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum over the wave, returned in every lane (all lanes active): inclusive
+// prefix sums inside each row of 16 lanes by DPP row shifts (no LDS round
+// trips), then the four row totals read from lanes 15, 31, 47 and 63.
+__device__ __forceinline__ float wave_sum_rows(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_readlane(b, 15)) +
+         __int_as_float(__builtin_amdgcn_readlane(b, 31)) +
+         __int_as_float(__builtin_amdgcn_readlane(b, 47)) +
+         __int_as_float(__builtin_amdgcn_readlane(b, 63));
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);

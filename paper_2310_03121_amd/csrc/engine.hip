@@ -101,7 +101,7 @@ struct Plan {
   BoxConst B{};
   int ncell = 0;
   size_t total = 0;
-  size_t status, dims, gt, xyzs, mol, row, perm, hist, nbr, counts;
+  size_t status, dims, gt, xyzs, mol, row, perm, hist, nbr, counts, rec;
   size_t cell_of, cell_cnt, cell_start, cursor, cell_atoms, cell_xyzs;
   size_t X, H1, H2, H3, D3, D2, D1, G, erow, uprow, wpart, pos32;
 };
@@ -162,6 +162,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B) {
   P.hist = take((size_t)(kMaxS + 1) * P.nblk * 4);
   P.nbr = take(N * P.cap * 4);
   P.counts = take(N * 8);
+  P.rec = take(N * P.cap * 16);
   if (B.periodic) {
     P.cell_of = take(N * 4);
     P.cell_cnt = take((size_t)P.ncell * 4);
@@ -227,6 +228,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   int* hist = at<int>(ws, P.hist);
   int* nbr = at<int>(ws, P.nbr);
   int2* counts = at<int2>(ws, P.counts);
+  float4* rec = at<float4>(ws, P.rec);
   const int S = h->S, Fp = h->Fp;
   const int w1 = h->width[1], w2 = h->width[2], w3 = h->width[3];
   const bool bf = h->prec == NNP_MLP_BF16;
@@ -245,15 +247,15 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       launch_pairs_cell(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.cell_of),
                         at<int>(ws, P.cell_cnt), at<int>(ws, P.cell_start),
                         at<int>(ws, P.cursor), at<int>(ws, P.cell_atoms),
-                        at<float4>(ws, P.cell_xyzs), P.cap, nbr, counts, status, st);
+                        at<float4>(ws, P.cell_xyzs), P.cap, nbr, rec, counts, status, st);
     } else {
-      launch_pairs_mol(dims, P.n, h->C, xyzs, mol, io.off, P.cap, nbr, counts, status, st);
+      launch_pairs_mol(dims, P.n, h->C, xyzs, mol, io.off, P.cap, nbr, rec, counts, status, st);
     }
   }
   T* X = at<T>(ws, P.X);
   {
     StageTimer t(h, ST_AEV, st);
-    launch_aev_fwd<T>(dims, P.n, h->C, P.B, xyzs, nbr, counts, P.cap, row, X, Fp, st);
+    launch_aev_fwd<T>(dims, P.n, h->C, rec, counts, P.cap, row, X, Fp, st);
   }
 
   T* H1 = at<T>(ws, P.H1);
@@ -377,8 +379,8 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       ok &= launch_gemm<T>(EPI_OUT, g, P.rows_cap, st);
     }
     StageTimer t(h, ST_AEVBWD, st);
-    launch_aev_bwd<T>(dims, P.n, h->C, P.B, xyzs, nbr, counts, P.cap, row, G, Fp, io.out3,
-                      io.sign, st);
+    launch_aev_bwd<T>(dims, P.n, h->C, rec, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
+                      st);
   }
   if (io.dparams) {
     StageTimer t(h, ST_WGRAD, st);
@@ -731,12 +733,12 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
     launch_pairs_cell(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.cell_of), at<int>(ws, P.cell_cnt),
                       at<int>(ws, P.cell_start), at<int>(ws, P.cursor), at<int>(ws, P.cell_atoms),
                       at<float4>(ws, P.cell_xyzs), P.cap, at<int>(ws, P.nbr),
-                      at<int2>(ws, P.counts), status, st);
+                      at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
   else
     launch_pairs_mol(dims, P.n, h->C, xyzs, at<int>(ws, P.mol), off, P.cap, at<int>(ws, P.nbr),
-                     at<int2>(ws, P.counts), status, st);
-  launch_aev_fwd<float>(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.nbr), at<int2>(ws, P.counts),
-                        P.cap, nullptr, aev, h->F, st);
+                     at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
+  launch_aev_fwd<float>(dims, P.n, h->C, at<float4>(ws, P.rec), at<int2>(ws, P.counts), P.cap,
+                        nullptr, aev, h->F, st);
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
 }
 

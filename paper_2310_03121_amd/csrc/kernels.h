@@ -97,24 +97,26 @@ void launch_fill_f32(float* p, float v, long n, hipStream_t st);
 void launch_fill_f64(double* p, double v, int n, hipStream_t st);
 
 // neighbors.hip
+// Neighbor rows (ELL, row i at i * cap): nbr holds atom indices, rec the
+// matching records (dx, dy, dz, species bits) with d = x_j - x_i (minimum
+// image when periodic), computed by the cutoff predicate's own arithmetic.
 void launch_pairs_mol(const int* dims, int n_cap, const AevConst& C, const float4* xyzs,
-                      const int* mol, const int* off, int cap, int* nbr, int2* counts,
-                      uint32_t* status, hipStream_t st);
+                      const int* mol, const int* off, int cap, int* nbr, float4* rec,
+                      int2* counts, uint32_t* status, hipStream_t st);
 void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                        const float4* xyzs, int* cell_of, int* cell_cnt, int* cell_start,
                        int* cursor, int* cell_atoms, float4* cell_xyzs, int cap, int* nbr,
-                       int2* counts, uint32_t* status, hipStream_t st);
+                       float4* rec, int2* counts, uint32_t* status, hipStream_t st);
 
 // aev.hip
 template <typename OutT>
-void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
-                    const float4* xyzs, const int* nbr, const int2* counts, int cap,
-                    const int* row_of, OutT* out, int ld, hipStream_t st);
-template <typename GT>
-void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
-                    const float4* xyzs, const int* nbr, const int2* counts, int cap,
-                    const int* row_of, const GT* g, int ldg, float* out, float sign,
+void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
+                    const int2* counts, int cap, const int* row_of, OutT* out, int ld,
                     hipStream_t st);
+template <typename GT>
+void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
+                    const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
+                    int ldg, float* out, float sign, hipStream_t st);
 
 // mlp.hip
 template <typename T>

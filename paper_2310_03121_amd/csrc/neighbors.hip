@@ -10,7 +10,9 @@
 // keys (angular flag, species, atom index).  The list is then ordered by key
 // (angular neighbors first, grouped by species, ascending index) so that every
 // later sum runs in a fixed order, and written to a fixed-capacity row
-// (ELL layout: row i at i * cap) with counts (radial, angular).
+// (ELL layout: row i at i * cap) with counts (radial, angular), together
+// with each neighbor's displacement and species, so that the symmetry
+// function kernels start from the records instead of gathering positions.
 //
 // Molecules without a box: candidates are the atoms of the same molecule,
 // read as contiguous float4 records.  Periodic boxes (one system): atoms are
@@ -28,15 +30,18 @@ __device__ __forceinline__ int make_key(int j, int s, bool ang) {
   return (ang ? 0 : (1 << 30)) | (s << kKeyJBits) | j;
 }
 
-// Sorts the wave's keys [0, nr) by rank (keys are distinct) and writes the row.
-__device__ __forceinline__ void finish_list(const int* key, int nr, int na, int i, int cap,
-                                            int* __restrict__ nbr, int2* __restrict__ counts) {
+// Sorts the wave's keys [0, nr) by rank (keys are distinct) and writes the
+// row: indices to nbr, the matching displacement records to rec.
+__device__ __forceinline__ void finish_list(const int* key, const float4* lrec, int nr, int na,
+                                            int i, int cap, int* __restrict__ nbr,
+                                            float4* __restrict__ rec, int2* __restrict__ counts) {
   const int lane = lane_id();
   for (int e = lane; e < nr; e += kWave) {
     const int k = key[e];
     int rank = 0;
     for (int q = 0; q < nr; ++q) rank += key[q] < k;
     nbr[(size_t)i * cap + rank] = k & kKeyJMask;
+    rec[(size_t)i * cap + rank] = lrec[e];
   }
   if (lane == 0) counts[i] = make_int2(nr, na);
 }
@@ -45,15 +50,17 @@ __global__ __launch_bounds__(256) void k_pairs_mol(const int* __restrict__ dims,
                                                    const float4* __restrict__ xyzs,
                                                    const int* __restrict__ mol,
                                                    const int* __restrict__ off, int cap,
-                                                   int* __restrict__ nbr, int2* __restrict__ counts,
+                                                   int* __restrict__ nbr, float4* __restrict__ rec,
+                                                   int2* __restrict__ counts,
                                                    uint32_t* __restrict__ status) {
-  extern __shared__ int lds_keys[];
+  extern __shared__ float4 lds_mol[];
   const int n = dims[0];
   const int w = threadIdx.x >> 6;
   const int lane = lane_id();
   const int i = blockIdx.x * 4 + w;
   if (i >= n) return;
-  int* key = lds_keys + w * cap;
+  float4* lrec = lds_mol + (size_t)w * cap;
+  int* key = reinterpret_cast<int*>(lds_mol + (size_t)4 * cap) + w * cap;
   const float4 pi = xyzs[i];
   const int m = mol[i];
   int a = off[m], b = off[m + 1];
@@ -64,10 +71,12 @@ __global__ __launch_bounds__(256) void k_pairs_mol(const int* __restrict__ dims,
     const int j = base + lane;
     bool inR = false, inA = false;
     int sj = 0;
+    float dx = 0.f, dy = 0.f, dz = 0.f;
     if (j < b && j != i) {
       const float4 pj = xyzs[j];
-      const float dx = __fsub_rn(pj.x, pi.x), dy = __fsub_rn(pj.y, pi.y),
-                  dz = __fsub_rn(pj.z, pi.z);
+      dx = __fsub_rn(pj.x, pi.x);
+      dy = __fsub_rn(pj.y, pi.y);
+      dz = __fsub_rn(pj.z, pi.z);
       const float d2 = dist2(dx, dy, dz);
       inR = d2 < C.rc2_r;
       inA = d2 < C.rc2_a;
@@ -75,7 +84,10 @@ __global__ __launch_bounds__(256) void k_pairs_mol(const int* __restrict__ dims,
     }
     const uint64_t mr = ballot(inR);
     const int p = nr + popc_below(mr);
-    if (inR && p < cap) key[p] = make_key(j, sj, inA);
+    if (inR && p < cap) {
+      key[p] = make_key(j, sj, inA);
+      lrec[p] = make_float4(dx, dy, dz, __int_as_float(sj));
+    }
     nr += __popcll(mr);
     na += __popcll(ballot(inA));
   }
@@ -85,7 +97,7 @@ __global__ __launch_bounds__(256) void k_pairs_mol(const int* __restrict__ dims,
     na = na < nr ? na : nr;
   }
   wave_lds_sync();
-  finish_list(key, nr, na, i, cap, nbr, counts);
+  finish_list(key, lrec, nr, na, i, cap, nbr, rec, counts);
 }
 
 // ---------------------------------------------------------------- cell list
@@ -166,15 +178,17 @@ __global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims
                                                     const int* __restrict__ cell_atoms,
                                                     const float4* __restrict__ cell_xyzs, int cap,
                                                     int* __restrict__ nbr,
+                                                    float4* __restrict__ rec,
                                                     int2* __restrict__ counts,
                                                     uint32_t* __restrict__ status) {
-  extern __shared__ int lds[];
+  extern __shared__ float4 lds_cell[];
   const int n = dims[0];
   const int w = threadIdx.x >> 6;
   const int lane = lane_id();
   const int slot_i = blockIdx.x * 4 + w;
   if (slot_i >= n) return;
-  int* key = lds + w * (cap + 64);
+  float4* lrec = lds_cell + (size_t)w * cap;
+  int* key = reinterpret_cast<int*>(lds_cell + (size_t)4 * cap) + w * (cap + 64);
   int* pref = key + cap;  // 28 prefix entries + 27 cell starts
   int* cst = pref + 28;
   const int i = cell_atoms[slot_i];
@@ -214,6 +228,7 @@ __global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims
     const int t = base + lane;
     bool inR = false, inA = false;
     int j = 0, sj = 0;
+    float dx = 0.f, dy = 0.f, dz = 0.f;
     if (t < total) {
       // largest q < nst with pref[q] <= t (that cell is non-empty and holds t)
       int q = 0, hi = nst;
@@ -225,9 +240,9 @@ __global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims
       j = cell_atoms[slot];
       if (j != i) {
         const float4 pj = cell_xyzs[slot];
-        const float dx = disp(pi.x, pj.x, B.L[0], B.invL[0], 1);
-        const float dy = disp(pi.y, pj.y, B.L[1], B.invL[1], 1);
-        const float dz = disp(pi.z, pj.z, B.L[2], B.invL[2], 1);
+        dx = disp(pi.x, pj.x, B.L[0], B.invL[0], 1);
+        dy = disp(pi.y, pj.y, B.L[1], B.invL[1], 1);
+        dz = disp(pi.z, pj.z, B.L[2], B.invL[2], 1);
         const float d2 = dist2(dx, dy, dz);
         inR = d2 < C.rc2_r;
         inA = d2 < C.rc2_a;
@@ -236,7 +251,10 @@ __global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims
     }
     const uint64_t mr = ballot(inR);
     const int p = nr + popc_below(mr);
-    if (inR && p < cap) key[p] = make_key(j, sj, inA);
+    if (inR && p < cap) {
+      key[p] = make_key(j, sj, inA);
+      lrec[p] = make_float4(dx, dy, dz, __int_as_float(sj));
+    }
     nr += __popcll(mr);
     na += __popcll(ballot(inA));
   }
@@ -246,23 +264,24 @@ __global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims
     na = na < nr ? na : nr;
   }
   wave_lds_sync();
-  finish_list(key, nr, na, i, cap, nbr, counts);
+  finish_list(key, lrec, nr, na, i, cap, nbr, rec, counts);
 }
 
 // ----------------------------------------------------------------- launchers
 
 void launch_pairs_mol(const int* dims, int n_cap, const AevConst& C, const float4* xyzs,
-                      const int* mol, const int* off, int cap, int* nbr, int2* counts,
-                      uint32_t* status, hipStream_t st) {
+                      const int* mol, const int* off, int cap, int* nbr, float4* rec,
+                      int2* counts, uint32_t* status, hipStream_t st) {
   if (n_cap <= 0) return;
-  hipLaunchKernelGGL(k_pairs_mol, dim3((n_cap + 3) / 4), dim3(256), 4 * cap * sizeof(int), st,
-                     dims, C, xyzs, mol, off, cap, nbr, counts, status);
+  hipLaunchKernelGGL(k_pairs_mol, dim3((n_cap + 3) / 4), dim3(256),
+                     4 * cap * (sizeof(float4) + sizeof(int)), st, dims, C, xyzs, mol, off, cap,
+                     nbr, rec, counts, status);
 }
 
 void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                        const float4* xyzs, int* cell_of, int* cell_cnt, int* cell_start,
                        int* cursor, int* cell_atoms, float4* cell_xyzs, int cap, int* nbr,
-                       int2* counts, uint32_t* status, hipStream_t st) {
+                       float4* rec, int2* counts, uint32_t* status, hipStream_t st) {
   if (n_cap <= 0) return;
   const int ncell = B.nc[0] * B.nc[1] * B.nc[2];
   hipLaunchKernelGGL(k_fill_i32, dim3((ncell + 255) / 256), dim3(256), 0, st, cell_cnt, 0, ncell);
@@ -272,9 +291,9 @@ void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxC
                      cursor);
   hipLaunchKernelGGL(k_cell_fill, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, xyzs,
                      cell_of, cursor, cell_atoms, cell_xyzs);
-  hipLaunchKernelGGL(k_pairs_cell, dim3((n_cap + 3) / 4), dim3(256), 4 * (cap + 64) * sizeof(int),
-                     st, dims, C, B, cell_of, cell_start, cell_atoms, cell_xyzs, cap, nbr, counts,
-                     status);
+  hipLaunchKernelGGL(k_pairs_cell, dim3((n_cap + 3) / 4), dim3(256),
+                     4 * (cap * sizeof(float4) + (cap + 64) * sizeof(int)), st, dims, C, B,
+                     cell_of, cell_start, cell_atoms, cell_xyzs, cap, nbr, rec, counts, status);
 }
 
 }  // namespace nnp
