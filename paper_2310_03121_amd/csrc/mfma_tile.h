@@ -71,11 +71,12 @@ struct BRing {
 #pragma unroll
     for (int j = 0; j < TN; ++j) r[U][j] = *reinterpret_cast<const uint4*>(p + j * tile);
   }
+  template <int U = 0>
   __device__ __forceinline__ void prologue() {
-    load<0>(0);
-    if constexpr (P > 1) load<1>(1);
-    if constexpr (P > 2) load<2>(2);
-    if constexpr (P > 3) load<3>(3);
+    if constexpr (U < P) {
+      load<U>(U);
+      prologue<U + 1>();
+    }
   }
 };
 
@@ -132,7 +133,9 @@ __device__ __forceinline__ void zero_acc(f32x4_t (&acc)[TM][TN]) {
 
 // Workgroup b of nb -> row tile, so that the tiles of one XCD (dispatch goes
 // round-robin over the eight XCDs) are consecutive: neighbouring tiles share
-// an element and hence the weights their XCD's L2 holds.
+// an element and hence the weights their XCD's L2 holds.  nb must be the
+// number of tiles that hold rows (not the grid size): every XCD then gets
+// its share of real tiles, and blocks b >= nb exit.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + (x < r ? x : r) + (b >> 3);

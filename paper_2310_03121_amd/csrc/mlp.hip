@@ -53,8 +53,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
 
   const GroupTable* gt = a.gt;
-  const int row0 = xcd_tile(blockIdx.x, gridDim.x) * BM;
-  if (row0 >= gt->total_rows) return;
+  // tiles holding rows (groups are padded to whole tiles); the grid covers
+  // the capacity, and blocks past the used tiles exit
+  const int nt = gt->total_rows / BM;
+  if ((int)blockIdx.x >= nt) return;
+  const int row0 = xcd_tile(blockIdx.x, nt) * BM;
   const int s = tile_species(gt, row0);
   const int row_end = gt->pstart[s] + gt->cnt[s];
   if (row0 >= row_end) return;  // a tile of pad rows only
@@ -151,11 +154,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
   };
 
   if constexpr (RESIDENT) {
-    uint4 ra[NVA];
-    for (int c = 0; c < nchunks; ++c) {
-      aload(c, ra);
-      astore(c, ra);
-    }
+    // every chunk's loads are in flight before the first LDS store
+    uint4 ra[kMaxResident][NVA];
+#pragma unroll
+    for (int c = 0; c < kMaxResident; ++c)
+      if (c < nchunks) aload(c, ra[c]);
+#pragma unroll
+    for (int c = 0; c < kMaxResident; ++c)
+      if (c < nchunks) astore(c, ra[c]);
     __syncthreads();
     for (int p = 0; p < npass; ++p) {
       for (int c = 0; c < nchunks; ++c)

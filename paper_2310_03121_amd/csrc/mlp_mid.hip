@@ -10,7 +10,9 @@
 //
 // CELU'(z) is recovered from the stored activation: 1 for h > 0, else
 // 1 + h/alpha (for D1 from H1 in global memory, which the tile loaded at the
-// start and which is still L2 resident).  The four products are MFMA GEMMs
+// start and which is still L2 resident; it is fetched ahead of the last
+// product).  Every global load is issued well ahead of its use: the tile's H1
+// vectors all before their LDS stores, the first weights before the tile.  The four products are MFMA GEMMs
 // with the A operand resident in LDS and the weights streamed into registers
 // (mfma_tile.h); 8 waves per workgroup.  This removes three launches and the
 // HBM round trips of H2, D3 and D2 that separate layer kernels would need.
@@ -34,20 +36,36 @@ struct MidCfg {
   static_assert(WM * TM * 16 == kMidBM && WN * TN * 16 == N, "one pass covers N");
 };
 
-// acc = A (LDS, row stride sa bytes, K columns) * B^T (global [N][K]).
+template <int N>
+using MidRing = BRing<bf16_t, MidCfg<N>::TN, MidCfg<N>::P>;
+
+// Starts the weight ring of a product with N columns and K inner (the
+// weights do not depend on the activations, so this can run early).
+template <int N, int K>
+__device__ __forceinline__ void mid_ring(MidRing<N>& br, const bf16_t* B, int lane, int wv) {
+  static_assert(K % Frag<bf16_t>::KS == 0, "whole k-steps");
+  br.init(B, (wv % MidCfg<N>::WN) * MidCfg<N>::TN * 16, -1, lane, K);
+  br.prologue();
+}
+
+// acc = A (LDS, row stride sa bytes, K columns) * B^T, B from a started ring.
+template <int N, int K>
+__device__ __forceinline__ void mid_steps(const unsigned char* As, int sa, MidRing<N>& br, int lane,
+                                          int wv, f32x4_t (&acc)[MidCfg<N>::TM][MidCfg<N>::TN]) {
+  using C = MidCfg<N>;
+  const int wm = wv / C::WN;
+  zero_acc(acc);
+  const unsigned char* a0 = As + (wm * C::TM * 16 + (lane & 15)) * sa + (lane >> 4) * 16;
+  ksteps_ct<bf16_t, C::TM, C::TN, C::P, K / Frag<bf16_t>::KS>(a0, 16 * sa, br, acc);
+}
+
 template <int N, int K>
 __device__ __forceinline__ void mid_product(const unsigned char* As, int sa, const bf16_t* B,
                                             int lane, int wv,
                                             f32x4_t (&acc)[MidCfg<N>::TM][MidCfg<N>::TN]) {
-  using C = MidCfg<N>;
-  static_assert(K % Frag<bf16_t>::KS == 0, "whole k-steps");
-  const int wm = wv / C::WN, wn = wv % C::WN;
-  zero_acc(acc);
-  BRing<bf16_t, C::TN, C::P> br;
-  br.init(B, wn * C::TN * 16, -1, lane, K);
-  br.prologue();
-  const unsigned char* a0 = As + (wm * C::TM * 16 + (lane & 15)) * sa + (lane >> 4) * 16;
-  ksteps_ct<bf16_t, C::TM, C::TN, C::P, K / Frag<bf16_t>::KS>(a0, 16 * sa, br, acc);
+  MidRing<N> br;
+  mid_ring<N, K>(br, B, lane, wv);
+  mid_steps<N, K>(As, sa, br, lane, wv, acc);
 }
 
 __device__ __forceinline__ void lds_put4(unsigned char* p, float4 v) {
@@ -70,8 +88,11 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
   float* epart = reinterpret_cast<float*>(X2 + kMidBM * S2);  // [WN][128]
 
   const GroupTable* gt = a.gt;
-  const int row0 = xcd_tile(blockIdx.x, gridDim.x) * kMidBM;
-  if (row0 >= gt->total_rows) return;
+  // tiles holding rows (groups are padded to whole tiles); the grid covers
+  // the capacity, and blocks past the used tiles exit
+  const int nt = gt->total_rows / kMidBM;
+  if ((int)blockIdx.x >= nt) return;
+  const int row0 = xcd_tile(blockIdx.x, nt) * kMidBM;
   const int s = tile_species(gt, row0);
   const int row_end = gt->pstart[s] + gt->cnt[s];
   if (row0 >= row_end) return;
@@ -79,14 +100,30 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
   const int rl = lane & 15, cq = (lane >> 4) * 4;
   const float alpha = a.alpha, ia = 1.f / a.alpha, ial2e = a.inv_alpha_l2e;
 
-  // H1 tile -> LDS (zero rows past the group)
-  constexpr int V1 = W1 / 8;  // 16-byte vectors per row
-  for (int idx = tid; idx < kMidBM * V1; idx += 512) {
-    const int r = idx / V1, c = idx % V1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (row0 + r < row_end)
-      v = *reinterpret_cast<const uint4*>(a.H1 + (size_t)(row0 + r) * W1 + c * 8);
-    *reinterpret_cast<uint4*>(X1 + r * S1 + c * 16) = v;
+  // the first product's weights are requested before the H1 tile, so the
+  // two latencies overlap
+  MidRing<W2> br1;
+  mid_ring<W2, W1>(br1, a.W1 + (size_t)s * W2 * W1, lane, wv);
+
+  // H1 tile -> LDS (zero rows past the group): every load is issued before
+  // the first store
+  {
+    constexpr int V1 = W1 / 8;  // 16-byte vectors per row
+    constexpr int NV = kMidBM * V1 / 512;
+    static_assert(kMidBM * V1 % 512 == 0, "whole vectors per thread");
+    uint4 v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int idx = tid + q * 512, r = idx / V1, c = idx % V1;
+      v[q] = make_uint4(0, 0, 0, 0);
+      if (row0 + r < row_end)
+        v[q] = *reinterpret_cast<const uint4*>(a.H1 + (size_t)(row0 + r) * W1 + c * 8);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int idx = tid + q * 512, r = idx / V1, c = idx % V1;
+      *reinterpret_cast<uint4*>(X1 + r * S1 + c * 16) = v[q];
+    }
   }
   __syncthreads();
 
@@ -94,7 +131,7 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
   {
     using C = MidCfg<W2>;
     f32x4_t acc[C::TM][C::TN];
-    mid_product<W2, W1>(X1, S1, a.W1 + (size_t)s * W2 * W1, lane, wv, acc);
+    mid_steps<W2, W1>(X1, S1, br1, lane, wv, acc);
     const int wm = wv / C::WN, wn = wv % C::WN;
     const float* b1 = a.b1 + (size_t)s * W2;
 #pragma unroll
@@ -199,9 +236,21 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
   // ---- D1 = (D2 W1) * CELU'(z1) -> global
   {
     using C = MidCfg<W1>;
+    const int wm = wv / C::WN, wn = wv % C::WN;
+    // H1 for the slopes is fetched before the product (4 bf16 per tile)
+    uint2 h1[C::TM][C::TN];
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i) {
+      const int row = row0 + wm * C::TM * 16 + i * 16 + rl;
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int c = wn * C::TN * 16 + j * 16 + cq;
+        h1[i][j] = row < row_end ? *reinterpret_cast<const uint2*>(a.H1 + (size_t)row * W1 + c)
+                                 : make_uint2(0, 0);
+      }
+    }
     f32x4_t acc[C::TM][C::TN];
     mid_product<W1, W2>(X2, S2, a.W1T + (size_t)s * W1 * W2, lane, wv, acc);
-    const int wm = wv / C::WN, wn = wv % C::WN;
 #pragma unroll
     for (int i = 0; i < C::TM; ++i) {
       const int r = wm * C::TM * 16 + i * 16 + rl;
@@ -210,12 +259,12 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
         const int c = wn * C::TN * 16 + j * 16 + cq;
-        float4 d = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (rv) {
-          const float4 h = Vec4<bf16_t>::get(a.H1 + (size_t)row * W1 + c);
-          d = make_float4(acc[i][j][0] * celu_slope(h.x, ia), acc[i][j][1] * celu_slope(h.y, ia),
-                          acc[i][j][2] * celu_slope(h.z, ia), acc[i][j][3] * celu_slope(h.w, ia));
-        }
+        const uint2 u = h1[i][j];
+        const float4 h = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                                     __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+        float4 d = make_float4(acc[i][j][0] * celu_slope(h.x, ia), acc[i][j][1] * celu_slope(h.y, ia),
+                               acc[i][j][2] * celu_slope(h.z, ia), acc[i][j][3] * celu_slope(h.w, ia));
+        if (!rv) d = make_float4(0.f, 0.f, 0.f, 0.f);
         Store<bf16_t>::put4(a.D1 + (size_t)row * W1 + c, d);
       }
     }

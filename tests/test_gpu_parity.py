@@ -194,6 +194,41 @@ def test_parameter_gradients_fp32():
     assert rel_rms(gp.cpu().numpy(), dpos_o) <= 1e-5
 
 
+@pytest.mark.parametrize("S", [7, 4])
+def test_parameter_gradients_bf16(S):
+    # BF16 network operands (activations, deltas and weights rounded to
+    # 8-bit mantissas, FP32 accumulation): each operand carries a relative
+    # rounding error up to 2^-9, so the per-block gradients are held to 3e-2
+    # relative RMS and dL/dpos to 1e-2, the force bar of the BF16 path.
+    s = w.conformer_batch(8, 64, seed=1) if S == 7 else w.water_box(60, 12.0, seed=7)
+    announce(f"parameter gradients bf16, {S} elements, {s.n_atoms} atoms")
+    pot, at, mt = get_pot(S, "bf16")
+    pos, sp, off = to_dev(s)
+    rng = np.random.default_rng(5)
+    dLdE = rng.normal(size=s.n_mol)
+    gp, gw, E = pot.backward(pos, sp, off, torch.from_numpy(dLdE).cuda(), box=s.box)
+    pot.check()
+    gw_o, dpos_o = o.weight_gradients(s, aev_table=at, mlp_table=mt, dL_dE=dLdE)
+    gw = gw.cpu().numpy()
+    worst = 0.0
+    o_ = 0
+    present = set(int(x) for x in s.species)
+    for sp_ in range(S):
+        for l in range(4):
+            n = mt.W[sp_][l].size + mt.b[sp_][l].size
+            blk = slice(o_, o_ + n)
+            if sp_ in present:
+                err = rel_rms(gw[blk], gw_o[blk])
+                worst = max(worst, err)
+                assert err <= 3e-2, (sp_, l, err)
+            else:
+                assert np.all(gw[blk] == 0)
+            o_ += n
+    dp = rel_rms(gp.cpu().numpy(), dpos_o)
+    print(f"worst block dL/dparams rel-RMS {worst:.3e}; dL/dpos rel-RMS {dp:.3e}")
+    assert dp <= 1e-2
+
+
 def test_autograd_function_matches_forces():
     from paper_2310_03121_amd import NNPFunction
     s = w.config_system(0)
