@@ -546,28 +546,19 @@ static bool launch_head(const GemmArgs& a, int rows_cap, hipStream_t st) {
   }
 }
 
-// BF16 body layers whose A tile stays resident in LDS (K <= 384) use the
-// register-streamed kernel (B in fragment order): they are latency-bound,
-// and it keeps A on chip across the column passes.  Longer K (layer 1),
-// FP32 and the head use the LDS-staged kernel (B row-major).
+// BF16 body layers use the register-streamed kernel (B in fragment order);
+// FP32 body layers, whose MFMA rate rather than latency bounds them, and the
+// head use the LDS-staged kernel (B row-major).
 template <typename T>
 bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st);
 template <>
 bool launch_gemm<bf16_t>(int epi, const GemmArgs& a, int rows_cap, hipStream_t st) {
-  const int nchunks = (int)((a.K * sizeof(bf16_t) + kChunkBytes - 1) / kChunkBytes);
-  const bool rb = a.Bq != nullptr && nchunks <= kMaxResident;
-  if (epi != EPI_HEAD && !rb && a.B == nullptr) return false;
+  if (epi != EPI_HEAD && a.Bq == nullptr) return false;
   switch (epi) {
-    case EPI_CELU:
-      return rb ? launch_body<bf16_t, EPI_CELU>(a, rows_cap, st)
-                : launch_lds_body<bf16_t, EPI_CELU>(a, rows_cap, st);
+    case EPI_CELU: return launch_body<bf16_t, EPI_CELU>(a, rows_cap, st);
     case EPI_HEAD: return launch_head<bf16_t>(a, rows_cap, st);
-    case EPI_BWD:
-      return rb ? launch_body<bf16_t, EPI_BWD>(a, rows_cap, st)
-                : launch_lds_body<bf16_t, EPI_BWD>(a, rows_cap, st);
-    case EPI_OUT:
-      return rb ? launch_body<bf16_t, EPI_OUT>(a, rows_cap, st)
-                : launch_lds_body<bf16_t, EPI_OUT>(a, rows_cap, st);
+    case EPI_BWD: return launch_body<bf16_t, EPI_BWD>(a, rows_cap, st);
+    case EPI_OUT: return launch_body<bf16_t, EPI_OUT>(a, rows_cap, st);
   }
   return false;
 }
