@@ -66,6 +66,10 @@ __device__ __forceinline__ float cutoff_val(float r, float inv_rc, float& dfc, f
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// v_sqrt_f32 (about 1 ulp): neighbor distances and the angle sine are
+// normal numbers, so the IEEE-exact expansion (denormal scaling and two
+// correction steps) buys nothing here
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Per-lane entry of a table held in the (uniform) kernel arguments, by
 // unrolled selects: indexing the argument struct with a lane-dependent index
@@ -83,7 +87,7 @@ __device__ __forceinline__ float pick(const float (&tab)[N], int idx) {
 // pairs before row a number a*na - a*(a+1)/2).
 __device__ __forceinline__ void decode_pair(int t, int na, int& a, int& b) {
   const float c2 = (float)(2 * na - 1);
-  int r = (int)((c2 - sqrtf(fmaxf(c2 * c2 - 8.f * (float)t, 0.f))) * 0.5f);
+  int r = (int)((c2 - fast_sqrt(fmaxf(c2 * c2 - 8.f * (float)t, 0.f))) * 0.5f);
   r = r < 0 ? 0 : (r > na - 2 ? na - 2 : r);
   while (r > 0 && r * na - r * (r + 1) / 2 > t) --r;
   while (r + 1 <= na - 2 && (r + 1) * na - (r + 1) * (r + 2) / 2 <= t) ++r;
@@ -132,16 +136,17 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   const int2 cn = counts[i];
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
   const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
-  for (int e = lane; e < nr; e += kWave) {
-    const float4 q = e < kWave ? q0 : nrec[e];
-    const float r = sqrtf(dist2(q.x, q.y, q.z));
+  auto setup = [&](int e, const float4 q) __attribute__((always_inline)) {
+    const float r = fast_sqrt(dist2(q.x, q.y, q.z));
     float dfr, dfa;
     const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
     const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
     nd[e] = make_float4(q.x, q.y, q.z, r);
     nf[e] = make_float2(fr, fa);
     nsp[e] = species_of(q);
-  }
+  };
+  if (lane < nr) setup(lane, q0);
+  for (int e = lane + kWave; e < nr; e += kWave) setup(e, nrec[e]);
   wave_lds_sync();
   const int S = C.S;
   OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
         const float fj = nf[ej].y, fk = nf[ek].y;
         const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
         const float kc = C.kappa * cs;
-        const float sn = sqrtf(fmaxf(1.f - kc * kc, 0.f));
+        const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 0.f));
         const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
         const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fj * fk;
         const float dbar = 0.5f * (vj.w + vk.w);
@@ -265,16 +270,17 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   const GT* grow = g + (size_t)row_of[i] * ldg;
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
   const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
-  for (int e = lane; e < nr; e += kWave) {
-    const float4 q = e < kWave ? q0 : nrec[e];
-    const float r = sqrtf(dist2(q.x, q.y, q.z));
+  auto setup = [&](int e, const float4 q) __attribute__((always_inline)) {
+    const float r = fast_sqrt(dist2(q.x, q.y, q.z));
     float dfr, dfa = 0.f;
     const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
     const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
     nd[e] = make_float4(q.x, q.y, q.z, r);
     nf[e] = make_float4(fr, fa, dfr, dfa);
     nsp[e] = species_of(q);
-  }
+  };
+  if (lane < nr) setup(lane, q0);
+  for (int e = lane + kWave; e < nr; e += kWave) setup(e, nrec[e]);
   wave_lds_sync();
   const int S = C.S;
 
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
         const float ijk = fast_rcp(vj.w * vk.w);
         cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * ijk;
         const float kc = C.kappa * cs;
-        const float sn = sqrtf(fmaxf(1.f - kc * kc, 1e-12f));
+        const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 1e-12f));
         const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
         const float pw = fast_exp2(C.zeta * fast_log2(base_));
         const float f1 = 2.f * pw;
