@@ -80,17 +80,23 @@ struct BRing {
   }
 };
 
-// One k-step: TM A fragments from LDS (`arow` points at this lane's row and
-// k-group in the step's first column), TM x TN MFMAs against ring slot U,
+template <int TM>
+__device__ __forceinline__ void load_a(const unsigned char* arow, int astride16, uint4 (&fa)[TM]) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i) fa[i] = *reinterpret_cast<const uint4*>(arow + i * astride16);
+}
+
+// One k-step: TM x TN MFMAs of the A fragments `fa` (already in registers)
+// against ring slot U; if PREF, the next step's A fragments (at `anext`) are
+// read from LDS into `fn` first, so their latency hides behind these MFMAs;
 // then (if REFILL) the slot is refilled with step s_next.  The scheduling
 // barrier keeps the refill right behind the step: left alone, the compiler
 // sinks all refills of a group to its end, which removes the prefetch.
-template <typename T, int TM, int TN, int P, int U, bool REFILL>
-__device__ __forceinline__ void kstep(const unsigned char* arow, int astride16, BRing<T, TN, P>& br,
-                                      int s_next, f32x4_t (&acc)[TM][TN]) {
-  uint4 fa[TM];
-#pragma unroll
-  for (int i = 0; i < TM; ++i) fa[i] = *reinterpret_cast<const uint4*>(arow + i * astride16);
+template <typename T, int TM, int TN, int P, int U, bool REFILL, bool PREF>
+__device__ __forceinline__ void kstep(const unsigned char* anext, int astride16,
+                                      BRing<T, TN, P>& br, int s_next, f32x4_t (&acc)[TM][TN],
+                                      const uint4 (&fa)[TM], uint4 (&fn)[TM]) {
+  if constexpr (PREF) load_a<TM>(anext, astride16, fn);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -104,22 +110,33 @@ __device__ __forceinline__ void kstep(const unsigned char* arow, int astride16, 
 template <typename T, int TM, int TN, int P>
 __device__ __forceinline__ void kgroup(const unsigned char* ap, int astride16, BRing<T, TN, P>& br,
                                        int s0, f32x4_t (&acc)[TM][TN]) {
+  static_assert(P == 4, "four steps per group");
   constexpr int SB = Frag<T>::KS * sizeof(T);
-  kstep<T, TM, TN, P, 0, true>(ap, astride16, br, s0 + P, acc);
-  if constexpr (P > 1) kstep<T, TM, TN, P, 1, true>(ap + SB, astride16, br, s0 + 1 + P, acc);
-  if constexpr (P > 2) kstep<T, TM, TN, P, 2, true>(ap + 2 * SB, astride16, br, s0 + 2 + P, acc);
-  if constexpr (P > 3) kstep<T, TM, TN, P, 3, true>(ap + 3 * SB, astride16, br, s0 + 3 + P, acc);
+  uint4 f0[TM], f1[TM];
+  load_a<TM>(ap, astride16, f0);
+  kstep<T, TM, TN, P, 0, true, true>(ap + SB, astride16, br, s0 + P, acc, f0, f1);
+  kstep<T, TM, TN, P, 1, true, true>(ap + 2 * SB, astride16, br, s0 + 1 + P, acc, f1, f0);
+  kstep<T, TM, TN, P, 2, true, true>(ap + 3 * SB, astride16, br, s0 + 2 + P, acc, f0, f1);
+  kstep<T, TM, TN, P, 3, true, false>(ap, astride16, br, s0 + 3 + P, acc, f1, f0);
 }
 
 // All NS k-steps of a product with compile-time K, fully unrolled: slot
-// refills stop at the last step, so no load is wasted.
+// refills stop at the last step, so no load is wasted.  The two A fragment
+// sets alternate by step parity.
 template <typename T, int TM, int TN, int P, int NS, int S = 0>
 __device__ __forceinline__ void ksteps_ct(const unsigned char* a0, int astride16,
-                                          BRing<T, TN, P>& br, f32x4_t (&acc)[TM][TN]) {
+                                          BRing<T, TN, P>& br, f32x4_t (&acc)[TM][TN],
+                                          uint4 (&fe)[TM], uint4 (&fo)[TM]) {
   if constexpr (S < NS) {
     constexpr int SB = Frag<T>::KS * sizeof(T);
-    kstep<T, TM, TN, P, S % P, (S + P < NS)>(a0 + S * SB, astride16, br, S + P, acc);
-    ksteps_ct<T, TM, TN, P, NS, S + 1>(a0, astride16, br, acc);
+    if constexpr (S == 0) load_a<TM>(a0, astride16, fe);
+    if constexpr (S % 2 == 0)
+      kstep<T, TM, TN, P, S % P, (S + P < NS), (S + 1 < NS)>(a0 + (S + 1) * SB, astride16, br,
+                                                             S + P, acc, fe, fo);
+    else
+      kstep<T, TM, TN, P, S % P, (S + P < NS), (S + 1 < NS)>(a0 + (S + 1) * SB, astride16, br,
+                                                             S + P, acc, fo, fe);
+    ksteps_ct<T, TM, TN, P, NS, S + 1>(a0, astride16, br, acc, fe, fo);
   }
 }
 

@@ -56,7 +56,8 @@ __device__ __forceinline__ void mid_steps(const unsigned char* As, int sa, MidRi
   const int wm = wv / C::WN;
   zero_acc(acc);
   const unsigned char* a0 = As + (wm * C::TM * 16 + (lane & 15)) * sa + (lane >> 4) * 16;
-  ksteps_ct<bf16_t, C::TM, C::TN, C::P, K / Frag<bf16_t>::KS>(a0, 16 * sa, br, acc);
+  uint4 fe[C::TM], fo[C::TM];
+  ksteps_ct<bf16_t, C::TM, C::TN, C::P, K / Frag<bf16_t>::KS>(a0, 16 * sa, br, acc, fe, fo);
 }
 
 template <int N, int K>
