@@ -66,6 +66,10 @@ __device__ __forceinline__ float cutoff_val(float r, float inv_rc, float& dfc, f
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Records read before the neighbor count is known: enough for a molecule's
+// atoms (up to 16 neighbors) without fetching the whole 64-entry window.
+constexpr int kSpecRec = 16;
+
 // v_sqrt_f32 (about 1 ulp): neighbor distances and the angle sine are
 // normal numbers, so the IEEE-exact expansion (denormal scaling and two
 // correction steps) buys nothing here
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
 
   // the first 64 records are fetched together with the counts
   const float4* nrec = rec + (size_t)i * cap;
-  const float4 q0 = lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 q0 = lane < kSpecRec && lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
   const int2 cn = counts[i];
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
   const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
@@ -145,8 +149,11 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
     nf[e] = make_float2(fr, fa);
     nsp[e] = species_of(q);
   };
-  if (lane < nr) setup(lane, q0);
-  for (int e = lane + kWave; e < nr; e += kWave) setup(e, nrec[e]);
+  if (nr <= kSpecRec) {  // wave-uniform
+    if (lane < nr) setup(lane, q0);
+  } else {
+    for (int e = lane; e < nr; e += kWave) setup(e, nrec[e]);
+  }
   wave_lds_sync();
   const int S = C.S;
   OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
@@ -264,8 +271,8 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   // are all first-level loads
   const int* nrow = nbr + (size_t)i * cap;
   const float4* nrec = rec + (size_t)i * cap;
-  const float4 q0 = lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-  const int j0 = lane < cap ? nrow[lane] : 0;
+  const float4 q0 = lane < kSpecRec && lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const int j0 = lane < kSpecRec && lane < cap ? nrow[lane] : 0;
   const int2 cn = counts[i];
   const GT* grow = g + (size_t)row_of[i] * ldg;
   const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
@@ -279,8 +286,11 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
     nf[e] = make_float4(fr, fa, dfr, dfa);
     nsp[e] = species_of(q);
   };
-  if (lane < nr) setup(lane, q0);
-  for (int e = lane + kWave; e < nr; e += kWave) setup(e, nrec[e]);
+  if (nr <= kSpecRec) {  // wave-uniform
+    if (lane < nr) setup(lane, q0);
+  } else {
+    for (int e = lane; e < nr; e += kWave) setup(e, nrec[e]);
+  }
   wave_lds_sync();
   const int S = C.S;
 
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   float sx = 0.f, sy = 0.f, sz2 = 0.f;
   for (int e = lane; e < nr; e += kWave) {
     const float4 gv = grad[e];
-    const int j = clampi(e < kWave ? j0 : nrow[e], n);
+    const int j = clampi(e < kSpecRec ? j0 : nrow[e], n);
     unsafeAtomicAdd(out + 3 * j, -sign * gv.x);
     unsafeAtomicAdd(out + 3 * j + 1, -sign * gv.y);
     unsafeAtomicAdd(out + 3 * j + 2, -sign * gv.z);
