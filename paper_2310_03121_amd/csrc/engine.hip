@@ -325,7 +325,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   if (fused) {
     if (io.E) {
       StageTimer t(h, ST_ENERGY, st);
-      launch_energy(dims, P.nmol, io.off, xyzs, row, erow, h->eself, io.E, status, st);
+      launch_energy(dims, P.nmol, io.off, xyzs, erow, h->eself, io.E, status, st);
     }
   } else {
     // layer 2: H2 = CELU(H1 W1^T + b1)
@@ -351,7 +351,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     g.uprow = nullptr;
     if (io.E) {
       StageTimer t(h, ST_ENERGY, st);
-      launch_energy(dims, P.nmol, io.off, xyzs, row, erow, h->eself, io.E, status, st);
+      launch_energy(dims, P.nmol, io.off, xyzs, erow, h->eself, io.E, status, st);
     }
     if (need_bwd) {
       // delta2 = (delta3 W2) * CELU'(z2)

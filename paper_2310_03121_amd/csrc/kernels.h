@@ -25,7 +25,7 @@ struct GemmArgs {
   const float* w_out;  // EPI_HEAD: output-layer weights [S][N]
   int sWout;
   const float* b_out;  // [S]
-  float* erow;         // [rows] atomic energies (EPI_HEAD)
+  float* erow;         // [atoms] atomic energies in input atom order (EPI_HEAD)
   void* H3;            // optional store of the last hidden activation
   int ldh3;
   const int* perm;     // sorted row -> atom
@@ -47,7 +47,7 @@ struct MidArgs {
   const float* b2;                // [S][W3]
   const float* wout;              // [S][W3]
   const float* bout;              // [S]
-  float* erow;                    // [rows]
+  float* erow;                    // [atoms] atomic energies, input atom order
   bf16_t* D1;                     // [rows][W1]
   bf16_t* H2;                     // optional [rows][W2]
   bf16_t* H3;                     // optional [rows][W3]
@@ -90,7 +90,7 @@ void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt,
 void launch_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const int* hist,
                     int* row, int* perm, hipStream_t st);
 void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* xyzs,
-                   const int* row, const float* erow, const double* eself, double* E,
+                   const float* eatom, const double* eself, double* E,
                    uint32_t* status, hipStream_t st);
 void launch_fill_i32(int* p, int v, int n, hipStream_t st);
 void launch_fill_f32(float* p, float v, long n, hipStream_t st);

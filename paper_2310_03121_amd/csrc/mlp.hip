@@ -487,7 +487,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
       float e = a.b_out[s];
 #pragma unroll
       for (int q = 0; q < WN; ++q) e += part[q * BM + t];
-      if (row < row_end) a.erow[row] = e;
+      if (row < row_end) a.erow[a.perm[row]] = e;  // input atom order
       if (a.uprow) {
         float up = 0.f;
         if (row < row_end) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;

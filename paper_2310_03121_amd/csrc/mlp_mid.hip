@@ -202,7 +202,7 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
     float e = a.bout[s];
 #pragma unroll
     for (int q = 0; q < MidCfg<W3>::WN; ++q) e += epart[q * kMidBM + tid];
-    if (row < row_end) a.erow[row] = e;
+    if (row < row_end) a.erow[a.perm[row]] = e;  // input atom order
     if (a.uprow) {
       float up = 0.f;
       if (row < row_end) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;

@@ -181,27 +181,35 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ dims, i
   }
 }
 
-// One wave per molecule: E_m = sum_i (double)E_row[row[i]] + e_self[s_i].
+// One workgroup per molecule: E_m = sum_i (double)E_i + e_self[s_i], with the
+// atomic energies in input atom order.  Thread t sums the atoms t, t + 256,
+// ... of the molecule (counted from its first atom), then the waves and the
+// four wave sums combine in a fixed order: the result depends only on the
+// molecule's own atoms, not on where it sits in a batch.
 __global__ __launch_bounds__(256) void k_energy(const int* __restrict__ dims,
                                                 const int* __restrict__ off,
                                                 const float4* __restrict__ xyzs,
-                                                const int* __restrict__ row,
-                                                const float* __restrict__ erow,
+                                                const float* __restrict__ eatom,
                                                 const double* __restrict__ eself,
                                                 double* __restrict__ E, uint32_t* __restrict__ status) {
+  __shared__ double part[4];
   const int n = dims[0], nmol = dims[1];
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int m = blockIdx.x;
   if (m >= nmol) return;
   int a = off[m], b = off[m + 1];
   a = a < 0 ? 0 : (a > n ? n : a);
   b = b < a ? a : (b > n ? n : b);
   double acc = 0.0;
-  for (int i = a + lane_id(); i < b; i += kWave)
-    acc += (double)erow[row[i]] + eself[species_of(xyzs[i])];
+#pragma unroll 4
+  for (int i = a + (int)threadIdx.x; i < b; i += 256)
+    acc += (double)eatom[i] + eself[species_of(xyzs[i])];
   acc = wave_sum_d(acc);
-  if (lane_id() == 0) {
-    E[m] = acc;
-    if (!isfinite(acc)) atomicOr(status, kStNonFinite);
+  if (lane_id() == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double e = ((part[0] + part[1]) + part[2]) + part[3];
+    E[m] = e;
+    if (!isfinite(e)) atomicOr(status, kStNonFinite);
   }
 }
 
@@ -244,11 +252,11 @@ void launch_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const
 }
 
 void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* xyzs,
-                   const int* row, const float* erow, const double* eself, double* E,
-                   uint32_t* status, hipStream_t st) {
+                   const float* eatom, const double* eself, double* E, uint32_t* status,
+                   hipStream_t st) {
   if (nmol_cap <= 0) return;
-  hipLaunchKernelGGL(k_energy, dim3((nmol_cap + 3) / 4), dim3(256), 0, st, dims, off, xyzs, row,
-                     erow, eself, E, status);
+  hipLaunchKernelGGL(k_energy, dim3(nmol_cap), dim3(256), 0, st, dims, off, xyzs, eatom, eself, E,
+                     status);
 }
 
 void launch_fill_i32(int* p, int v, int n, hipStream_t st) {
