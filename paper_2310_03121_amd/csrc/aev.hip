@@ -87,16 +87,20 @@ __device__ __forceinline__ float pick(const float (&tab)[N], int idx) {
   return r;
 }
 
-// Unordered pair t of the list prefix [0, na) -> entries a < b (row-major:
-// pairs before row a number a*na - a*(a+1)/2).
+// Unordered pair t of the list prefix [0, na) -> entries a < b, row-major:
+// row r starts at pair r (2 na - r - 1) / 2.  The row is the floor of the
+// smaller root of that quadratic; the float square root (exact operands for
+// na <= 2048) can put it one row off either way near a row start, which one
+// compare-and-select step in each direction corrects.  Branch-free, so the
+// lanes of a pass never diverge.
 __device__ __forceinline__ void decode_pair(int t, int na, int& a, int& b) {
   const float c2 = (float)(2 * na - 1);
   int r = (int)((c2 - fast_sqrt(fmaxf(c2 * c2 - 8.f * (float)t, 0.f))) * 0.5f);
   r = r < 0 ? 0 : (r > na - 2 ? na - 2 : r);
-  while (r > 0 && r * na - r * (r + 1) / 2 > t) --r;
-  while (r + 1 <= na - 2 && (r + 1) * na - (r + 1) * (r + 2) / 2 <= t) ++r;
+  r = (r * (2 * na - r - 1)) >> 1 > t ? r - 1 : r;
+  r = (r + 1 <= na - 2 && ((r + 1) * (2 * na - r - 2)) >> 1 <= t) ? r + 1 : r;
   a = r;
-  b = t - (r * na - r * (r + 1) / 2) + r + 1;
+  b = t - ((r * (2 * na - r - 1)) >> 1) + r + 1;
 }
 
 __device__ __forceinline__ int pair_block(int p, int q, int S) {
@@ -112,7 +116,10 @@ constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
 typedef float aev_f32x4 __attribute__((ext_vector_type(4)));
 
 // acc += A * B for one 16 x 16 x 4 FP32 MFMA: lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16] and holds C[4 * (l / 16) + r][l % 16], r = 0..3.
+// and B[l / 16][l % 16] and holds C[4 * (l / 16) + r][l % 16], r = 0..3.  The
+// forward pass passes the terms as A and the one-hot as B, so C is the
+// transposed feature block: lane l holds features 4 (l / 16) .. +3 of
+// species (or block) l % 16, stored as one vector.
 __device__ __forceinline__ aev_f32x4 mfma4(float a, float b, aev_f32x4 acc) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
 }
@@ -173,13 +180,10 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
         term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x;
         hot = nsp[e] == l16 ? 1.f : 0.f;
       }
-      acc = mfma4(hot, term, acc);
+      acc = mfma4(term, hot, acc);
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int s = kq * 4 + r;
-      if (s < S) Store<OutT>::put(orow + s * kNR + l16, acc[r]);
-    }
+    if (l16 < S)
+      Store<OutT>::put4(orow + l16 * kNR + 4 * kq, make_float4(acc[0], acc[1], acc[2], acc[3]));
   }
 
   // ---- angular: G[blk][a z] = sum over unordered pairs of angular neighbors
@@ -216,25 +220,23 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
         h0 = blk == l16 ? 1.f : 0.f;
         h1 = blk == l16 + 16 ? 1.f : 0.f;
       }
-      c00 = mfma4(h0, b0, c00);
-      c01 = mfma4(h0, b1, c01);
-      if (nblk > 16) {
-        c10 = mfma4(h1, b0, c10);
-        c11 = mfma4(h1, b1, c11);
-      }
+      // h1 is zero unless there are more than 16 blocks; the two extra MFMAs
+      // cost less than a branch that keeps the accumulators apart
+      c00 = mfma4(b0, h0, c00);
+      c01 = mfma4(b1, h0, c01);
+      c10 = mfma4(b0, h1, c10);
+      c11 = mfma4(b1, h1, c11);
     }
-    OutT* ang = orow + S * kNR;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int b = kq * 4 + r;
-      if (b < nblk) {
-        Store<OutT>::put(ang + b * 32 + l16, c00[r]);
-        Store<OutT>::put(ang + b * 32 + 16 + l16, c01[r]);
-      }
-      if (b + 16 < nblk) {
-        Store<OutT>::put(ang + (b + 16) * 32 + l16, c10[r]);
-        Store<OutT>::put(ang + (b + 16) * 32 + 16 + l16, c11[r]);
-      }
+    // column c of c00 is feature c of the block (a = c / 8 for the low
+    // radial shifts, z = c % 8); c01 holds features 16 + c
+    OutT* ang = orow + S * kNR + l16 * 32 + 4 * kq;
+    if (l16 < nblk) {
+      Store<OutT>::put4(ang, make_float4(c00[0], c00[1], c00[2], c00[3]));
+      Store<OutT>::put4(ang + 16, make_float4(c01[0], c01[1], c01[2], c01[3]));
+    }
+    if (l16 + 16 < nblk) {
+      Store<OutT>::put4(ang + 512, make_float4(c10[0], c10[1], c10[2], c10[3]));
+      Store<OutT>::put4(ang + 528, make_float4(c11[0], c11[1], c11[2], c11[3]));
     }
   }
   for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
