@@ -75,18 +75,6 @@ constexpr int kSpecRec = 16;
 // correction steps) buys nothing here
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Per-lane entry of a table held in the (uniform) kernel arguments, by
-// unrolled selects: indexing the argument struct with a lane-dependent index
-// would copy it to scratch memory, and a table in global memory would add a
-// memory round trip to every wave.
-template <int N>
-__device__ __forceinline__ float pick(const float (&tab)[N], int idx) {
-  float r = tab[0];
-#pragma unroll
-  for (int k = 1; k < N; ++k) r = (idx == k) ? tab[k] : r;
-  return r;
-}
-
 // Unordered pair t of the list prefix [0, na) -> entries a < b, row-major:
 // row r starts at pair r (2 na - r - 1) / 2.  The row is the floor of the
 // smaller root of that quadratic; the float square root (exact operands for
@@ -170,7 +158,7 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   // as MFMA products of a one-hot (species x 4 neighbors) with the terms
   // (4 neighbors x 16 shifts); lane (kq, l16) computes neighbor kq, shift l16.
   {
-    const float Rm = pick(C.shf_r, l16);
+    const float Rm = C.lane_tab[l16];
     aev_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int e0 = 0; e0 < nr; e0 += 4) {
       const int e = e0 + kq;
@@ -195,7 +183,7 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
     const int T = na * (na - 1) / 2;
     const int nblk = S * (S + 1) / 2;
     const int z = l16 & 7, ah = l16 >> 3;
-    const float cz = pick(C.cos_z, z), sz = pick(C.sin_z, z);
+    const float cz = C.lane_tab[kNR + z], sz = C.lane_tab[kNR + kNZ + z];
     const float ra_lo = ah ? C.shf_a[1] : C.shf_a[0];
     const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
     aev_f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
@@ -299,7 +287,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   // ---- radial: dE/dr_ij per neighbor, reduced over the 16 shift lanes
   {
     const int gq = lane >> 4, m = lane & 15;
-    const float Rm = pick(C.shf_r, m);
+    const float Rm = C.lane_tab[m];
     for (int e0 = 0; e0 < nr; e0 += 4) {
       const int e = e0 + gq;
       float contrib = 0.f;
@@ -311,8 +299,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
         const float ex = C.cR * fast_exp2(-C.eta_r_l2e * u * u);
         contrib = Store<GT>::get(grow + nsp[e] * kNR + m) * ex * (f.z - C.eta_r2 * u * f.x);
       }
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) contrib += __shfl_xor(contrib, o, 64);
+      contrib = group16_sum(contrib);
       if (e < nr && m == 0) {
         const float sc = contrib * fast_rcp(v.w);
         grad[e] = make_float4(v.x * sc, v.y * sc, v.z * sc, 0.f);
@@ -324,7 +311,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   // ---- angular: lanes (t, z), eight unordered pairs per pass
   {
     const int tz = lane & 7, tg = lane >> 3;
-    const float cz = pick(C.cos_z, tz), sz = pick(C.sin_z, tz);
+    const float cz = C.lane_tab[kNR + tz], sz = C.lane_tab[kNR + kNZ + tz];
     const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
     const int T = na * (na - 1) / 2;
     const GT* gang = grow + S * kNR + tz;
@@ -362,12 +349,9 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
         X1 = f1 * A1 * C.eta_a;
         Xc = df1 * A0;
       }
-#pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
-        X0 += __shfl_xor(X0, o, 64);
-        X1 += __shfl_xor(X1, o, 64);
-        Xc += __shfl_xor(Xc, o, 64);
-      }
+      X0 = group8_sum(X0);
+      X1 = group8_sum(X1);
+      Xc = group8_sum(Xc);
       if (t < T && tz == 0) {
         const float fcc = fj * fk;
         const float dEdc = Xc * fcc;

@@ -44,6 +44,9 @@ struct AevConst {
   float shf_a[kNA];
   float cos_z[kNZ];
   float sin_z[kNZ];
+  // device copy of shf_r, cos_z, sin_z (kNR + 2 kNZ floats): per-lane
+  // constants are one cached load each instead of a select chain
+  const float* lane_tab;
 };
 
 // Periodic-box description (orthorhombic).  ncell[d] == 1 means that
@@ -90,6 +93,27 @@ __device__ __forceinline__ float wave_sum_rows(float v) {
          __int_as_float(__builtin_amdgcn_readlane(b, 31)) +
          __int_as_float(__builtin_amdgcn_readlane(b, 47)) +
          __int_as_float(__builtin_amdgcn_readlane(b, 63));
+}
+
+// Butterfly sums over groups of 8 and 16 consecutive lanes by DPP (all
+// lanes active), the same pairing as exchanges at lane distance 1, 2, 4 (and
+// 8): swaps inside quads, then the half-row and row mirrors, which pair each
+// lane with one of the other quad (half-row).  Every lane of a group gets the
+// group's sum, with the same rounding in every lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp_get(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float group8_sum(float v) {
+  v += dpp_get<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_get<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_get<0x141>(v);  // row_half_mirror
+  return v;
+}
+__device__ __forceinline__ float group16_sum(float v) {
+  v = group8_sum(v);
+  v += dpp_get<0x140>(v);  // row_mirror
+  return v;
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {

@@ -531,6 +531,7 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
   const size_t o_bout = take((size_t)S * 4);
   const size_t o_eself = take(kMaxS * 8);
   const size_t o_poff = take((size_t)kLayers * S * 8);
+  const size_t o_lane = take((size_t)(kNR + 2 * kNZ) * 4);
   if (hipMalloc(&h->dmem, bytes) != hipSuccess) {
     delete h;
     return NNP_E_OOM;
@@ -548,6 +549,13 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
   h->bout = reinterpret_cast<float*>(h->dmem + o_bout);
   h->eself = reinterpret_cast<double*>(h->dmem + o_eself);
   h->param_off_dev = reinterpret_cast<long*>(h->dmem + o_poff);
+  C.lane_tab = reinterpret_cast<const float*>(h->dmem + o_lane);
+  float lane_host[kNR + 2 * kNZ];
+  for (int m = 0; m < kNR; ++m) lane_host[m] = C.shf_r[m];
+  for (int z = 0; z < kNZ; ++z) {
+    lane_host[kNR + z] = C.cos_z[z];
+    lane_host[kNR + kNZ + z] = C.sin_z[z];
+  }
 
   double es[kMaxS] = {};
   for (int s = 0; s < S; ++s) es[s] = mlp->self_energy ? mlp->self_energy[s] : 0.0;
@@ -556,7 +564,9 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
     for (int s = 0; s < S; ++s) po[(size_t)l * S + s] = h->param_off[s][l];
   bool ok = hip_ok(hipMemcpy(h->flat, mlp->params, o * 4, hipMemcpyHostToDevice)) &&
             hip_ok(hipMemcpy(h->eself, es, sizeof(es), hipMemcpyHostToDevice)) &&
-            hip_ok(hipMemcpy(h->param_off_dev, po.data(), po.size() * 8, hipMemcpyHostToDevice));
+            hip_ok(hipMemcpy(h->param_off_dev, po.data(), po.size() * 8, hipMemcpyHostToDevice)) &&
+            hip_ok(hipMemcpy(const_cast<float*>(C.lane_tab), lane_host, sizeof(lane_host),
+                             hipMemcpyHostToDevice));
   if (ok) ok = nnp_set_params_device(h, h->flat, nullptr) == NNP_OK &&
                hip_ok(hipDeviceSynchronize());
   if (!ok) {

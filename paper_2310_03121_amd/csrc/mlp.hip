@@ -474,11 +474,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        float v = epart[i][e];
-        v += __shfl_xor(v, 1, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 8, 64);
+        const float v = group16_sum(epart[i][e]);
         if (rl == 0) part[wn * BM + wm * WTM + i * 16 + rq + e] = v;
       }
     __syncthreads();
