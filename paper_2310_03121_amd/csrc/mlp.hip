@@ -67,15 +67,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
   const T* A = reinterpret_cast<const T*>(a.A);
   const T* B = reinterpret_cast<const T*>(a.Bq) + (size_t)s * a.sB;
 
+  // A is read through a buffer resource that spans exactly the tile's valid
+  // rows: loads of pad rows, and of columns past K (sent past the range),
+  // return zeros in hardware.  So no load sits behind a branch, which would
+  // make the compiler assume it may not have been issued and let every later
+  // wait for the weight ring also wait for one more ring slot.
+  const __amdgpu_buffer_rsrc_t arsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<T*>(A + (size_t)row0 * a.lda), (short)0,
+      (row_end - row0) * a.lda * (int)sizeof(T), kBufferRsrcWord3);
   auto aload = [&](int c, uint4 (&ra)[NVA]) __attribute__((always_inline)) {
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * NT;
       const int r = idx / VPR, k = c * KC + (idx % VPR) * (16 / (int)sizeof(T));
-      uint4 val = make_uint4(0, 0, 0, 0);
-      if (row0 + r < row_end && k < K)
-        val = *reinterpret_cast<const uint4*>(A + (size_t)(row0 + r) * a.lda + k);
-      ra[v] = val;
+      const unsigned off = k < K ? (unsigned)((r * a.lda + k) * (int)sizeof(T)) : kOutOfRange;
+      const u32x4_t val = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
+      ra[v] = make_uint4(val[0], val[1], val[2], val[3]);
     }
   };
   auto astore = [&](int buf, const uint4 (&ra)[NVA]) __attribute__((always_inline)) {

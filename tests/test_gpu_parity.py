@@ -123,6 +123,34 @@ def test_energy_forces_bf16(name):
     _check_ef(name, "bf16", 1e-2, 1e-2)
 
 
+@pytest.mark.parametrize("prec,f_tol,e_tol", [("fp32", 1e-5, 1e-5), ("bf16", 1e-2, 1e-2)])
+def test_energy_forces_five_elements(prec, f_tol, e_tol):
+    """Five elements (560 features, 576 padded) and hidden widths 224/160/96:
+    the first layer's K is not a multiple of the 128-column A chunk, widths
+    that are not multiples of 64 take the 32-row wave layout, and no fused
+    middle kernel exists for these widths."""
+    base = w.conformer_batch(24, 40, seed=3)
+    sp = np.random.default_rng(11).integers(0, 5, base.n_atoms).astype(np.int32)
+    s = w.System(base.pos, sp, base.mol_offsets, None, 5, "five-elements")
+    at = w.aev_table(5)
+    mt = w.mlp_table(5, widths=(560, 224, 160, 96, 1))
+    announce(f"five elements {prec} N={s.n_atoms}")
+    pot, _, _ = potential(5, prec, aev=at, mlp=mt)
+    pos, spd, off = to_dev(s)
+    E, F = pot.energy_forces(pos, spd, off, None)
+    pot.check()
+    E = E.cpu().numpy()
+    F = F.cpu().numpy()
+    r = o.energy_forces(s, aev_table=at, mlp_table=mt)
+    scale = np.array([np.abs(r.E_atom[s.mol_offsets[m]:s.mol_offsets[m + 1]]).sum()
+                      for m in range(s.n_mol)])
+    de = np.abs(E - r.E) / np.maximum(scale, 1e-30)
+    fr = rel_rms(F, r.F)
+    print(f"{prec}: max |dE|/sum|E_i| {de.max():.3e}  force rel-RMS {fr:.3e}")
+    assert de.max() <= e_tol
+    assert fr <= f_tol
+
+
 def test_full_batch_512x64():
     s = w.config_system(1)
     announce(f"full batch 512x64 N={s.n_atoms}")
