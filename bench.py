@@ -102,11 +102,12 @@ def profiled_traffic(stage, workload_key):
     return rows[stage]
 
 
-WORKLOAD_KEYS = {"batch": "batch512x64", "water1500": "water1500", "water7667": "water7667"}
+WORKLOAD_KEYS = {"batch": "batch512x64", "water1500": "water1500", "water7667": "water7667",
+                 "mol24": "mol24"}
 # Neighbor-list capacity per atom (the handle's max_neighbors): the batch's
 # longest list is 14 entries, the water boxes' 71.  Overflow is detected on
 # the device and reported, never silently truncated.
-MAX_NEIGHBORS = {"batch": 64, "water1500": 128, "water7667": 128}
+MAX_NEIGHBORS = {"batch": 64, "water1500": 128, "water7667": 128, "mol24": 64}
 
 
 def workload(name):
@@ -117,6 +118,8 @@ def workload(name):
         return w.config_system(2), 4, "1,500-water box (4,500 atoms), L=35.5 A, 4 elements, 384 features"
     if name == "water7667":
         return w.config_system(4), 7, "7,667-water box (23,001 atoms), L=61.2 A, 7 elements, 1008 features"
+    if name == "mol24":
+        return w.config_system(0), 4, "one 24-atom molecule, 4 elements, 384 features, no box"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -154,6 +157,105 @@ def time_path(pot, pos, sp, off, box, steps, warmup):
     stages = pot.profile_read()
     pot.profile(False)
     return dt, dt_graph, out, stages
+
+
+def latency_leg(pot, pos, sp, off, box, n_evals=1000, warmup=50):
+    """Per-evaluation latency: each captured evaluation is launched and waited
+    for on its own (median and p99 over n_evals, after warm-up)."""
+    g = pot.capture(pos, sp, off, box)
+    for _ in range(warmup):
+        g.launch()
+    g.synchronize()
+    lat = np.empty(n_evals)
+    for k in range(n_evals):
+        t0 = time.perf_counter()
+        g.launch()
+        g.synchronize()
+        lat[k] = time.perf_counter() - t0
+    g.check()
+    del g
+    return {"evals": n_evals, "warmup": warmup, "median_us": float(np.median(lat) * 1e6),
+            "p99_us": float(np.percentile(lat, 99) * 1e6), "launch": "graph replay, synchronized"}
+
+
+def nve_leg(pot, s, n_steps=1000, dt=0.5, every=10, seed=4):
+    """NVE velocity Verlet from Maxwell-Boltzmann velocities at 300 K: total
+    energy sampled every `every` steps; drift is the least-squares slope of
+    E_tot(t), plus the largest excursion from the first sample, both per atom."""
+    import torch
+    import workloads as w
+    dev = torch.device("cuda:0")
+    m = w.MASS_AMU[s.species]
+    v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(seed))
+    x = torch.from_numpy(s.pos.astype(np.float64)).to(dev)
+    v = torch.from_numpy(v0).to(dev)
+    md = torch.from_numpy(m).to(dev)
+    sp = torch.from_numpy(s.species).to(dev)
+    off = torch.from_numpy(s.mol_offsets).to(dev)
+    E0, F = pot.energy_forces(x.float(), sp, off, s.box)
+    # E_tot as the integrator reports it (potential + kinetic after each
+    # chunk of steps); the series starts after the first chunk
+    t, tot, ek = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n_steps // every):
+        Ep, Ek = pot.md_steps(x, v, F, md, sp, off, dt, every, s.box)
+        t.append((k + 1) * every * dt)
+        tot.append(float(Ep.sum().item()) + float(Ek.sum().item()))
+        ek.append(float(Ek.sum().item()))
+    wall = time.perf_counter() - t0
+    pot.check()
+    t = np.array(t) * 1e-3  # ps
+    e = (np.array(tot) - tot[0]) * 1e3 / s.n_atoms  # meV per atom
+    slope = float(np.polyfit(t, e, 1)[0])
+    return {"steps": n_steps, "dt_fs": dt, "sample_every": every,
+            "drift_meV_per_ps_per_atom": slope, "max_abs_dev_meV_per_atom": float(np.abs(e).max()),
+            "kinetic_energy_eV_first_last_sample": [ek[0], ek[-1]],
+            "ms_per_step": wall * 1e3 / n_steps}
+
+
+def ceilings():
+    """Device ceilings measured here: a large device copy, large square GEMMs
+    (hipBLASLt through torch) in BF16 and FP32, and library GEMMs at the
+    network's own layer shapes for comparison with the fused kernels."""
+    import torch
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3  # s
+
+    out = {}
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dt = timed(lambda: dst.copy_(src), 20)
+    out["copy_GBps"] = 2 * src.numel() / dt / 1e9
+    del src, dst
+    for dtype, name, n in ((torch.bfloat16, "bf16", 8192), (torch.float32, "fp32", 8192)):
+        a = torch.randn(n, n, device="cuda", dtype=dtype)
+        b = torch.randn(n, n, device="cuda", dtype=dtype)
+        dt = timed(lambda: a @ b, 10)
+        out[f"gemm_{name}_{n}^3_TFLOPs"] = 2 * n ** 3 / dt / 1e12
+        del a, b
+    shapes = []
+    for M, K, N in ((32768, 1024, 256), (32768, 256, 192), (32768, 192, 160), (32768, 160, 192),
+                    (32768, 192, 256), (32768, 256, 1024)):
+        a = torch.randn(M, K, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(K, N, device="cuda", dtype=torch.bfloat16)
+        dt = timed(lambda: a @ b, 30)
+        shapes.append({"M": M, "K": K, "N": N, "us": dt * 1e6})
+        del a, b
+    out["library_bf16_gemm_at_layer_shapes"] = shapes
+    torch.cuda.empty_cache()
+    return out
 
 
 def serve_leg(pot, reqs, rate=None, max_atoms=8192, max_mols=256):
@@ -259,6 +361,11 @@ def main():
                     help="first run a plain 512 MiB device copy (a known-size reference for "
                          "hardware byte counters)")
     ap.add_argument("--precision", default="both", choices=("both", "bf16", "fp32"))
+    ap.add_argument("--nve", type=int, default=None,
+                    help="NVE steps of the drift leg (default 1000 for water7667, else off)")
+    ap.add_argument("--nve-dt", type=float, default=0.5, help="time step of the drift leg, fs")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="also measure copy bandwidth and library GEMM rates on this device")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is measured on one GPU's share "
@@ -305,6 +412,11 @@ def main():
             r["energy_max_abs_err_eV"] = float(np.max(np.abs(E.cpu().numpy() - ref.E)))
         if prec == precs[0]:
             r["pairs"], r["triples"] = pair_counts(pot, s.n_atoms)
+        if args.workload == "mol24":
+            r["latency"] = latency_leg(pot, pos, sp, off, box)
+        n_nve = args.nve if args.nve is not None else (1000 if args.workload == "water7667" else 0)
+        if n_nve:
+            r["nve"] = nve_leg(pot, s, n_steps=n_nve, dt=args.nve_dt)
         results[prec] = r
         del pot
         torch.cuda.empty_cache()
@@ -362,10 +474,15 @@ def main():
         "mlp_path_frac_of_peak": path_tflops / PEAK_TFLOPS[main_prec],
         "roofline": roof,
     }
+    for k in ("latency", "nve"):
+        if k in main_r:
+            out[k] = main_r[k]
     if not args.no_serve:
         sv = serving(w.aev_table(7), w.mlp_table(7))
         out["serving"] = sv
         out["p99_latency_ms_bf16_0.8mu"] = sv["bf16"]["open_loop_0.8mu"]["p99_ms"]
+    if args.ceilings:
+        out["ceilings"] = ceilings()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, S)
     print(json.dumps(out))
