@@ -15,7 +15,8 @@ Model Support"):
 * ``neighbors``  pair sets under the float32 distance predicate;
 * ``aev``        radial and angular atomic environment vectors;
 * ``mlp``        per-element networks with CELU, energies and their adjoint;
-* ``potential``  energy per molecule, analytic forces, weight gradients;
+* ``potential``  energy per molecule, analytic forces, weight gradients,
+                 and the mean over an ensemble of networks;
 * ``integrator`` velocity-Verlet MD in eV, A, amu and fs.
 
 Every function is plain float64 NumPy with no blocking or fusion.
@@ -23,12 +24,13 @@ Every function is plain float64 NumPy with no blocking or fusion.
 from .neighbors import pair_list, pair_list_loops
 from .aev import aev, aev_backward, pair_block_index, n_features
 from .mlp import celu, celu_grad, mlp_forward, mlp_backward_input, mlp_weight_grads
-from .potential import energy_forces, energy, weight_gradients, EFResult
+from .potential import energy_forces, energy, weight_gradients, EFResult, ensemble_energy_forces
 from .integrator import velocity_verlet, kinetic_energy
 
 __all__ = [
     "pair_list", "pair_list_loops", "aev", "aev_backward", "pair_block_index",
     "n_features", "celu", "celu_grad", "mlp_forward", "mlp_backward_input",
     "mlp_weight_grads", "energy_forces", "energy", "weight_gradients", "EFResult",
+    "ensemble_energy_forces",
     "velocity_verlet", "kinetic_energy",
 ]

@@ -99,3 +99,43 @@ def weight_gradients(sys_or_pos, species=None, mol_offsets=None, box=None, *,
     g = mlp_backward_input(mc, up, mlp_table)
     dpos = aev_backward(g, ac)
     return np.concatenate(parts), dpos
+
+
+def ensemble_energy_forces(sys_or_pos, species=None, mol_offsets=None, box=None, *,
+                           aev_table, mlp_tables, forces: bool = True) -> EFResult:
+    """Ensemble of independently trained networks over one set of symmetry
+    functions (Results, "Performance of MLPs": ANI-2x averages eight models,
+    Table 3 times the ensemble against a single member).  The ensemble energy
+    is the mean of the members' energies, so its forces are the mean of the
+    members' forces; by linearity the adjoint of the symmetry functions is
+    applied once, to the mean of the members' dE/dG.  Self energies are the
+    first member's (members share them)."""
+    if species is None:
+        s = sys_or_pos
+        pos, species, mol_offsets, box = s.pos, s.species, s.mol_offsets, s.box
+    else:
+        pos = sys_or_pos
+    M = len(mlp_tables)
+    if M < 1:
+        raise ValueError("an ensemble needs at least one member")
+    for t in mlp_tables:
+        _check(species, aev_table, t)
+    N = pos.shape[0]
+    mol = _mol_index(mol_offsets, N)
+    n_mol = len(mol_offsets) - 1
+    G, ac = aev(pos, species, mol_offsets, box, aev_table)
+    Ea = np.zeros(N)
+    g = None
+    for t in mlp_tables:
+        Ea_k, mc = mlp_forward(G, species, t)
+        Ea += Ea_k
+        if forces:
+            g_k = mlp_backward_input(mc, np.ones(N), t)
+            g = g_k if g is None else g + g_k
+    Ea /= M
+    Etot = Ea + mlp_tables[0].self_energy[np.asarray(species)]
+    E = np.bincount(mol, weights=Etot, minlength=n_mol)
+    F = None
+    if forces:
+        F = -aev_backward(g / M, ac)
+    return EFResult(E, F, Ea, G)

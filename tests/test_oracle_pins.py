@@ -459,3 +459,56 @@ def test_golden_regression_c0():
     r = o.energy_forces(s, aev_table=w.aev_table(4), mlp_table=w.mlp_table(4))
     assert abs(r.E[0] - ref["E"][0]) < 1e-12 * abs(ref["E"][0])
     np.testing.assert_allclose(r.F, np.array(ref["F"]), rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- ensembles
+def _ens_case():
+    s = w.single_molecule(24, seed=0, n_species=4)
+    at = w.aev_table(4)
+    members = [w.mlp_table(4, seed=100 + k) for k in range(3)]
+    return s, at, members
+
+
+def test_ensemble_of_one_is_the_model():
+    s, at, (m0, _, _) = _ens_case()
+    a = o.energy_forces(s, aev_table=at, mlp_table=m0)
+    b = o.ensemble_energy_forces(s, aev_table=at, mlp_tables=[m0])
+    assert np.array_equal(a.E, b.E) and np.array_equal(a.F, b.F)
+
+
+def test_ensemble_of_identical_copies_is_the_model():
+    s, at, (m0, _, _) = _ens_case()
+    a = o.energy_forces(s, aev_table=at, mlp_table=m0)
+    b = o.ensemble_energy_forces(s, aev_table=at, mlp_tables=[m0, m0, m0])
+    np.testing.assert_allclose(b.E, a.E, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(b.F, a.F, rtol=1e-13, atol=1e-15)
+
+
+def test_ensemble_is_the_mean_of_separate_evaluations():
+    # each member evaluated on its own (own symmetry functions, own adjoint)
+    s, at, members = _ens_case()
+    sep = [o.energy_forces(s, aev_table=at, mlp_table=m) for m in members]
+    ens = o.ensemble_energy_forces(s, aev_table=at, mlp_tables=members)
+    E = sum(r.E for r in sep) / 3
+    F = sum(r.F for r in sep) / 3
+    np.testing.assert_allclose(ens.E, E, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(ens.F, F, rtol=1e-11, atol=1e-12)
+    # and it differs from every member (the members really differ)
+    assert all(np.abs(r.E - ens.E).max() > 1e-3 for r in sep)
+
+
+def test_ensemble_with_negated_twin_cancels_exactly():
+    # a member whose output layer is negated gives -E_i exactly: the mean of
+    # the pair leaves only the self energies, and no force at all
+    s, at, (m0, _, _) = _ens_case()
+    se = np.array([-0.6, -38.0, -54.7, -75.2])
+    m0 = w.MLPTable(m0.widths, m0.W, m0.b, se, m0.celu_alpha)
+    Wn = [[W.copy() for W in ws] for ws in m0.W]
+    bn = [[b.copy() for b in bs] for bs in m0.b]
+    for sp in range(4):
+        Wn[sp][-1] = -Wn[sp][-1]
+        bn[sp][-1] = -bn[sp][-1]
+    twin = w.MLPTable(m0.widths, Wn, bn, se, m0.celu_alpha)
+    r = o.ensemble_energy_forces(s, aev_table=at, mlp_tables=[m0, twin])
+    assert np.all(r.E_atom == 0.0) and np.all(r.F == 0.0)
+    np.testing.assert_allclose(r.E, [se[s.species].sum()], rtol=1e-15)
