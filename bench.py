@@ -214,6 +214,43 @@ def nve_leg(pot, s, n_steps=1000, dt=0.5, every=10, seed=4):
             "ms_per_step": wall * 1e3 / n_steps}
 
 
+def ensemble_leg(s, at, S, args, single):
+    """The same workload with an ensemble of M networks (seeds 101.. for 7
+    elements, 100.. for 4): mean energy and forces, one neighbor search and
+    one symmetry-function pass per evaluation.  Reports the time per
+    evaluation and its ratio to the single network measured above, plus the
+    force error against the FP64 ensemble oracle."""
+    import torch
+    import oracle
+    import workloads as w
+    from paper_2310_03121_amd import Potential
+    M = args.ensemble
+    base = 101 if S == 7 else 100
+    members = [w.mlp_table(S, seed=base + k) for k in range(M)]
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(s.pos).to(dev)
+    sp = torch.from_numpy(s.species).to(dev)
+    off = torch.from_numpy(s.mol_offsets).to(dev)
+    ref = None if args.no_oracle else oracle.ensemble_energy_forces(s, aev_table=at,
+                                                                     mlp_tables=members)
+    out = {"members": M}
+    for prec in single:
+        pot = Potential.ensemble_from_tables(at, members, precision=prec,
+                                             max_neighbors=MAX_NEIGHBORS[args.workload])
+        dt_e, dt_g, (E, F), _ = time_path(pot, pos, sp, off, s.box, args.steps, args.warmup)
+        dt = min(dt_e, dt_g)
+        r = {"ms_per_step": 1e3 * dt / args.steps, "value": s.n_atoms * args.steps / dt,
+             "ratio_to_single": (1e3 * dt / args.steps) / single[prec]["ms_per_step"]}
+        if ref is not None:
+            Fn = F.cpu().numpy().astype(np.float64)
+            r["force_rel_rms"] = float(np.linalg.norm(Fn - ref.F) / np.linalg.norm(ref.F))
+            r["force_rmse_eV_per_A"] = float(np.sqrt(np.mean((Fn - ref.F) ** 2)))
+        out[prec] = r
+        del pot
+        torch.cuda.empty_cache()
+    return out
+
+
 def ceilings():
     """Device ceilings measured here: a large device copy, large square GEMMs
     (hipBLASLt through torch) in BF16 and FP32, and library GEMMs at the
@@ -364,6 +401,8 @@ def main():
     ap.add_argument("--nve", type=int, default=None,
                     help="NVE steps of the drift leg (default 1000 for water7667, else off)")
     ap.add_argument("--nve-dt", type=float, default=0.5, help="time step of the drift leg, fs")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="also time an ensemble of this many networks (BF16 and FP32)")
     ap.add_argument("--ceilings", action="store_true",
                     help="also measure copy bandwidth and library GEMM rates on this device")
     args = ap.parse_args()
@@ -481,6 +520,8 @@ def main():
         sv = serving(w.aev_table(7), w.mlp_table(7))
         out["serving"] = sv
         out["p99_latency_ms_bf16_0.8mu"] = sv["bf16"]["open_loop_0.8mu"]["p99_ms"]
+    if args.ensemble > 1:
+        out["ensemble"] = ensemble_leg(s, at, S, args, results)
     if args.ceilings:
         out["ceilings"] = ceilings()
     if not args.no_cpu:

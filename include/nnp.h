@@ -116,13 +116,30 @@ typedef struct {
  * unsupported layout, NNP_E_OOM / NNP_E_HIP on device failures. */
 nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
                       nnp_precision precision, nnp_handle** out);
+
+/* An ensemble of n_models (1..8) independently trained networks over one set
+ * of symmetry functions (Results, "Performance of MLPs": ANI-2x averages
+ * eight models; Table 3 times the ensemble against a single member).
+ * `mlps` is host memory, n_models entries with identical n_layers, widths
+ * and celu_alpha (else NNP_E_INVALID); self energies are taken from mlps[0].
+ * Every evaluation call then returns the ensemble mean: E_m is the mean of
+ * the members' molecular energies and the forces are the mean of their
+ * forces.  Neighbor lists and symmetry functions are computed once per
+ * evaluation, the networks run member by member, and the members' dE/dG are
+ * summed inside one product before the symmetry-function adjoint, which runs
+ * once.  nnp_create(aev, mlp, p, out) is nnp_create_ensemble(aev, mlp, 1, p,
+ * out).  Weight gradients (nnp_backward with dL_dparams) need n_models == 1. */
+nnp_status nnp_create_ensemble(const nnp_aev_params* aev, const nnp_mlp_params* mlps,
+                               int32_t n_models, nnp_precision precision, nnp_handle** out);
 void nnp_destroy(nnp_handle* h);
 
-/* Number of float32 network parameters (the length of `params`). */
+/* Number of float32 network parameters (the length of `params`; for an
+ * ensemble, the members' vectors one after the other). */
 size_t nnp_param_count(const nnp_handle* h);
 
 /* Replaces the network weights from a device vector in the `params` layout
- * (float32, nnp_param_count() entries); enqueued on `stream`. */
+ * (float32, nnp_param_count() entries; ensembles: all members, member-major);
+ * enqueued on `stream`. */
 nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* stream);
 
 /* Neighbor-list capacity per atom (default 128, range 16..512, rounded up to

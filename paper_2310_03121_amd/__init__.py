@@ -35,6 +35,8 @@ class Potential:
     Parameters are plain arrays: the radial/angular shift tables and scalars
     of the symmetry functions, the layer widths, and the flat float32
     parameter vector (per species, per layer: W row-major out x in, then b).
+    A list of parameter vectors makes an ensemble of networks that share the
+    widths and self energies; evaluations then return the ensemble mean.
     """
 
     def __init__(self, *, n_species, rc_rad, eta_r, shf_r, rc_ang, eta_a, zeta, shf_a, shf_z,
@@ -54,18 +56,25 @@ class Potential:
                             shf_z.size, _f32p(shf_z), float(radial_prefactor),
                             float(angle_cos_scale))
         w = np.ascontiguousarray(self.widths, np.int32)
-        p = np.ascontiguousarray(params, np.float32)
+        members = list(params) if isinstance(params, (list, tuple)) else [params]
+        ps = [np.ascontiguousarray(m, np.float32) for m in members]
+        self.n_models = len(ps)
         es = None if self_energy is None else np.ascontiguousarray(self_energy, np.float64)
-        mp = capi.MlpParams(len(self.widths) - 1, w.ctypes.data_as(C.POINTER(C.c_int32)),
-                            float(celu_alpha), _f32p(p),
-                            None if es is None else es.ctypes.data_as(C.POINTER(C.c_double)))
+        self._keep += [w, es] + ps
+        mps = (capi.MlpParams * len(ps))(*[
+            capi.MlpParams(len(self.widths) - 1, w.ctypes.data_as(C.POINTER(C.c_int32)),
+                           float(celu_alpha), _f32p(p),
+                           None if es is None else es.ctypes.data_as(C.POINTER(C.c_double)))
+            for p in ps])
         prec = NNP_MLP_BF16 if precision == "bf16" else NNP_MLP_FP32
         h = C.c_void_p()
-        capi.check(self._lib.nnp_create(C.byref(ap), C.byref(mp), prec, C.byref(h)), "nnp_create")
+        capi.check(self._lib.nnp_create_ensemble(C.byref(ap), mps, len(ps), prec, C.byref(h)),
+                   "nnp_create_ensemble")
         self._h = h
         self.n_params = int(self._lib.nnp_param_count(h))
-        if p.size != self.n_params:
-            raise ValueError(f"params has {p.size} entries, expected {self.n_params}")
+        if sum(p.size for p in ps) != self.n_params:
+            raise ValueError(f"params have {sum(p.size for p in ps)} entries, "
+                             f"expected {self.n_params}")
         if max_neighbors != 128:
             capi.check(self._lib.nnp_set_max_neighbors(h, int(max_neighbors)), "set_max_neighbors")
         self.max_neighbors = int(max_neighbors)
@@ -81,6 +90,19 @@ class Potential:
                    angle_cos_scale=aev.angle_cos_scale, widths=mlp.widths, params=mlp.flat(),
                    celu_alpha=mlp.celu_alpha, self_energy=mlp.self_energy, precision=precision,
                    **kw)
+
+    @classmethod
+    def ensemble_from_tables(cls, aev, mlps, precision="fp32", **kw):
+        """An ensemble of networks (``workloads.MLPTable`` objects with equal
+        widths) over one set of symmetry functions; self energies from the
+        first member."""
+        m0 = mlps[0]
+        return cls(n_species=aev.n_species, rc_rad=aev.rc_rad, eta_r=aev.eta_r, shf_r=aev.shf_r,
+                   rc_ang=aev.rc_ang, eta_a=aev.eta_a, zeta=aev.zeta, shf_a=aev.shf_a,
+                   shf_z=aev.shf_z, radial_prefactor=aev.radial_prefactor,
+                   angle_cos_scale=aev.angle_cos_scale, widths=m0.widths,
+                   params=[m.flat() for m in mlps], celu_alpha=m0.celu_alpha,
+                   self_energy=m0.self_energy, precision=precision, **kw)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -48,6 +48,8 @@ _P = C.c_void_p
 _I = C.c_int32
 _SIGS = [
     ("nnp_create", C.c_int, [C.POINTER(AevParams), C.POINTER(MlpParams), C.c_int, C.POINTER(_P)]),
+    ("nnp_create_ensemble", C.c_int, [C.POINTER(AevParams), C.POINTER(MlpParams), _I, C.c_int,
+                                      C.POINTER(_P)]),
     ("nnp_destroy", None, [_P]),
     ("nnp_param_count", C.c_size_t, [_P]),
     ("nnp_set_params_device", C.c_int, [_P, _P, _P]),

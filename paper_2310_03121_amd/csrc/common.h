@@ -11,6 +11,7 @@ constexpr int kNR = 16;       // radial shifts per species block
 constexpr int kNA = 4;        // angular radial shifts
 constexpr int kNZ = 8;        // angle shifts
 constexpr int kMaxS = 8;      // species supported
+constexpr int kMaxModels = 8; // ensemble members supported
 constexpr int kPad = 128;     // species groups start at multiples of this row count
 constexpr int kLayers = 4;    // Linear layers per element network
 

@@ -31,8 +31,9 @@ struct nnp_handle {
   int width[kLayers + 1] = {};
   float alpha = 0.1f;
   int max_nbr = 128;
-  size_t n_params = 0;
-  long param_off[kMaxS][kLayers] = {};  // flat offset of W for (species, layer)
+  int n_models = 1;                     // ensemble members (weight slot = member * S + element)
+  size_t n_params = 0;                  // all members
+  long param_off[kMaxModels * kMaxS][kLayers] = {};  // flat offset of W for (slot, layer)
   char* dmem = nullptr;
   float* flat = nullptr;
   float* Wf[kLayers] = {};     // row-major W and W^T (LDS-staged kernels)
@@ -41,6 +42,8 @@ struct nnp_handle {
   bf16_t* Wqb[kLayers] = {};   // fragment order, W and W^T (BF16 body kernels)
   bf16_t* WTqb[kLayers] = {};
   float* bias[kLayers] = {};
+  float* WT0cf = nullptr;      // ensembles: member-concatenated W_0^T (dE/dG in one product)
+  bf16_t* WT0cq = nullptr;
   float* wout = nullptr;
   float* bout = nullptr;
   double* eself = nullptr;
@@ -180,9 +183,9 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B) {
   P.H3 = take(R * w3 * esz);
   P.D3 = take(R * w3 * esz);
   P.D2 = take(R * w2 * esz);
-  P.D1 = take(R * w1 * esz);
+  P.D1 = take(R * w1 * h->n_models * esz);  // members side by side in each row
   P.G = take(R * h->Fp * esz);
-  P.erow = take(R * 4);
+  P.erow = take(R * 4 * h->n_models);
   P.uprow = take(R * 4);
   size_t maxlen = 0;
   for (int l = 0; l < kLayers; ++l) {
@@ -278,102 +281,138 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     Wq[l] = bf ? (const void*)h->Wqb[l] : nullptr;
     WTq[l] = bf ? (const void*)h->WTqb[l] : nullptr;
   }
-  GemmArgs g{};
-  g.gt = gt;
-  g.alpha = h->alpha;
-  g.inv_alpha_l2e = (float)(1.4426950408889634 / h->alpha);
+  const int M = h->n_models;
+  const int ldd1 = M * w1;  // D1 row: the members' delta1 side by side
+  const float escale = 1.f / (float)M;
+  const size_t esz = sizeof(T);
   bool ok = true;
-  // layer 1: H1 = CELU(X W0^T + b0)
-  g.A = X; g.lda = Fp; g.B = W[0]; g.Bq = Wq[0]; g.sB = (long)w1 * Fp; g.ldb = Fp;
-  g.bias = h->bias[0]; g.sBias = w1; g.N = w1; g.K = Fp; g.C = H1; g.ldc = w1;
-  {
-    StageTimer t(h, ST_L1, st);
-    ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
-  }
-  // BF16 with gradients: one fused launch for layer 2, the energy head and the
-  // adjoint of layers 3 and 2 (intermediates stay in LDS)
-  bool fused = false;
-  if (bf && need_bwd) {
-    MidArgs ma{};
-    ma.gt = gt;
-    ma.H1 = reinterpret_cast<const bf16_t*>(H1);
-    ma.W1 = h->Wqb[1];
-    ma.W2 = h->Wqb[2];
-    ma.W2T = h->WTqb[2];
-    ma.W1T = h->WTqb[1];
-    ma.b1 = h->bias[1];
-    ma.b2 = h->bias[2];
-    ma.wout = h->wout;
-    ma.bout = h->bout;
-    ma.erow = erow;
-    ma.D1 = reinterpret_cast<bf16_t*>(D1);
-    if (io.dparams) {
-      ma.H2 = reinterpret_cast<bf16_t*>(H2);
-      ma.H3 = reinterpret_cast<bf16_t*>(H3);
-      ma.D3 = reinterpret_cast<bf16_t*>(D3);
-      ma.D2 = reinterpret_cast<bf16_t*>(D2);
-      ma.uprow = at<float>(ws, P.uprow);
+  for (int k = 0; k < M; ++k) {
+    // member k: weight slots k * S .. k * S + S - 1
+    const int q0 = k * S;
+    float* erow_k = erow + (size_t)k * P.rows_cap;
+    T* D1k = D1 + (size_t)k * w1;
+    const void* Wk[kLayers];
+    const void* WTk[kLayers];
+    const void* Wqk[kLayers];
+    const void* WTqk[kLayers];
+    for (int l = 0; l < kLayers - 1; ++l) {
+      const size_t inp = l == 0 ? (size_t)Fp : (size_t)h->width[l];
+      const size_t slot = (size_t)h->width[l + 1] * inp;  // elements per weight slot
+      Wk[l] = W[l] ? (const char*)W[l] + q0 * slot * esz : nullptr;
+      WTk[l] = WT[l] ? (const char*)WT[l] + q0 * slot * esz : nullptr;
+      Wqk[l] = Wq[l] ? (const char*)Wq[l] + q0 * slot * esz : nullptr;
+      WTqk[l] = WTq[l] ? (const char*)WTq[l] + q0 * slot * esz : nullptr;
     }
-    ma.perm = perm;
-    ma.mol = mol;
-    ma.dLdE = io.dLdE;
-    ma.alpha = h->alpha;
-    ma.inv_alpha_l2e = g.inv_alpha_l2e;
-    StageTimer t(h, ST_MID, st);
-    fused = launch_mlp_mid(h->width, ma, P.rows_cap, st);
-  }
-  if (fused) {
-    if (io.E) {
-      StageTimer t(h, ST_ENERGY, st);
-      launch_energy(dims, P.nmol, io.off, xyzs, erow, h->eself, io.E, status, st);
-    }
-  } else {
-    // layer 2: H2 = CELU(H1 W1^T + b1)
-    g.A = H1; g.lda = w1; g.B = W[1]; g.Bq = Wq[1]; g.sB = (long)w2 * w1; g.ldb = w1;
-    g.bias = h->bias[1]; g.sBias = w2; g.N = w2; g.K = w1; g.C = H2; g.ldc = w2;
+    const float* bias_k[kLayers - 1];
+    for (int l = 0; l < kLayers - 1; ++l) bias_k[l] = h->bias[l] + (size_t)q0 * h->width[l + 1];
+    const float* wout_k = h->wout + (size_t)q0 * w3;
+    const float* bout_k = h->bout + q0;
+    GemmArgs g{};
+    g.gt = gt;
+    g.alpha = h->alpha;
+    g.inv_alpha_l2e = (float)(1.4426950408889634 / h->alpha);
+    g.escale = escale;
+    // layer 1: H1 = CELU(X W0^T + b0)
+    g.A = X; g.lda = Fp; g.B = Wk[0]; g.Bq = Wqk[0]; g.sB = (long)w1 * Fp; g.ldb = Fp;
+    g.bias = bias_k[0]; g.sBias = w1; g.N = w1; g.K = Fp; g.C = H1; g.ldc = w1;
     {
-      StageTimer t(h, ST_L2, st);
+      StageTimer t(h, ST_L1, st);
       ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
     }
-    // layer 3 + output: E_i, delta3
-    g.A = H2; g.lda = w2; g.B = W[2]; g.Bq = nullptr; g.sB = (long)w3 * w2; g.ldb = w2;
-    g.bias = h->bias[2]; g.sBias = w3; g.N = w3; g.K = w2;
-    g.C = need_bwd ? (void*)D3 : nullptr; g.ldc = w3;
-    g.w_out = h->wout; g.sWout = w3; g.b_out = h->bout; g.erow = erow;
-    g.H3 = io.dparams ? (void*)H3 : nullptr; g.ldh3 = w3;
-    g.perm = perm; g.mol = mol; g.dLdE = io.dLdE;
-    g.uprow = io.dparams ? at<float>(ws, P.uprow) : nullptr;
-    {
-      StageTimer t(h, ST_HEAD, st);
-      ok &= launch_gemm<T>(EPI_HEAD, g, P.rows_cap, st);
-    }
-    g.H3 = nullptr;
-    g.uprow = nullptr;
-    if (io.E) {
-      StageTimer t(h, ST_ENERGY, st);
-      launch_energy(dims, P.nmol, io.off, xyzs, erow, h->eself, io.E, status, st);
-    }
-    if (need_bwd) {
-      // delta2 = (delta3 W2) * CELU'(z2)
-      g.A = D3; g.lda = w3; g.B = WT[2]; g.Bq = WTq[2]; g.sB = (long)w2 * w3; g.ldb = w3;
-      g.bias = nullptr; g.N = w2; g.K = w3; g.C = D2; g.ldc = w2; g.H = H2; g.ldh = w2;
-      {
-        StageTimer t(h, ST_BWD3, st);
-        ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+    // BF16 with gradients: one fused launch for layer 2, the energy head and the
+    // adjoint of layers 3 and 2 (intermediates stay in LDS)
+    bool fused = false;
+    if (bf && need_bwd) {
+      MidArgs ma{};
+      ma.gt = gt;
+      ma.H1 = reinterpret_cast<const bf16_t*>(H1);
+      ma.W1 = static_cast<const bf16_t*>(Wqk[1]);
+      ma.W2 = static_cast<const bf16_t*>(Wqk[2]);
+      ma.W2T = static_cast<const bf16_t*>(WTqk[2]);
+      ma.W1T = static_cast<const bf16_t*>(WTqk[1]);
+      ma.b1 = bias_k[1];
+      ma.b2 = bias_k[2];
+      ma.wout = wout_k;
+      ma.bout = bout_k;
+      ma.erow = erow_k;
+      ma.D1 = reinterpret_cast<bf16_t*>(D1k);
+      ma.ld_d1 = ldd1;
+      ma.escale = escale;
+      if (io.dparams) {
+        ma.H2 = reinterpret_cast<bf16_t*>(H2);
+        ma.H3 = reinterpret_cast<bf16_t*>(H3);
+        ma.D3 = reinterpret_cast<bf16_t*>(D3);
+        ma.D2 = reinterpret_cast<bf16_t*>(D2);
+        ma.uprow = at<float>(ws, P.uprow);
       }
-      // delta1 = (delta2 W1) * CELU'(z1)
-      g.A = D2; g.lda = w2; g.B = WT[1]; g.Bq = WTq[1]; g.sB = (long)w1 * w2; g.ldb = w2;
-      g.N = w1; g.K = w2; g.C = D1; g.ldc = w1; g.H = H1; g.ldh = w1;
+      ma.perm = perm;
+      ma.mol = mol;
+      ma.dLdE = io.dLdE;
+      ma.alpha = h->alpha;
+      ma.inv_alpha_l2e = g.inv_alpha_l2e;
+      StageTimer t(h, ST_MID, st);
+      fused = launch_mlp_mid(h->width, ma, P.rows_cap, st);
+    }
+    if (!fused) {
+      // layer 2: H2 = CELU(H1 W1^T + b1)
+      g.A = H1; g.lda = w1; g.B = Wk[1]; g.Bq = Wqk[1]; g.sB = (long)w2 * w1; g.ldb = w1;
+      g.bias = bias_k[1]; g.sBias = w2; g.N = w2; g.K = w1; g.C = H2; g.ldc = w2;
       {
-        StageTimer t(h, ST_BWD2, st);
-        ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+        StageTimer t(h, ST_L2, st);
+        ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
+      }
+      // layer 3 + output: E_i, delta3
+      g.A = H2; g.lda = w2; g.B = Wk[2]; g.Bq = nullptr; g.sB = (long)w3 * w2; g.ldb = w2;
+      g.bias = bias_k[2]; g.sBias = w3; g.N = w3; g.K = w2;
+      g.C = need_bwd ? (void*)D3 : nullptr; g.ldc = w3;
+      g.w_out = wout_k; g.sWout = w3; g.b_out = bout_k; g.erow = erow_k;
+      g.H3 = io.dparams ? (void*)H3 : nullptr; g.ldh3 = w3;
+      g.perm = perm; g.mol = mol; g.dLdE = io.dLdE;
+      g.uprow = io.dparams ? at<float>(ws, P.uprow) : nullptr;
+      {
+        StageTimer t(h, ST_HEAD, st);
+        ok &= launch_gemm<T>(EPI_HEAD, g, P.rows_cap, st);
+      }
+      g.H3 = nullptr;
+      g.uprow = nullptr;
+      if (need_bwd) {
+        // delta2 = (delta3 W2) * CELU'(z2)
+        g.A = D3; g.lda = w3; g.B = WTk[2]; g.Bq = WTqk[2]; g.sB = (long)w2 * w3; g.ldb = w3;
+        g.bias = nullptr; g.N = w2; g.K = w3; g.C = D2; g.ldc = w2; g.H = H2; g.ldh = w2;
+        {
+          StageTimer t(h, ST_BWD3, st);
+          ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+        }
+        // delta1 = (delta2 W1) * CELU'(z1)
+        g.A = D2; g.lda = w2; g.B = WTk[1]; g.Bq = WTqk[1]; g.sB = (long)w1 * w2; g.ldb = w2;
+        g.N = w1; g.K = w2; g.C = D1k; g.ldc = ldd1; g.H = H1; g.ldh = w1;
+        {
+          StageTimer t(h, ST_BWD2, st);
+          ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
+        }
       }
     }
+  }  // members
+  if (io.E) {
+    StageTimer t(h, ST_ENERGY, st);
+    launch_energy(dims, P.nmol, io.off, xyzs, erow, M, (long)P.rows_cap, h->eself, io.E, status,
+                  st);
   }
   if (io.out3) {
     // g = dE/dG = delta1 W0 (in the network operand type)
-    g.A = D1; g.lda = w1; g.B = WT[0]; g.Bq = WTq[0]; g.sB = (long)Fp * w1; g.ldb = w1;
-    g.N = Fp; g.K = w1; g.C = G; g.ldc = Fp; g.H = nullptr;
+    // (ensembles: one product over the members' delta1 side by side and the
+    // member-concatenated W0^T, so the mean of their dE/dG is accumulated in
+    // FP32 inside the product; the 1/M is already in delta1)
+    GemmArgs g{};
+    g.gt = gt;
+    g.alpha = h->alpha;
+    g.inv_alpha_l2e = (float)(1.4426950408889634 / h->alpha);
+    const bool cat = M > 1;
+    g.A = D1; g.lda = ldd1;
+    g.B = cat ? (bf ? nullptr : (const void*)h->WT0cf) : WT[0];
+    g.Bq = cat ? (bf ? (const void*)h->WT0cq : nullptr) : WTq[0];
+    g.sB = (long)Fp * ldd1; g.ldb = ldd1;
+    g.N = Fp; g.K = ldd1; g.C = G; g.ldc = Fp; g.H = nullptr;
     {
       StageTimer t(h, ST_GRADG, st);
       ok &= launch_gemm<T>(EPI_OUT, g, P.rows_cap, st);
@@ -445,8 +484,15 @@ const char* nnp_status_string(nnp_status s) {
 
 nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
                       nnp_precision precision, nnp_handle** out) {
-  if (!aev || !mlp || !out) return NNP_E_INVALID;
+  return nnp_create_ensemble(aev, mlp, 1, precision, out);
+}
+
+nnp_status nnp_create_ensemble(const nnp_aev_params* aev, const nnp_mlp_params* mlps,
+                               int32_t n_models, nnp_precision precision, nnp_handle** out) {
+  if (!aev || !mlps || !out) return NNP_E_INVALID;
   *out = nullptr;
+  if (n_models < 1 || n_models > kMaxModels) return NNP_E_INVALID;
+  const nnp_mlp_params* mlp = &mlps[0];
   const int S = aev->n_species;
   if (S < 1 || S > kMaxS) return NNP_E_INVALID;
   if (aev->n_shf_r != kNR || aev->n_shf_a != kNA || aev->n_shf_z != kNZ) return NNP_E_INVALID;
@@ -461,6 +507,13 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
   for (int l = 1; l < kLayers; ++l)
     if (mlp->width[l] < 32 || mlp->width[l] > 256 || mlp->width[l] % 32) return NNP_E_INVALID;
   if (!(mlp->celu_alpha > 0.f)) return NNP_E_INVALID;
+  for (int k = 1; k < n_models; ++k) {  // members share the architecture
+    const nnp_mlp_params& q = mlps[k];
+    if (q.n_layers != kLayers || !q.width || !q.params || q.celu_alpha != mlp->celu_alpha)
+      return NNP_E_INVALID;
+    for (int l = 0; l <= kLayers; ++l)
+      if (q.width[l] != mlp->width[l]) return NNP_E_INVALID;
+  }
 
   nnp_handle* h = new (std::nothrow) nnp_handle();
   if (!h) return NNP_E_OOM;
@@ -499,14 +552,17 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
     C.cos_z[z] = (float)std::cos((double)aev->shf_z[z]);
     C.sin_z[z] = (float)std::sin((double)aev->shf_z[z]);
   }
-  // flat parameter offsets
+  // flat parameter offsets: member-major, then element, then layer
+  h->n_models = n_models;
+  const int Q = n_models * S;  // weight slots
   size_t o = 0;
-  for (int s = 0; s < S; ++s)
+  for (int q = 0; q < Q; ++q)
     for (int l = 0; l < kLayers; ++l) {
-      h->param_off[s][l] = (long)o;
+      h->param_off[q][l] = (long)o;
       o += (size_t)h->width[l + 1] * h->width[l] + h->width[l + 1];
     }
   h->n_params = o;
+  const size_t per_model = o / n_models;
   // one device allocation for all weight copies
   size_t bytes = 0;
   auto take = [&](size_t b) {
@@ -519,16 +575,19 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
       o_b[kLayers];
   for (int l = 0; l < kLayers - 1; ++l) {
     const size_t inp = l == 0 ? h->Fp : h->width[l];
-    const size_t el = (size_t)S * h->width[l + 1] * inp;
+    const size_t el = (size_t)Q * h->width[l + 1] * inp;
     o_wf[l] = take(el * 4);
     o_wb[l] = take(el * 2);
     o_wtf[l] = take(el * 4);
     o_wqb[l] = take(el * 2);
     o_wtqb[l] = take(el * 2);
-    o_b[l] = take((size_t)S * h->width[l + 1] * 4);
+    o_b[l] = take((size_t)Q * h->width[l + 1] * 4);
   }
-  const size_t o_wout = take((size_t)S * h->width[3] * 4);
-  const size_t o_bout = take((size_t)S * 4);
+  const size_t cat_el = n_models > 1 ? (size_t)S * h->Fp * n_models * h->width[1] : 0;
+  const size_t o_wt0cf = take(cat_el * 4);
+  const size_t o_wt0cq = take(cat_el * 2);
+  const size_t o_wout = take((size_t)Q * h->width[3] * 4);
+  const size_t o_bout = take((size_t)Q * 4);
   const size_t o_eself = take(kMaxS * 8);
   const size_t o_poff = take((size_t)kLayers * S * 8);
   const size_t o_lane = take((size_t)(kNR + 2 * kNZ) * 4);
@@ -544,6 +603,10 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
     h->Wqb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wqb[l]);
     h->WTqb[l] = reinterpret_cast<bf16_t*>(h->dmem + o_wtqb[l]);
     h->bias[l] = reinterpret_cast<float*>(h->dmem + o_b[l]);
+  }
+  if (n_models > 1) {
+    h->WT0cf = reinterpret_cast<float*>(h->dmem + o_wt0cf);
+    h->WT0cq = reinterpret_cast<bf16_t*>(h->dmem + o_wt0cq);
   }
   h->wout = reinterpret_cast<float*>(h->dmem + o_wout);
   h->bout = reinterpret_cast<float*>(h->dmem + o_bout);
@@ -562,8 +625,11 @@ nnp_status nnp_create(const nnp_aev_params* aev, const nnp_mlp_params* mlp,
   std::vector<long> po((size_t)kLayers * S);
   for (int l = 0; l < kLayers; ++l)
     for (int s = 0; s < S; ++s) po[(size_t)l * S + s] = h->param_off[s][l];
-  bool ok = hip_ok(hipMemcpy(h->flat, mlp->params, o * 4, hipMemcpyHostToDevice)) &&
-            hip_ok(hipMemcpy(h->eself, es, sizeof(es), hipMemcpyHostToDevice)) &&
+  bool ok = true;
+  for (int k = 0; k < n_models && ok; ++k)
+    ok = hip_ok(hipMemcpy(h->flat + k * per_model, mlps[k].params, per_model * 4,
+                          hipMemcpyHostToDevice));
+  ok = ok && hip_ok(hipMemcpy(h->eself, es, sizeof(es), hipMemcpyHostToDevice)) &&
             hip_ok(hipMemcpy(h->param_off_dev, po.data(), po.size() * 8, hipMemcpyHostToDevice)) &&
             hip_ok(hipMemcpy(const_cast<float*>(C.lane_tab), lane_host, sizeof(lane_host),
                              hipMemcpyHostToDevice));
@@ -597,8 +663,13 @@ nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* s
     return NNP_E_HIP;
   PackArgs p{};
   p.flat = h->flat;
-  for (int s = 0; s < h->S; ++s)
-    for (int l = 0; l < kLayers; ++l) p.off[s * kLayers + l] = h->param_off[s][l];
+  const int Q = h->n_models * h->S;
+  for (int q = 0; q < Q; ++q)
+    for (int l = 0; l < kLayers; ++l) p.off[q * kLayers + l] = h->param_off[q][l];
+  p.S = h->S;
+  p.n_models = h->n_models;
+  p.WT0cf = h->WT0cf;
+  p.WT0cq = h->WT0cq;
   for (int l = 0; l <= kLayers; ++l) p.width[l] = h->width[l];
   p.width[0] = h->F;
   p.Fp = h->Fp;
@@ -612,7 +683,7 @@ nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* s
   }
   p.wout = h->wout;
   p.bout = h->bout;
-  launch_pack(p, h->S, st);
+  launch_pack(p, Q, st);
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
 }
 
@@ -689,6 +760,7 @@ nnp_status nnp_backward(nnp_handle* h, int32_t n, int32_t nmol, const float* pos
   nnp_status s = check_common(h, n, nmol, pos, species, off, box, ws, ws_bytes, P);
   if (s != NNP_OK) return s;
   if (!dLdE) return NNP_E_INVALID;
+  if (dL_dparams && h && h->n_models > 1) return NNP_E_INVALID;  // weight gradients: one network
   EvalIO io{n, nmol, pos, nullptr, species, off, E, dL_dpos, -1.f, dLdE, dL_dparams};
   return run(h, P, ws, io, static_cast<hipStream_t>(stream));
 }

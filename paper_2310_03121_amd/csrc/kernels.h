@@ -34,6 +34,7 @@ struct GemmArgs {
   float* uprow;        // optional store of the per-row upstream gradient (EPI_HEAD)
   float alpha;
   float inv_alpha_l2e; // log2(e) / alpha
+  float escale = 1.f;  // EPI_HEAD: factor on the upstream gradient (1 / ensemble size)
 };
 
 struct MidArgs {
@@ -48,7 +49,7 @@ struct MidArgs {
   const float* wout;              // [S][W3]
   const float* bout;              // [S]
   float* erow;                    // [atoms] atomic energies, input atom order
-  bf16_t* D1;                     // [rows][W1]
+  bf16_t* D1;                     // [rows][ld_d1], columns [0, W1)
   bf16_t* H2;                     // optional [rows][W2]
   bf16_t* H3;                     // optional [rows][W3]
   bf16_t* D3;                     // optional [rows][W3]
@@ -59,14 +60,21 @@ struct MidArgs {
   const double* dLdE;
   float alpha;
   float inv_alpha_l2e;
+  float escale = 1.f;             // factor on the upstream gradient (1 / ensemble size)
+  int ld_d1 = 0;                  // row stride of D1 (0: W1)
 };
 
+// Weight slots: member k of an ensemble, element s -> slot k * S + s.
 struct PackArgs {
   const float* flat;
-  long off[kMaxS * kLayers];  // flat offset of W for (species, layer)
+  long off[kMaxModels * kMaxS * kLayers];  // flat offset of W for (slot, layer)
+  int S;                  // elements (slot = member * S + element)
+  int n_models;
+  float* WT0cf;           // ensembles: [S][F_pad][M * width1] member-concatenated W_0^T
+  bf16_t* WT0cq;          // the same in MFMA fragment order (N = F_pad, K = M * width1)
   int width[kLayers + 1];
   int Fp;
-  float* Wf[kLayers];     // W [S][out][in_pad], row-major
+  float* Wf[kLayers];     // W [slots][out][in_pad], row-major
   bf16_t* Wb[kLayers];
   float* WTf[kLayers];    // W^T [S][in_pad][out], row-major
   bf16_t* Wqb[kLayers];   // W in MFMA fragment order (N = out, K = in_pad)
@@ -90,8 +98,8 @@ void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt,
 void launch_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const int* hist,
                     int* row, int* perm, hipStream_t st);
 void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* xyzs,
-                   const float* eatom, const double* eself, double* E,
-                   uint32_t* status, hipStream_t st);
+                   const float* eatom, int n_models, long mstride, const double* eself,
+                   double* E, uint32_t* status, hipStream_t st);
 void launch_fill_i32(int* p, int v, int n, hipStream_t st);
 void launch_fill_f32(float* p, float v, long n, hipStream_t st);
 void launch_fill_f64(double* p, double v, int n, hipStream_t st);
@@ -125,7 +133,7 @@ template <typename TD, typename TH>
 void launch_wgrad(const GroupTable* gt, int S, int n_chunks_cap, const TD* D, int ldd, int Nout,
                   const TH* H, int ldh, int Nin, int chunk, float* partial, float* dparams,
                   const long* param_off_dev, hipStream_t st);
-void launch_pack(const PackArgs& p, int S, hipStream_t st);
+void launch_pack(const PackArgs& p, int slots, hipStream_t st);
 
 // mlp_mid.hip
 bool launch_mlp_mid(const int* width, const MidArgs& a, int rows_cap, hipStream_t st);

@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
         const int row = row0 + rloc;
         const bool rv = row < row_end;
         float up = 0.f;
-        if (rv) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
+        if (rv) up = (a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f) * a.escale;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const int col = n0 + wn * WTN + j * 16 + rl;
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
       if (row < row_end) a.erow[a.perm[row]] = e;  // input atom order
       if (a.uprow) {
         float up = 0.f;
-        if (row < row_end) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
+        if (row < row_end) up = (a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f) * a.escale;
         a.uprow[row] = up;
       }
     }
@@ -699,7 +699,7 @@ __device__ __forceinline__ size_t frag_off(int n, int k, int K) {
 
 __global__ __launch_bounds__(256) void k_pack(PackArgs p) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int l = blockIdx.y, s = blockIdx.z;
+  const int l = blockIdx.y, s = blockIdx.z;  // s: weight slot (member * S + element)
   const int in = p.width[l], out = p.width[l + 1];
   const int inp = l == 0 ? p.Fp : in;
   const float* src = p.flat + p.off[s * kLayers + l];
@@ -714,6 +714,13 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs p) {
     p.Wqb[l][ws + frag_off<bf16_t>(o, i, inp)] = f2bf(v);
     p.WTqb[l][ws + frag_off<bf16_t>(i, o, out)] = f2bf(v);
     if (i == 0) p.bias[l][(size_t)s * out + o] = src[(size_t)out * in + o];
+    if (l == 0 && p.n_models > 1) {
+      // member k's W_0^T as columns [k out, (k + 1) out) of one K = M out operand
+      const int k = s / p.S, e = s % p.S, KM = p.n_models * out;
+      const size_t wc = (size_t)e * inp * KM;
+      p.WT0cf[wc + (size_t)i * KM + (size_t)k * out + o] = v;
+      p.WT0cq[wc + frag_off<bf16_t>(i, k * out + o, KM)] = f2bf(v);
+    }
   } else {
     if (t >= in) return;
     p.wout[(size_t)s * in + t] = src[t];
@@ -721,14 +728,14 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs p) {
   }
 }
 
-void launch_pack(const PackArgs& p, int S, hipStream_t st) {
+void launch_pack(const PackArgs& p, int slots, hipStream_t st) {
   long maxel = 0;
   for (int l = 0; l < kLayers; ++l) {
     const long inp = l == 0 ? p.Fp : p.width[l];
     const long el = (long)p.width[l + 1] * inp;
     maxel = el > maxel ? el : maxel;
   }
-  dim3 grid((unsigned)((maxel + 255) / 256), kLayers, S);
+  dim3 grid((unsigned)((maxel + 255) / 256), kLayers, slots);
   hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, st, p);
 }
 

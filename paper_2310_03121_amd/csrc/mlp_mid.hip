@@ -169,7 +169,7 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
       const int row = row0 + r;
       const bool rv = row < row_end;
       float up = 0.f;
-      if (rv) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
+      if (rv) up = (a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f) * a.escale;
       float ep = 0.f;
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
     if (row < row_end) a.erow[a.perm[row]] = e;  // input atom order
     if (a.uprow) {
       float up = 0.f;
-      if (row < row_end) up = a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f;
+      if (row < row_end) up = (a.dLdE ? (float)a.dLdE[a.mol[a.perm[row]]] : 1.f) * a.escale;
       a.uprow[row] = up;
     }
   }
@@ -238,6 +238,7 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
   {
     using C = MidCfg<W1>;
     const int wm = wv / C::WN, wn = wv % C::WN;
+    const int ldd1 = a.ld_d1 ? a.ld_d1 : W1;
     // H1 for the slopes is fetched before the product (4 bf16 per tile)
     uint2 h1[C::TM][C::TN];
 #pragma unroll
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
         float4 d = make_float4(acc[i][j][0] * celu_slope(h.x, ia), acc[i][j][1] * celu_slope(h.y, ia),
                                acc[i][j][2] * celu_slope(h.z, ia), acc[i][j][3] * celu_slope(h.w, ia));
         if (!rv) d = make_float4(0.f, 0.f, 0.f, 0.f);
-        Store<bf16_t>::put4(a.D1 + (size_t)row * W1 + c, d);
+        Store<bf16_t>::put4(a.D1 + (size_t)row * ldd1 + c, d);
       }
     }
   }

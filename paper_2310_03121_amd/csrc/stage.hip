@@ -181,16 +181,18 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ dims, i
   }
 }
 
-// One workgroup per molecule: E_m = sum_i (double)E_i + e_self[s_i], with the
-// atomic energies in input atom order.  Thread t sums the atoms t, t + 256,
-// ... of the molecule (counted from its first atom), then the waves and the
-// four wave sums combine in a fixed order: the result depends only on the
-// molecule's own atoms, not on where it sits in a batch.
+// One workgroup per molecule: E_m = sum_i (e_i + e_self[s_i]) with the
+// atomic energies in input atom order; for an ensemble of M members e_i is
+// the mean of the members' atomic energies (member k at eatom + k * mstride).
+// Thread t sums the atoms t, t + 256, ... of the molecule (counted from its
+// first atom), then the waves and the four wave sums combine in a fixed
+// order: the result depends only on the molecule's own atoms, not on where
+// it sits in a batch.
 __global__ __launch_bounds__(256) void k_energy(const int* __restrict__ dims,
                                                 const int* __restrict__ off,
                                                 const float4* __restrict__ xyzs,
-                                                const float* __restrict__ eatom,
-                                                const double* __restrict__ eself,
+                                                const float* __restrict__ eatom, int n_models,
+                                                long mstride, const double* __restrict__ eself,
                                                 double* __restrict__ E, uint32_t* __restrict__ status) {
   __shared__ double part[4];
   const int n = dims[0], nmol = dims[1];
@@ -199,10 +201,14 @@ __global__ __launch_bounds__(256) void k_energy(const int* __restrict__ dims,
   int a = off[m], b = off[m + 1];
   a = a < 0 ? 0 : (a > n ? n : a);
   b = b < a ? a : (b > n ? n : b);
+  const double inv_m = 1.0 / n_models;
   double acc = 0.0;
 #pragma unroll 4
-  for (int i = a + (int)threadIdx.x; i < b; i += 256)
-    acc += (double)eatom[i] + eself[species_of(xyzs[i])];
+  for (int i = a + (int)threadIdx.x; i < b; i += 256) {
+    double e = (double)eatom[i];
+    for (int k = 1; k < n_models; ++k) e += (double)eatom[k * mstride + i];
+    acc += e * inv_m + eself[species_of(xyzs[i])];
+  }
   acc = wave_sum_d(acc);
   if (lane_id() == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -252,11 +258,11 @@ void launch_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const
 }
 
 void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* xyzs,
-                   const float* eatom, const double* eself, double* E, uint32_t* status,
-                   hipStream_t st) {
+                   const float* eatom, int n_models, long mstride, const double* eself,
+                   double* E, uint32_t* status, hipStream_t st) {
   if (nmol_cap <= 0) return;
-  hipLaunchKernelGGL(k_energy, dim3(nmol_cap), dim3(256), 0, st, dims, off, xyzs, eatom, eself, E,
-                     status);
+  hipLaunchKernelGGL(k_energy, dim3(nmol_cap), dim3(256), 0, st, dims, off, xyzs, eatom,
+                     n_models, mstride, eself, E, status);
 }
 
 void launch_fill_i32(int* p, int v, int n, hipStream_t st) {

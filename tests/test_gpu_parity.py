@@ -360,3 +360,70 @@ def test_graph_replay_matches_eager():
             g.check()
             assert torch.equal(g.E.cpu(), E_ref.cpu()), (prec, k)
             assert rel_rms(g.F.cpu().numpy(), F_ref.cpu().numpy()) <= 1e-6, (prec, k)
+
+
+# ------------------------------------------------------------------ ensembles
+def _ensemble_case(S):
+    if S == 7:
+        s = w.conformer_batch(12, 64, seed=1)
+        seeds = (101, 102, 103)
+    else:
+        s = w.config_system(0)
+        seeds = (100, 107, 108)
+    return s, w.aev_table(S), [w.mlp_table(S, seed=k) for k in seeds]
+
+
+@pytest.mark.parametrize("S,prec,f_tol,e_tol", [(7, "fp32", 1e-5, 1e-5), (7, "bf16", 1e-2, 1e-2),
+                                                (4, "fp32", 1e-5, 1e-5), (4, "bf16", 1e-2, 1e-2)])
+def test_ensemble_energy_forces(S, prec, f_tol, e_tol):
+    s, at, members = _ensemble_case(S)
+    announce(f"ensemble of {len(members)} S={S} {prec} N={s.n_atoms}")
+    from paper_2310_03121_amd import Potential
+    pot = Potential.ensemble_from_tables(at, members, precision=prec)
+    pos, sp, off = to_dev(s)
+    E, F = pot.energy_forces(pos, sp, off, s.box)
+    E_only, _ = pot.energy_forces(pos, sp, off, s.box, forces=False)
+    pot.check()
+    E, F, E_only = E.cpu().numpy(), F.cpu().numpy(), E_only.cpu().numpy()
+    r = o.ensemble_energy_forces(s, aev_table=at, mlp_tables=members)
+    scale = np.array([np.abs(r.E_atom[s.mol_offsets[m]:s.mol_offsets[m + 1]]).sum()
+                      for m in range(s.n_mol)])
+    de = np.abs(E - r.E) / np.maximum(scale, 1e-30)
+    fr = rel_rms(F, r.F)
+    print(f"ensemble {prec}: max |dE|/sum|E_i| {de.max():.3e}  force rel-RMS {fr:.3e}")
+    assert de.max() <= e_tol
+    assert fr <= f_tol
+    # the energy-only path runs the forward kernels alone; same mean energy
+    assert np.abs(E_only - E).max() <= 1e-6 * max(1.0, np.abs(E).max())
+
+
+def test_ensemble_of_one_equals_single_network():
+    s, at, members = _ensemble_case(7)
+    announce("ensemble of one vs single network")
+    from paper_2310_03121_amd import Potential
+    pos, sp, off = to_dev(s)
+    for prec in ("fp32", "bf16"):
+        a = Potential.from_tables(at, members[0], precision=prec)
+        b = Potential.ensemble_from_tables(at, members[:1], precision=prec)
+        Ea, Fa = a.energy_forces(pos, sp, off, None)
+        Eb, Fb = b.energy_forces(pos, sp, off, None)
+        a.check()
+        b.check()
+        # energies are reduced in a fixed order (bitwise equal); forces are
+        # scattered with atomics, whose order varies from run to run
+        assert torch.equal(Ea, Eb)
+        assert rel_rms(Fb.cpu().numpy(), Fa.cpu().numpy()) <= 1e-6
+
+
+def test_ensemble_rejects_weight_gradients():
+    s, at, members = _ensemble_case(4)
+    announce("ensemble weight gradients are rejected")
+    from paper_2310_03121_amd import Potential
+    from paper_2310_03121_amd.capi import NNPError
+    pot = Potential.ensemble_from_tables(at, members, precision="fp32")
+    pos, sp, off = to_dev(s)
+    dLdE = torch.ones(s.n_mol, dtype=torch.float64, device="cuda")
+    with pytest.raises(NNPError):
+        pot.backward(pos, sp, off, dLdE, None, want_pos=True, want_params=True)
+    gp, gw, _ = pot.backward(pos, sp, off, dLdE, None, want_pos=True, want_params=False)
+    assert gw is None and torch.isfinite(gp).all()
