@@ -512,3 +512,66 @@ def test_ensemble_with_negated_twin_cancels_exactly():
     r = o.ensemble_energy_forces(s, aev_table=at, mlp_tables=[m0, twin])
     assert np.all(r.E_atom == 0.0) and np.all(r.F == 0.0)
     np.testing.assert_allclose(r.E, [se[s.species].sum()], rtol=1e-15)
+
+
+# ------------------------------------------------- Langevin (LF-Middle) + RNG
+def test_philox_known_answers():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert o.philox4x32_10(v[0:4], v[4:6]) == tuple(v[6:10])
+
+
+def test_box_muller_normals_are_standard():
+    from oracle.rng import normals
+    z = np.concatenate([normals(5000, step, seed=12345).ravel() for step in (0, 1)])
+    n = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    # distinct steps and atoms draw independent numbers
+    a, b = z[: n // 2], z[n // 2:]
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5 / math.sqrt(n // 2)
+    assert abs(((z ** 4).mean()) - 3.0) < 0.15  # kurtosis of a normal
+
+
+def _spring(k=0.5):
+    def ff(x32):
+        x = x32.astype(np.float64)
+        return np.array([0.5 * k * np.sum(x * x)]), -k * x
+    return ff
+
+
+def test_langevin_without_friction_is_velocity_verlet():
+    # c = 1 removes the noise; leapfrog from v_{-1/2} = v_0 - dt/2 a(x_0)
+    # then visits exactly the velocity-Verlet positions
+    rng = np.random.default_rng(0)
+    x0 = rng.normal(size=(6, 3))
+    v0 = rng.normal(scale=0.01, size=(6, 3))
+    m = np.array([1.008, 12.011, 15.999, 1.008, 14.007, 32.06])
+    ff = _spring()
+    dt = 0.5
+    _, F0 = ff(x0.astype(np.float32))
+    vh = v0 - 0.5 * dt * o.integrator.ACC_UNIT * F0 / m[:, None]
+    for n in (1, 7, 25):
+        xl, _, _ = o.langevin_middle(x0, vh, m, ff, dt, n, 300.0, 0.0, seed=1)
+        xv, _, _ = o.velocity_verlet(x0, v0, m, ff, dt, n)
+        np.testing.assert_allclose(xl, xv, rtol=0, atol=1e-12)
+
+
+def test_langevin_free_particles_follow_ornstein_uhlenbeck():
+    # no force: v_{n+1/2} = c v + sqrt(1 - c^2) sigma R is an exact OU
+    # process, so from v = 0 the variance after n steps is
+    # sigma^2 (1 - c^(2n)), sigma^2 = kB T / m in A^2/fs^2
+    N, n, T, gam, dt = 4000, 12, 300.0, 100.0, 0.5
+    m = np.full(N, 12.011)
+    zero = lambda x32: (np.zeros(1), np.zeros_like(x32, dtype=np.float64))
+    _, v, _ = o.langevin_middle(np.zeros((N, 3)), np.zeros((N, 3)), m, zero, dt, n, T, gam,
+                                seed=7)
+    c = math.exp(-gam * 1e-3 * dt)
+    var = o.integrator.KB_EV * T * o.integrator.ACC_UNIT / 12.011 * (1 - c ** (2 * n))
+    z = v.ravel()
+    assert abs(z.var() / var - 1.0) < 5 * math.sqrt(2.0 / z.size)
+    assert abs(z.mean()) < 5 * math.sqrt(var / z.size)
