@@ -259,6 +259,34 @@ nnp_status nnp_md_steps(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
                         double* E_pot, double* E_kin, void* workspace,
                         size_t workspace_bytes, void* stream);
 
+/* n_steps of LF-Middle Langevin dynamics (NVT; Methods, "Other Features":
+ * the LF-Middle discretization; Results, GFP example: 300 K, 0.5 fs,
+ * 1 / ps).  A leapfrog scheme whose velocities live at half steps.  From
+ * x_n, v_{n-1/2} and F(x_n), each step does, per atom and component
+ *   v += dt a;  x += dt/2 v;  v = c v + sqrt((1 - c^2) kB T / m) R;
+ *   x += dt/2 v;  F = F(x)
+ * with a = 9.648533e-3 F / m, c = exp(-friction * dt) and kB = 8.617333262e-5
+ * eV/K.  R are standard normals: Philox4x32-10 (Salmon et al., SC '11) block
+ * with counter (atom index, step mod 2^32, step div 2^32, 0) and key (seed
+ * mod 2^32, seed div 2^32), words (0, 1) and (2, 3) through Box-Muller in
+ * FP64 (u = (w + 1) 2^-32, theta = 2 pi w' 2^-32); the first three normals
+ * drive x, y, z.  Step k of this call uses step index step0 + k, so a run
+ * split over several calls draws the same numbers as one call.
+ *   x, v   device float64 [n_atoms][3], in place (v: half-step velocities).
+ *   F      device float32 [n_atoms][3]: forces at x on entry and on exit.
+ *   mass   device float64 [n_atoms] (amu).
+ *   temperature (K) >= 0, friction (1/ps) >= 0 (0 is leapfrog Verlet).
+ *   E_pot  device float64 [n_mol] at the final x; E_kin of the final
+ *          half-step velocities (either may be NULL).
+ * Workspace as for nnp_md_steps.  NNP_E_INVALID for a negative temperature,
+ * friction or step count, or dt <= 0. */
+nnp_status nnp_langevin_steps(nnp_handle* h, int32_t n_atoms, int32_t n_mol, double* x,
+                              double* v, float* F, const double* mass, const int32_t* species,
+                              const int32_t* mol_offsets, const float* box, double dt,
+                              int32_t n_steps, double temperature, double friction,
+                              uint64_t seed, uint64_t step0, double* E_pot, double* E_kin,
+                              void* workspace, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of MD requests (molecules without a box).
  * A server owns fixed-capacity device buffers (max_atoms atoms, max_mols

@@ -239,6 +239,24 @@ class Potential:
         return Ep, Ek
 
 
+    def langevin_steps(self, x, v, F, mass, species, mol_offsets, dt, n_steps, temperature,
+                       friction, seed, step0=0, box=None):
+        """LF-Middle Langevin steps in place on float64 x and half-step v
+        (F: forces at x); friction in 1/ps.  Returns (E_pot, E_kin)."""
+        n = x.shape[0]
+        n_mol = mol_offsets.shape[0] - 1
+        Ep = torch.empty(n_mol, dtype=torch.float64, device=x.device)
+        Ek = torch.empty(n_mol, dtype=torch.float64, device=x.device)
+        ws = self.workspace(n, n_mol, box, x.device)
+        b, bp = self._box_arg(box)
+        capi.check(self._lib.nnp_langevin_steps(
+            self._h, n, n_mol, _ptr(x), _ptr(v), _ptr(F), _ptr(mass), _ptr(species),
+            _ptr(mol_offsets), bp, float(dt), int(n_steps), float(temperature), float(friction),
+            int(seed), int(step0), _ptr(Ep), _ptr(Ek), _ptr(ws), ws.numel(), _stream()),
+            "nnp_langevin_steps")
+        return Ep, Ek
+
+
 class Graph:
     """A captured energy + force evaluation (nnp_graph_*)."""
 

@@ -72,6 +72,9 @@ _SIGS = [
     ("nnp_profile_read", C.c_int, [_P, _P, _P, _I]),
     ("nnp_md_steps", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P, C.c_double, _I, _P, _P,
                                 _P, C.c_size_t, _P]),
+    ("nnp_langevin_steps", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P, C.c_double, _I,
+                                      C.c_double, C.c_double, C.c_uint64, C.c_uint64, _P, _P,
+                                      _P, C.c_size_t, _P]),
     ("nnp_server_create", C.c_int, [_P, C.c_size_t, _I, _I, C.c_double, _P, _P, C.POINTER(_P)]),
     ("nnp_server_destroy", None, [_P]),
     ("nnp_server_submit", C.c_int, [_P, C.c_int64, _I, _P, _P, _P, _I]),

@@ -929,6 +929,44 @@ nnp_status nnp_md_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, doubl
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
 }
 
+nnp_status nnp_langevin_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, double* v,
+                              float* F, const double* mass, const int32_t* species,
+                              const int32_t* off, const float* box, double dt, int32_t n_steps,
+                              double temperature, double friction, uint64_t seed, uint64_t step0,
+                              double* E_pot, double* E_kin, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!x || !v || !F || !mass || n_steps < 0 || !(dt > 0.0) || !(temperature >= 0.0) ||
+      !(friction >= 0.0))
+    return NNP_E_INVALID;
+  Plan P;
+  float* pos32 = nullptr;
+  {
+    nnp_status s = check_common(h, n, nmol, reinterpret_cast<const float*>(x), species, off, box,
+                                ws, ws_bytes, P);
+    if (s != NNP_OK) return s;
+    pos32 = at<float>(ws, P.pos32);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int* dims = at<int>(ws, P.dims);
+  const double kB = 8.617333262e-5;         // eV / K
+  const double acc = 9.648533e-3;           // A/fs^2 per eV/A/amu
+  const double c = std::exp(-friction * 1e-3 * dt);  // friction in 1/ps, dt in fs
+  const double kT_acc = kB * temperature * acc;
+  nnp_status s = NNP_OK;
+  // the integration kernel reads the atom count the staging kernel writes;
+  // before the first evaluation of this call it is set here
+  launch_fill_i32(dims, n, 1, st);
+  launch_fill_i32(dims + 1, nmol, 1, st);
+  for (int k = 0; k < n_steps && s == NNP_OK; ++k) {
+    launch_lfm_step(dims, n, x, v, F, mass, dt, c, kT_acc, seed, step0 + (uint64_t)k, pos32, st);
+    EvalIO io{n, nmol, pos32, nullptr, species, off, E_pot, F, 1.f, nullptr, nullptr};
+    s = run(h, P, ws, io, st);
+  }
+  if (s == NNP_OK && E_kin) launch_kinetic(dims, nmol, off, v, mass, E_kin, nullptr, st);
+  if (s != NNP_OK) return s;
+  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+}
+
 }  // extern "C"
 
 // =================================================================== serving

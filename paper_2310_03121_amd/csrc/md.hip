@@ -1,5 +1,6 @@
-// Velocity-Verlet integration (FP64 state, FP32 forces) and the device-side
-// repacking used by the continuous-batching server.
+// Velocity-Verlet and LF-Middle Langevin integration (FP64 state, FP32
+// forces) and the device-side repacking used by the continuous-batching
+// server.
 //
 // Units: A, fs, amu, eV; a = 9.648533e-3 * F / m in A/fs^2.  The positions fed
 // to the potential are the FP32 rounding of the FP64 positions.
@@ -47,6 +48,81 @@ __global__ __launch_bounds__(256) void k_vv_kick(const int* __restrict__ dims, d
   const double s = 0.5 * dt * kAccUnit / mass[i];
 #pragma unroll
   for (int c = 0; c < 3; ++c) v[3 * i + c] += s * (double)F[3 * i + c];
+}
+
+// ---------------------------------------------------------- LF-Middle Langevin
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC '11): 128-bit counter, 64-bit
+// key, ten rounds of two 32x32->64 multiplies by fixed odd constants with
+// the high halves folded into the other words and the key; Weyl increments
+// bump the key between rounds.  Written from the published definition.
+struct Philox4 {
+  uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+  constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(kM0, c0), lo0 = kM0 * c0;
+    const uint32_t hi1 = __umulhi(kM1, c2), lo1 = kM1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += kW0;
+    k1 += kW1;
+  }
+  return Philox4{{c0, c1, c2, c3}};
+}
+
+// Box-Muller in FP64 over two 32-bit words: u = (wa + 1) 2^-32 in (0, 1],
+// theta = 2 pi wb 2^-32.
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& n0, double& n1) {
+  const double u = ((double)wa + 1.0) * 0x1p-32;
+  const double th = 6.283185307179586477 * (double)wb * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u));
+  double s, c;
+  sincos(th, &s, &c);
+  n0 = r * c;
+  n1 = r * s;
+}
+
+// One LF-Middle step for every atom (x_n, v_{n-1/2}, F(x_n) -> x_{n+1},
+// v_{n+1/2}):  v += dt a;  x += dt/2 v;  v = c v + sqrt((1 - c^2) kB T / m) R;
+// x += dt/2 v.  R: the first three normals of Philox block (atom, step lo,
+// step hi, 0) under key (seed lo, seed hi).  kT_acc = kB T * (A/fs^2 per
+// eV/A/amu), so kT_acc / m is the velocity variance in A^2/fs^2.
+__global__ __launch_bounds__(256) void k_lfm_step(const int* __restrict__ dims,
+                                                  double* __restrict__ x, double* __restrict__ v,
+                                                  const float* __restrict__ F,
+                                                  const double* __restrict__ mass, double dt,
+                                                  double c, double kT_acc, uint32_t seed_lo,
+                                                  uint32_t seed_hi, uint32_t step_lo,
+                                                  uint32_t step_hi, float* __restrict__ pos32) {
+  const int n = dims[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Philox4 w = philox4x32_10((uint32_t)i, step_lo, step_hi, 0u, seed_lo, seed_hi);
+  double R[4];
+  box_muller(w.v[0], w.v[1], R[0], R[1]);
+  box_muller(w.v[2], w.v[3], R[2], R[3]);
+  const double m = mass[i];
+  const double s = dt * kAccUnit / m;
+  const double sig = sqrt((1.0 - c * c) * kT_acc / m);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double vv = v[3 * i + k] + s * (double)F[3 * i + k];
+    double xx = x[3 * i + k] + 0.5 * dt * vv;
+    vv = c * vv + sig * R[k];
+    xx += 0.5 * dt * vv;
+    v[3 * i + k] = vv;
+    x[3 * i + k] = xx;
+    pos32[3 * i + k] = (float)xx;
+  }
 }
 
 // Kinetic energy per molecule; with `kdone`, also advances the molecule's
@@ -147,6 +223,15 @@ void launch_vv_kick(const int* dims, int n_cap, double* v, const float* F, const
                     double dt, hipStream_t st) {
   if (n_cap <= 0) return;
   hipLaunchKernelGGL(k_vv_kick, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, v, F, mass, dt);
+}
+
+void launch_lfm_step(const int* dims, int n_cap, double* x, double* v, const float* F,
+                     const double* mass, double dt, double c, double kT_acc, uint64_t seed,
+                     uint64_t step, float* pos32, hipStream_t st) {
+  if (n_cap <= 0) return;
+  hipLaunchKernelGGL(k_lfm_step, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, x, v, F, mass,
+                     dt, c, kT_acc, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)step,
+                     (uint32_t)(step >> 32), pos32);
 }
 
 void launch_kinetic(const int* dims, int nmol_cap, const int* off, const double* v,

@@ -167,3 +167,75 @@ def test_serving_respects_capacity_and_budget():
         got.update(small.poll())
         assert rounds < 20000
     print(f"{len(ids)} requests served under a 24 MiB budget in {rounds} rounds (largest {big} atoms)")
+
+
+# ------------------------------------------------------- LF-Middle Langevin
+def test_langevin_matches_oracle():
+    s = w.single_molecule(24, seed=5, n_species=4)
+    announce("LF-Middle Langevin vs oracle, 24 atoms, 20 steps, 300 K, 50/ps")
+    pot, at, mt = potential(4, "fp32")
+    v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(1))
+    pos, sp, off = to_dev(s)
+    x = torch.from_numpy(s.pos.astype(np.float64)).cuda()
+    v = torch.from_numpy(v0.copy()).cuda()
+    m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+    _, F = pot.energy_forces(pos, sp, off, None)
+    Ep, Ek = pot.langevin_steps(x, v, F, m, sp, off, 0.5, 20, 300.0, 50.0, seed=2024)
+    pot.check()
+
+    def ff(x32):
+        r = o.energy_forces(x32, s.species, s.mol_offsets, None, aev_table=at, mlp_table=mt)
+        return r.E, r.F
+
+    xo, vo, rec = o.langevin_middle(s.pos.astype(np.float64), v0, w.MASS_AMU[s.species], ff,
+                                    0.5, 20, 300.0, 50.0, seed=2024)
+    dx = np.abs(x.cpu().numpy() - xo).max()
+    dv = np.abs(v.cpu().numpy() - vo).max()
+    print(f"max|dx| {dx:.2e}  max|dv| {dv:.2e}  KE {Ek.item():.4f} vs {rec[-1][2]:.4f}")
+    assert dx <= 1e-6 and dv <= 1e-6
+    assert abs(Ek.item() - rec[-1][2]) <= 1e-5 * abs(rec[-1][2])
+    assert abs(Ep.item() - rec[-1][1]) <= 1e-5 * max(1.0, abs(rec[-1][1]))
+
+
+def test_langevin_split_calls_draw_the_same_noise():
+    s = w.single_molecule(40, seed=6, n_species=7)
+    announce("Langevin 20 steps in one call vs 10 + 10")
+    pot, at, mt = potential(7, "fp32")
+    v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(2))
+    pos, sp, off = to_dev(s)
+    m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+    res = []
+    for split in ((20,), (10, 10)):
+        x = torch.from_numpy(s.pos.astype(np.float64)).cuda()
+        v = torch.from_numpy(v0.copy()).cuda()
+        _, F = pot.energy_forces(pos, sp, off, None)
+        k0 = 0
+        for nstep in split:
+            pot.langevin_steps(x, v, F, m, sp, off, 0.5, nstep, 300.0, 5.0, seed=99, step0=k0)
+            k0 += nstep
+        pot.check()
+        res.append((x.cpu().numpy(), v.cpu().numpy()))
+    # the same draws: only the order of the FP32 force atomics differs
+    # (a different draw would move atoms by ~1e-2 A)
+    assert np.abs(res[0][0] - res[1][0]).max() <= 1e-7
+    assert np.abs(res[0][1] - res[1][1]).max() <= 1e-7
+
+
+def test_langevin_full_friction_draws_the_temperature():
+    # c = exp(-friction dt) ~ 0: after one step every velocity is a fresh
+    # Maxwell-Boltzmann draw, so 2 KE / (3 N kB) estimates T
+    s = w.config_system(2)
+    announce(f"Langevin thermalization, {s.n_atoms}-atom water box")
+    pot, at, mt = potential(4, "fp32")
+    pos, sp, off = to_dev(s)
+    x = torch.from_numpy(s.pos.astype(np.float64)).cuda()
+    v = torch.zeros((s.n_atoms, 3), dtype=torch.float64, device="cuda")
+    m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+    _, F = pot.energy_forces(pos, sp, off, s.box)
+    for T in (300.0, 77.0):
+        _, Ek = pot.langevin_steps(x, v, F, m, sp, off, 0.5, 1, T, 1e6, seed=5, step0=int(T),
+                                   box=s.box)
+        pot.check()
+        T_est = 2 * Ek.item() / (3 * s.n_atoms * o.integrator.KB_EV)
+        print(f"T {T}: estimate {T_est:.2f}")
+        assert abs(T_est / T - 1) < 5 * np.sqrt(2.0 / (3 * s.n_atoms))
