@@ -306,6 +306,16 @@ nnp_status nnp_server_create(nnp_handle* h, size_t hbm_budget_bytes,
                              void* stream, nnp_server** out);
 void nnp_server_destroy(nnp_server* s);
 
+/* Switches the server from velocity Verlet to LF-Middle Langevin dynamics
+ * (NVT; Methods, "Other Features"; the scheme and the noise of
+ * nnp_langevin_steps).  Only before the first nnp_server_step (else
+ * NNP_E_INVALID).  A request's noise stream is keyed by its req_id (as the
+ * seed) and counted by the atom's index inside the request and the request's
+ * own step, so a request draws the same numbers alone and in any batch; its
+ * submitted v is taken as v_{-1/2}, and its result holds x_n and v_{n-1/2}
+ * after n steps (n + 1 force evaluations, as with velocity Verlet). */
+nnp_status nnp_server_set_langevin(nnp_server* s, double temperature_K, double friction_per_ps);
+
 /* Queues a request (host arrays are copied).  x, v: float64 [n_atoms][3];
  * species: int32 [n_atoms]; n_steps >= 1.  NNP_E_BUSY if the request can
  * never fit the server's capacity. */

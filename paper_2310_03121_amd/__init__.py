@@ -356,6 +356,12 @@ class Server:
                 pass
             self._s = None
 
+    def set_langevin(self, temperature_K, friction_per_ps):
+        """LF-Middle Langevin instead of velocity Verlet (before the first step)."""
+        capi.check(self._lib.nnp_server_set_langevin(self._s, float(temperature_K),
+                                                     float(friction_per_ps)),
+                   "nnp_server_set_langevin")
+
     def submit(self, req_id, x, v, species, n_steps):
         x = np.ascontiguousarray(x, np.float64)
         v = np.ascontiguousarray(v, np.float64)

@@ -77,6 +77,7 @@ _SIGS = [
                                       _P, C.c_size_t, _P]),
     ("nnp_server_create", C.c_int, [_P, C.c_size_t, _I, _I, C.c_double, _P, _P, C.POINTER(_P)]),
     ("nnp_server_destroy", None, [_P]),
+    ("nnp_server_set_langevin", C.c_int, [_P, C.c_double, C.c_double]),
     ("nnp_server_submit", C.c_int, [_P, C.c_int64, _I, _P, _P, _P, _I]),
     ("nnp_server_step", C.c_int, [_P]),
     ("nnp_server_active", _I, [_P]),

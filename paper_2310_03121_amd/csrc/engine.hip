@@ -995,6 +995,9 @@ struct nnp_server {
   nnp_handle* h = nullptr;
   hipStream_t st = nullptr;
   double dt = 0.5;
+  // integrator: velocity Verlet, or LF-Middle Langevin after nnp_server_set_langevin
+  bool lfm = false;
+  double lfm_c = 1.0, lfm_kT = 0.0;
   double mass_tab[kMaxS] = {};
   int max_atoms = 0, max_mols = 0;
   size_t bytes = 0;
@@ -1006,6 +1009,7 @@ struct nnp_server {
   float* pos32 = nullptr;
   int *off = nullptr, *kdone = nullptr, *nsteps = nullptr;
   double *epot = nullptr, *ekin = nullptr;
+  uint64_t* seed = nullptr;  // per molecule: the request id (Langevin noise key)
   // repack scratch and staging of admitted atoms
   double *x2 = nullptr, *v2 = nullptr, *m2 = nullptr;
   int* sp2 = nullptr;
@@ -1020,6 +1024,7 @@ struct nnp_server {
   int *h_src = nullptr, *h_off = nullptr, *h_kdone = nullptr, *h_nsteps = nullptr,
       *h_dims = nullptr, *h_in_sp = nullptr;
   double *h_in_x = nullptr, *h_in_v = nullptr, *h_in_m = nullptr, *h_out = nullptr;
+  uint64_t* h_seed = nullptr;
   hipEvent_t ev_upload = nullptr;
   // graph of one step
   hipGraph_t graph = nullptr;
@@ -1053,6 +1058,7 @@ size_t server_state_bytes(int A, int M) {
   add((size_t)A * 24); add((size_t)A * 24); add((size_t)A * 8); add((size_t)A * 4);
   add((size_t)A * 12); add((size_t)A * 4);
   add((size_t)A * 24); add((size_t)A * 24); add((size_t)A * 8); add((size_t)A * 4);
+  add((size_t)M * 8);
   return b;
 }
 
@@ -1067,8 +1073,12 @@ nnp_status server_enqueue_step(nnp_server* s) {
   EvalIO io{-1, -1, nullptr, s->x, s->sp, s->off, s->epot, s->F, 1.f, nullptr, nullptr};
   nnp_status r = run(h, P, s->ws, io, s->st);
   if (r != NNP_OK) return r;
-  launch_serve_integrate(dims, s->max_atoms, at<int>(s->ws, P.mol), s->kdone, s->nsteps, s->x,
-                         s->v, s->F, s->m, s->dt, s->st);
+  if (s->lfm)
+    launch_serve_lfm(dims, s->max_atoms, at<int>(s->ws, P.mol), s->off, s->kdone, s->nsteps,
+                     s->seed, s->x, s->v, s->F, s->m, s->dt, s->lfm_c, s->lfm_kT, s->st);
+  else
+    launch_serve_integrate(dims, s->max_atoms, at<int>(s->ws, P.mol), s->kdone, s->nsteps, s->x,
+                           s->v, s->F, s->m, s->dt, s->st);
   launch_kinetic(dims, s->max_mols, s->off, s->v, s->m, s->ekin, s->kdone, s->st);
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
 }
@@ -1139,11 +1149,12 @@ nnp_status nnp_server_create(nnp_handle* h, size_t budget, int32_t max_atoms, in
   s->in_v = (double*)take((size_t)A * 24);
   s->in_m = (double*)take((size_t)A * 8);
   s->in_sp = (int*)take((size_t)A * 4);
+  s->seed = (uint64_t*)take((size_t)max_mols * 8);
   s->ws = s->dmem + align_up(sb, 256);
   // pinned host mirrors
   // src, in_sp | off, kdone, nsteps | dims | in_x, in_v, in_m | out (x, v, energies)
   const size_t hb = (size_t)A * 8 + (size_t)(max_mols + 1) * 12 + 64 + (size_t)A * 56 +
-                    (size_t)A * 48 + (size_t)max_mols * 16 + 4096;
+                    (size_t)A * 48 + (size_t)max_mols * 24 + 4096;
   if (hipHostMalloc((void**)&s->hmem, hb) != hipSuccess) {
     (void)hipFree(s->dmem);
     (void)hipStreamDestroy(s->st);
@@ -1166,6 +1177,7 @@ nnp_status nnp_server_create(nnp_handle* h, size_t budget, int32_t max_atoms, in
   s->h_in_v = (double*)htake((size_t)A * 24);
   s->h_in_m = (double*)htake((size_t)A * 8);
   s->h_out = (double*)htake((size_t)A * 48 + (size_t)max_mols * 16);
+  s->h_seed = (uint64_t*)htake((size_t)max_mols * 8);
   (void)hipEventCreateWithFlags(&s->ev_upload, hipEventDisableTiming);
   // empty batch: counts 0, offsets {0}
   s->h_dims[0] = 0;
@@ -1212,6 +1224,16 @@ nnp_status nnp_server_submit(nnp_server* s, int64_t id, int32_t n, const double*
   r->sp.assign(species, species + n);
   r->t_submit = now_s();
   s->pending.push_back(r);
+  return NNP_OK;
+}
+
+nnp_status nnp_server_set_langevin(nnp_server* s, double temperature, double friction) {
+  if (!s || !(temperature >= 0.0) || !(friction >= 0.0)) return NNP_E_INVALID;
+  // the integrator is part of the captured step: fixed before the first step
+  if (s->warmed || !s->active.empty()) return NNP_E_INVALID;
+  s->lfm = true;
+  s->lfm_c = std::exp(-friction * 1e-3 * s->dt);
+  s->lfm_kT = 8.617333262e-5 * temperature * 9.648533e-3;
   return NNP_OK;
 }
 
@@ -1266,6 +1288,7 @@ nnp_status nnp_server_step(nnp_server* s) {
       for (int i = 0; i < r->n; ++i) s->h_src[t++] = old_start[q] + i;
       s->h_kdone[mcount] = r->k;
       s->h_nsteps[mcount] = r->n_steps;
+      s->h_seed[mcount] = (uint64_t)r->id;
       s->h_off[++mcount] = t;
       ++aq;
     }
@@ -1285,6 +1308,7 @@ nnp_status nnp_server_step(nnp_server* s) {
       r->t_admit = now;
       s->h_kdone[mcount] = 0;
       s->h_nsteps[mcount] = r->n_steps;
+      s->h_seed[mcount] = (uint64_t)r->id;
       s->h_off[++mcount] = t;
     }
     s->h_dims[0] = t;
@@ -1302,6 +1326,7 @@ nnp_status nnp_server_step(nnp_server* s) {
     if (mcount) {
       ok &= hip_ok(hipMemcpyAsync(s->kdone, s->h_kdone, (size_t)mcount * 4, hipMemcpyHostToDevice, st));
       ok &= hip_ok(hipMemcpyAsync(s->nsteps, s->h_nsteps, (size_t)mcount * 4, hipMemcpyHostToDevice, st));
+      ok &= hip_ok(hipMemcpyAsync(s->seed, s->h_seed, (size_t)mcount * 8, hipMemcpyHostToDevice, st));
     }
     ok &= hip_ok(hipMemcpyAsync(at<int>(s->ws, s->P.dims), s->h_dims, 8, hipMemcpyHostToDevice, st));
     ok &= hip_ok(hipEventRecord(s->ev_upload, st));

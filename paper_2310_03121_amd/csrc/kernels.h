@@ -146,6 +146,10 @@ void launch_vv_kick(const int* dims, int n_cap, double* v, const float* F, const
 void launch_lfm_step(const int* dims, int n_cap, double* x, double* v, const float* F,
                      const double* mass, double dt, double c, double kT_acc, uint64_t seed,
                      uint64_t step, float* pos32, hipStream_t st);
+void launch_serve_lfm(const int* dims, int n_cap, const int* mol, const int* off,
+                      const int* kdone, const int* nsteps, const uint64_t* seed, double* x,
+                      double* v, const float* F, const double* mass, double dt, double c,
+                      double kT_acc, hipStream_t st);
 void launch_kinetic(const int* dims, int nmol_cap, const int* off, const double* v,
                     const double* mass, double* ke, int* kdone, hipStream_t st);
 void launch_gather_rows(const int* src, int n, const double* x_old, const double* v_old,

@@ -96,33 +96,65 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& n0,
 // x += dt/2 v.  R: the first three normals of Philox block (atom, step lo,
 // step hi, 0) under key (seed lo, seed hi).  kT_acc = kB T * (A/fs^2 per
 // eV/A/amu), so kT_acc / m is the velocity variance in A^2/fs^2.
-__global__ __launch_bounds__(256) void k_lfm_step(const int* __restrict__ dims,
-                                                  double* __restrict__ x, double* __restrict__ v,
-                                                  const float* __restrict__ F,
-                                                  const double* __restrict__ mass, double dt,
-                                                  double c, double kT_acc, uint32_t seed_lo,
-                                                  uint32_t seed_hi, uint32_t step_lo,
-                                                  uint32_t step_hi, float* __restrict__ pos32) {
-  const int n = dims[0];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const Philox4 w = philox4x32_10((uint32_t)i, step_lo, step_hi, 0u, seed_lo, seed_hi);
+__device__ __forceinline__ void lfm_update(double* __restrict__ x, double* __restrict__ v,
+                                           const float* __restrict__ F, double m, double dt,
+                                           double c, double kT_acc, uint32_t ctr0, uint64_t step,
+                                           uint64_t seed, float* __restrict__ pos32) {
+  const Philox4 w = philox4x32_10(ctr0, (uint32_t)step, (uint32_t)(step >> 32), 0u,
+                                  (uint32_t)seed, (uint32_t)(seed >> 32));
   double R[4];
   box_muller(w.v[0], w.v[1], R[0], R[1]);
   box_muller(w.v[2], w.v[3], R[2], R[3]);
-  const double m = mass[i];
   const double s = dt * kAccUnit / m;
   const double sig = sqrt((1.0 - c * c) * kT_acc / m);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double vv = v[3 * i + k] + s * (double)F[3 * i + k];
-    double xx = x[3 * i + k] + 0.5 * dt * vv;
+    double vv = v[k] + s * (double)F[k];
+    double xx = x[k] + 0.5 * dt * vv;
     vv = c * vv + sig * R[k];
     xx += 0.5 * dt * vv;
-    v[3 * i + k] = vv;
-    x[3 * i + k] = xx;
-    pos32[3 * i + k] = (float)xx;
+    v[k] = vv;
+    x[k] = xx;
+    if (pos32) pos32[k] = (float)xx;
   }
+}
+
+__global__ __launch_bounds__(256) void k_lfm_step(const int* __restrict__ dims,
+                                                  double* __restrict__ x, double* __restrict__ v,
+                                                  const float* __restrict__ F,
+                                                  const double* __restrict__ mass, double dt,
+                                                  double c, double kT_acc, uint64_t seed,
+                                                  uint64_t step, float* __restrict__ pos32) {
+  const int n = dims[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  lfm_update(x + 3 * i, v + 3 * i, F + 3 * i, mass[i], dt, c, kT_acc, (uint32_t)i, step, seed,
+             pos32 + 3 * i);
+}
+
+// Server step, LF-Middle: a molecule with k < n steps done takes one step
+// with its own noise stream (counter: the atom's index inside its molecule
+// and the molecule's step k; key: the request's seed), so a request draws
+// the same numbers alone and inside any batch; at k == n it waits to be
+// retired with x_n and v_{n-1/2}.
+__global__ __launch_bounds__(256) void k_serve_lfm(const int* __restrict__ dims,
+                                                   const int* __restrict__ mol,
+                                                   const int* __restrict__ off,
+                                                   const int* __restrict__ kdone,
+                                                   const int* __restrict__ nsteps,
+                                                   const uint64_t* __restrict__ seed,
+                                                   double* __restrict__ x, double* __restrict__ v,
+                                                   const float* __restrict__ F,
+                                                   const double* __restrict__ mass, double dt,
+                                                   double c, double kT_acc) {
+  const int n = dims[0], nmol = dims[1];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int m = clampi(mol[i], nmol);
+  const int k = kdone[m], ns = nsteps[m];
+  if (k >= ns) return;
+  lfm_update(x + 3 * i, v + 3 * i, F + 3 * i, mass[i], dt, c, kT_acc, (uint32_t)(i - off[m]),
+             (uint64_t)k, seed[m], nullptr);
 }
 
 // Kinetic energy per molecule; with `kdone`, also advances the molecule's
@@ -230,8 +262,16 @@ void launch_lfm_step(const int* dims, int n_cap, double* x, double* v, const flo
                      uint64_t step, float* pos32, hipStream_t st) {
   if (n_cap <= 0) return;
   hipLaunchKernelGGL(k_lfm_step, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, x, v, F, mass,
-                     dt, c, kT_acc, (uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)step,
-                     (uint32_t)(step >> 32), pos32);
+                     dt, c, kT_acc, seed, step, pos32);
+}
+
+void launch_serve_lfm(const int* dims, int n_cap, const int* mol, const int* off,
+                      const int* kdone, const int* nsteps, const uint64_t* seed, double* x,
+                      double* v, const float* F, const double* mass, double dt, double c,
+                      double kT_acc, hipStream_t st) {
+  if (n_cap <= 0) return;
+  hipLaunchKernelGGL(k_serve_lfm, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, mol, off,
+                     kdone, nsteps, seed, x, v, F, mass, dt, c, kT_acc);
 }
 
 void launch_kinetic(const int* dims, int nmol_cap, const int* off, const double* v,

@@ -239,3 +239,48 @@ def test_langevin_full_friction_draws_the_temperature():
         T_est = 2 * Ek.item() / (3 * s.n_atoms * o.integrator.KB_EV)
         print(f"T {T}: estimate {T_est:.2f}")
         assert abs(T_est / T - 1) < 5 * np.sqrt(2.0 / (3 * s.n_atoms))
+
+
+def test_serving_langevin_alone_equals_mix():
+    # each request's noise is keyed by its id and counted by its own atoms
+    # and steps: inside the batch it follows the same trajectory as the same
+    # molecule integrated alone with nnp_langevin_steps(seed=id)
+    from paper_2310_03121_amd import Server
+    announce("server, LF-Middle Langevin: batch vs each request alone")
+    pot, at, mt = potential(7, "fp32")
+    reqs = _requests(16, seed=4)
+    srv = Server(pot, hbm_budget_bytes=8 << 30, max_atoms=700, max_mols=10, dt_fs=0.5,
+                 mass_amu=w.MASS_AMU)
+    srv.set_langevin(300.0, 20.0)
+    for r in reqs:
+        assert srv.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
+                          r.n_steps) == 0
+    done = {}
+    steps = 0
+    max_active = 0
+    while len(done) < len(reqs):
+        srv.step()
+        steps += 1
+        max_active = max(max_active, srv.active)
+        for i in srv.poll():
+            done[i] = srv.result(i, reqs[i].system.n_atoms)
+        assert steps < 5000
+    assert max_active > 1
+    worst = 0.0
+    for r in reqs[:8]:
+        s = r.system
+        pos, sp, off = to_dev(s)
+        x = torch.from_numpy(s.pos.astype(np.float64)).cuda()
+        v = torch.from_numpy(r.vel.copy()).cuda()
+        m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+        _, F = pot.energy_forces(pos, sp, off, None)
+        Ep, Ek = pot.langevin_steps(x, v, F, m, sp, off, 0.5, r.n_steps, 300.0, 20.0,
+                                    seed=r.req_id)
+        pot.check()
+        d = done[r.req_id]
+        dx = np.abs(d["x"] - x.cpu().numpy()).max()
+        worst = max(worst, dx)
+        assert dx <= 1e-4, (r.req_id, dx)
+        assert abs(d["e_pot"] - Ep.item()) <= 1e-5 * max(1.0, abs(Ep.item()))
+        assert abs(d["e_kin"] - Ek.item()) <= 1e-5 * max(1.0, abs(Ek.item()))
+    print(f"Langevin alone vs mix: worst max|dx| {worst:.2e} A")
