@@ -16,7 +16,8 @@ Model Support"):
 * ``aev``        radial and angular atomic environment vectors;
 * ``mlp``        per-element networks with CELU, energies and their adjoint;
 * ``potential``  energy per molecule, analytic forces, weight gradients,
-                 and the mean over an ensemble of networks;
+                 the mean over an ensemble of networks, and a subset of a
+                 larger system (mechanical embedding);
 * ``integrator`` velocity-Verlet and LF-Middle Langevin MD in eV, A, amu, fs;
 * ``rng``        the Philox4x32-10 counter-based generator and Box-Muller.
 
@@ -25,7 +26,8 @@ Every function is plain float64 NumPy with no blocking or fusion.
 from .neighbors import pair_list, pair_list_loops
 from .aev import aev, aev_backward, pair_block_index, n_features
 from .mlp import celu, celu_grad, mlp_forward, mlp_backward_input, mlp_weight_grads
-from .potential import energy_forces, energy, weight_gradients, EFResult, ensemble_energy_forces
+from .potential import (energy_forces, energy, weight_gradients, EFResult,
+                        ensemble_energy_forces, subset_energy_forces)
 from .integrator import velocity_verlet, kinetic_energy, langevin_middle
 from .rng import philox4x32_10, atom_normals
 
@@ -33,6 +35,6 @@ __all__ = [
     "pair_list", "pair_list_loops", "aev", "aev_backward", "pair_block_index",
     "n_features", "celu", "celu_grad", "mlp_forward", "mlp_backward_input",
     "mlp_weight_grads", "energy_forces", "energy", "weight_gradients", "EFResult",
-    "ensemble_energy_forces",
+    "ensemble_energy_forces", "subset_energy_forces",
     "velocity_verlet", "kinetic_energy", "langevin_middle", "philox4x32_10", "atom_normals",
 ]

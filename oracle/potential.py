@@ -139,3 +139,24 @@ def ensemble_energy_forces(sys_or_pos, species=None, mol_offsets=None, box=None,
     if forces:
         F = -aev_backward(g / M, ac)
     return EFResult(E, F, Ea, G)
+
+
+def subset_energy_forces(pos_all, idx, species, mol_offsets, box=None, *, aev_table,
+                         mlp_table, F_other=None):
+    """The potential on a subset of a larger system (Results, "Performance
+    of MLPs": a ligand modelled by the network inside a classically modelled
+    system; mechanical embedding, so the network sees only the subset).
+    Subset atom i is row idx[i] of ``pos_all``; ``species`` and
+    ``mol_offsets`` are subset-local.  Returns the subset's molecular
+    energies and the full-system force array: ``F_other`` (zeros if None)
+    plus the subset's forces added at rows idx."""
+    idx = np.asarray(idx, dtype=np.int64)
+    pos_all = np.asarray(pos_all)
+    if idx.size != np.unique(idx).size:
+        raise ValueError("subset rows must be distinct")
+    r = energy_forces(pos_all[idx], species, mol_offsets, box, aev_table=aev_table,
+                      mlp_table=mlp_table)
+    F = np.zeros(pos_all.shape, dtype=np.float64) if F_other is None else \
+        np.array(F_other, dtype=np.float64)
+    F[idx] += r.F
+    return r.E, F

@@ -575,3 +575,48 @@ def test_langevin_free_particles_follow_ornstein_uhlenbeck():
     z = v.ravel()
     assert abs(z.var() / var - 1.0) < 5 * math.sqrt(2.0 / z.size)
     assert abs(z.mean()) < 5 * math.sqrt(var / z.size)
+
+
+# ------------------------------------------------- subset of a larger system
+def _subset_case():
+    lig = w.single_molecule(24, seed=3, n_species=4)
+    rng = np.random.default_rng(8)
+    mm = rng.uniform(-20.0, 30.0, size=(300, 3)).astype(np.float32)
+    full = np.concatenate([mm, lig.pos]).astype(np.float32)
+    perm = rng.permutation(full.shape[0])
+    full = full[perm]
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    idx = inv[300 + np.arange(24)]  # rows of the ligand atoms after the shuffle
+    return lig, full, idx
+
+
+def test_subset_is_the_subset_alone():
+    lig, full, idx = _subset_case()
+    at, mt = w.aev_table(4), w.mlp_table(4)
+    assert np.array_equal(full[idx], lig.pos)
+    E, F = o.subset_energy_forces(full, idx, lig.species, lig.mol_offsets, None, aev_table=at,
+                                  mlp_table=mt)
+    r = o.energy_forces(lig, aev_table=at, mlp_table=mt)
+    assert np.array_equal(E, r.E) and np.array_equal(F[idx], r.F)
+    rest = np.setdiff1d(np.arange(full.shape[0]), idx)
+    assert np.all(F[rest] == 0.0)
+
+
+def test_subset_ignores_the_other_atoms_and_keeps_their_forces():
+    # mechanical embedding: moving atoms outside the subset changes nothing
+    # in the subset's energy, and their forces are passed through untouched
+    lig, full, idx = _subset_case()
+    at, mt = w.aev_table(4), w.mlp_table(4)
+    rest = np.setdiff1d(np.arange(full.shape[0]), idx)
+    moved = full.copy()
+    moved[rest] += np.float32(0.37)
+    Fo = np.random.default_rng(2).normal(size=full.shape)
+    E1, F1 = o.subset_energy_forces(full, idx, lig.species, lig.mol_offsets, None,
+                                    aev_table=at, mlp_table=mt, F_other=Fo)
+    E2, F2 = o.subset_energy_forces(moved, idx, lig.species, lig.mol_offsets, None,
+                                    aev_table=at, mlp_table=mt, F_other=Fo)
+    assert np.array_equal(E1, E2) and np.array_equal(F1, F2)
+    assert np.array_equal(F1[rest], Fo[rest])
+    # the subset's forces still sum to zero (momentum conservation)
+    assert np.abs((F1[idx] - Fo[idx]).sum(0)).max() < 1e-10
