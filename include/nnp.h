@@ -173,6 +173,27 @@ nnp_status nnp_energy_forces(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
                              double* E, float* F, void* workspace,
                              size_t workspace_bytes, void* stream);
 
+/* A subset of a larger system (the ML/MM setting of Results, "Performance of
+ * MLPs": the potential covers a 53-atom ligand inside a 134,099-atom system,
+ * the rest is classical; mechanical embedding, so the potential sees only
+ * the subset).  Subset atom i is row idx[i] of the full-system arrays:
+ *   idx      device int32 [n_sub], distinct rows in [0, n_total);
+ *   pos_all  device float32 [n_total][3];
+ *   species, mol_offsets  device int32, per subset atom / subset molecule
+ *            (subset-local, as in nnp_energy_forces);
+ *   E        device float64 [n_mol], the subset's molecular energies;
+ *   F_all    device float32 [n_total][3] or NULL: the subset's forces are
+ *            ADDED to rows idx[i] (other rows untouched), so a caller can
+ *            pass an array that already holds the classical forces.
+ * Rows of idx outside [0, n_total) set NNP_E_INVALID in the status word and
+ * are neither read nor written; repeated rows are the caller's error.  The
+ * workspace is sized for n_sub atoms (nnp_workspace_bytes(h, n_sub, ...)). */
+nnp_status nnp_energy_forces_subset(nnp_handle* h, int32_t n_sub, int32_t n_mol,
+                                    const int32_t* idx, int32_t n_total, const float* pos_all,
+                                    const int32_t* species, const int32_t* mol_offsets,
+                                    const float* box, double* E, float* F_all, void* workspace,
+                                    size_t ws_bytes, void* stream);
+
 /* Adjoint for L = sum_m dL_dE[m] * E_m.  Recomputes the forward pass (the
  * symmetry functions are recomputed, not stored between calls), then writes
  *   dL_dpos    device, float32 [n_atoms][3] = sum_m dL_dE[m] dE_m/dpos, or NULL;

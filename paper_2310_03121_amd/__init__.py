@@ -155,6 +155,22 @@ class Potential:
             _ptr(ws), ws.numel(), _stream()), "nnp_energy_forces")
         return E, F
 
+    def energy_forces_subset(self, idx, pos_all, species, mol_offsets, F_all=None, box=None):
+        """Energies of the subset rows idx of a larger system; its forces are
+        added into F_all (float32 [n_total, 3]) when given.  Returns E."""
+        idx = idx.to(torch.int32).contiguous()
+        pos_all = pos_all.contiguous()
+        n_sub = idx.shape[0]
+        n_mol = mol_offsets.shape[0] - 1
+        E = torch.empty(n_mol, dtype=torch.float64, device=pos_all.device)
+        ws = self.workspace(n_sub, n_mol, box, pos_all.device)
+        b, bp = self._box_arg(box)
+        capi.check(self._lib.nnp_energy_forces_subset(
+            self._h, n_sub, n_mol, _ptr(idx), pos_all.shape[0], _ptr(pos_all), _ptr(species),
+            _ptr(mol_offsets), bp, _ptr(E), _ptr(F_all), _ptr(ws), ws.numel(), _stream()),
+            "nnp_energy_forces_subset")
+        return E
+
     def backward(self, pos, species, mol_offsets, dL_dE, box=None, want_pos=True,
                  want_params=True):
         """(dL/dpos float32 [N,3] or None, dL/dparams float32 [P] or None, E)."""

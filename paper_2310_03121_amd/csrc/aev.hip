@@ -238,6 +238,8 @@ constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 
 // Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
 // sign = +1 writes forces (-dE/dr); sign = -1 writes the gradient dE/dr.
+// With gidx, atom i's force goes to row gidx[i] of out ([n_total][3]; rows
+// outside [0, n_total) are skipped; staging reports them).
 template <typename GT>
 __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C,
                                                  const float4* __restrict__ rec,
@@ -245,7 +247,8 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
                                                  const int2* __restrict__ counts, int cap,
                                                  const int* __restrict__ row_of,
                                                  const GT* __restrict__ g, int ldg,
-                                                 float* __restrict__ out, float sign) {
+                                                 float* __restrict__ out, float sign,
+                                                 const int* __restrict__ gidx, int n_total) {
   extern __shared__ float4 lds4[];
   const int n = dims[0];
   const int w = threadIdx.x >> 6;
@@ -376,10 +379,13 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   float sx = 0.f, sy = 0.f, sz2 = 0.f;
   for (int e = lane; e < nr; e += kWave) {
     const float4 gv = grad[e];
-    const int j = clampi(e < kSpecRec ? j0 : nrow[e], n);
-    unsafeAtomicAdd(out + 3 * j, -sign * gv.x);
-    unsafeAtomicAdd(out + 3 * j + 1, -sign * gv.y);
-    unsafeAtomicAdd(out + 3 * j + 2, -sign * gv.z);
+    int j = clampi(e < kSpecRec ? j0 : nrow[e], n);
+    if (gidx) j = gidx[j];
+    if (!gidx || (j >= 0 && j < n_total)) {
+      unsafeAtomicAdd(out + 3 * j, -sign * gv.x);
+      unsafeAtomicAdd(out + 3 * j + 1, -sign * gv.y);
+      unsafeAtomicAdd(out + 3 * j + 2, -sign * gv.z);
+    }
     sx += gv.x;
     sy += gv.y;
     sz2 += gv.z;
@@ -387,10 +393,11 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   sx = wave_sum_rows(sx);
   sy = wave_sum_rows(sy);
   sz2 = wave_sum_rows(sz2);
-  if (lane == 0) {
-    unsafeAtomicAdd(out + 3 * i, sign * sx);
-    unsafeAtomicAdd(out + 3 * i + 1, sign * sy);
-    unsafeAtomicAdd(out + 3 * i + 2, sign * sz2);
+  const int gi = gidx ? gidx[i] : i;
+  if (lane == 0 && (!gidx || (gi >= 0 && gi < n_total))) {
+    unsafeAtomicAdd(out + 3 * gi, sign * sx);
+    unsafeAtomicAdd(out + 3 * gi + 1, sign * sy);
+    unsafeAtomicAdd(out + 3 * gi + 2, sign * sz2);
   }
 }
 
@@ -415,19 +422,20 @@ template void launch_aev_fwd<bf16_t>(const int*, int, const AevConst&, const flo
 template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
-                    int ldg, float* out, float sign, hipStream_t st) {
+                    int ldg, float* out, float sign, const int* gidx, int n_total,
+                    hipStream_t st) {
   if (n_cap <= 0) return;
   const size_t lds = (size_t)4 * cap * kBwdBytesPerNbr;
   static const bool attr = (ensure_lds(k_aev_bwd<GT>), true);
   (void)attr;
   hipLaunchKernelGGL(k_aev_bwd<GT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec, nbr,
-                     counts, cap, row_of, g, ldg, out, sign);
+                     counts, cap, row_of, g, ldg, out, sign, gidx, n_total);
 }
 template void launch_aev_bwd<float>(const int*, int, const AevConst&, const float4*, const int*,
                                     const int2*, int, const int*, const float*, int, float*, float,
-                                    hipStream_t);
+                                    const int*, int, hipStream_t);
 template void launch_aev_bwd<bf16_t>(const int*, int, const AevConst&, const float4*, const int*,
                                      const int2*, int, const int*, const bf16_t*, int, float*,
-                                     float, hipStream_t);
+                                     float, const int*, int, hipStream_t);
 
 }  // namespace nnp

@@ -217,6 +217,8 @@ struct EvalIO {
   float sign;
   const double* dLdE;   // null: unit upstream
   float* dparams;       // weight gradients, may be null
+  const int* gidx = nullptr;  // subset mode: rows of pos and out3 ([n_total][3]) per atom;
+  int n_total = 0;            // forces are added to out3, not stored
 };
 
 template <typename T>
@@ -239,8 +241,8 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
 
   {
     StageTimer t(h, ST_STAGE, st);
-    launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.species, io.off, S, xyzs,
-                 mol, io.out3, hist, status, st);
+    launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.gidx, io.n_total,
+                 io.species, io.off, S, xyzs, mol, io.gidx ? nullptr : io.out3, hist, status, st);
     launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
     launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
   }
@@ -419,7 +421,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
     StageTimer t(h, ST_AEVBWD, st);
     launch_aev_bwd<T>(dims, P.n, h->C, rec, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
-                      st);
+                      io.gidx, io.n_total, st);
   }
   if (io.dparams) {
     StageTimer t(h, ST_WGRAD, st);
@@ -752,6 +754,22 @@ nnp_status nnp_energy_forces(nnp_handle* h, int32_t n, int32_t nmol, const float
   return run(h, P, ws, io, static_cast<hipStream_t>(stream));
 }
 
+nnp_status nnp_energy_forces_subset(nnp_handle* h, int32_t n_sub, int32_t nmol,
+                                    const int32_t* idx, int32_t n_total, const float* pos_all,
+                                    const int32_t* species, const int32_t* off,
+                                    const float* box, double* E, float* F_all, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (!idx || n_total < 1 || !pos_all) return NNP_E_INVALID;
+  Plan P;
+  nnp_status s = check_common(h, n_sub, nmol, pos_all, species, off, box, ws, ws_bytes, P);
+  if (s != NNP_OK) return s;
+  if (!E) return NNP_E_INVALID;
+  EvalIO io{n_sub, nmol, pos_all, nullptr, species, off, E, F_all, 1.f, nullptr, nullptr};
+  io.gidx = idx;
+  io.n_total = n_total;
+  return run(h, P, ws, io, static_cast<hipStream_t>(stream));
+}
+
 nnp_status nnp_backward(nnp_handle* h, int32_t n, int32_t nmol, const float* pos,
                         const int32_t* species, const int32_t* off, const float* box,
                         const double* dLdE, float* dL_dpos, float* dL_dparams, double* E,
@@ -807,8 +825,8 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   int* dims = at<int>(ws, P.dims);
   uint32_t* status = at<uint32_t>(ws, P.status);
   float4* xyzs = at<float4>(ws, P.xyzs);
-  launch_stage(n, nmol, P.n, dims, pos, nullptr, species, off, h->S, xyzs, at<int>(ws, P.mol),
-               nullptr, at<int>(ws, P.hist), status, st);
+  launch_stage(n, nmol, P.n, dims, pos, nullptr, nullptr, 0, species, off, h->S, xyzs,
+               at<int>(ws, P.mol), nullptr, at<int>(ws, P.hist), status, st);
   launch_groups(dims, P.n, h->S, at<int>(ws, P.hist), at<GroupTable>(ws, P.gt),
                 at<int>(ws, P.perm), P.rows_cap, off, kWChunk, status, st);
   if (P.B.periodic)

@@ -90,8 +90,9 @@ __global__ void k_fill_i32(int* p, int v, int n);
 __global__ void k_fill_f32(float* p, float v, long n);
 __global__ void k_fill_f64(double* p, double v, int n);
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
-                  const double* pos64, const int* species, const int* off, int S, float4* xyzs,
-                  int* mol, float* Fzero, int* hist, uint32_t* status, hipStream_t st);
+                  const double* pos64, const int* gidx, int n_total, const int* species,
+                  const int* off, int S, float4* xyzs, int* mol, float* Fzero, int* hist,
+                  uint32_t* status, hipStream_t st);
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
                    int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
                    hipStream_t st);
@@ -124,7 +125,8 @@ void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4*
 template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
-                    int ldg, float* out, float sign, hipStream_t st);
+                    int ldg, float* out, float sign, const int* gidx, int n_total,
+                    hipStream_t st);
 
 // mlp.hip
 template <typename T>

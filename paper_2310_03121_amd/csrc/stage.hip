@@ -15,6 +15,7 @@ namespace nnp {
 __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __restrict__ dims,
                                                const float* __restrict__ pos,
                                                const double* __restrict__ pos64,
+                                               const int* __restrict__ gidx, int n_total,
                                                const int* __restrict__ species,
                                                const int* __restrict__ off, int S,
                                                float4* __restrict__ xyzs, int* __restrict__ mol,
@@ -34,17 +35,25 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __r
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     float x, y, z;
+    uint32_t st = 0;
+    int g = i;  // row of the position arrays
+    if (gidx) {  // subset of a larger system: gather by index
+      g = gidx[i];
+      if (g < 0 || g >= n_total) {
+        st |= kStOffsets;
+        g = 0;
+      }
+    }
     if (pos64) {  // MD state: the potential sees the FP32 rounding of x
-      x = (float)pos64[3 * i];
-      y = (float)pos64[3 * i + 1];
-      z = (float)pos64[3 * i + 2];
+      x = (float)pos64[3 * g];
+      y = (float)pos64[3 * g + 1];
+      z = (float)pos64[3 * g + 2];
     } else {
-      x = pos[3 * i];
-      y = pos[3 * i + 1];
-      z = pos[3 * i + 2];
+      x = pos[3 * g];
+      y = pos[3 * g + 1];
+      z = pos[3 * g + 2];
     }
     int s = species[i];
-    uint32_t st = 0;
     if (s < 0 || s >= S) {
       st |= kStSpecies;
       s = clampi(s, S);
@@ -237,11 +246,12 @@ __global__ void k_fill_f64(double* __restrict__ p, double v, int n) {
 // ----------------------------------------------------------------- launchers
 
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
-                  const double* pos64, const int* species, const int* off, int S, float4* xyzs,
-                  int* mol, float* Fzero, int* hist, uint32_t* status, hipStream_t st) {
+                  const double* pos64, const int* gidx, int n_total, const int* species,
+                  const int* off, int S, float4* xyzs, int* mol, float* Fzero, int* hist,
+                  uint32_t* status, hipStream_t st) {
   const int nblk = stage_blocks(n_cap);
   hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, dims, pos, pos64,
-                     species, off, S, xyzs, mol, Fzero, hist, status);
+                     gidx, n_total, species, off, S, xyzs, mol, Fzero, hist, status);
 }
 
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,

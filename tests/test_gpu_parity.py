@@ -427,3 +427,51 @@ def test_ensemble_rejects_weight_gradients():
         pot.backward(pos, sp, off, dLdE, None, want_pos=True, want_params=True)
     gp, gw, _ = pot.backward(pos, sp, off, dLdE, None, want_pos=True, want_params=False)
     assert gw is None and torch.isfinite(gp).all()
+
+
+# ------------------------------------------------ subset of a larger system
+@pytest.mark.parametrize("prec,f_tol,e_tol", [("fp32", 1e-5, 1e-5), ("bf16", 1e-2, 1e-2)])
+def test_subset_in_larger_system(prec, f_tol, e_tol):
+    # a 53-atom, seven-element ligand scattered through a 6,000-atom system
+    # whose other rows already hold (random) classical forces
+    lig = w.single_molecule(53, seed=3, n_species=7)
+    rng = np.random.default_rng(9)
+    n_total = 6000
+    full = rng.uniform(-30.0, 40.0, size=(n_total, 3)).astype(np.float32)
+    idx = rng.choice(n_total, size=53, replace=False).astype(np.int32)
+    full[idx] = lig.pos
+    F_mm = rng.normal(size=(n_total, 3)).astype(np.float32)
+    announce(f"subset {prec}: 53 of {n_total} atoms")
+    pot, at, mt = get_pot(7, prec)
+    sp = torch.from_numpy(lig.species).cuda()
+    off = torch.from_numpy(lig.mol_offsets).cuda()
+    F_all = torch.from_numpy(F_mm.copy()).cuda()
+    E = pot.energy_forces_subset(torch.from_numpy(idx).cuda(), torch.from_numpy(full).cuda(), sp,
+                                 off, F_all=F_all)
+    pot.check()
+    Eo, Fo = o.subset_energy_forces(full, idx, lig.species, lig.mol_offsets, None, aev_table=at,
+                                    mlp_table=mt, F_other=F_mm)
+    r = o.energy_forces(lig, aev_table=at, mlp_table=mt)
+    F = F_all.cpu().numpy()
+    rest = np.setdiff1d(np.arange(n_total), idx)
+    assert np.array_equal(F[rest], F_mm[rest])  # untouched
+    fr = rel_rms(F[idx] - F_mm[idx], Fo[idx] - F_mm[idx])
+    de = abs(E.item() - Eo[0]) / np.abs(r.E_atom).sum()
+    print(f"subset {prec}: |dE|/sum|E_i| {de:.3e}  force rel-RMS {fr:.3e}")
+    assert fr <= f_tol and de <= e_tol
+
+
+def test_subset_rejects_rows_outside_the_system():
+    lig = w.single_molecule(24, seed=3, n_species=4)
+    announce("subset with an out-of-range row")
+    pot, at, mt = get_pot(4, "fp32")
+    n_total = 100
+    full = torch.zeros((n_total, 3), dtype=torch.float32, device="cuda")
+    idx = torch.arange(24, dtype=torch.int32, device="cuda")
+    idx[5] = n_total + 7
+    F_all = torch.zeros((n_total, 3), dtype=torch.float32, device="cuda")
+    from paper_2310_03121_amd.capi import NNPError
+    pot.energy_forces_subset(idx, full, torch.from_numpy(lig.species).cuda(),
+                             torch.from_numpy(lig.mol_offsets).cuda(), F_all=F_all)
+    with pytest.raises(NNPError):
+        pot.check()
