@@ -102,6 +102,29 @@ def profiled_traffic(stage, workload_key):
     return rows[stage]
 
 
+def profiled_valu(stage, workload_key):
+    """(wave64 VALU instructions per wavefront, wavefronts per launch) of the
+    stage's kernel from the committed instruction-counter summary, or None
+    when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload_key}.md")
+    if not os.path.exists(path):
+        return None
+    digest, hit = None, None
+    for line in open(path):
+        if line.startswith("source_digest:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("|") and not line.startswith("|--"):
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 4 and cells[0] == stage:
+                try:
+                    hit = (float(cells[3]), float(cells[2]))
+                except ValueError:
+                    pass
+    if digest != source_digest():
+        return None
+    return hit
+
+
 WORKLOAD_KEYS = {"batch": "batch512x64", "water1500": "water1500", "water7667": "water7667",
                  "mol24": "mol24"}
 # Neighbor-list capacity per atom (the handle's max_neighbors): the batch's
@@ -481,6 +504,13 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
                 "flop_per_launch": ops, "avg_launch_ms": st[dom],
                 "pairs": main_r["pairs"], "triples": main_r["triples"]}
+        pv = profiled_valu(dom, WORKLOAD_KEYS[args.workload] + "_" + main_prec)
+        if pv is not None:
+            # issue-slot use: a wave64 VALU instruction occupies a 16-lane
+            # SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz
+            per_wave, waves = pv
+            roof["valu_instr_per_wave"] = per_wave
+            roof["valu_issue_frac"] = per_wave * waves * 4 / (1024 * 2.4e9 * st[dom] * 1e-3)
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": st[dom]}
