@@ -204,19 +204,27 @@ __global__ __launch_bounds__(256) void k_energy(const int* __restrict__ dims,
                                                 long mstride, const double* __restrict__ eself,
                                                 double* __restrict__ E, uint32_t* __restrict__ status) {
   __shared__ double part[4];
+  __shared__ double es[kMaxS];  // self energies: no dependent global gather per atom
   const int n = dims[0], nmol = dims[1];
   const int m = blockIdx.x;
   if (m >= nmol) return;
+  if (threadIdx.x < kMaxS) es[threadIdx.x] = eself[threadIdx.x];
+  __syncthreads();
   int a = off[m], b = off[m + 1];
   a = a < 0 ? 0 : (a > n ? n : a);
   b = b < a ? a : (b > n ? n : b);
-  const double inv_m = 1.0 / n_models;
   double acc = 0.0;
+  if (n_models == 1) {  // straight-line loop body: loads of several atoms in flight
 #pragma unroll 4
-  for (int i = a + (int)threadIdx.x; i < b; i += 256) {
-    double e = (double)eatom[i];
-    for (int k = 1; k < n_models; ++k) e += (double)eatom[k * mstride + i];
-    acc += e * inv_m + eself[species_of(xyzs[i])];
+    for (int i = a + (int)threadIdx.x; i < b; i += 256)
+      acc += (double)eatom[i] + es[__float_as_int(xyzs[i].w) & (kMaxS - 1)];
+  } else {
+    const double inv_m = 1.0 / n_models;
+    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
+      double e = (double)eatom[i];
+      for (int k = 1; k < n_models; ++k) e += (double)eatom[k * mstride + i];
+      acc += e * inv_m + es[__float_as_int(xyzs[i].w) & (kMaxS - 1)];
+    }
   }
   acc = wave_sum_d(acc);
   if (lane_id() == 0) part[threadIdx.x >> 6] = acc;
