@@ -96,9 +96,28 @@ __device__ __forceinline__ int pair_block(int p, int q, int S) {
   return lo * S - lo * (lo - 1) / 2 + (hi - lo);
 }
 
+// Angular pairs are decoded in chunks of 64, one pair per lane, into a
+// per-wave LDS table of codes (entry a | entry b << 10 | block << 20;
+// entries < 1024, blocks < 64); the passes then read a code instead of
+// decoding the same pair in each of its lanes.
+constexpr int kPairChunk = 64;
+__device__ __forceinline__ void decode_chunk(int c0, int T, int na, int S,
+                                             const int* __restrict__ nsp, int* __restrict__ lpair,
+                                             int lane) {
+  const int t = c0 + lane;
+  int code = 0;
+  if (t < T) {
+    int a, b;
+    decode_pair(t, na, a, b);
+    code = a | (b << 10) | (pair_block(nsp[a], nsp[b], S) << 20);
+  }
+  lpair[lane] = code;
+}
+
 // LDS per wave (forward): per neighbor float4 (dx, dy, dz, r), float2
-// (fc_rad, fc_ang), int species.  The feature row is accumulated in
-// registers and stored block by block, so no LDS row is needed.
+// (fc_rad, fc_ang), int species; a 64-entry table of angular pair codes.
+// The feature row is accumulated in registers and stored block by block, so
+// no LDS row is needed.
 constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
 
 typedef float aev_f32x4 __attribute__((ext_vector_type(4)));
@@ -128,6 +147,8 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   float2* nf = reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) + (size_t)w * cap;
   int* nsp = reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
                                     (size_t)4 * cap) + w * cap;
+  int* lpair = reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
+                                      (size_t)4 * cap) + 4 * cap + w * kPairChunk;
 
   // the first 64 records are fetched together with the counts
   const float4* nrec = rec + (size_t)i * cap;
@@ -187,12 +208,16 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
     const float ra_lo = ah ? C.shf_a[1] : C.shf_a[0];
     const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
     aev_f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
-    for (int t0 = 0; t0 < T; t0 += 4) {
+    for (int c0 = 0; c0 < T; c0 += kPairChunk) {
+    decode_chunk(c0, T, na, S, nsp, lpair, lane);
+    wave_lds_sync();
+    const int tn = T - c0 < kPairChunk ? T - c0 : kPairChunk;
+    for (int t0 = 0; t0 < tn; t0 += 4) {
       const int t = t0 + kq;
       float b0 = 0.f, b1 = 0.f, h0 = 0.f, h1 = 0.f;
-      if (t < T) {
-        int ej, ek;
-        decode_pair(t, na, ej, ek);
+      if (t < tn) {
+        const int code = lpair[t];
+        const int ej = code & 1023, ek = (code >> 10) & 1023, blk = code >> 20;
         const float4 vj = nd[ej], vk = nd[ek];
         const float fj = nf[ej].y, fk = nf[ek].y;
         const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
@@ -204,7 +229,6 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
         const float u0 = dbar - ra_lo, u1 = dbar - ra_hi;
         b0 = wgt * fast_exp2(-C.eta_a_l2e * u0 * u0);
         b1 = wgt * fast_exp2(-C.eta_a_l2e * u1 * u1);
-        const int blk = pair_block(nsp[ej], nsp[ek], S);
         h0 = blk == l16 ? 1.f : 0.f;
         h1 = blk == l16 + 16 ? 1.f : 0.f;
       }
@@ -214,6 +238,8 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
       c01 = mfma4(b1, h0, c01);
       c10 = mfma4(b0, h1, c10);
       c11 = mfma4(b1, h1, c11);
+    }
+    wave_lds_sync();  // the next chunk overwrites the table
     }
     // column c of c00 is feature c of the block (a = c / 8 for the low
     // radial shifts, z = c % 8); c01 holds features 16 + c
@@ -233,7 +259,9 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
 // LDS per wave (adjoint): per neighbor float4 (dx, dy, dz, r), float4
 // (fc_rad, fc_ang, dfc_rad, dfc_ang), float4 accumulated dE/d(displacement),
 // int species.  The dE/dG row is read from global memory where a term needs
-// it (an atom touches only the blocks of the species around it).
+// it (an atom touches only the blocks of the species around it).  Pairs are
+// decoded per lane here: with eight lanes per pair the chunked table of the
+// forward pass measured no gain.
 constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 
 // Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
@@ -408,7 +436,7 @@ void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4*
                     const int2* counts, int cap, const int* row_of, OutT* out, int ld,
                     hipStream_t st) {
   if (n_cap <= 0) return;
-  const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr;
+  const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr + (size_t)4 * kPairChunk * 4;
   static const bool attr = (ensure_lds(k_aev_fwd<OutT>), true);
   (void)attr;
   hipLaunchKernelGGL(k_aev_fwd<OutT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec,
