@@ -50,11 +50,17 @@ def cutoff_grad(d, R):
 
 
 def displacement(pos64, i, j, box):
-    """v_ij = r_j - r_i in float64, minimum image when a box is given."""
+    """v_ij = r_j - r_i in float64, minimum image when a box is given (edge
+    lengths, or the rows of a reduced triclinic cell: image removed along c,
+    b, a in turn)."""
     v = pos64[j] - pos64[i]
     if box is not None:
-        L = np.asarray(box, dtype=np.float64)
-        v = v - L * np.rint(v / L)
+        B = np.asarray(box, dtype=np.float64)
+        if B.shape == (3, 3):
+            for k in (2, 1, 0):
+                v = v - np.rint(v[:, k] / B[k, k])[:, None] * B[k]
+        else:
+            v = v - B * np.rint(v / B)
     return v
 
 

@@ -620,3 +620,67 @@ def test_subset_ignores_the_other_atoms_and_keeps_their_forces():
     assert np.array_equal(F1[rest], Fo[rest])
     # the subset's forces still sum to zero (momentum conservation)
     assert np.abs((F1[idx] - Fo[idx]).sum(0)).max() < 1e-10
+
+
+# ---------------------------------------------------------- triclinic boxes
+_TRIC = np.array([[16.0, 0.0, 0.0], [3.0, 15.0, 0.0], [-4.0, 5.0, 14.0]], dtype=np.float32)
+
+
+def test_triclinic_without_tilt_is_orthorhombic():
+    from oracle.neighbors import pair_list
+    s = w.water_box(60, 12.0, seed=7)
+    at, mt = w.aev_table(4), w.mlp_table(4)
+    L = np.asarray(s.box, dtype=np.float32)
+    tri = np.diag(L).astype(np.float32)
+    for rc in (at.rc_rad, at.rc_ang):
+        a = pair_list(s.pos, s.mol_offsets, L, rc)
+        b = pair_list(s.pos, s.mol_offsets, tri, rc)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    ra = o.energy_forces(s.pos, s.species, s.mol_offsets, L, aev_table=at, mlp_table=mt)
+    rb = o.energy_forces(s.pos, s.species, s.mol_offsets, tri, aev_table=at, mlp_table=mt)
+    assert np.array_equal(ra.E, rb.E) and np.array_equal(ra.F, rb.F)
+
+
+def test_triclinic_pairs_match_an_image_search():
+    # every pair closer than the cutoff in some periodic image, and only
+    # those (pairs within 1e-4 A of the cutoff are left out: float32 decides)
+    from oracle.neighbors import pair_list
+    s = w.triclinic_system(250, _TRIC, seed=2)
+    rc = 5.1
+    I, J = pair_list(s.pos, s.mol_offsets, _TRIC, rc)
+    got = set(zip(I.tolist(), J.tolist()))
+    B = _TRIC.astype(np.float64)
+    p = s.pos.astype(np.float64)
+    d = p[None, :, :] - p[:, None, :]
+    best = np.full(d.shape[:2], np.inf)
+    for i in range(-2, 3):
+        for j in range(-2, 3):
+            for k in range(-2, 3):
+                best = np.minimum(best, np.linalg.norm(d + i * B[0] + j * B[1] + k * B[2], axis=-1))
+    np.fill_diagonal(best, np.inf)
+    want = set(zip(*np.nonzero(best < rc - 1e-4)))
+    unsure = set(zip(*np.nonzero(np.abs(best - rc) <= 1e-4)))
+    assert want <= got and got <= want | unsure
+    assert len(want) > 1000
+
+
+def test_triclinic_energy_is_lattice_periodic():
+    # moving every atom by a lattice vector changes nothing but float32
+    # rounding of the positions
+    s = w.triclinic_system(200, _TRIC, seed=3)
+    at, mt = w.aev_table(4), w.mlp_table(4)
+    r0 = o.energy_forces(s, aev_table=at, mlp_table=mt)
+    moved = (s.pos.astype(np.float64) + _TRIC[1] - _TRIC[2]).astype(np.float32)
+    r1 = o.energy_forces(moved, s.species, s.mol_offsets, _TRIC, aev_table=at, mlp_table=mt)
+    np.testing.assert_allclose(r1.E, r0.E, rtol=1e-5)
+    assert np.linalg.norm(r1.F - r0.F) <= 1e-4 * np.linalg.norm(r0.F)
+
+
+def test_triclinic_box_checks():
+    from oracle.neighbors import check_triclinic
+    check_triclinic(_TRIC, 5.1)
+    for bad in ([[16, 1, 0], [3, 15, 0], [-4, 5, 14]],     # a not along x
+                [[16, 0, 0], [9, 15, 0], [-4, 5, 14]],     # |bx| > ax/2
+                [[16, 0, 0], [3, 15, 0], [-4, 5, 9.0]]):   # narrower than 2 rc
+        with pytest.raises(ValueError):
+            check_triclinic(np.array(bad, dtype=np.float32), 5.1)

@@ -9,6 +9,7 @@ forces or integration) lives here.
 from .params import (AEVTable, MLPTable, aev_table, mlp_table, SPECIES7, SPECIES4,
                      MASS_AMU, feature_count)
 from .geometry import (random_molecule, single_molecule, conformer_batch, water_box, System,
+                       triclinic_system,
                        pack_molecules,
                        config_system, CONFIGS)
 from .requests import poisson_requests, maxwell_boltzmann, Request
@@ -16,6 +17,6 @@ from .requests import poisson_requests, maxwell_boltzmann, Request
 __all__ = [
     "AEVTable", "MLPTable", "aev_table", "mlp_table", "SPECIES7", "SPECIES4",
     "MASS_AMU", "feature_count", "random_molecule", "single_molecule", "pack_molecules", "conformer_batch", "water_box",
-    "System", "config_system", "CONFIGS", "poisson_requests", "maxwell_boltzmann",
+    "System", "triclinic_system", "config_system", "CONFIGS", "poisson_requests", "maxwell_boltzmann",
     "Request",
 ]

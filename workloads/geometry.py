@@ -161,6 +161,34 @@ def water_box(n_water: int, L: float, seed: int, n_species: int = 4) -> System:
                   np.full(3, L, np.float32), n_species, f"water{n_water}")
 
 
+def triclinic_system(n_atoms: int, box, seed: int = 0, n_species: int = 4,
+                     min_sep: float = 0.9) -> System:
+    """Atoms uniform in a triclinic cell (rows a, b, c of ``box``), placed by
+    sequential rejection at a minimum-image separation of ``min_sep``; the
+    positions are wrapped into the cell (fractional coordinates in [0, 1))."""
+    rng = np.random.default_rng(seed)
+    B = np.asarray(box, dtype=np.float64)
+    pts = np.empty((n_atoms, 3))
+    k = 0
+    tries = 0
+    while k < n_atoms:
+        tries += 1
+        if tries > 1000000:
+            raise RuntimeError("rejection sampling did not converge")
+        p = rng.uniform(0.0, 1.0, 3) @ B
+        if k:
+            d = pts[:k] - p
+            for r in (2, 1, 0):
+                d = d - np.rint(d[:, r] / B[r, r])[:, None] * B[r]
+            if np.min(np.sum(d * d, axis=1)) < min_sep * min_sep:
+                continue
+        pts[k] = p
+        k += 1
+    sp = draw_species(n_atoms, n_species, rng)
+    return System(pts.astype(np.float32), sp, np.array([0, n_atoms], np.int32),
+                  np.asarray(box, dtype=np.float32), n_species, f"triclinic{n_atoms}")
+
+
 def config_system(k: int, **kw) -> System:
     """The synthetic system of workload k (0: 24-atom molecule; 1: 512x64
     conformations; 2: 1,500-water box; 3: a packed batch of serving-sized
