@@ -146,6 +146,19 @@ nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* s
  * a multiple of 16).  A larger capacity needs a larger workspace. */
 nnp_status nnp_set_max_neighbors(nnp_handle* h, int32_t max_neighbors);
 
+/* Box format of every later call on this handle (the paper's GFP example ran
+ * in a periodic cell; Results, "Example: MLP for Anionic Green Fluorescent
+ * Protein Chromophore in Water").  on == 0 (default): `box` is 3 floats,
+ * the edges of an orthorhombic cell.  on != 0: `box` is 9 floats, the rows
+ * a = (ax, 0, 0), b = (bx, by, 0), c = (cx, cy, cz) of a triclinic cell in
+ * reduced form (ax, by, cz > 0; |bx|, |cx| <= ax/2; |cy| <= by/2).  The
+ * image of a displacement is removed along c, then b, then a, each step
+ * n = rint(fl32(d_k * fl32(1 / v_kk))), d -= fl32(v_k * n), float32 without
+ * contraction; this is the minimum image when every perpendicular width is
+ * at least twice the radial cutoff, which is required (else NNP_E_BOX, as is
+ * a cell not in reduced form).  Atoms are binned in fractional coordinates. */
+nnp_status nnp_set_triclinic(nnp_handle* h, int32_t on);
+
 /* Bytes of workspace an evaluation of this shape needs.  `box` is host memory
  * (3 floats) or NULL, as for nnp_energy_forces.  Returns 0 for invalid shapes. */
 size_t nnp_workspace_bytes(const nnp_handle* h, int32_t n_atoms, int32_t n_mol,

@@ -41,7 +41,7 @@ class Potential:
 
     def __init__(self, *, n_species, rc_rad, eta_r, shf_r, rc_ang, eta_a, zeta, shf_a, shf_z,
                  widths, params, celu_alpha=0.1, self_energy=None, radial_prefactor=0.25,
-                 angle_cos_scale=0.95, precision="fp32", max_neighbors=128):
+                 angle_cos_scale=0.95, precision="fp32", max_neighbors=128, triclinic=False):
         self._lib = capi.lib()
         self.n_species = int(n_species)
         self.widths = tuple(int(w) for w in widths)
@@ -78,6 +78,10 @@ class Potential:
         if max_neighbors != 128:
             capi.check(self._lib.nnp_set_max_neighbors(h, int(max_neighbors)), "set_max_neighbors")
         self.max_neighbors = int(max_neighbors)
+        # boxes: 3 edge lengths, or (triclinic) the 3 x 3 rows of a reduced cell
+        self.triclinic = bool(triclinic)
+        if self.triclinic:
+            capi.check(self._lib.nnp_set_triclinic(h, 1), "set_triclinic")
         self._ws = None
 
     @classmethod
@@ -114,11 +118,10 @@ class Potential:
             self._h = None
 
     # ------------------------------------------------------------ workspace
-    @staticmethod
-    def _box_arg(box):
+    def _box_arg(self, box):
         if box is None:
             return None, None
-        b = np.ascontiguousarray(np.asarray(box, dtype=np.float32).reshape(3))
+        b = np.ascontiguousarray(np.asarray(box, dtype=np.float32).reshape(9 if self.triclinic else 3))
         return b, C.c_void_p(b.ctypes.data)
 
     def workspace_bytes(self, n_atoms, n_mol, box=None):

@@ -50,14 +50,19 @@ struct AevConst {
   const float* lane_tab;
 };
 
-// Periodic-box description (orthorhombic).  ncell[d] == 1 means that
-// dimension is not binned (the box is too small for three cells).
+// Periodic-box description.  periodic: 0 none, 1 orthorhombic (edges L),
+// 2 triclinic (rows v[0] = a = (ax,0,0), v[1] = b = (bx,by,0),
+// v[2] = c = (cx,cy,cz), reduced form; cells are binned in fractional
+// coordinates).  nc[d] == 1 means that dimension is not binned (the box is
+// too small for three cells).
 struct BoxConst {
   int periodic;
   float L[3];
   float invL[3];
   int nc[3];
   float cell_scale[3];   // nc / L
+  float v[3][3];         // triclinic cell rows
+  float inv_diag[3];     // fl32(1 / v[d][d])
 };
 
 // Group table written by the species sort (device memory, int32):
@@ -179,6 +184,26 @@ __device__ __forceinline__ float disp(float xi, float xj, float L, float invL, i
   float d = __fsub_rn(xj, xi);
   if (per) d = __fsub_rn(d, __fmul_rn(L, rintf(__fmul_rn(d, invL))));
   return d;
+}
+
+// Displacement in a reduced triclinic cell, float32 without contraction: the
+// image is removed along c, then b, then a, n = rint(d_k / v_kk) each time.
+// With the cutoff at most half of every perpendicular width this is the
+// minimum image of every pair inside the cutoff.
+__device__ __forceinline__ void tric_disp(float4 pi, float4 pj, const BoxConst& B, float& dx,
+                                          float& dy, float& dz) {
+  dx = __fsub_rn(pj.x, pi.x);
+  dy = __fsub_rn(pj.y, pi.y);
+  dz = __fsub_rn(pj.z, pi.z);
+  float n = rintf(__fmul_rn(dz, B.inv_diag[2]));
+  dx = __fsub_rn(dx, __fmul_rn(B.v[2][0], n));
+  dy = __fsub_rn(dy, __fmul_rn(B.v[2][1], n));
+  dz = __fsub_rn(dz, __fmul_rn(B.v[2][2], n));
+  n = rintf(__fmul_rn(dy, B.inv_diag[1]));
+  dx = __fsub_rn(dx, __fmul_rn(B.v[1][0], n));
+  dy = __fsub_rn(dy, __fmul_rn(B.v[1][1], n));
+  n = rintf(__fmul_rn(dx, B.inv_diag[0]));
+  dx = __fsub_rn(dx, __fmul_rn(B.v[0][0], n));
 }
 
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {

@@ -31,6 +31,7 @@ struct nnp_handle {
   int width[kLayers + 1] = {};
   float alpha = 0.1f;
   int max_nbr = 128;
+  bool triclinic = false;               // box arguments are 9 floats (cell rows)
   int n_models = 1;                     // ensemble members (weight slot = member * S + element)
   size_t n_params = 0;                  // all members
   long param_off[kMaxModels * kMaxS][kLayers] = {};  // flat offset of W for (slot, layer)
@@ -120,8 +121,45 @@ bool make_box(const nnp_handle* h, const float* box, BoxConst& B) {
     }
     return true;
   }
-  B.periodic = 1;
   const float rc = 1.f / h->C.inv_rc_r;
+  if (h->triclinic) {
+    // rows a, b, c of a reduced cell; cells are binned along the fractional
+    // coordinates, sized by the perpendicular widths
+    B.periodic = 2;
+    double v[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) {
+        if (!std::isfinite(box[3 * r + q])) return false;
+        v[r][q] = box[3 * r + q];
+        B.v[r][q] = box[3 * r + q];
+      }
+    if (v[0][1] != 0.0 || v[0][2] != 0.0 || v[1][2] != 0.0) return false;
+    if (!(v[0][0] > 0.0 && v[1][1] > 0.0 && v[2][2] > 0.0)) return false;
+    if (std::fabs(v[1][0]) > 0.5 * v[0][0] || std::fabs(v[2][0]) > 0.5 * v[0][0] ||
+        std::fabs(v[2][1]) > 0.5 * v[1][1])
+      return false;
+    auto cross_norm = [&](int p, int q) {
+      const double x = v[p][1] * v[q][2] - v[p][2] * v[q][1];
+      const double y = v[p][2] * v[q][0] - v[p][0] * v[q][2];
+      const double z = v[p][0] * v[q][1] - v[p][1] * v[q][0];
+      return std::sqrt(x * x + y * y + z * z);
+    };
+    const double vol = v[0][0] * v[1][1] * v[2][2];
+    const double wd[3] = {vol / cross_norm(1, 2), vol / cross_norm(2, 0), vol / cross_norm(0, 1)};
+    for (int d = 0; d < 3; ++d) {
+      if (!(wd[d] >= 2.0 * rc)) return false;
+      int nc = (int)std::floor(wd[d] / ((double)rc + 1e-3));
+      if (nc < 3) nc = 1;
+      if (nc > 128) nc = 128;
+      B.nc[d] = nc;
+      B.L[d] = (float)v[d][d];
+      B.invL[d] = 1.0f / B.v[d][d];
+      B.inv_diag[d] = 1.0f / B.v[d][d];
+      B.cell_scale[d] = (float)nc;
+    }
+    return true;
+  }
+  B.periodic = 1;
   for (int d = 0; d < 3; ++d) {
     const float L = box[d];
     if (!(L >= 2.f * rc) || !std::isfinite(L)) return false;
@@ -727,6 +765,12 @@ nnp_status nnp_profile_read(const nnp_handle* h, double* total_ms, int64_t* coun
     if (total_ms) total_ms[i] = h->prof_ms[i];
     if (count) count[i] = h->prof_n[i];
   }
+  return NNP_OK;
+}
+
+nnp_status nnp_set_triclinic(nnp_handle* h, int32_t on) {
+  if (!h) return NNP_E_INVALID;
+  h->triclinic = on != 0;
   return NNP_OK;
 }
 

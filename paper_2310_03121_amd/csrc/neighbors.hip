@@ -117,9 +117,20 @@ __global__ __launch_bounds__(256) void k_cell_count(const int* __restrict__ dims
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 p = xyzs[i];
-  const int cx = cell_coord(p.x, B.L[0], B.invL[0], B.cell_scale[0], B.nc[0]);
-  const int cy = cell_coord(p.y, B.L[1], B.invL[1], B.cell_scale[1], B.nc[1]);
-  const int cz = cell_coord(p.z, B.L[2], B.invL[2], B.cell_scale[2], B.nc[2]);
+  int cx, cy, cz;
+  if (B.periodic == 2) {
+    // fractional coordinates, wrapped into [0, 1), then binned
+    const float sz = p.z * B.inv_diag[2];
+    const float sy = (p.y - B.v[2][1] * sz) * B.inv_diag[1];
+    const float sx = (p.x - B.v[1][0] * sy - B.v[2][0] * sz) * B.inv_diag[0];
+    cx = cell_coord(sx, 1.f, 1.f, (float)B.nc[0], B.nc[0]);
+    cy = cell_coord(sy, 1.f, 1.f, (float)B.nc[1], B.nc[1]);
+    cz = cell_coord(sz, 1.f, 1.f, (float)B.nc[2], B.nc[2]);
+  } else {
+    cx = cell_coord(p.x, B.L[0], B.invL[0], B.cell_scale[0], B.nc[0]);
+    cy = cell_coord(p.y, B.L[1], B.invL[1], B.cell_scale[1], B.nc[1]);
+    cz = cell_coord(p.z, B.L[2], B.invL[2], B.cell_scale[2], B.nc[2]);
+  }
   const int c = cx + B.nc[0] * (cy + B.nc[1] * cz);
   cell_of[i] = c;
   atomicAdd(&cell_cnt[c], 1);
@@ -240,9 +251,13 @@ __global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims
       j = cell_atoms[slot];
       if (j != i) {
         const float4 pj = cell_xyzs[slot];
-        dx = disp(pi.x, pj.x, B.L[0], B.invL[0], 1);
-        dy = disp(pi.y, pj.y, B.L[1], B.invL[1], 1);
-        dz = disp(pi.z, pj.z, B.L[2], B.invL[2], 1);
+        if (B.periodic == 2) {
+          tric_disp(pi, pj, B, dx, dy, dz);
+        } else {
+          dx = disp(pi.x, pj.x, B.L[0], B.invL[0], 1);
+          dy = disp(pi.y, pj.y, B.L[1], B.invL[1], 1);
+          dz = disp(pi.z, pj.z, B.L[2], B.invL[2], 1);
+        }
         const float d2 = dist2(dx, dy, dz);
         inR = d2 < C.rc2_r;
         inA = d2 < C.rc2_a;

@@ -475,3 +475,65 @@ def test_subset_rejects_rows_outside_the_system():
                              torch.from_numpy(lig.mol_offsets).cuda(), F_all=F_all)
     with pytest.raises(NNPError):
         pot.check()
+
+
+# ------------------------------------------------------------ triclinic box
+_TRIC = np.array([[24.0, 0.0, 0.0], [5.0, 22.0, 0.0], [-6.0, 7.0, 21.0]], dtype=np.float32)
+
+
+def _tric_pot(S, prec):
+    key = ("tric", S, prec)
+    if key not in _POT:
+        _POT[key] = potential(S, prec, triclinic=True)
+    return _POT[key]
+
+
+def test_triclinic_pairs_aev_and_forces():
+    s = w.triclinic_system(800, _TRIC, seed=5)
+    announce(f"triclinic box, {s.n_atoms} atoms")
+    pot, at, mt = _tric_pot(4, "fp32")
+    pos, sp, off = to_dev(s)
+    pot.energy_forces(pos, sp, off, s.box, forces=False)
+    pot.check()
+    counts, nbr = pot.debug_neighbors(s.n_atoms)
+    I, J = pair_set_from_ell(counts, nbr)
+    Io, Jo = pair_list(s.pos, s.mol_offsets, s.box, at.rc_rad)
+    assert np.array_equal(I, Io) and np.array_equal(J, Jo)
+    G = pot.debug_aev(pos, sp, off, s.box).cpu().numpy()
+    Go, _ = o.aev(s.pos, s.species, s.mol_offsets, s.box, at)
+    assert rel_rms(G, Go) <= 2e-6
+    r = o.energy_forces(s, aev_table=at, mlp_table=mt)
+    for prec, f_tol, e_tol in (("fp32", 1e-5, 1e-5), ("bf16", 1e-2, 1e-2)):
+        p, _, _ = _tric_pot(4, prec)
+        E, F = p.energy_forces(pos, sp, off, s.box)
+        p.check()
+        de = abs(E.item() - r.E[0]) / np.abs(r.E_atom).sum()
+        fr = rel_rms(F.cpu().numpy(), r.F)
+        print(f"triclinic {prec}: |dE|/sum|E_i| {de:.3e}  force rel-RMS {fr:.3e}")
+        assert de <= e_tol and fr <= f_tol
+
+
+def test_triclinic_without_tilt_equals_orthorhombic():
+    s, S = get_sys("c2-water1500")
+    announce("zero-tilt triclinic cell vs orthorhombic box")
+    ortho, at, mt = get_pot(S, "fp32")
+    tric, _, _ = _tric_pot(S, "fp32")
+    pos, sp, off = to_dev(s)
+    E0, F0 = ortho.energy_forces(pos, sp, off, s.box)
+    E1, F1 = tric.energy_forces(pos, sp, off, np.diag(np.asarray(s.box, np.float32)))
+    ortho.check()
+    tric.check()
+    assert torch.equal(E0, E1)
+    assert rel_rms(F1.cpu().numpy(), F0.cpu().numpy()) <= 1e-6
+
+
+def test_triclinic_rejects_unreduced_cells():
+    announce("triclinic cell checks")
+    s = w.triclinic_system(100, _TRIC, seed=6)
+    pot, at, mt = _tric_pot(4, "fp32")
+    pos, sp, off = to_dev(s)
+    from paper_2310_03121_amd.capi import NNPError
+    bad = _TRIC.copy()
+    bad[1, 0] = 13.0  # |bx| > ax / 2
+    with pytest.raises(NNPError):
+        pot.energy_forces(pos, sp, off, bad)
