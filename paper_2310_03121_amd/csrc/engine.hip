@@ -281,8 +281,13 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     StageTimer t(h, ST_STAGE, st);
     launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.gidx, io.n_total,
                  io.species, io.off, S, xyzs, mol, io.gidx ? nullptr : io.out3, hist, status, st);
-    launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
-    launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
+    if (P.nblk <= kFusedSortBlocks) {
+      launch_sort_scatter(dims, P.n, S, xyzs, hist, gt, row, perm, P.rows_cap, io.off, kWChunk,
+                          status, st);
+    } else {
+      launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
+      launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
+    }
   }
   {
     StageTimer t(h, ST_PAIRS, st);

@@ -96,6 +96,11 @@ void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* po
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
                    int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
                    hipStream_t st);
+// k_groups + k_scatter in one launch; for n_cap <= 256 * kFusedSortBlocks
+constexpr int kFusedSortBlocks = 256;
+void launch_sort_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const int* hist,
+                         GroupTable* gt, int* row, int* perm, int rows_cap, const int* off,
+                         int wchunk_rows, uint32_t* status, hipStream_t st);
 void launch_scatter(const int* dims, int n_cap, int S, const float4* xyzs, const int* hist,
                     int* row, int* perm, hipStream_t st);
 void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* xyzs,
