@@ -102,6 +102,28 @@ def profiled_traffic(stage, workload_key):
     return rows[stage]
 
 
+def profiled_kernel_ms(stage, workload_key):
+    """Mean duration (ms) of the stage's kernel in the committed rocprofv3
+    kernel-trace summary, or None when missing or taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"kernels_{workload_key}.md")
+    if not os.path.exists(path):
+        return None
+    digest, hit = None, None
+    for line in open(path):
+        if line.startswith("source_digest:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("|") and not line.startswith("|--"):
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 4 and cells[0] == stage and hit is None:
+                try:
+                    hit = float(cells[3]) * 1e-3
+                except ValueError:
+                    pass
+    if digest != source_digest():
+        return None
+    return hit
+
+
 def profiled_valu(stage, workload_key):
     """(wave64 VALU instructions per wavefront, wavefronts per launch) of the
     stage's kernel from the committed instruction-counter summary, or None
@@ -522,6 +544,10 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": st[dom]}
+    # the same kernel's mean duration in the committed kernel trace (event
+    # timing adds the record/launch gap of one stage)
+    roof["profiled_avg_ms"] = profiled_kernel_ms(dom, WORKLOAD_KEYS[args.workload] + "_" +
+                                                 main_prec)
     fwd, bwd = mlp_flops_per_atom(mt.widths, F_feat)
     path_tflops = (fwd + bwd) * s.n_atoms / (main_r["ms_per_step"] * 1e-3) / 1e12
 
