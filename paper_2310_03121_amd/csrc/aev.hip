@@ -86,7 +86,8 @@ __device__ __forceinline__ void decode_pair(int t, int na, int& a, int& b) {
   int r = (int)((c2 - fast_sqrt(fmaxf(c2 * c2 - 8.f * (float)t, 0.f))) * 0.5f);
   r = r < 0 ? 0 : (r > na - 2 ? na - 2 : r);
   r = (r * (2 * na - r - 1)) >> 1 > t ? r - 1 : r;
-  r = (r + 1 <= na - 2 && ((r + 1) * (2 * na - r - 2)) >> 1 <= t) ? r + 1 : r;
+  const bool up = (r + 1 <= na - 2) & ((((r + 1) * (2 * na - r - 2)) >> 1) <= t);
+  r = up ? r + 1 : r;
   a = r;
   b = t - ((r * (2 * na - r - 1)) >> 1) + r + 1;
 }
@@ -347,48 +348,44 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
     const int T = na * (na - 1) / 2;
     const GT* gang = grow + S * kNR + tz;
     for (int t0 = 0; t0 < T; t0 += 8) {
+      // lanes past the last pair recompute it and contribute zero: every lane
+      // runs the same straight-line code, with no branch around the terms
       const int t = t0 + tg;
-      float X0 = 0.f, X1 = 0.f, Xc = 0.f;
-      int ej = 0, ek = 0;
-      float4 vj = make_float4(0.f, 0.f, 0.f, 1.f), vk = vj;
-      float fj = 0.f, fk = 0.f, dfj = 0.f, dfk = 0.f, cs = 0.f;
-      if (t < T) {
-        decode_pair(t, na, ej, ek);
-        vj = nd[ej];
-        vk = nd[ek];
-        const float4 cj = nf[ej], ck = nf[ek];
-        fj = cj.y; fk = ck.y; dfj = cj.w; dfk = ck.w;
-        const GT* gb = gang + pair_block(nsp[ej], nsp[ek], S) * 32;
-        const float g0 = Store<GT>::get(gb), g1 = Store<GT>::get(gb + 8),
-                    g2 = Store<GT>::get(gb + 16), g3 = Store<GT>::get(gb + 24);
-        const float ijk = fast_rcp(vj.w * vk.w);
-        cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * ijk;
-        const float kc = C.kappa * cs;
-        const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 1e-12f));
-        const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
-        const float pw = fast_exp2(C.zeta * fast_log2(base_));
-        const float f1 = 2.f * pw;
-        // d f1 / d c = zeta base^(zeta-1) d(kappa c cos_z + sqrt(1-kappa^2 c^2) sin_z)/dc
-        const float df1 = C.zeta * pw * fast_rcp(base_) * (C.kappa * (cz - kc * sz * fast_rcp(sn)));
-        const float dbar = 0.5f * (vj.w + vk.w);
-        float u, e2, A0 = 0.f, A1 = 0.f;
-        u = dbar - ra0; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g0 * e2; A1 -= g0 * u * e2;
-        u = dbar - ra1; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g1 * e2; A1 -= g1 * u * e2;
-        u = dbar - ra2; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g2 * e2; A1 -= g2 * u * e2;
-        u = dbar - ra3; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g3 * e2; A1 -= g3 * u * e2;
-        X0 = f1 * A0;
-        X1 = f1 * A1 * C.eta_a;
-        Xc = df1 * A0;
-      }
+      const bool valid = t < T;
+      int ej, ek;
+      decode_pair(valid ? t : T - 1, na, ej, ek);
+      const float4 vj = nd[ej], vk = nd[ek];
+      const float4 cj = nf[ej], ck = nf[ek];
+      const float fj = cj.y, fk = ck.y, dfj = cj.w, dfk = ck.w;
+      const GT* gb = gang + pair_block(nsp[ej], nsp[ek], S) * 32;
+      const float g0 = Store<GT>::get(gb), g1 = Store<GT>::get(gb + 8),
+                  g2 = Store<GT>::get(gb + 16), g3 = Store<GT>::get(gb + 24);
+      const float rj = fast_rcp(vj.w), rk = fast_rcp(vk.w);
+      const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * (rj * rk);
+      const float kc = C.kappa * cs;
+      const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 1e-12f));
+      const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
+      const float pw = fast_exp2(C.zeta * fast_log2(base_));
+      const float f1 = 2.f * pw;
+      // d f1 / d c = zeta base^(zeta-1) d(kappa c cos_z + sqrt(1-kappa^2 c^2) sin_z)/dc
+      const float df1 = C.zeta * pw * fast_rcp(base_) * (C.kappa * (cz - kc * sz * fast_rcp(sn)));
+      const float dbar = 0.5f * (vj.w + vk.w);
+      float u, e2, A0 = 0.f, A1 = 0.f;
+      u = dbar - ra0; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g0 * e2; A1 -= g0 * u * e2;
+      u = dbar - ra1; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g1 * e2; A1 -= g1 * u * e2;
+      u = dbar - ra2; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g2 * e2; A1 -= g2 * u * e2;
+      u = dbar - ra3; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g3 * e2; A1 -= g3 * u * e2;
+      float X0 = valid ? f1 * A0 : 0.f;
+      float X1 = valid ? f1 * A1 * C.eta_a : 0.f;
+      float Xc = valid ? df1 * A0 : 0.f;
       X0 = group8_sum(X0);
       X1 = group8_sum(X1);
       Xc = group8_sum(Xc);
-      if (t < T && tz == 0) {
+      if (valid && tz == 0) {
         const float fcc = fj * fk;
         const float dEdc = Xc * fcc;
         const float dEdj = X1 * fcc + X0 * dfj * fk;
         const float dEdk = X1 * fcc + X0 * fj * dfk;
-        const float rj = fast_rcp(vj.w), rk = fast_rcp(vk.w);
         const float aj = (dEdj - dEdc * cs * rj) * rj;
         const float ak = (dEdk - dEdc * cs * rk) * rk;
         const float bb = dEdc * rj * rk;
