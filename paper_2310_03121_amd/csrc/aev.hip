@@ -26,6 +26,7 @@
 // atomic add per neighbor and component for the neighbors, and one
 // wave-reduced add for the centre atom.
 #include "kernels.h"
+#include "energy_sum.h"
 
 namespace nnp {
 
@@ -268,7 +269,10 @@ constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 // Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
 // sign = +1 writes forces (-dE/dr); sign = -1 writes the gradient dE/dr.
 // With gidx, atom i's force goes to row gidx[i] of out ([n_total][3]; rows
-// outside [0, n_total) are skipped; staging reports them).
+// outside [0, n_total) are skipped; staging reports them).  Blocks from
+// nb_adj on sum the molecular energies (one block per molecule), which need
+// only the atomic energies of the forward pass: they fill the tail of the
+// scatter instead of a launch of their own.
 template <typename GT>
 __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C,
                                                  const float4* __restrict__ rec,
@@ -277,8 +281,13 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
                                                  const int* __restrict__ row_of,
                                                  const GT* __restrict__ g, int ldg,
                                                  float* __restrict__ out, float sign,
-                                                 const int* __restrict__ gidx, int n_total) {
+                                                 const int* __restrict__ gidx, int n_total,
+                                                 int nb_adj, EnergyArgs EA) {
   extern __shared__ float4 lds4[];
+  if ((int)blockIdx.x >= nb_adj) {  // block-uniform: the molecular energy sums
+    energy_block((int)blockIdx.x - nb_adj, dims, EA);
+    return;
+  }
   const int n = dims[0];
   const int w = threadIdx.x >> 6;
   const int lane = lane_id();
@@ -448,19 +457,22 @@ template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
                     int ldg, float* out, float sign, const int* gidx, int n_total,
-                    hipStream_t st) {
-  if (n_cap <= 0) return;
+                    const EnergyArgs* energy, int nmol_cap, hipStream_t st) {
+  const int nb_adj = n_cap > 0 ? (n_cap + 3) / 4 : 0;
+  const int nb_e = energy && energy->E && nmol_cap > 0 ? nmol_cap : 0;
+  if (nb_adj + nb_e == 0) return;
   const size_t lds = (size_t)4 * cap * kBwdBytesPerNbr;
   static const bool attr = (ensure_lds(k_aev_bwd<GT>), true);
   (void)attr;
-  hipLaunchKernelGGL(k_aev_bwd<GT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec, nbr,
-                     counts, cap, row_of, g, ldg, out, sign, gidx, n_total);
+  const EnergyArgs ea = nb_e ? *energy : EnergyArgs{};
+  hipLaunchKernelGGL(k_aev_bwd<GT>, dim3(nb_adj + nb_e), dim3(256), lds, st, dims, C, rec, nbr,
+                     counts, cap, row_of, g, ldg, out, sign, gidx, n_total, nb_adj, ea);
 }
 template void launch_aev_bwd<float>(const int*, int, const AevConst&, const float4*, const int*,
                                     const int2*, int, const int*, const float*, int, float*, float,
-                                    const int*, int, hipStream_t);
+                                    const int*, int, const EnergyArgs*, int, hipStream_t);
 template void launch_aev_bwd<bf16_t>(const int*, int, const AevConst&, const float4*, const int*,
                                      const int2*, int, const int*, const bf16_t*, int, float*,
-                                     float, const int*, int, hipStream_t);
+                                     float, const int*, int, const EnergyArgs*, int, hipStream_t);
 
 }  // namespace nnp

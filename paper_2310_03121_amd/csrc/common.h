@@ -212,13 +212,20 @@ __device__ __forceinline__ float dist2(float dx, float dy, float dz) {
 
 __device__ __forceinline__ int species_of(float4 p) { return __float_as_int(p.w); }
 
-// Raises a kernel's dynamic LDS limit to the gfx950 maximum (160 KB per
-// workgroup; the default is 64 KB), once per kernel, before its first launch
-// (so never while a stream is being captured into a graph).
+// Raises a kernel's dynamic LDS limit to what the gfx950 maximum (160 KB per
+// workgroup; the default is 64 KB) leaves beside the kernel's static LDS, once
+// per kernel, before its first launch (so never while a stream is being
+// captured into a graph).  A limit above that maximum would be rejected.
 template <typename K>
 inline void ensure_lds(K* kernel) {
+  hipFuncAttributes fa{};
+  size_t stat = 0;
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) == hipSuccess)
+    stat = fa.sharedSizeBytes;
+  const size_t lim = 160 * 1024;
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(stat < lim ? lim - stat : 0));
 }
 
 // Clamp a (possibly corrupt) index into [0, n).

@@ -20,6 +20,7 @@
 
 #include "../../include/nnp.h"
 #include "kernels.h"
+#include "energy_sum.h"
 
 using namespace nnp;
 
@@ -105,7 +106,7 @@ struct Plan {
   BoxConst B{};
   int ncell = 0;
   size_t total = 0;
-  size_t status, dims, gt, xyzs, mol, row, perm, hist, nbr, counts, rec;
+  size_t status, dims, gt, xyzs, mol, mrange, row, perm, hist, nbr, counts, rec;
   size_t cell_of, cell_cnt, cell_start, cursor, cell_atoms, cell_xyzs;
   size_t X, H1, H2, H3, D3, D2, D1, G, erow, uprow, wpart, pos32;
 };
@@ -211,7 +212,9 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B) {
     P.cursor = take((size_t)P.ncell * 4);
     P.cell_atoms = take(N * 4);
     P.cell_xyzs = take(N * 16);
+    P.mrange = 0;
   } else {
+    P.mrange = take(N * 8);
     P.cell_of = P.cell_cnt = P.cell_start = P.cursor = P.cell_atoms = P.cell_xyzs = 0;
   }
   const int w1 = h->width[1], w2 = h->width[2], w3 = h->width[3];
@@ -266,6 +269,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   GroupTable* gt = at<GroupTable>(ws, P.gt);
   float4* xyzs = at<float4>(ws, P.xyzs);
   int* mol = at<int>(ws, P.mol);
+  int2* mrange = P.mrange ? at<int2>(ws, P.mrange) : nullptr;
   int* row = at<int>(ws, P.row);
   int* perm = at<int>(ws, P.perm);
   int* hist = at<int>(ws, P.hist);
@@ -280,24 +284,29 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   {
     StageTimer t(h, ST_STAGE, st);
     launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.gidx, io.n_total,
-                 io.species, io.off, S, xyzs, mol, io.gidx ? nullptr : io.out3, hist, status, st);
-    if (P.nblk <= kFusedSortBlocks) {
-      launch_sort_scatter(dims, P.n, S, xyzs, hist, gt, row, perm, P.rows_cap, io.off, kWChunk,
-                          status, st);
-    } else {
+                 io.species, io.off, S, xyzs, mol, mrange, io.gidx ? nullptr : io.out3, hist,
+                 status, st);
+    if (P.nblk > kFusedSortBlocks) {
       launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
       launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
+    } else if (P.B.periodic) {
+      launch_sort_scatter(dims, P.n, S, xyzs, hist, gt, row, perm, P.rows_cap, io.off, kWChunk,
+                          status, st);
     }
   }
   {
     StageTimer t(h, ST_PAIRS, st);
-    if (P.B.periodic) {
+    if (!P.B.periodic && P.nblk <= kFusedSortBlocks) {
+      // molecules: the sort and the pair scan share one launch
+      launch_sort_pairs_mol(dims, P.n, S, hist, gt, row, perm, P.rows_cap, io.off, kWChunk,
+                            h->C, xyzs, mrange, P.cap, nbr, rec, counts, status, st);
+    } else if (P.B.periodic) {
       launch_pairs_cell(dims, P.n, h->C, P.B, xyzs, at<int>(ws, P.cell_of),
                         at<int>(ws, P.cell_cnt), at<int>(ws, P.cell_start),
                         at<int>(ws, P.cursor), at<int>(ws, P.cell_atoms),
                         at<float4>(ws, P.cell_xyzs), P.cap, nbr, rec, counts, status, st);
     } else {
-      launch_pairs_mol(dims, P.n, h->C, xyzs, mol, io.off, P.cap, nbr, rec, counts, status, st);
+      launch_pairs_mol(dims, P.n, h->C, xyzs, mrange, P.cap, nbr, rec, counts, status, st);
     }
   }
   T* X = at<T>(ws, P.X);
@@ -438,7 +447,9 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       }
     }
   }  // members
-  if (io.E) {
+  // the molecular energies: beside the force scatter when there is one
+  const EnergyArgs ea{io.off, xyzs, erow, M, (long)P.rows_cap, h->eself, io.E, status};
+  if (io.E && !io.out3) {
     StageTimer t(h, ST_ENERGY, st);
     launch_energy(dims, P.nmol, io.off, xyzs, erow, M, (long)P.rows_cap, h->eself, io.E, status,
                   st);
@@ -464,7 +475,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
     StageTimer t(h, ST_AEVBWD, st);
     launch_aev_bwd<T>(dims, P.n, h->C, rec, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
-                      io.gidx, io.n_total, st);
+                      io.gidx, io.n_total, &ea, P.nmol, st);
   }
   if (io.dparams) {
     StageTimer t(h, ST_WGRAD, st);
@@ -874,8 +885,9 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   int* dims = at<int>(ws, P.dims);
   uint32_t* status = at<uint32_t>(ws, P.status);
   float4* xyzs = at<float4>(ws, P.xyzs);
+  int2* mrange = P.mrange ? at<int2>(ws, P.mrange) : nullptr;
   launch_stage(n, nmol, P.n, dims, pos, nullptr, nullptr, 0, species, off, h->S, xyzs,
-               at<int>(ws, P.mol), nullptr, at<int>(ws, P.hist), status, st);
+               at<int>(ws, P.mol), mrange, nullptr, at<int>(ws, P.hist), status, st);
   launch_groups(dims, P.n, h->S, at<int>(ws, P.hist), at<GroupTable>(ws, P.gt),
                 at<int>(ws, P.perm), P.rows_cap, off, kWChunk, status, st);
   if (P.B.periodic)
@@ -884,7 +896,7 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
                       at<float4>(ws, P.cell_xyzs), P.cap, at<int>(ws, P.nbr),
                       at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
   else
-    launch_pairs_mol(dims, P.n, h->C, xyzs, at<int>(ws, P.mol), off, P.cap, at<int>(ws, P.nbr),
+    launch_pairs_mol(dims, P.n, h->C, xyzs, mrange, P.cap, at<int>(ws, P.nbr),
                      at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
   launch_aev_fwd<float>(dims, P.n, h->C, at<float4>(ws, P.rec), at<int2>(ws, P.counts), P.cap,
                         nullptr, aev, h->F, st);

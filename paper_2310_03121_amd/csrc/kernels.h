@@ -84,15 +84,19 @@ struct PackArgs {
   float* bout;
 };
 
+struct EnergyArgs;  // energy_sum.h
+
 // stage.hip
 inline int stage_blocks(int n_cap) { return n_cap > 0 ? (n_cap + 255) / 256 : 1; }
+// molecule offsets sampled into LDS by each staging block
+constexpr int kOffSamples = 1024;
 __global__ void k_fill_i32(int* p, int v, int n);
 __global__ void k_fill_f32(float* p, float v, long n);
 __global__ void k_fill_f64(double* p, double v, int n);
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
                   const double* pos64, const int* gidx, int n_total, const int* species,
-                  const int* off, int S, float4* xyzs, int* mol, float* Fzero, int* hist,
-                  uint32_t* status, hipStream_t st);
+                  const int* off, int S, float4* xyzs, int* mol, int2* mrange, float* Fzero,
+                  int* hist, uint32_t* status, hipStream_t st);
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
                    int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
                    hipStream_t st);
@@ -115,8 +119,14 @@ void launch_fill_f64(double* p, double v, int n, hipStream_t st);
 // matching records (dx, dy, dz, species bits) with d = x_j - x_i (minimum
 // image when periodic), computed by the cutoff predicate's own arithmetic.
 void launch_pairs_mol(const int* dims, int n_cap, const AevConst& C, const float4* xyzs,
-                      const int* mol, const int* off, int cap, int* nbr, float4* rec,
-                      int2* counts, uint32_t* status, hipStream_t st);
+                      const int2* mrange, int cap, int* nbr, float4* rec, int2* counts,
+                      uint32_t* status, hipStream_t st);
+// launch_sort_scatter and launch_pairs_mol in one launch (n_cap <= 256 * kFusedSortBlocks)
+void launch_sort_pairs_mol(const int* dims, int n_cap, int S, const int* hist, GroupTable* gt,
+                           int* row, int* perm, int rows_cap, const int* off, int wchunk_rows,
+                           const AevConst& C, const float4* xyzs, const int2* mrange, int cap,
+                           int* nbr, float4* rec, int2* counts, uint32_t* status,
+                           hipStream_t st);
 void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                        const float4* xyzs, int* cell_of, int* cell_cnt, int* cell_start,
                        int* cursor, int* cell_atoms, float4* cell_xyzs, int cap, int* nbr,
@@ -131,7 +141,7 @@ template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
                     int ldg, float* out, float sign, const int* gidx, int n_total,
-                    hipStream_t st);
+                    const EnergyArgs* energy, int nmol_cap, hipStream_t st);
 
 // mlp.hip
 template <typename T>

@@ -20,6 +20,7 @@
 // concatenation of the 27 surrounding cells (fewer when a dimension has fewer
 // than three cells) from a cell-ordered copy of the records.
 #include "kernels.h"
+#include "sort_scatter.h"
 
 namespace nnp {
 
@@ -46,26 +47,20 @@ __device__ __forceinline__ void finish_list(const int* key, const float4* lrec, 
   if (lane == 0) counts[i] = make_int2(nr, na);
 }
 
-__global__ __launch_bounds__(256) void k_pairs_mol(const int* __restrict__ dims, AevConst C,
-                                                   const float4* __restrict__ xyzs,
-                                                   const int* __restrict__ mol,
-                                                   const int* __restrict__ off, int cap,
-                                                   int* __restrict__ nbr, float4* __restrict__ rec,
-                                                   int2* __restrict__ counts,
-                                                   uint32_t* __restrict__ status) {
-  extern __shared__ float4 lds_mol[];
-  const int n = dims[0];
-  const int w = threadIdx.x >> 6;
+// Wave w of a block scans for atom i: the candidates are the atoms of its
+// molecule, [mrange[i].x, mrange[i].y), read as contiguous records.
+__device__ __forceinline__ void pairs_mol_wave(int i, int w, float4* lds, const AevConst& C,
+                                               const float4* __restrict__ xyzs,
+                                               const int2* __restrict__ mrange, int cap,
+                                               int* __restrict__ nbr, float4* __restrict__ rec,
+                                               int2* __restrict__ counts,
+                                               uint32_t* __restrict__ status) {
   const int lane = lane_id();
-  const int i = blockIdx.x * 4 + w;
-  if (i >= n) return;
-  float4* lrec = lds_mol + (size_t)w * cap;
-  int* key = reinterpret_cast<int*>(lds_mol + (size_t)4 * cap) + w * cap;
+  float4* lrec = lds + (size_t)w * cap;
+  int* key = reinterpret_cast<int*>(lds + (size_t)4 * cap) + w * cap;
   const float4 pi = xyzs[i];
-  const int m = mol[i];
-  int a = off[m], b = off[m + 1];
-  a = a < 0 ? 0 : (a > n ? n : a);
-  b = b < a ? a : (b > n ? n : b);
+  const int2 ab = mrange[i];  // clamped to [0, n] by staging
+  const int a = ab.x, b = ab.y;
   int nr = 0, na = 0;
   for (int base = a; base < b; base += kWave) {
     const int j = base + lane;
@@ -98,6 +93,40 @@ __global__ __launch_bounds__(256) void k_pairs_mol(const int* __restrict__ dims,
   }
   wave_lds_sync();
   finish_list(key, lrec, nr, na, i, cap, nbr, rec, counts);
+}
+
+__global__ __launch_bounds__(256) void k_pairs_mol(const int* __restrict__ dims, AevConst C,
+                                                   const float4* __restrict__ xyzs,
+                                                   const int2* __restrict__ mrange, int cap,
+                                                   int* __restrict__ nbr, float4* __restrict__ rec,
+                                                   int2* __restrict__ counts,
+                                                   uint32_t* __restrict__ status) {
+  extern __shared__ float4 lds_mol[];
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= dims[0]) return;
+  pairs_mol_wave(i, w, lds_mol, C, xyzs, mrange, cap, nbr, rec, counts, status);
+}
+
+// The species sort (blocks [0, nsort)) and the molecule neighbor search (the
+// blocks after them) in one launch: both read only what staging wrote, and
+// the pair scan no longer waits behind the sort's tail.
+__global__ __launch_bounds__(256) void k_sort_pairs_mol(
+    const int* __restrict__ dims, int nsort, int S, const int* __restrict__ hist,
+    GroupTable* __restrict__ gt, int* __restrict__ row, int* __restrict__ perm, int rows_cap,
+    const int* __restrict__ off, int wchunk_rows, AevConst C, const float4* __restrict__ xyzs,
+    const int2* __restrict__ mrange, int cap, int* __restrict__ nbr, float4* __restrict__ rec,
+    int2* __restrict__ counts, uint32_t* __restrict__ status) {
+  extern __shared__ float4 lds_mol[];
+  if ((int)blockIdx.x < nsort) {  // block-uniform
+    sort_scatter_block(blockIdx.x, nsort, dims, S, xyzs, hist, gt, row, perm, rows_cap, off,
+                       wchunk_rows, status);
+    return;
+  }
+  const int w = threadIdx.x >> 6;
+  const int i = ((int)blockIdx.x - nsort) * 4 + w;
+  if (i >= dims[0]) return;
+  pairs_mol_wave(i, w, lds_mol, C, xyzs, mrange, cap, nbr, rec, counts, status);
 }
 
 // ---------------------------------------------------------------- cell list
@@ -285,12 +314,25 @@ __global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims
 // ----------------------------------------------------------------- launchers
 
 void launch_pairs_mol(const int* dims, int n_cap, const AevConst& C, const float4* xyzs,
-                      const int* mol, const int* off, int cap, int* nbr, float4* rec,
-                      int2* counts, uint32_t* status, hipStream_t st) {
+                      const int2* mrange, int cap, int* nbr, float4* rec, int2* counts,
+                      uint32_t* status, hipStream_t st) {
   if (n_cap <= 0) return;
   hipLaunchKernelGGL(k_pairs_mol, dim3((n_cap + 3) / 4), dim3(256),
-                     4 * cap * (sizeof(float4) + sizeof(int)), st, dims, C, xyzs, mol, off, cap,
-                     nbr, rec, counts, status);
+                     4 * cap * (sizeof(float4) + sizeof(int)), st, dims, C, xyzs, mrange, cap, nbr,
+                     rec, counts, status);
+}
+
+void launch_sort_pairs_mol(const int* dims, int n_cap, int S, const int* hist, GroupTable* gt,
+                           int* row, int* perm, int rows_cap, const int* off, int wchunk_rows,
+                           const AevConst& C, const float4* xyzs, const int2* mrange, int cap,
+                           int* nbr, float4* rec, int2* counts, uint32_t* status,
+                           hipStream_t st) {
+  const int nsort = stage_blocks(n_cap);
+  const int npair = n_cap > 0 ? (n_cap + 3) / 4 : 0;
+  hipLaunchKernelGGL(k_sort_pairs_mol, dim3(nsort + npair), dim3(256),
+                     4 * cap * (sizeof(float4) + sizeof(int)), st, dims, nsort, S, hist, gt, row,
+                     perm, rows_cap, off, wchunk_rows, C, xyzs, mrange, cap, nbr, rec, counts,
+                     status);
 }
 
 void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,

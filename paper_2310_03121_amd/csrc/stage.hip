@@ -9,6 +9,8 @@
 // Methods "OpenMM-ML").  The molecular energy is the FP64 sum of the FP32
 // atomic energies plus self energies.
 #include "kernels.h"
+#include "sort_scatter.h"
+#include "energy_sum.h"
 
 namespace nnp {
 
@@ -19,18 +21,32 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __r
                                                const int* __restrict__ species,
                                                const int* __restrict__ off, int S,
                                                float4* __restrict__ xyzs, int* __restrict__ mol,
+                                               int2* __restrict__ mrange,
                                                float* __restrict__ Fzero, int* __restrict__ hist,
                                                uint32_t* __restrict__ status) {
   __shared__ int h[kMaxS];
   __shared__ uint32_t bits;
+  __shared__ int smp[kOffSamples + 1];
   const int n = n_arg >= 0 ? n_arg : dims[0];
   const int nmol = nmol_arg >= 0 ? nmol_arg : dims[1];
-  if (blockIdx.x == 0 && threadIdx.x == 0 && n_arg >= 0) {
-    dims[0] = n;
-    dims[1] = nmol;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (n_arg >= 0) {
+      dims[0] = n;
+      dims[1] = nmol;
+    }
+    *status = 0u;  // later kernels of the evaluation only add bits
   }
   if (threadIdx.x < kMaxS) h[threadIdx.x] = 0;
   if (threadIdx.x == 0) bits = 0;
+  // every step-th molecule offset, step chosen so that at most kOffSamples
+  // intervals remain: the molecule search runs in LDS and ends with at most
+  // log2(step) dependent global loads (none for up to kOffSamples molecules)
+  const int step = nmol > 0 ? (nmol + kOffSamples - 1) / kOffSamples : 1;
+  const int K = nmol > 0 ? (nmol + step - 1) / step : 0;
+  for (int k = threadIdx.x; k <= K; k += blockDim.x) {
+    const int m = k * step;
+    smp[k] = off[m < nmol ? m : nmol];
+  }
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -62,13 +78,26 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __r
       st |= kStNonFinite;
       x = y = z = 0.f;
     }
-    // molecule: the last m with off[m] <= i (off is non-decreasing when valid)
-    int lo = 0, hi = nmol;
+    // molecule: the last m with off[m] <= i (off is non-decreasing when
+    // valid), first over the samples, then inside one sample interval
+    int klo = 0, khi = K;
+    while (khi - klo > 1) {
+      const int mid = (klo + khi) >> 1;
+      if (smp[mid] <= i) klo = mid; else khi = mid;
+    }
+    int lo = klo * step, hi = khi * step < nmol ? khi * step : nmol;
     while (hi - lo > 1) {
-      int mid = (lo + hi) >> 1;
+      const int mid = (lo + hi) >> 1;
       if (off[mid] <= i) lo = mid; else hi = mid;
     }
     mol[i] = lo;
+    if (mrange) {  // the molecule's atom range, clamped to [0, n]
+      int a = step == 1 ? smp[lo] : off[lo];
+      int b = step == 1 ? smp[lo + 1 <= K ? lo + 1 : K] : off[lo + 1 <= nmol ? lo + 1 : nmol];
+      a = a < 0 ? 0 : (a > n ? n : a);
+      b = b < a ? a : (b > n ? n : b);
+      mrange[i] = make_int2(a, b);
+    }
     xyzs[i] = make_float4(x, y, z, __int_as_float(s));
     if (Fzero) {
       Fzero[3 * i] = 0.f;
@@ -88,8 +117,8 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __r
 // padded group starts, per-block bases of the stable scatter (wave-level
 // prefix sums, no block barriers inside the scans), pad-row markers,
 // molecule-offset validation, the chunk table of the weight-gradient
-// reduction, and the evaluation's status word (overwritten here; kernels
-// that run later only add bits).
+// reduction, and the staging bits of the evaluation's status word (cleared
+// by staging; every later kernel only adds bits).
 __global__ __launch_bounds__(512) void k_groups(const int* __restrict__ dims, int nblk, int S,
                                                 int* __restrict__ hist, GroupTable* __restrict__ gt,
                                                 int* __restrict__ perm, int rows_cap,
@@ -160,7 +189,7 @@ __global__ __launch_bounds__(512) void k_groups(const int* __restrict__ dims, in
   for (int o = 32; o >= 1; o >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, o, 64);
   if (lane == 0 && bits) atomicOr(&bits_all, bits);
   __syncthreads();
-  if (t == 0) *status = bits_all;
+  if (t == 0 && bits_all) atomicOr(status, bits_all);
 }
 
 // Stable scatter into species-sorted rows: rank = block base + earlier waves
@@ -191,17 +220,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int* __restrict__ dims, i
 }
 
 // The species sort and scatter in one launch, for up to kFusedSortBlocks
-// staging blocks: every block sums the staging histograms itself (totals,
-// and its own prefix over earlier blocks), so no separate scan kernel is
-// needed; block 0 also writes the group table, the pad-row markers and the
-// status word, as k_groups does.  Rows are the same as with k_groups +
-// k_scatter.
-__device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
+// staging blocks.
 __global__ __launch_bounds__(256) void k_sort_scatter(const int* __restrict__ dims, int S,
                                                       const float4* __restrict__ xyzs,
                                                       const int* __restrict__ hist,
@@ -209,132 +228,12 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const int* __restrict__ di
                                                       int* __restrict__ row, int* __restrict__ perm,
                                                       int rows_cap, const int* __restrict__ off,
                                                       int wchunk_rows, uint32_t* __restrict__ status) {
-  __shared__ int tot[kMaxS], pre[kMaxS], pst[kMaxS + 1];
-  __shared__ int wcnt[4][kMaxS];
-  __shared__ unsigned int bits_all;
-  const int nblk = gridDim.x, blk = blockIdx.x;
-  const int n = dims[0], nmol = dims[1];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  if (t == 0) bits_all = 0u;
-  for (int q = w; q < kMaxS; q += 4) {
-    int all = 0, before = 0;
-    if (q < S)
-      for (int b = lane; b < nblk; b += kWave) {
-        const int v = hist[q * nblk + b];
-        all += v;
-        before += b < blk ? v : 0;
-      }
-    all = wave_sum_i(all);
-    before = wave_sum_i(before);
-    if (lane == 0) {
-      tot[q] = all;
-      pre[q] = before;
-    }
-  }
-  __syncthreads();
-  if (t == 0) {
-    int p = 0, c = 0;
-    for (int q = 0; q < kMaxS; ++q) {
-      const int cnt = q < S ? tot[q] : 0;
-      pst[q] = p;
-      if (blk == 0) {
-        gt->cnt[q] = cnt;
-        gt->pstart[q] = p;
-        gt->wchunk[q] = c;
-      }
-      p += (cnt + kPad - 1) / kPad * kPad;
-      c += (cnt + wchunk_rows - 1) / wchunk_rows;
-    }
-    pst[kMaxS] = p;
-    if (blk == 0) {
-      gt->pstart[kMaxS] = p;
-      gt->wchunk[kMaxS] = c;
-      gt->total_rows = p;
-      gt->n_wchunks = c;
-    }
-  }
-  __syncthreads();
-  // stable scatter: rank = group start + earlier blocks + earlier waves of
-  // this block + earlier lanes of the wave with the same species
-  const int i = blk * blockDim.x + t;
-  const int s = i < n ? species_of(xyzs[i]) : -1;
-  int rank = 0;
-  for (int q = 0; q < S; ++q) {
-    uint64_t m = ballot(s == q);
-    if (s == q) rank = popc_below(m);
-    if (lane == 0) wcnt[w][q] = __popcll(m);
-  }
-  __syncthreads();
-  if (i < n) {
-    int base = pst[s] + pre[s];
-    for (int v = 0; v < w; ++v) base += wcnt[v][s];
-    const int r = base + rank;
-    row[i] = r;
-    perm[r] = i;
-  }
-  if (blk != 0) return;
-  // block 0: pad rows, offsets, staging error bits
-  for (int q = 0; q < kMaxS; ++q) {
-    const int a = pst[q] + (q < S ? tot[q] : 0), e = pst[q + 1];
-    for (int r = a + t; r < e; r += blockDim.x) perm[r] = -1;
-  }
-  for (int r = pst[kMaxS] + t; r < rows_cap; r += blockDim.x) perm[r] = -1;
-  bool bad = false;
-  for (int m = t; m < nmol; m += blockDim.x) bad |= off[m] > off[m + 1];
-  if (t == 0) bad |= off[0] != 0 || off[nmol] != n;
-  uint32_t bits = bad ? kStOffsets : 0u;
-  for (int b = t; b < nblk; b += blockDim.x) bits |= (uint32_t)hist[kMaxS * nblk + b];
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) bits |= (uint32_t)__shfl_xor((int)bits, o, 64);
-  if (lane == 0 && bits) atomicOr(&bits_all, bits);
-  __syncthreads();
-  if (t == 0) *status = bits_all;
+  sort_scatter_block(blockIdx.x, gridDim.x, dims, S, xyzs, hist, gt, row, perm, rows_cap, off,
+                     wchunk_rows, status);
 }
 
-// One workgroup per molecule: E_m = sum_i (e_i + e_self[s_i]) with the
-// atomic energies in input atom order; for an ensemble of M members e_i is
-// the mean of the members' atomic energies (member k at eatom + k * mstride).
-// Thread t sums the atoms t, t + 256, ... of the molecule (counted from its
-// first atom), then the waves and the four wave sums combine in a fixed
-// order: the result depends only on the molecule's own atoms, not on where
-// it sits in a batch.
-__global__ __launch_bounds__(256) void k_energy(const int* __restrict__ dims,
-                                                const int* __restrict__ off,
-                                                const float4* __restrict__ xyzs,
-                                                const float* __restrict__ eatom, int n_models,
-                                                long mstride, const double* __restrict__ eself,
-                                                double* __restrict__ E, uint32_t* __restrict__ status) {
-  __shared__ double part[4];
-  __shared__ double es[kMaxS];  // self energies: no dependent global gather per atom
-  const int n = dims[0], nmol = dims[1];
-  const int m = blockIdx.x;
-  if (m >= nmol) return;
-  if (threadIdx.x < kMaxS) es[threadIdx.x] = eself[threadIdx.x];
-  __syncthreads();
-  int a = off[m], b = off[m + 1];
-  a = a < 0 ? 0 : (a > n ? n : a);
-  b = b < a ? a : (b > n ? n : b);
-  double acc = 0.0;
-  if (n_models == 1) {  // straight-line loop body: loads of several atoms in flight
-#pragma unroll 4
-    for (int i = a + (int)threadIdx.x; i < b; i += 256)
-      acc += (double)eatom[i] + es[__float_as_int(xyzs[i].w) & (kMaxS - 1)];
-  } else {
-    const double inv_m = 1.0 / n_models;
-    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
-      double e = (double)eatom[i];
-      for (int k = 1; k < n_models; ++k) e += (double)eatom[k * mstride + i];
-      acc += e * inv_m + es[__float_as_int(xyzs[i].w) & (kMaxS - 1)];
-    }
-  }
-  acc = wave_sum_d(acc);
-  if (lane_id() == 0) part[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double e = ((part[0] + part[1]) + part[2]) + part[3];
-    E[m] = e;
-    if (!isfinite(e)) atomicOr(status, kStNonFinite);
-  }
+__global__ __launch_bounds__(256) void k_energy(const int* __restrict__ dims, EnergyArgs A) {
+  energy_block(blockIdx.x, dims, A);
 }
 
 __global__ void k_fill_i32(int* __restrict__ p, int v, int n) {
@@ -356,11 +255,11 @@ __global__ void k_fill_f64(double* __restrict__ p, double v, int n) {
 
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
                   const double* pos64, const int* gidx, int n_total, const int* species,
-                  const int* off, int S, float4* xyzs, int* mol, float* Fzero, int* hist,
-                  uint32_t* status, hipStream_t st) {
+                  const int* off, int S, float4* xyzs, int* mol, int2* mrange, float* Fzero,
+                  int* hist, uint32_t* status, hipStream_t st) {
   const int nblk = stage_blocks(n_cap);
   hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, dims, pos, pos64,
-                     gidx, n_total, species, off, S, xyzs, mol, Fzero, hist, status);
+                     gidx, n_total, species, off, S, xyzs, mol, mrange, Fzero, hist, status);
 }
 
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
@@ -387,8 +286,8 @@ void launch_energy(const int* dims, int nmol_cap, const int* off, const float4* 
                    const float* eatom, int n_models, long mstride, const double* eself,
                    double* E, uint32_t* status, hipStream_t st) {
   if (nmol_cap <= 0) return;
-  hipLaunchKernelGGL(k_energy, dim3(nmol_cap), dim3(256), 0, st, dims, off, xyzs, eatom,
-                     n_models, mstride, eself, E, status);
+  const EnergyArgs A{off, xyzs, eatom, n_models, mstride, eself, E, status};
+  hipLaunchKernelGGL(k_energy, dim3(nmol_cap), dim3(256), 0, st, dims, A);
 }
 
 void launch_fill_i32(int* p, int v, int n, hipStream_t st) {
