@@ -174,6 +174,68 @@ def test_full_batch_512x64():
         assert rel_rms(F, r.F) <= ftol
 
 
+def _many_small(n_mol, seed):
+    """n_mol molecules of 0..6 atoms (about one in seven empty), 7 elements."""
+    rng = np.random.default_rng(seed)
+    mols = []
+    for m in range(n_mol):
+        n = int(rng.integers(0, 7))
+        if n == 0:
+            mols.append(w.System(np.zeros((0, 3), np.float32), np.zeros(0, np.int32),
+                                 np.array([0, 0], np.int32), None, 7))
+        else:
+            mols.append(w.single_molecule(n, seed=1000 + m, n_species=7))
+    return w.pack_molecules(mols, 7, f"many-small-{n_mol}")
+
+
+def _check_against_oracle(s, S, prec, f_tol, e_tol, pairs=False):
+    """Energies against a per-molecule scale: sum_i |E_i|, but for BF16 at
+    least n_m times the mean |E_i| of the whole input.  BF16 rounds the
+    activations and weights, so its error per atom follows the typical size
+    of the terms, not E_i itself, which for a one- or two-atom molecule can
+    nearly cancel."""
+    pot, at, mt = get_pot(S, prec)
+    pos, sp, off = to_dev(s)
+    E, F = pot.energy_forces(pos, sp, off, None)
+    pot.check()
+    if pairs:
+        counts, nbr = pot.debug_neighbors(s.n_atoms)
+        I, J = pair_set_from_ell(counts, nbr)
+        Io, Jo = pair_list(s.pos, s.mol_offsets, None, at.rc_rad)
+        assert np.array_equal(I, Io) and np.array_equal(J, Jo)
+    r = o.energy_forces(s, aev_table=at, mlp_table=mt)
+    E = E.cpu().numpy()
+    F = F.cpu().numpy()
+    scale = np.array([np.abs(r.E_atom[s.mol_offsets[m]:s.mol_offsets[m + 1]]).sum()
+                      for m in range(s.n_mol)])
+    if prec == "bf16":
+        scale = np.maximum(scale, np.diff(s.mol_offsets) * np.abs(r.E_atom).mean())
+    empty = np.diff(s.mol_offsets) == 0
+    assert np.all(E[empty] == r.E[empty])  # both 0: no atoms, no self energies
+    de = np.abs(E - r.E)[~empty] / np.maximum(scale[~empty], 1e-30)
+    fr = rel_rms(F, r.F)
+    print(f"{prec}: max |dE|/sum|E_i| {de.max():.3e}  force rel-RMS {fr:.3e}")
+    assert de.max() <= e_tol
+    assert fr <= f_tol
+
+
+@pytest.mark.parametrize("prec,f_tol,e_tol", [("fp32", 1e-5, 1e-5), ("bf16", 1e-2, 1e-2)])
+def test_many_small_molecules(prec, f_tol, e_tol):
+    """2,500 molecules (more than the 1,024 offsets each staging block samples,
+    so the molecule search ends with global loads), empty ones among them."""
+    s = _many_small(2500, seed=11)
+    announce(f"many small molecules {prec} n_mol={s.n_mol} N={s.n_atoms}")
+    _check_against_oracle(s, 7, prec, f_tol, e_tol, pairs=prec == "fp32")
+
+
+def test_molecule_batch_above_fused_sort_limit():
+    """1,040 x 64 atoms = 66,560 > 65,536: the species sort takes the
+    scan-kernel path and the pair scan its own launch."""
+    s = w.conformer_batch(1040, 64, seed=1)
+    announce(f"molecule batch above the fused-sort limit N={s.n_atoms}")
+    _check_against_oracle(s, 7, "fp32", 1e-5, 1e-5, pairs=True)
+
+
 def test_batch_position_independence():
     # a molecule alone and inside a batch: same pairs, same energy bits, forces
     # equal up to the order of atomic additions
