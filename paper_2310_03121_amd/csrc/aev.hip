@@ -258,6 +258,9 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
 }
 
+// Atoms per workgroup of the molecule adjoint.
+constexpr int kMolBlock = 64;
+
 // LDS per wave (adjoint): per neighbor float4 (dx, dy, dz, r), float4
 // (fc_rad, fc_ang, dfc_rad, dfc_ang), float4 accumulated dE/d(displacement),
 // int species.  The dE/dG row is read from global memory where a term needs
@@ -266,38 +269,20 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
 // forward pass measured no gain.
 constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 
-// Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
-// sign = +1 writes forces (-dE/dr); sign = -1 writes the gradient dE/dr.
-// With gidx, atom i's force goes to row gidx[i] of out ([n_total][3]; rows
-// outside [0, n_total) are skipped; staging reports them).  Blocks from
-// nb_adj on sum the molecular energies (one block per molecule), which need
-// only the atomic energies of the forward pass: they fill the tail of the
-// scatter instead of a launch of their own.
-template <typename GT>
-__global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C,
-                                                 const float4* __restrict__ rec,
-                                                 const int* __restrict__ nbr,
-                                                 const int2* __restrict__ counts, int cap,
-                                                 const int* __restrict__ row_of,
-                                                 const GT* __restrict__ g, int ldg,
-                                                 float* __restrict__ out, float sign,
-                                                 const int* __restrict__ gidx, int n_total,
-                                                 int nb_adj, EnergyArgs EA) {
-  extern __shared__ float4 lds4[];
-  if ((int)blockIdx.x >= nb_adj) {  // block-uniform: the molecular energy sums
-    energy_block((int)blockIdx.x - nb_adj, dims, EA);
-    return;
-  }
-  const int n = dims[0];
-  const int w = threadIdx.x >> 6;
+// The adjoint of one atom i, by one wave: dE/d(displacement) of every
+// neighbor entry into the wave's LDS region, then put(j, x, y, z) adds
+// -sign * dE/dv to neighbor j and (lane 0) +sign * sum to the centre i.
+// nd, nf, grad: cap float4 each; nsp: cap ints.
+template <typename GT, typename Put>
+__device__ __forceinline__ void adjoint_atom(int i, int n, const AevConst& C,
+                                             const float4* __restrict__ rec,
+                                             const int* __restrict__ nbr,
+                                             const int2* __restrict__ counts, int cap,
+                                             const int* __restrict__ row_of,
+                                             const GT* __restrict__ g, int ldg, float sign,
+                                             float4* nd, float4* nf, float4* grad, int* nsp,
+                                             Put&& put) {
   const int lane = lane_id();
-  const int i = blockIdx.x * 4 + w;
-  if (i >= n) return;
-  float4* nd = lds4 + (size_t)w * cap * 3;
-  float4* nf = nd + cap;
-  float4* grad = nf + cap;
-  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)4 * cap * 3) + w * cap;
-
   // records, counts, the dE/dG row and the neighbor indices of the scatter
   // are all first-level loads
   const int* nrow = nbr + (size_t)i * cap;
@@ -413,13 +398,7 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   float sx = 0.f, sy = 0.f, sz2 = 0.f;
   for (int e = lane; e < nr; e += kWave) {
     const float4 gv = grad[e];
-    int j = clampi(e < kSpecRec ? j0 : nrow[e], n);
-    if (gidx) j = gidx[j];
-    if (!gidx || (j >= 0 && j < n_total)) {
-      unsafeAtomicAdd(out + 3 * j, -sign * gv.x);
-      unsafeAtomicAdd(out + 3 * j + 1, -sign * gv.y);
-      unsafeAtomicAdd(out + 3 * j + 2, -sign * gv.z);
-    }
+    put(clampi(e < kSpecRec ? j0 : nrow[e], n), -sign * gv.x, -sign * gv.y, -sign * gv.z);
     sx += gv.x;
     sy += gv.y;
     sz2 += gv.z;
@@ -427,11 +406,118 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
   sx = wave_sum_rows(sx);
   sy = wave_sum_rows(sy);
   sz2 = wave_sum_rows(sz2);
-  const int gi = gidx ? gidx[i] : i;
-  if (lane == 0 && (!gidx || (gi >= 0 && gi < n_total))) {
-    unsafeAtomicAdd(out + 3 * gi, sign * sx);
-    unsafeAtomicAdd(out + 3 * gi + 1, sign * sy);
-    unsafeAtomicAdd(out + 3 * gi + 2, sign * sz2);
+  if (lane == 0) put(i, sign * sx, sign * sy, sign * sz2);
+}
+
+// Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
+// sign = +1 writes forces (-dE/dr); sign = -1 writes the gradient dE/dr.
+// With gidx, atom i's force goes to row gidx[i] of out ([n_total][3]; rows
+// outside [0, n_total) are skipped; staging reports them).  Blocks from
+// nb_adj on sum the molecular energies (one block per molecule), which need
+// only the atomic energies of the forward pass: they fill the tail of the
+// scatter instead of a launch of their own.
+template <typename GT>
+__global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C,
+                                                 const float4* __restrict__ rec,
+                                                 const int* __restrict__ nbr,
+                                                 const int2* __restrict__ counts, int cap,
+                                                 const int* __restrict__ row_of,
+                                                 const GT* __restrict__ g, int ldg,
+                                                 float* __restrict__ out, float sign,
+                                                 const int* __restrict__ gidx, int n_total,
+                                                 int nb_adj, EnergyArgs EA) {
+  extern __shared__ float4 lds4[];
+  if ((int)blockIdx.x >= nb_adj) {  // block-uniform: the molecular energy sums
+    energy_block((int)blockIdx.x - nb_adj, dims, EA);
+    return;
+  }
+  const int n = dims[0];
+  const int w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 4 + w;
+  if (i >= n) return;
+  float4* nd = lds4 + (size_t)w * cap * 3;
+  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)4 * cap * 3) + w * cap;
+  adjoint_atom<GT>(i, n, C, rec, nbr, counts, cap, row_of, g, ldg, sign, nd, nd + cap,
+                   nd + 2 * cap, nsp, [&](int j, float x, float y, float z) {
+                     if (gidx) {
+                       j = gidx[j];
+                       if (j < 0 || j >= n_total) return;
+                     }
+                     unsafeAtomicAdd(out + 3 * j, x);
+                     unsafeAtomicAdd(out + 3 * j + 1, y);
+                     unsafeAtomicAdd(out + 3 * j + 2, z);
+                   });
+}
+
+// Molecules (no box, no index map): a workgroup owns the kMolBlock atoms
+// [b * kMolBlock, (b + 1) * kMolBlock), its waves taking them in turn, and
+// adds every force into an LDS window over the atoms [b - 1, b + 2) *
+// kMolBlock, which holds all neighbors of its atoms for molecules of up to
+// kMolBlock + 1 atoms (neighbors outside it, in larger molecules, are added
+// to global memory directly).  At the end each touched window atom is written
+// once: with a plain store if its whole molecule lies inside the workgroup's
+// atoms (nothing else adds to it; staging zeroed the output), else with one
+// atomic add per component.  This replaces the contended per-entry global
+// atomics of the per-atom kernel (about nine adds per atom on the same lines).
+template <typename GT>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_aev_bwd_mol(const int* __restrict__ dims, AevConst C,
+                                                      const float4* __restrict__ rec,
+                                                      const int* __restrict__ nbr,
+                                                      const int2* __restrict__ counts, int cap,
+                                                      const int* __restrict__ row_of,
+                                                      const GT* __restrict__ g, int ldg,
+                                                      float* __restrict__ out, float sign,
+                                                      const int2* __restrict__ mrange,
+                                                      int nb_adj, EnergyArgs EA) {
+  extern __shared__ float4 lds4[];
+  if ((int)blockIdx.x >= nb_adj) {  // block-uniform: the molecular energy sums
+    energy_block((int)blockIdx.x - nb_adj, dims, EA);
+    return;
+  }
+  constexpr int kWin = 3 * kMolBlock;
+  const int n = dims[0];
+  const int nw = (int)blockDim.x >> 6, w = (int)threadIdx.x >> 6;
+  const int base = (int)blockIdx.x * kMolBlock, w0 = base - kMolBlock;
+  float4* nd = lds4 + (size_t)w * cap * 3;
+  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)nw * cap * 3) + w * cap;
+  float* win = reinterpret_cast<float*>(reinterpret_cast<int*>(lds4 + (size_t)nw * cap * 3) +
+                                        (size_t)nw * cap);
+  for (int t = threadIdx.x; t < 3 * kWin; t += blockDim.x) win[t] = 0.f;
+  __syncthreads();
+  for (int a = w; a < kMolBlock; a += nw) {
+    const int i = base + a;
+    if (i >= n) break;  // wave-uniform
+    adjoint_atom<GT>(i, n, C, rec, nbr, counts, cap, row_of, g, ldg, sign, nd, nd + cap,
+                     nd + 2 * cap, nsp, [&](int j, float x, float y, float z) {
+                       const int t = j - w0;
+                       if (t >= 0 && t < kWin) {
+                         atomicAdd(win + 3 * t, x);
+                         atomicAdd(win + 3 * t + 1, y);
+                         atomicAdd(win + 3 * t + 2, z);
+                       } else {
+                         unsafeAtomicAdd(out + 3 * j, x);
+                         unsafeAtomicAdd(out + 3 * j + 1, y);
+                         unsafeAtomicAdd(out + 3 * j + 2, z);
+                       }
+                     });
+    wave_lds_sync();  // the next atom reuses this wave's region
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kWin; t += blockDim.x) {
+    const int j = w0 + t;
+    if (j < 0 || j >= n) continue;
+    const float x = win[3 * t], y = win[3 * t + 1], z = win[3 * t + 2];
+    if (x == 0.f && y == 0.f && z == 0.f) continue;
+    const int2 mr = mrange[j];
+    if (mr.x >= base && mr.y <= base + kMolBlock) {
+      out[3 * j] = x;
+      out[3 * j + 1] = y;
+      out[3 * j + 2] = z;
+    } else {
+      unsafeAtomicAdd(out + 3 * j, x);
+      unsafeAtomicAdd(out + 3 * j + 1, y);
+      unsafeAtomicAdd(out + 3 * j + 2, z);
+    }
   }
 }
 
@@ -457,22 +543,37 @@ template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
                     int ldg, float* out, float sign, const int* gidx, int n_total,
-                    const EnergyArgs* energy, int nmol_cap, hipStream_t st) {
-  const int nb_adj = n_cap > 0 ? (n_cap + 3) / 4 : 0;
+                    const int2* mrange, const EnergyArgs* energy, int nmol_cap,
+                    hipStream_t st) {
   const int nb_e = energy && energy->E && nmol_cap > 0 ? nmol_cap : 0;
+  const EnergyArgs ea = nb_e ? *energy : EnergyArgs{};
+  if (mrange && !gidx) {
+    // waves per workgroup: 16 while two workgroups fit a CU's LDS, else fewer
+    const int nw = cap <= 64 ? 16 : (cap <= 128 ? 8 : 4);
+    const int nb_adj = n_cap > 0 ? (n_cap + kMolBlock - 1) / kMolBlock : 0;
+    if (nb_adj + nb_e == 0) return;
+    const size_t lds = (size_t)nw * cap * kBwdBytesPerNbr + (size_t)3 * kMolBlock * 3 * 4;
+    static const bool attr = (ensure_lds(k_aev_bwd_mol<GT>), true);
+    (void)attr;
+    hipLaunchKernelGGL(k_aev_bwd_mol<GT>, dim3(nb_adj + nb_e), dim3(64 * nw), lds, st, dims, C,
+                       rec, nbr, counts, cap, row_of, g, ldg, out, sign, mrange, nb_adj, ea);
+    return;
+  }
+  const int nb_adj = n_cap > 0 ? (n_cap + 3) / 4 : 0;
   if (nb_adj + nb_e == 0) return;
   const size_t lds = (size_t)4 * cap * kBwdBytesPerNbr;
   static const bool attr = (ensure_lds(k_aev_bwd<GT>), true);
   (void)attr;
-  const EnergyArgs ea = nb_e ? *energy : EnergyArgs{};
   hipLaunchKernelGGL(k_aev_bwd<GT>, dim3(nb_adj + nb_e), dim3(256), lds, st, dims, C, rec, nbr,
                      counts, cap, row_of, g, ldg, out, sign, gidx, n_total, nb_adj, ea);
 }
 template void launch_aev_bwd<float>(const int*, int, const AevConst&, const float4*, const int*,
                                     const int2*, int, const int*, const float*, int, float*, float,
-                                    const int*, int, const EnergyArgs*, int, hipStream_t);
+                                    const int*, int, const int2*, const EnergyArgs*, int,
+                                    hipStream_t);
 template void launch_aev_bwd<bf16_t>(const int*, int, const AevConst&, const float4*, const int*,
                                      const int2*, int, const int*, const bf16_t*, int, float*,
-                                     float, const int*, int, const EnergyArgs*, int, hipStream_t);
+                                     float, const int*, int, const int2*, const EnergyArgs*, int,
+                                     hipStream_t);
 
 }  // namespace nnp

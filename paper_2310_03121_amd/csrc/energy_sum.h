@@ -16,7 +16,7 @@ struct EnergyArgs {
   uint32_t* status;
 };
 
-// One workgroup of 256 threads per molecule m: E_m = sum_i (e_i + e_self[s_i])
+// One workgroup (256 threads or more; the first 256 do the sums) per molecule m: E_m = sum_i (e_i + e_self[s_i])
 // with the atomic energies in input atom order; for an ensemble of M members
 // e_i is the mean of the members' atomic energies.  Thread t sums the atoms
 // t, t + 256, ... of the molecule (counted from its first atom), then the
@@ -42,20 +42,23 @@ __device__ __forceinline__ void energy_block(int m, const int* __restrict__ dims
   a = a < 0 ? 0 : (a > n ? n : a);
   b = b < a ? a : (b > n ? n : b);
   double acc = 0.0;
+  // the first 256 threads sum, whatever the workgroup size, so that the
+  // order of the additions (and so the result) is the same in every launch
+  const int nt = threadIdx.x < 256 ? 256 : 0;
   if (n_models == 1) {  // straight-line loop body: loads of several atoms in flight
 #pragma unroll 4
-    for (int i = a + (int)threadIdx.x; i < b; i += 256)
+    for (int i = a + (int)threadIdx.x; i < b && nt; i += 256)
       acc += (double)eatom[i] + es[__float_as_int(xyzs[i].w) & (kMaxS - 1)];
   } else {
     const double inv_m = 1.0 / n_models;
-    for (int i = a + (int)threadIdx.x; i < b; i += 256) {
+    for (int i = a + (int)threadIdx.x; i < b && nt; i += 256) {
       double e = (double)eatom[i];
       for (int k = 1; k < n_models; ++k) e += (double)eatom[k * mstride + i];
       acc += e * inv_m + es[__float_as_int(xyzs[i].w) & (kMaxS - 1)];
     }
   }
   acc = wave_sum_d(acc);
-  if (lane_id() == 0) part[threadIdx.x >> 6] = acc;
+  if (lane_id() == 0 && threadIdx.x < 256) part[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     const double e = ((part[0] + part[1]) + part[2]) + part[3];

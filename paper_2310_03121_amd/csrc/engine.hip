@@ -475,7 +475,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
     StageTimer t(h, ST_AEVBWD, st);
     launch_aev_bwd<T>(dims, P.n, h->C, rec, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
-                      io.gidx, io.n_total, &ea, P.nmol, st);
+                      io.gidx, io.n_total, mrange, &ea, P.nmol, st);
   }
   if (io.dparams) {
     StageTimer t(h, ST_WGRAD, st);

@@ -141,7 +141,8 @@ template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
                     int ldg, float* out, float sign, const int* gidx, int n_total,
-                    const EnergyArgs* energy, int nmol_cap, hipStream_t st);
+                    const int2* mrange, const EnergyArgs* energy, int nmol_cap,
+                    hipStream_t st);
 
 // mlp.hip
 template <typename T>
