@@ -99,28 +99,36 @@ __device__ __forceinline__ int pair_block(int p, int q, int S) {
 }
 
 // Angular pairs are decoded in chunks of 64, one pair per lane, into a
-// per-wave LDS table of codes (entry a | entry b << 10 | block << 20;
-// entries < 1024, blocks < 64); the passes then read a code instead of
-// decoding the same pair in each of its lanes.
+// per-wave LDS table that the passes then read.
 constexpr int kPairChunk = 64;
-__device__ __forceinline__ void decode_chunk(int c0, int T, int na, int S,
-                                             const int* __restrict__ nsp, int* __restrict__ lpair,
-                                             int lane) {
+
+// LDS per wave (forward): per neighbor float4 (dx, dy, dz, r), float2
+// (fc_rad, fc_ang), int species; a 64-entry table of angular pairs (float4
+// geometry and int block each).  The feature row is accumulated in registers
+// and stored block by block, so no LDS row is needed.
+constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
+constexpr int kFwdPairBytes = 16 + 4;
+
+// The angular pairs [c0, c0 + 64) of the list, one per lane: what a pair's
+// 32 terms share, computed once instead of in each of the 16 lanes of its
+// pass: (kappa cos theta, sqrt(1 - kappa^2 cos^2), mean distance,
+// fc_j fc_k) and the pair's block.
+__device__ __forceinline__ void pair_chunk_geometry(int c0, int T, int na, const AevConst& C,
+                                                    const float4* nd, const float2* nf,
+                                                    const int* nsp, float4* pgeo, int* pblk,
+                                                    int lane) {
   const int t = c0 + lane;
-  int code = 0;
   if (t < T) {
     int a, b;
     decode_pair(t, na, a, b);
-    code = a | (b << 10) | (pair_block(nsp[a], nsp[b], S) << 20);
+    const float4 vj = nd[a], vk = nd[b];
+    const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
+    const float kc = C.kappa * cs;
+    pgeo[lane] = make_float4(kc, fast_sqrt(fmaxf(1.f - kc * kc, 0.f)), 0.5f * (vj.w + vk.w),
+                             nf[a].y * nf[b].y);
+    pblk[lane] = pair_block(nsp[a], nsp[b], C.S);
   }
-  lpair[lane] = code;
 }
-
-// LDS per wave (forward): per neighbor float4 (dx, dy, dz, r), float2
-// (fc_rad, fc_ang), int species; a 64-entry table of angular pair codes.
-// The feature row is accumulated in registers and stored block by block, so
-// no LDS row is needed.
-constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
 
 typedef float aev_f32x4 __attribute__((ext_vector_type(4)));
 
@@ -149,8 +157,10 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   float2* nf = reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) + (size_t)w * cap;
   int* nsp = reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
                                     (size_t)4 * cap) + w * cap;
-  int* lpair = reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
-                                      (size_t)4 * cap) + 4 * cap + w * kPairChunk;
+  float4* pgeo = reinterpret_cast<float4*>(
+                     reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
+                                            (size_t)4 * cap) + 4 * cap) + w * kPairChunk;
+  int* pblk = reinterpret_cast<int*>(pgeo + (4 - w) * kPairChunk) + w * kPairChunk;
 
   // the first 64 records are fetched together with the counts
   const float4* nrec = rec + (size_t)i * cap;
@@ -211,24 +221,18 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
     const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
     aev_f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
     for (int c0 = 0; c0 < T; c0 += kPairChunk) {
-    decode_chunk(c0, T, na, S, nsp, lpair, lane);
+    pair_chunk_geometry(c0, T, na, C, nd, nf, nsp, pgeo, pblk, lane);
     wave_lds_sync();
     const int tn = T - c0 < kPairChunk ? T - c0 : kPairChunk;
     for (int t0 = 0; t0 < tn; t0 += 4) {
       const int t = t0 + kq;
       float b0 = 0.f, b1 = 0.f, h0 = 0.f, h1 = 0.f;
       if (t < tn) {
-        const int code = lpair[t];
-        const int ej = code & 1023, ek = (code >> 10) & 1023, blk = code >> 20;
-        const float4 vj = nd[ej], vk = nd[ek];
-        const float fj = nf[ej].y, fk = nf[ek].y;
-        const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
-        const float kc = C.kappa * cs;
-        const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 0.f));
-        const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
-        const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fj * fk;
-        const float dbar = 0.5f * (vj.w + vk.w);
-        const float u0 = dbar - ra_lo, u1 = dbar - ra_hi;
+        const float4 q = pgeo[t];  // kappa cos, sine, mean distance, fc_j fc_k
+        const int blk = pblk[t];
+        const float base_ = 0.5f + 0.5f * (q.x * cz + q.y * sz);
+        const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * q.w;
+        const float u0 = q.z - ra_lo, u1 = q.z - ra_hi;
         b0 = wgt * fast_exp2(-C.eta_a_l2e * u0 * u0);
         b1 = wgt * fast_exp2(-C.eta_a_l2e * u1 * u1);
         h0 = blk == l16 ? 1.f : 0.f;
@@ -528,7 +532,7 @@ void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4*
                     const int2* counts, int cap, const int* row_of, OutT* out, int ld,
                     hipStream_t st) {
   if (n_cap <= 0) return;
-  const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr + (size_t)4 * kPairChunk * 4;
+  const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr + (size_t)4 * kPairChunk * kFwdPairBytes;
   static const bool attr = (ensure_lds(k_aev_fwd<OutT>), true);
   (void)attr;
   hipLaunchKernelGGL(k_aev_fwd<OutT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec,
