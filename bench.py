@@ -396,12 +396,16 @@ def serving(at, mt, n_req=300, n_steps=100):
     return out
 
 
-def cpu_baseline(s, S, budget_s=12.0, gpu=None):
+def cpu_baseline(s, S, budget_s=12.0, gpu=None, one_thread=False):
     """The FP64 oracle on a bounded sample of the workload (host cores).  The
     last oracle evaluation of the sample also gives the force and energy
     error of each GPU path (``gpu``: {precision: (E, F)} of the whole
     workload; the sample is its first molecules, which interact with nothing
-    else, or the whole system)."""
+    else, or the whole system).  one_thread: BLAS limited to one thread."""
+    if one_thread:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            return cpu_baseline(s, S, budget_s, gpu, one_thread=False)
     import oracle
     import workloads as w
     try:
@@ -596,6 +600,8 @@ def main():
             target = out if prec == main_prec else out.get("fp32_path")
             if target is not None:
                 target.update(e)
+        # the same oracle with BLAS on one thread (shorter sample)
+        out["cpu_baseline_one_thread"], _ = cpu_baseline(s, S, budget_s=6.0, one_thread=True)
     print(json.dumps(out))
 
 
