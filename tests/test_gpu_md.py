@@ -73,7 +73,7 @@ def test_time_reversibility():
 
 def test_nve_energy_error_matches_oracle_integrator():
     # The random-weight potential heats a water box quickly (kinetic energy
-    # grows ~20x in 100 fs), so energy conservation is judged against the FP64
+    # grows ~20x in 100 fs), so energy conservation is checked against the FP64
     # oracle integrator on the same system and step: the GPU path's
     # max |E_tot - E_0| must be no worse than the oracle's, up to a small
     # FP32 allowance.
