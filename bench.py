@@ -333,6 +333,41 @@ def ceilings():
     return out
 
 
+def measured_peak(bound, prec):
+    """The ceiling measured on this device for the roofline's bound: a large
+    square library GEMM (hipBLASLt through torch) of the path's precision for
+    `mfma`, a 1 GiB device copy for `hbm`; none for `alu` (no VALU
+    microbenchmark here)."""
+    import torch
+    if bound not in ("mfma", "hbm"):
+        return None
+    c = {}
+    if bound == "hbm":
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        fn, work, unit = (lambda: dst.copy_(src)), 2 * src.numel() / 1e9, "GB/s"
+    else:
+        n = 8192
+        dtype = torch.bfloat16 if prec == "bf16" else torch.float32
+        c["a"] = torch.randn(n, n, device="cuda", dtype=dtype)
+        c["b"] = torch.randn(n, n, device="cuda", dtype=dtype)
+        fn, work, unit = (lambda: c["a"] @ c["b"]), 2 * n ** 3 / 1e12, "TFLOP/s"
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    val = work / (e0.elapsed_time(e1) / 10 * 1e-3)
+    c.clear()
+    torch.cuda.empty_cache()
+    return {"value": val, "unit": unit,
+            "what": "1 GiB device copy" if bound == "hbm" else f"{prec} 8192^3 library GEMM"}
+
+
 def serve_leg(srv, reqs, rate=None, id_base=0):
     """Drive the continuous-batching server with a request stream.
 
@@ -557,6 +592,11 @@ def main():
     # timing adds the record/launch gap of one stage)
     roof["profiled_avg_ms"] = profiled_kernel_ms(dom, WORKLOAD_KEYS[args.workload] + "_" +
                                                  main_prec)
+    # the same achieved rate against the ceiling measured here
+    mp = measured_peak(roof["bound"], main_prec)
+    roof["measured_peak"] = mp
+    roof["frac_of_measured"] = (roof["achieved"] / mp["value"]
+                                if mp and roof.get("achieved") is not None else None)
     fwd, bwd = mlp_flops_per_atom(mt.widths, F_feat)
     path_tflops = (fwd + bwd) * s.n_atoms / (main_r["ms_per_step"] * 1e-3) / 1e12
 
