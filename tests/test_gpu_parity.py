@@ -174,6 +174,28 @@ def test_full_batch_512x64():
         assert rel_rms(F, r.F) <= ftol
 
 
+def test_full_batch_512x64_bench_capacity():
+    """The full batch at the neighbor capacity the benchmark times (64: the
+    molecule adjoint then runs 16 waves per workgroup), both precisions."""
+    s = w.config_system(1)
+    announce(f"full batch 512x64 at capacity 64 N={s.n_atoms}")
+    r = None
+    for prec, ftol, etol in (("fp32", 1e-5, 1e-5), ("bf16", 1e-2, 1e-2)):
+        pot, at, mt = potential(7, prec, max_neighbors=64)
+        pos, sp, off = to_dev(s)
+        E, F = pot.energy_forces(pos, sp, off, None)
+        pot.check()
+        if r is None:
+            r = o.energy_forces(s, aev_table=at, mlp_table=mt)
+        E = E.cpu().numpy()
+        F = F.cpu().numpy()
+        scale = np.abs(r.E_atom).reshape(512, 64).sum(1)
+        print(f"{prec}: max dE rel {np.max(np.abs(E - r.E) / scale):.3e} "
+              f"F rel-RMS {rel_rms(F, r.F):.3e}")
+        assert np.max(np.abs(E - r.E) / scale) <= etol
+        assert rel_rms(F, r.F) <= ftol
+
+
 def _many_small(n_mol, seed):
     """n_mol molecules of 0..6 atoms (about one in seven empty), 7 elements."""
     rng = np.random.default_rng(seed)
