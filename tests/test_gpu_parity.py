@@ -15,6 +15,7 @@ import oracle as o
 import workloads as w
 from oracle.neighbors import pair_list
 from gpu_util import potential, to_dev, rel_rms, pair_set_from_ell
+from neighborhood import neighborhood_reference
 
 pytestmark = pytest.mark.gpu
 
@@ -194,6 +195,33 @@ def test_full_batch_512x64_bench_capacity():
               f"F rel-RMS {rel_rms(F, r.F):.3e}")
         assert np.max(np.abs(E - r.E) / scale) <= etol
         assert rel_rms(F, r.F) <= ftol
+
+
+def test_water7667_sampled():
+    """The 23,001-atom water box in the benchmark's configuration (neighbor
+    capacity 128), both precisions: neighbor lists and forces of 12 sampled
+    atoms against the oracle on each atom's neighborhood (the whole box is
+    too large for the oracle in a test)."""
+    s = w.config_system(4)
+    announce(f"water box 7667 sampled N={s.n_atoms}")
+    at, mt = w.aev_table(7), w.mlp_table(7)
+    ks = np.random.default_rng(5).choice(s.n_atoms, 12, replace=False)
+    ref = {int(k): neighborhood_reference(s, at, mt, int(k)) for k in ks}
+    for prec, ftol in (("fp32", 1e-5), ("bf16", 1e-2)):
+        pot, _, _ = potential(7, prec)
+        pos, sp, off = to_dev(s)
+        E, F = pot.energy_forces(pos, sp, off, s.box)
+        pot.check()
+        F = F.cpu().numpy()
+        if prec == "fp32":
+            counts, nbr = pot.debug_neighbors(s.n_atoms)
+            c, nb = counts.cpu().numpy(), nbr.cpu().numpy()
+            for k, (_, nset) in ref.items():
+                assert set(nb[k, :c[k, 0]].tolist()) == nset, k
+        Fg = np.stack([F[k] for k in ref])
+        Fr = np.stack([v[0] for v in ref.values()])
+        print(f"{prec}: sampled force rel-RMS {rel_rms(Fg, Fr):.3e}")
+        assert rel_rms(Fg, Fr) <= ftol
 
 
 def _many_small(n_mol, seed):

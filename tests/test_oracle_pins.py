@@ -684,3 +684,19 @@ def test_triclinic_box_checks():
                 [[16, 0, 0], [3, 15, 0], [-4, 5, 9.0]]):   # narrower than 2 rc
         with pytest.raises(ValueError):
             check_triclinic(np.array(bad, dtype=np.float32), 5.1)
+
+
+def test_neighborhood_reference_equals_whole_system():
+    """The per-atom force from the oracle on an atom's neighborhood (used by
+    the sampled GPU test of the 23,001-atom box) equals the whole-system
+    oracle force on the 1,500-water box: the force on an atom depends only
+    on the energies of the atom and its radial neighbors."""
+    from neighborhood import neighborhood_reference
+    s = w.config_system(2)
+    at, mt = w.aev_table(4), w.mlp_table(4)
+    full = o.energy_forces(s, aev_table=at, mlp_table=mt)
+    I, J = pair_list(s.pos, s.mol_offsets, s.box, at.rc_rad)
+    for k in (0, 17, 1234, 4499):
+        Fk, nset = neighborhood_reference(s, at, mt, k)
+        np.testing.assert_allclose(Fk, full.F[k], rtol=1e-12, atol=1e-12)
+        assert nset == set(J[I == k].tolist())
