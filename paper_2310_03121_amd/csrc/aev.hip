@@ -141,7 +141,9 @@ __device__ __forceinline__ aev_f32x4 mfma4(float a, float b, aev_f32x4 acc) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
 }
 
-template <typename OutT>
+// NT: 16-block tiles of the angular one-hot (ceil(S (S + 1) / 2 / 16): one
+// for up to five elements, two for six or seven, three for eight).
+template <typename OutT, int NT>
 __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, AevConst C,
                                                  const float4* __restrict__ rec,
                                                  const int2* __restrict__ counts, int cap,
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
   // of [block(pair) == blk] * term(pair, a, z), four pairs per pass.  Lane
   // (kq, l16) takes pair kq and column l16 of each of the two 16-column
   // halves: angle shift z = l16 % 8 and radial shifts a = l16 / 8 and
-  // l16 / 8 + 2.  Blocks 16.. (seven or more elements) use a second tile.
+  // l16 / 8 + 2.  Tile u of the one-hot covers blocks 16 u .. 16 u + 15.
   {
     const int T = na * (na - 1) / 2;
     const int nblk = S * (S + 1) / 2;
@@ -219,44 +221,51 @@ __global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, A
     const float cz = C.lane_tab[kNR + z], sz = C.lane_tab[kNR + kNZ + z];
     const float ra_lo = ah ? C.shf_a[1] : C.shf_a[0];
     const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
-    aev_f32x4 c00 = {0.f, 0.f, 0.f, 0.f}, c01 = c00, c10 = c00, c11 = c00;
-    for (int c0 = 0; c0 < T; c0 += kPairChunk) {
-    pair_chunk_geometry(c0, T, na, C, nd, nf, nsp, pgeo, pblk, lane);
+    aev_f32x4 c0[NT], c1[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      c0[u] = aev_f32x4{0.f, 0.f, 0.f, 0.f};
+      c1[u] = c0[u];
+    }
+    for (int p0 = 0; p0 < T; p0 += kPairChunk) {
+    pair_chunk_geometry(p0, T, na, C, nd, nf, nsp, pgeo, pblk, lane);
     wave_lds_sync();
-    const int tn = T - c0 < kPairChunk ? T - c0 : kPairChunk;
+    const int tn = T - p0 < kPairChunk ? T - p0 : kPairChunk;
     for (int t0 = 0; t0 < tn; t0 += 4) {
       const int t = t0 + kq;
-      float b0 = 0.f, b1 = 0.f, h0 = 0.f, h1 = 0.f;
+      float b0 = 0.f, b1 = 0.f;
+      int blk = -1;
       if (t < tn) {
         const float4 q = pgeo[t];  // kappa cos, sine, mean distance, fc_j fc_k
-        const int blk = pblk[t];
+        blk = pblk[t];
         const float base_ = 0.5f + 0.5f * (q.x * cz + q.y * sz);
         const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * q.w;
         const float u0 = q.z - ra_lo, u1 = q.z - ra_hi;
         b0 = wgt * fast_exp2(-C.eta_a_l2e * u0 * u0);
         b1 = wgt * fast_exp2(-C.eta_a_l2e * u1 * u1);
-        h0 = blk == l16 ? 1.f : 0.f;
-        h1 = blk == l16 + 16 ? 1.f : 0.f;
       }
-      // h1 is zero unless there are more than 16 blocks; the two extra MFMAs
-      // cost less than a branch that keeps the accumulators apart
-      c00 = mfma4(b0, h0, c00);
-      c01 = mfma4(b1, h0, c01);
-      c10 = mfma4(b0, h1, c10);
-      c11 = mfma4(b1, h1, c11);
+      // every tile's product runs on every pass: a tile without the pass's
+      // blocks adds zeros, which costs less than a branch that keeps the
+      // accumulators apart
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const float hot = blk == l16 + 16 * u ? 1.f : 0.f;
+        c0[u] = mfma4(b0, hot, c0[u]);
+        c1[u] = mfma4(b1, hot, c1[u]);
+      }
     }
     wave_lds_sync();  // the next chunk overwrites the table
     }
-    // column c of c00 is feature c of the block (a = c / 8 for the low
-    // radial shifts, z = c % 8); c01 holds features 16 + c
+    // column c of c0[u] is feature c of block 16 u + l16 (a = c / 8 for the
+    // low radial shifts, z = c % 8); c1[u] holds features 16 + c
     OutT* ang = orow + S * kNR + l16 * 32 + 4 * kq;
-    if (l16 < nblk) {
-      Store<OutT>::put4(ang, make_float4(c00[0], c00[1], c00[2], c00[3]));
-      Store<OutT>::put4(ang + 16, make_float4(c01[0], c01[1], c01[2], c01[3]));
-    }
-    if (l16 + 16 < nblk) {
-      Store<OutT>::put4(ang + 512, make_float4(c10[0], c10[1], c10[2], c10[3]));
-      Store<OutT>::put4(ang + 528, make_float4(c11[0], c11[1], c11[2], c11[3]));
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      if (l16 + 16 * u < nblk) {
+        Store<OutT>::put4(ang + 512 * u, make_float4(c0[u][0], c0[u][1], c0[u][2], c0[u][3]));
+        Store<OutT>::put4(ang + 512 * u + 16,
+                          make_float4(c1[u][0], c1[u][1], c1[u][2], c1[u][3]));
+      }
     }
   }
   for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
@@ -533,10 +542,14 @@ void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4*
                     hipStream_t st) {
   if (n_cap <= 0) return;
   const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr + (size_t)4 * kPairChunk * kFwdPairBytes;
-  static const bool attr = (ensure_lds(k_aev_fwd<OutT>), true);
+  static const bool attr = (ensure_lds(k_aev_fwd<OutT, 1>), ensure_lds(k_aev_fwd<OutT, 2>),
+                            ensure_lds(k_aev_fwd<OutT, 3>), true);
   (void)attr;
-  hipLaunchKernelGGL(k_aev_fwd<OutT>, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec,
-                     counts, cap, row_of, out, ld);
+  const int nblk = C.S * (C.S + 1) / 2;
+  auto kern = nblk <= 16 ? k_aev_fwd<OutT, 1> : (nblk <= 32 ? k_aev_fwd<OutT, 2>
+                                                             : k_aev_fwd<OutT, 3>);
+  hipLaunchKernelGGL(kern, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec, counts, cap,
+                     row_of, out, ld);
 }
 template void launch_aev_fwd<float>(const int*, int, const AevConst&, const float4*, const int2*,
                                     int, const int*, float*, int, hipStream_t);

@@ -152,6 +152,63 @@ def test_energy_forces_five_elements(prec, f_tol, e_tol):
     assert fr <= f_tol
 
 
+def _eight_element_system():
+    base = w.conformer_batch(24, 48, seed=8)
+    sp = np.random.default_rng(12).integers(0, 8, base.n_atoms).astype(np.int32)
+    return w.System(base.pos, sp, base.mol_offsets, None, 8, "eight-elements")
+
+
+def test_eight_elements_pairs_and_aev():
+    """Eight elements: 36 angular pair blocks (F = 1280), so the forward pass
+    needs a third 16-block one-hot tile.  Every block is populated."""
+    s = _eight_element_system()
+    at = w.aev_table(8)
+    mt = w.mlp_table(8, widths=(1280, 256, 192, 160, 1))
+    announce(f"eight elements pairs + aev N={s.n_atoms}")
+    pot, _, _ = potential(8, "fp32", aev=at, mlp=mt)
+    pos, spd, off = to_dev(s)
+    pot.energy_forces(pos, spd, off, None, forces=False)
+    pot.check()
+    counts, nbr = pot.debug_neighbors(s.n_atoms)
+    I, J = pair_set_from_ell(counts, nbr)
+    Io, Jo = pair_list(s.pos, s.mol_offsets, None, at.rc_rad)
+    assert np.array_equal(I, Io) and np.array_equal(J, Jo)
+    G = pot.debug_aev(pos, spd, off, None).cpu().numpy()
+    pot.check()
+    Go, _ = o.aev(s.pos, s.species, s.mol_offsets, None, at)
+    assert G.shape == Go.shape == (s.n_atoms, 1280)
+    # the last four pair blocks (32..35) are populated in this input
+    ang0 = 8 * 16
+    assert np.abs(Go[:, ang0 + 32 * 32:]).sum(1).astype(bool).sum() > 20
+    err = rel_rms(G, Go)
+    err_tail = rel_rms(G[:, ang0 + 32 * 32:], Go[:, ang0 + 32 * 32:])
+    print(f"aev rel-RMS {err:.3e}, blocks 32-35 {err_tail:.3e}")
+    assert err <= 2e-6 and err_tail <= 2e-6
+    assert np.all(G[Go == 0] == 0)
+
+
+@pytest.mark.parametrize("prec,f_tol,e_tol", [("fp32", 1e-5, 1e-5), ("bf16", 1e-2, 1e-2)])
+def test_energy_forces_eight_elements(prec, f_tol, e_tol):
+    s = _eight_element_system()
+    at = w.aev_table(8)
+    mt = w.mlp_table(8, widths=(1280, 256, 192, 160, 1))
+    announce(f"eight elements {prec} N={s.n_atoms}")
+    pot, _, _ = potential(8, prec, aev=at, mlp=mt)
+    pos, spd, off = to_dev(s)
+    E, F = pot.energy_forces(pos, spd, off, None)
+    pot.check()
+    E = E.cpu().numpy()
+    F = F.cpu().numpy()
+    r = o.energy_forces(s, aev_table=at, mlp_table=mt)
+    scale = np.array([np.abs(r.E_atom[s.mol_offsets[m]:s.mol_offsets[m + 1]]).sum()
+                      for m in range(s.n_mol)])
+    de = np.abs(E - r.E) / np.maximum(scale, 1e-30)
+    fr = rel_rms(F, r.F)
+    print(f"{prec}: max |dE|/sum|E_i| {de.max():.3e}  force rel-RMS {fr:.3e}")
+    assert de.max() <= e_tol
+    assert fr <= f_tol
+
+
 def test_full_batch_512x64():
     s = w.config_system(1)
     announce(f"full batch 512x64 N={s.n_atoms}")
