@@ -234,7 +234,12 @@ const char* nnp_status_string(nnp_status s);
  *                        lists the angular neighbors first, then the rest.
  *   nnp_debug_aev:       runs staging, neighbor search and the symmetry
  *                        functions and writes G as float32 [n_atoms][F] in
- *                        input atom order into `aev` (device). */
+ *                        input atom order into `aev` (device).
+ *   nnp_debug_atom_energies: the atomic network outputs E_i (without self
+ *                        energies) of the last nnp_energy_forces() or
+ *                        nnp_backward() on `workspace` with the same n_atoms,
+ *                        n_mol and box, float32 [n_models][n_atoms] in input
+ *                        atom order, into `e_atom` (device). */
 nnp_status nnp_debug_neighbors(nnp_handle* h, int32_t n_atoms, void* workspace,
                                size_t workspace_bytes, int32_t* counts,
                                int32_t* nbr, void* stream);
@@ -242,6 +247,9 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
                          const float* pos, const int32_t* species,
                          const int32_t* mol_offsets, const float* box, float* aev,
                          void* workspace, size_t workspace_bytes, void* stream);
+nnp_status nnp_debug_atom_energies(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
+                                   const float* box, void* workspace, size_t workspace_bytes,
+                                   float* e_atom, void* stream);
 
 /* Captured evaluations.  nnp_graph_capture() runs one nnp_energy_forces()
  * eagerly on `stream`, then captures the same call into a HIP graph; each

@@ -207,6 +207,17 @@ class Potential:
                                                  _stream()), "debug_neighbors")
         return counts, nbr
 
+    def debug_atom_energies(self, n_atoms, n_mol, box=None):
+        """Atomic network outputs E_i (no self energies) of the last
+        evaluation, float32 [n_models, n_atoms] in input atom order."""
+        dev = self._ws.device
+        out = torch.empty((self.n_models, n_atoms), dtype=torch.float32, device=dev)
+        b, bp = self._box_arg(box)
+        capi.check(self._lib.nnp_debug_atom_energies(self._h, int(n_atoms), int(n_mol), bp,
+                                                     _ptr(self._ws), self._ws.numel(), _ptr(out),
+                                                     _stream()), "debug_atom_energies")
+        return out
+
     def debug_aev(self, pos, species, mol_offsets, box=None):
         pos = pos.contiguous()
         n = pos.shape[0]

@@ -64,6 +64,7 @@ _SIGS = [
     ("nnp_status_string", C.c_char_p, [C.c_int]),
     ("nnp_debug_neighbors", C.c_int, [_P, _I, _P, C.c_size_t, _P, _P, _P]),
     ("nnp_debug_aev", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    ("nnp_debug_atom_energies", C.c_int, [_P, _I, _I, _P, _P, C.c_size_t, _P, _P]),
     ("nnp_graph_capture", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P,
                                      C.POINTER(_P)]),
     ("nnp_graph_launch", C.c_int, [_P, _P]),

@@ -874,6 +874,21 @@ nnp_status nnp_debug_neighbors(nnp_handle* h, int32_t n, void* ws, size_t ws_byt
   return NNP_OK;
 }
 
+nnp_status nnp_debug_atom_energies(nnp_handle* h, int32_t n, int32_t nmol, const float* box,
+                                   void* ws, size_t ws_bytes, float* e_atom, void* stream) {
+  if (!h || !ws || !e_atom || n < 0 || nmol < 1) return NNP_E_INVALID;
+  BoxConst B;
+  if (!make_box(h, box, B)) return NNP_E_BOX;
+  const Plan P = make_plan(h, n, nmol, B);
+  if (ws_bytes < P.total) return NNP_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int k = 0; k < h->n_models; ++k)
+    if (hipMemcpyAsync(e_atom + (size_t)k * n, at<float>(ws, P.erow) + (size_t)k * P.rows_cap,
+                       (size_t)n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return NNP_E_HIP;
+  return NNP_OK;
+}
+
 nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* pos,
                          const int32_t* species, const int32_t* off, const float* box, float* aev,
                          void* ws, size_t ws_bytes, void* stream) {
