@@ -186,6 +186,28 @@ nnp_status nnp_energy_forces(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
                              double* E, float* F, void* workspace,
                              size_t workspace_bytes, void* stream);
 
+/* Energies and forces without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * hosts that forbid allocation).  Arguments as nnp_energy_forces, plus
+ *   status  device uint32 or NULL: receives the evaluation's device status
+ *           word (the bits nnp_check() decodes) when the stream reaches the
+ *           end of the call.
+ * The workspace is a fixed 64 MiB device array inside the library (one per
+ * device, held until the process ends); a system whose workspace would not
+ * fit returns NNP_E_WORKSPACE and enqueues nothing.  At a neighbor capacity
+ * of 128 that is about 3,000 atoms of seven elements with FP32 networks,
+ * 6,000 with BF16, and 7,000 of four elements (BF16); the need is
+ * nnp_workspace_bytes() less the weight-gradient partials it includes.  The call itself allocates nothing: no hipMalloc, no
+ * event or stream creation.  Every call on a device uses the same array, so
+ * calls that may overlap on one device (other streams, other threads) race
+ * and must be serialised by the caller; consecutive calls on one stream are
+ * safe.  Host-checkable errors return synchronously as for
+ * nnp_energy_forces. */
+nnp_status nnp_energy_forces_noalloc(nnp_handle* h, int32_t n_atoms, int32_t n_mol,
+                                     const float* pos, const int32_t* species,
+                                     const int32_t* mol_offsets, const float* box,
+                                     double* E, float* F, uint32_t* status, void* stream);
+
 /* A subset of a larger system (the ML/MM setting of Results, "Performance of
  * MLPs": the potential covers a 53-atom ligand inside a 134,099-atom system,
  * the rest is classical; mechanical embedding, so the potential sees only

@@ -158,6 +158,26 @@ class Potential:
             _ptr(ws), ws.numel(), _stream()), "nnp_energy_forces")
         return E, F
 
+    def energy_forces_noalloc(self, pos, species, mol_offsets, box=None, forces=True, out=None):
+        """As energy_forces, on the library's own fixed workspace (the call
+        allocates no device memory).  Returns E, F and a device uint32 [1]
+        holding the evaluation's status word."""
+        pos = pos.contiguous()
+        n = pos.shape[0]
+        n_mol = mol_offsets.shape[0] - 1
+        dev = pos.device
+        if out is None:
+            E = torch.empty(n_mol, dtype=torch.float64, device=dev)
+            F = torch.empty((n, 3), dtype=torch.float32, device=dev) if forces else None
+            status = torch.empty(1, dtype=torch.int32, device=dev)
+        else:
+            E, F, status = out
+        b, bp = self._box_arg(box)
+        capi.check(self._lib.nnp_energy_forces_noalloc(
+            self._h, n, n_mol, _ptr(pos), _ptr(species), _ptr(mol_offsets), bp, _ptr(E), _ptr(F),
+            _ptr(status), _stream()), "nnp_energy_forces_noalloc")
+        return E, F, status
+
     def energy_forces_subset(self, idx, pos_all, species, mol_offsets, F_all=None, box=None):
         """Energies of the subset rows idx of a larger system; its forces are
         added into F_all (float32 [n_total, 3]) when given.  Returns E."""

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -59,9 +60,45 @@ struct nnp_handle {
   long long prof_n[32] = {};
 };
 
+// Workspace of the allocation-free entry point (nnp_energy_forces_noalloc):
+// one evaluation's workspace of at most kScratchBytes, held by every device
+// the library runs on until the process ends.  On the host the name stands
+// in for the symbol and is not a device address: host code uses only the
+// per-device address that scratch_ptr() looks up.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 constexpr int kWChunk = 1024;  // rows per weight-gradient partial
+
+// Device address of `scratch` on device `dev`: looked up once per device
+// (with that device current) by hipGetSymbolAddress, then cached.  Returns
+// null when the lookup fails.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+void* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return nullptr;
+    g_scratch[dev] = p;
+  }
+  return g_scratch[dev];
+}
+
+// Copies the evaluation's status word to the caller (one thread).
+__global__ void k_copy_status(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
 
 enum Stage {
   ST_STAGE = 0, ST_PAIRS, ST_AEV, ST_L1, ST_L2, ST_HEAD, ST_ENERGY, ST_BWD3, ST_BWD2, ST_GRADG,
@@ -87,8 +124,8 @@ struct StageTimer {
   int stage;
   hipStream_t st;
   hipEvent_t a = nullptr;
-  StageTimer(nnp_handle* h_, int s, hipStream_t st_) : h(h_), stage(s), st(st_) {
-    if (h->prof && (a = prof_event(h))) (void)hipEventRecord(a, st);
+  StageTimer(nnp_handle* h_, bool on, int s, hipStream_t st_) : h(h_), stage(s), st(st_) {
+    if (on && h->prof && (a = prof_event(h))) (void)hipEventRecord(a, st);
   }
   ~StageTimer() {
     if (!a) return;
@@ -175,7 +212,9 @@ bool make_box(const nnp_handle* h, const float* box, BoxConst& B) {
   return true;
 }
 
-Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B) {
+// wgrad = false leaves out the weight-gradient partials (calls that never ask
+// for parameter gradients).
+Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B, bool wgrad = true) {
   Plan P;
   P.n = n;
   P.nmol = nmol;
@@ -233,7 +272,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B) {
     const size_t in = l == 0 ? h->F : h->width[l];
     maxlen = std::max(maxlen, (size_t)h->width[l + 1] * in + h->width[l + 1]);
   }
-  P.wpart = take((size_t)P.nwchunks * maxlen * 4);
+  P.wpart = wgrad ? take((size_t)P.nwchunks * maxlen * 4) : 0;
   P.pos32 = take(N * 12);
   P.total = o;
   return P;
@@ -260,6 +299,7 @@ struct EvalIO {
   float* dparams;       // weight gradients, may be null
   const int* gidx = nullptr;  // subset mode: rows of pos and out3 ([n_total][3]) per atom;
   int n_total = 0;            // forces are added to out3, not stored
+  bool timed = true;          // stage events when profiling (they may create events)
 };
 
 template <typename T>
@@ -282,7 +322,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   const bool need_bwd = io.out3 || io.dparams;
 
   {
-    StageTimer t(h, ST_STAGE, st);
+    StageTimer t(h, io.timed, ST_STAGE, st);
     launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.gidx, io.n_total,
                  io.species, io.off, S, xyzs, mol, mrange, io.gidx ? nullptr : io.out3, hist,
                  status, st);
@@ -295,7 +335,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
   }
   {
-    StageTimer t(h, ST_PAIRS, st);
+    StageTimer t(h, io.timed, ST_PAIRS, st);
     if (!P.B.periodic && P.nblk <= kFusedSortBlocks) {
       // molecules: the sort and the pair scan share one launch
       launch_sort_pairs_mol(dims, P.n, S, hist, gt, row, perm, P.rows_cap, io.off, kWChunk,
@@ -311,7 +351,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   }
   T* X = at<T>(ws, P.X);
   {
-    StageTimer t(h, ST_AEV, st);
+    StageTimer t(h, io.timed, ST_AEV, st);
     launch_aev_fwd<T>(dims, P.n, h->C, rec, counts, P.cap, row, X, Fp, st);
   }
 
@@ -370,7 +410,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     g.A = X; g.lda = Fp; g.B = Wk[0]; g.Bq = Wqk[0]; g.sB = (long)w1 * Fp; g.ldb = Fp;
     g.bias = bias_k[0]; g.sBias = w1; g.N = w1; g.K = Fp; g.C = H1; g.ldc = w1;
     {
-      StageTimer t(h, ST_L1, st);
+      StageTimer t(h, io.timed, ST_L1, st);
       ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
     }
     // BF16 with gradients: one fused launch for layer 2, the energy head and the
@@ -404,7 +444,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       ma.dLdE = io.dLdE;
       ma.alpha = h->alpha;
       ma.inv_alpha_l2e = g.inv_alpha_l2e;
-      StageTimer t(h, ST_MID, st);
+      StageTimer t(h, io.timed, ST_MID, st);
       fused = launch_mlp_mid(h->width, ma, P.rows_cap, st);
     }
     if (!fused) {
@@ -412,7 +452,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       g.A = H1; g.lda = w1; g.B = Wk[1]; g.Bq = Wqk[1]; g.sB = (long)w2 * w1; g.ldb = w1;
       g.bias = bias_k[1]; g.sBias = w2; g.N = w2; g.K = w1; g.C = H2; g.ldc = w2;
       {
-        StageTimer t(h, ST_L2, st);
+        StageTimer t(h, io.timed, ST_L2, st);
         ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
       }
       // layer 3 + output: E_i, delta3
@@ -424,7 +464,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       g.perm = perm; g.mol = mol; g.dLdE = io.dLdE;
       g.uprow = io.dparams ? at<float>(ws, P.uprow) : nullptr;
       {
-        StageTimer t(h, ST_HEAD, st);
+        StageTimer t(h, io.timed, ST_HEAD, st);
         ok &= launch_gemm<T>(EPI_HEAD, g, P.rows_cap, st);
       }
       g.H3 = nullptr;
@@ -434,14 +474,14 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
         g.A = D3; g.lda = w3; g.B = WTk[2]; g.Bq = WTqk[2]; g.sB = (long)w2 * w3; g.ldb = w3;
         g.bias = nullptr; g.N = w2; g.K = w3; g.C = D2; g.ldc = w2; g.H = H2; g.ldh = w2;
         {
-          StageTimer t(h, ST_BWD3, st);
+          StageTimer t(h, io.timed, ST_BWD3, st);
           ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
         }
         // delta1 = (delta2 W1) * CELU'(z1)
         g.A = D2; g.lda = w2; g.B = WTk[1]; g.Bq = WTqk[1]; g.sB = (long)w1 * w2; g.ldb = w2;
         g.N = w1; g.K = w2; g.C = D1k; g.ldc = ldd1; g.H = H1; g.ldh = w1;
         {
-          StageTimer t(h, ST_BWD2, st);
+          StageTimer t(h, io.timed, ST_BWD2, st);
           ok &= launch_gemm<T>(EPI_BWD, g, P.rows_cap, st);
         }
       }
@@ -450,7 +490,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   // the molecular energies: beside the force scatter when there is one
   const EnergyArgs ea{io.off, xyzs, erow, M, (long)P.rows_cap, h->eself, io.E, status};
   if (io.E && !io.out3) {
-    StageTimer t(h, ST_ENERGY, st);
+    StageTimer t(h, io.timed, ST_ENERGY, st);
     launch_energy(dims, P.nmol, io.off, xyzs, erow, M, (long)P.rows_cap, h->eself, io.E, status,
                   st);
   }
@@ -470,15 +510,15 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     g.sB = (long)Fp * ldd1; g.ldb = ldd1;
     g.N = Fp; g.K = ldd1; g.C = G; g.ldc = Fp; g.H = nullptr;
     {
-      StageTimer t(h, ST_GRADG, st);
+      StageTimer t(h, io.timed, ST_GRADG, st);
       ok &= launch_gemm<T>(EPI_OUT, g, P.rows_cap, st);
     }
-    StageTimer t(h, ST_AEVBWD, st);
+    StageTimer t(h, io.timed, ST_AEVBWD, st);
     launch_aev_bwd<T>(dims, P.n, h->C, rec, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
                       io.gidx, io.n_total, mrange, &ea, P.nmol, st);
   }
   if (io.dparams) {
-    StageTimer t(h, ST_WGRAD, st);
+    StageTimer t(h, io.timed, ST_WGRAD, st);
     float* part = at<float>(ws, P.wpart);
     const float* up = at<float>(ws, P.uprow);
     const long* po = h->param_off_dev;
@@ -577,6 +617,9 @@ nnp_status nnp_create_ensemble(const nnp_aev_params* aev, const nnp_mlp_params* 
     delete h;
     return NNP_E_HIP;
   }
+  // the allocation-free entry point's scratch address on this device (a
+  // failed lookup is retried, and reported, by that entry point)
+  (void)scratch_ptr(h->device);
   h->prec = precision;
   h->S = S;
   h->F = F;
@@ -812,6 +855,33 @@ nnp_status nnp_energy_forces(nnp_handle* h, int32_t n, int32_t nmol, const float
   if (!E) return NNP_E_INVALID;
   EvalIO io{n, nmol, pos, nullptr, species, off, E, F, 1.f, nullptr, nullptr};
   return run(h, P, ws, io, static_cast<hipStream_t>(stream));
+}
+
+nnp_status nnp_energy_forces_noalloc(nnp_handle* h, int32_t n, int32_t nmol, const float* pos,
+                                     const int32_t* species, const int32_t* off,
+                                     const float* box, double* E, float* F, uint32_t* status,
+                                     void* stream) {
+  if (!h || n < 0 || nmol < 1 || !E) return NNP_E_INVALID;
+  if (n > 0 && (!pos || !species)) return NNP_E_INVALID;
+  if (!off || (box && nmol != 1) || n >= (1 << 27)) return NNP_E_INVALID;
+  BoxConst B;
+  if (!make_box(h, box, B)) return NNP_E_BOX;
+  const Plan P = make_plan(h, n, nmol, B, false);
+  if (P.total > kScratchBytes) return NNP_E_WORKSPACE;
+  if (hipSetDevice(h->device) != hipSuccess) return NNP_E_HIP;
+  void* ws = scratch_ptr(h->device);
+  if (!ws) return NNP_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  EvalIO io{n, nmol, pos, nullptr, species, off, E, F, 1.f, nullptr, nullptr};
+  io.timed = false;  // stage events would create HIP events
+  const nnp_status s = run(h, P, ws, io, st);
+  if (s != NNP_OK) return s;
+  if (status) {
+    hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st,
+                       static_cast<const uint32_t*>(at<uint32_t>(ws, P.status)), status);
+    if (hipGetLastError() != hipSuccess) return NNP_E_HIP;
+  }
+  return NNP_OK;
 }
 
 nnp_status nnp_energy_forces_subset(nnp_handle* h, int32_t n_sub, int32_t nmol,
