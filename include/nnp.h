@@ -357,12 +357,21 @@ nnp_status nnp_langevin_steps(nnp_handle* h, int32_t n_atoms, int32_t n_mol, dou
  * molecules, sized within hbm_budget_bytes), a pending queue, and one
  * captured HIP graph of a whole velocity-Verlet step over the packed active
  * set.  Each nnp_server_step():
- *   1. retires requests that finished their steps (results copied to host),
- *   2. admits pending requests in arrival order while atoms, slots and the
- *      HBM budget allow (their x, v, species are copied to the device and the
- *      batch is repacked on the device),
- *   3. replays the step graph once over every active request.
+ *   1. hands over the results whose copies to the host have completed,
+ *   2. drops requests that finished their steps and admits pending requests
+ *      in arrival order while atoms, slots and the HBM budget allow (their
+ *      x, v, species are copied to the device and the batch is repacked on
+ *      the device),
+ *   3. replays the step graph once over every active request,
+ *   4. for requests whose last step that was, enqueues the copies of their
+ *      state, energies and the device status word to pinned host memory
+ *      behind an event, read by a later round: no round waits for the GPU
+ *      (a round waits only when four rounds' results are still in flight, or
+ *      when nothing is left to run).
  * Every request's trajectory is independent of the others in the batch.
+ * Device errors (a neighbor list overflow, non-finite positions) are
+ * reported per request by nnp_server_result: every request that was on the
+ * device while a status bit was raised gets it.
  * ------------------------------------------------------------------------- */
 nnp_status nnp_server_create(nnp_handle* h, size_t hbm_budget_bytes,
                              int32_t max_atoms, int32_t max_mols, double dt_fs,
@@ -387,24 +396,36 @@ nnp_status nnp_server_submit(nnp_server* s, int64_t req_id, int32_t n_atoms,
                              const double* x, const double* v,
                              const int32_t* species, int32_t n_steps);
 
-/* One scheduling round (retire, admit, one MD step).  Returns after the step
- * has been enqueued; results of requests retired in this round are complete
- * on return. */
+/* One scheduling round (deliver, retire, admit, one MD step).  Returns after
+ * the step has been enqueued; with no request left on the device it waits
+ * for the results still in flight and delivers them. */
 nnp_status nnp_server_step(nnp_server* s);
 
-/* Number of active and pending requests. */
+/* Requests admitted whose results have not been delivered yet (on the
+ * device, or on their way back), and requests still queued. */
 int32_t nnp_server_active(const nnp_server* s);
 int32_t nnp_server_pending(const nnp_server* s);
 
-/* Finished request ids (up to `max`), oldest first; each id is reported once. */
+/* Delivered request ids (up to `max`), oldest first; each id is reported
+ * once.  Also delivers the results whose copies have completed (no wait). */
 int32_t nnp_server_poll(nnp_server* s, int64_t* done_ids, int32_t max);
 
-/* Result of a finished request: final x, v (host float64 [n][3], may be NULL),
- * final potential and kinetic energy, and host wall-clock times (seconds,
- * steady clock) of submission, admission and completion. */
+/* Result of a delivered request: final x, v (host float64 [n][3], may be
+ * NULL), final potential and kinetic energy, and host wall-clock times
+ * (seconds, steady clock) of submission, admission and delivery.  The
+ * outputs are written in any case; the return value is the request's device
+ * status (NNP_E_CAPACITY, NNP_E_NONFINITE, ... if a status bit was raised
+ * while it was on the device, else NNP_OK). */
 nnp_status nnp_server_result(nnp_server* s, int64_t req_id, double* x, double* v,
                              double* e_pot, double* e_kin, double* t_submit,
                              double* t_admit, double* t_done);
+
+/* Server statistics into out[0 .. n): the atom and molecule capacity (after
+ * fitting the HBM budget), atoms on the device now, the most atoms on the
+ * device in one round, rounds run, rounds whose repack kept survivors and
+ * admitted new requests, the most distinct request step counters in one
+ * launch, and rounds that waited for a retire slot. */
+nnp_status nnp_server_stats(const nnp_server* s, int64_t* out, int32_t n);
 
 #ifdef __cplusplus
 }

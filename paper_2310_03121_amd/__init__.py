@@ -436,13 +436,27 @@ class Server:
         k = self._lib.nnp_server_poll(self._s, C.c_void_p(ids.ctypes.data), max_n)
         return ids[:k].tolist()
 
-    def result(self, req_id, n_atoms):
+    def result(self, req_id, n_atoms, check=True):
+        """Final state, energies and times of a delivered request.  With
+        check, a device error raised while the request ran raises NNPError;
+        otherwise the dict carries its status code."""
         x = np.zeros((n_atoms, 3))
         v = np.zeros((n_atoms, 3))
         vals = (C.c_double * 5)()
-        capi.check(self._lib.nnp_server_result(
+        code = self._lib.nnp_server_result(
             self._s, int(req_id), C.c_void_p(x.ctypes.data), C.c_void_p(v.ctypes.data),
             C.byref(vals, 0), C.byref(vals, 8), C.byref(vals, 16), C.byref(vals, 24),
-            C.byref(vals, 32)), "nnp_server_result")
+            C.byref(vals, 32))
+        if check:
+            capi.check(code, "nnp_server_result")
         return dict(x=x, v=v, e_pot=vals[0], e_kin=vals[1], t_submit=vals[2], t_admit=vals[3],
-                    t_done=vals[4])
+                    t_done=vals[4], status=int(code))
+
+    def stats(self):
+        """Capacity and scheduling statistics (nnp_server_stats)."""
+        out = np.zeros(8, np.int64)
+        capi.check(self._lib.nnp_server_stats(self._s, C.c_void_p(out.ctypes.data), 8),
+                   "nnp_server_stats")
+        keys = ("capacity_atoms", "capacity_mols", "atoms_on_device", "peak_atoms", "rounds",
+                "mixed_rounds", "max_phases_per_launch", "retire_waits")
+        return dict(zip(keys, (int(x) for x in out)))

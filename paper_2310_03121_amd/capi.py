@@ -89,6 +89,7 @@ _SIGS = [
     ("nnp_server_pending", _I, [_P]),
     ("nnp_server_poll", _I, [_P, _P, _I]),
     ("nnp_server_result", C.c_int, [_P, C.c_int64, _P, _P, _P, _P, _P, _P, _P]),
+    ("nnp_server_stats", C.c_int, [_P, _P, _I]),
 ]
 SYMBOLS = [s[0] for s in _SIGS]
 

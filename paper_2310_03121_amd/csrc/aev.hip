@@ -109,27 +109,6 @@ constexpr int kPairChunk = 64;
 constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
 constexpr int kFwdPairBytes = 16 + 4;
 
-// The angular pairs [c0, c0 + 64) of the list, one per lane: what a pair's
-// 32 terms share, computed once instead of in each of the 16 lanes of its
-// pass: (kappa cos theta, sqrt(1 - kappa^2 cos^2), mean distance,
-// fc_j fc_k) and the pair's block.
-__device__ __forceinline__ void pair_chunk_geometry(int c0, int T, int na, const AevConst& C,
-                                                    const float4* nd, const float2* nf,
-                                                    const int* nsp, float4* pgeo, int* pblk,
-                                                    int lane) {
-  const int t = c0 + lane;
-  if (t < T) {
-    int a, b;
-    decode_pair(t, na, a, b);
-    const float4 vj = nd[a], vk = nd[b];
-    const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
-    const float kc = C.kappa * cs;
-    pgeo[lane] = make_float4(kc, fast_sqrt(fmaxf(1.f - kc * kc, 0.f)), 0.5f * (vj.w + vk.w),
-                             nf[a].y * nf[b].y);
-    pblk[lane] = pair_block(nsp[a], nsp[b], C.S);
-  }
-}
-
 typedef float aev_f32x4 __attribute__((ext_vector_type(4)));
 
 // acc += A * B for one 16 x 16 x 4 FP32 MFMA: lane l supplies A[l % 16][l / 16]
@@ -141,134 +120,206 @@ __device__ __forceinline__ aev_f32x4 mfma4(float a, float b, aev_f32x4 acc) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
 }
 
+// The angular pair t of atom-local list prefix [0, na), one per lane: what
+// a pair's 32 terms share, computed once instead of in each of the 16 lanes
+// of its pass, written to table slot `slot`.
+__device__ __forceinline__ void pair_geometry(int t, int na, const AevConst& C, const float4* nd,
+                                              const float2* nf, const int* nsp, float4* pgeo,
+                                              int* pblk, int slot) {
+  int a, b;
+  decode_pair(t, na, a, b);
+  const float4 vj = nd[a], vk = nd[b];
+  const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
+  const float kc = C.kappa * cs;
+  pgeo[slot] = make_float4(kc, fast_sqrt(fmaxf(1.f - kc * kc, 0.f)), 0.5f * (vj.w + vk.w),
+                           nf[a].y * nf[b].y);
+  pblk[slot] = pair_block(nsp[a], nsp[b], C.S);
+}
+
+// Four atoms per wave.  When each of a wave's four atoms has at most 16
+// neighbors ("quad" waves), the per-neighbor setup (distances, cutoffs,
+// species; in the adjoint also the force scatter and the centre-atom sum)
+// runs for all four at once, one 16-lane group per atom, and the pairs of
+// angular neighbors of all four share one table; the radial and angular
+// passes, which fill the wave with (neighbor, shift) and (pair, shift) lanes,
+// run atom by atom.  Other waves take their atoms one at a time with all 64
+// lanes.  Either way a wave's LDS region holds max(64, capacity) neighbor
+// entries: four 16-entry slots, or one atom's list.
+//
+// Quads pay off only where lists are short; where they are long, a wave per
+// atom keeps four times as many waves in flight to hide the latency of the
+// per-atom passes.  The launchers take the neighbor capacity as the hint:
+// Q = 4 atoms per wave up to a capacity of 64 (molecules), else Q = 1
+// (liquid-density boxes need more than 64).
+constexpr int kQuadNbr = 16;   // longest list of a quad wave (lanes per atom)
+
+__host__ __device__ constexpr int aev_region(int cap) { return cap > 64 ? cap : 64; }
+__host__ __device__ constexpr bool aev_quads(int cap) { return cap <= 64; }
+
 // NT: 16-block tiles of the angular one-hot (ceil(S (S + 1) / 2 / 16): one
 // for up to five elements, two for six or seven, three for eight).
-template <typename OutT, int NT>
-__global__ __launch_bounds__(256) void k_aev_fwd(const int* __restrict__ dims, AevConst C,
+template <typename OutT, int NT, int Q>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_aev_fwd(const int* __restrict__ dims, AevConst C,
                                                  const float4* __restrict__ rec,
                                                  const int2* __restrict__ counts, int cap,
                                                  const int* __restrict__ row_of,
                                                  OutT* __restrict__ out, int ld) {
   extern __shared__ float4 lds4[];
   const int n = dims[0];
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int lane = lane_id();
-  const int i = blockIdx.x * 4 + w;
-  if (i >= n) return;
-  float4* nd = lds4 + (size_t)w * cap;
-  float2* nf = reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) + (size_t)w * cap;
-  int* nsp = reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
-                                    (size_t)4 * cap) + w * cap;
-  float4* pgeo = reinterpret_cast<float4*>(
-                     reinterpret_cast<int*>(reinterpret_cast<float2*>(lds4 + (size_t)4 * cap) +
-                                            (size_t)4 * cap) + 4 * cap) + w * kPairChunk;
-  int* pblk = reinterpret_cast<int*>(pgeo + (4 - w) * kPairChunk) + w * kPairChunk;
+  const int i0 = ((int)blockIdx.x * 4 + w) * Q;  // the wave's first atom
+  if (i0 >= n) return;
+  const int reg = aev_region(cap);
+  float4* nd = lds4 + (size_t)w * reg;
+  float2* nf0 = reinterpret_cast<float2*>(lds4 + (size_t)4 * reg);
+  float2* nf = nf0 + (size_t)w * reg;
+  int* nsp0 = reinterpret_cast<int*>(nf0 + (size_t)4 * reg);
+  int* nsp = nsp0 + (size_t)w * reg;
+  float4* pgeo0 = reinterpret_cast<float4*>(nsp0 + (size_t)4 * reg);
+  float4* pgeo = pgeo0 + w * kPairChunk;
+  int* pblk = reinterpret_cast<int*>(pgeo0 + 4 * kPairChunk) + w * kPairChunk;
 
-  // the first 64 records are fetched together with the counts
-  const float4* nrec = rec + (size_t)i * cap;
-  const float4 q0 = lane < kSpecRec && lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-  const int2 cn = counts[i];
-  const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
-  const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
-  auto setup = [&](int e, const float4 q) __attribute__((always_inline)) {
+  auto setup = [&](int slot, const float4 q, bool ang) __attribute__((always_inline)) {
     const float r = fast_sqrt(dist2(q.x, q.y, q.z));
     float dfr, dfa;
     const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
-    const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
-    nd[e] = make_float4(q.x, q.y, q.z, r);
-    nf[e] = make_float2(fr, fa);
-    nsp[e] = species_of(q);
+    const float fa = ang ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
+    nd[slot] = make_float4(q.x, q.y, q.z, r);
+    nf[slot] = make_float2(fr, fa);
+    nsp[slot] = species_of(q);
   };
-  if (nr <= kSpecRec) {  // wave-uniform
-    if (lane < nr) setup(lane, q0);
-  } else {
-    for (int e = lane; e < nr; e += kWave) setup(e, nrec[e]);
-  }
-  wave_lds_sync();
-  const int S = C.S;
-  OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
-  const int l16 = lane & 15, kq = lane >> 4;
 
-  // ---- radial: G[s][m] = sum over neighbors e of [species(e) == s] * term(e, m)
-  // as MFMA products of a one-hot (species x 4 neighbors) with the terms
-  // (4 neighbors x 16 shifts); lane (kq, l16) computes neighbor kq, shift l16.
-  {
-    const float Rm = C.lane_tab[l16];
-    aev_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int e0 = 0; e0 < nr; e0 += 4) {
-      const int e = e0 + kq;
-      float term = 0.f, hot = 0.f;
-      if (e < nr) {
-        const float u = nd[e].w - Rm;
-        term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nf[e].x;
-        hot = nsp[e] == l16 ? 1.f : 0.f;
-      }
-      acc = mfma4(term, hot, acc);
-    }
-    if (l16 < S)
-      Store<OutT>::put4(orow + l16 * kNR + 4 * kq, make_float4(acc[0], acc[1], acc[2], acc[3]));
-  }
-
-  // ---- angular: G[blk][a z] = sum over unordered pairs of angular neighbors
-  // of [block(pair) == blk] * term(pair, a, z), four pairs per pass.  Lane
-  // (kq, l16) takes pair kq and column l16 of each of the two 16-column
-  // halves: angle shift z = l16 % 8 and radial shifts a = l16 / 8 and
-  // l16 / 8 + 2.  Tile u of the one-hot covers blocks 16 u .. 16 u + 15.
-  {
-    const int T = na * (na - 1) / 2;
-    const int nblk = S * (S + 1) / 2;
-    const int z = l16 & 7, ah = l16 >> 3;
-    const float cz = C.lane_tab[kNR + z], sz = C.lane_tab[kNR + kNZ + z];
-    const float ra_lo = ah ? C.shf_a[1] : C.shf_a[0];
-    const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
-    aev_f32x4 c0[NT], c1[NT];
-#pragma unroll
-    for (int u = 0; u < NT; ++u) {
-      c0[u] = aev_f32x4{0.f, 0.f, 0.f, 0.f};
-      c1[u] = c0[u];
-    }
-    for (int p0 = 0; p0 < T; p0 += kPairChunk) {
-    pair_chunk_geometry(p0, T, na, C, nd, nf, nsp, pgeo, pblk, lane);
+  // group g (lanes 16 g .. 16 g + 15) reads the counts and first 16 records
+  // of atom i0 + g (one atom per wave: every group reads atom i0)
+  const int g = Q > 1 ? lane >> 4 : 0, l = lane & 15;
+  const int ig = i0 + g;
+  const bool gin = ig < n;
+  const float4 q0 = gin ? rec[(size_t)ig * cap + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const int2 cn = gin ? counts[ig] : make_int2(0, 0);
+  const int nr_g = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
+  const int na_g = cn.y < 0 ? 0 : (cn.y > nr_g ? nr_g : cn.y);
+  const bool quad = Q > 1 && __ballot(nr_g > kQuadNbr) == 0;
+  const int T_g = na_g * (na_g - 1) / 2;
+  // quad waves with at most 16 pairs per atom: one pair table (slot 16 g + t)
+  const bool joint = quad && __ballot(T_g > kQuadNbr) == 0;
+  if (quad) {
+    if (l < nr_g) setup(kQuadNbr * g + l, q0, l < na_g);
     wave_lds_sync();
-    const int tn = T - p0 < kPairChunk ? T - p0 : kPairChunk;
-    for (int t0 = 0; t0 < tn; t0 += 4) {
-      const int t = t0 + kq;
-      float b0 = 0.f, b1 = 0.f;
-      int blk = -1;
-      if (t < tn) {
-        const float4 q = pgeo[t];  // kappa cos, sine, mean distance, fc_j fc_k
-        blk = pblk[t];
-        const float base_ = 0.5f + 0.5f * (q.x * cz + q.y * sz);
-        const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * q.w;
-        const float u0 = q.z - ra_lo, u1 = q.z - ra_hi;
-        b0 = wgt * fast_exp2(-C.eta_a_l2e * u0 * u0);
-        b1 = wgt * fast_exp2(-C.eta_a_l2e * u1 * u1);
+    if (joint) {
+      if (l < T_g)
+        pair_geometry(l, na_g, C, nd + kQuadNbr * g, nf + kQuadNbr * g, nsp + kQuadNbr * g, pgeo,
+                      pblk, lane);
+      wave_lds_sync();
+    }
+  }
+  const int S = C.S;
+  const int l16 = lane & 15, kq = lane >> 4;
+  const float Rm = C.lane_tab[l16];
+  const int z = l16 & 7, ah = l16 >> 3;
+  const float cz = C.lane_tab[kNR + z], sz = C.lane_tab[kNR + kNZ + z];
+  const float ra_lo = ah ? C.shf_a[1] : C.shf_a[0];
+  const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
+  const int nblk = S * (S + 1) / 2;
+
+  for (int a = 0; a < Q; ++a) {
+    const int i = i0 + a;
+    if (i >= n) break;  // wave-uniform
+    const int nr = __builtin_amdgcn_readlane(nr_g, kQuadNbr * a);
+    const int na = __builtin_amdgcn_readlane(na_g, kQuadNbr * a);
+    int base = kQuadNbr * a;
+    if (!quad) {
+      // this atom alone: every lane sets up its neighbors in slots [0, nr)
+      base = 0;
+      wave_lds_sync();  // the previous atom's passes have read the region
+      const float4* arec = rec + (size_t)i * cap;
+      for (int e = lane; e < nr; e += kWave) setup(e, arec[e], e < na);
+      wave_lds_sync();
+    }
+    const float4* nda = nd + base;
+    const float2* nfa = nf + base;
+    const int* nspa = nsp + base;
+    OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
+
+    // ---- radial: G[s][m] = sum over neighbors e of [species(e) == s] * term(e, m)
+    // as MFMA products of a one-hot (species x 4 neighbors) with the terms
+    // (4 neighbors x 16 shifts); lane (kq, l16) computes neighbor kq, shift l16.
+    {
+      aev_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      for (int e0 = 0; e0 < nr; e0 += 4) {
+        const int e = e0 + kq;
+        float term = 0.f, hot = 0.f;
+        if (e < nr) {
+          const float u = nda[e].w - Rm;
+          term = C.cR * fast_exp2(-C.eta_r_l2e * u * u) * nfa[e].x;
+          hot = nspa[e] == l16 ? 1.f : 0.f;
+        }
+        acc = mfma4(term, hot, acc);
       }
-      // every tile's product runs on every pass: a tile without the pass's
-      // blocks adds zeros, which costs less than a branch that keeps the
-      // accumulators apart
+      if (l16 < S)
+        Store<OutT>::put4(orow + l16 * kNR + 4 * kq, make_float4(acc[0], acc[1], acc[2], acc[3]));
+    }
+
+    // ---- angular: G[blk][a z] = sum over unordered pairs of angular
+    // neighbors of [block(pair) == blk] * term(pair, a, z), four pairs per
+    // pass.  Lane (kq, l16) takes pair kq and column l16 of each of the two
+    // 16-column halves: angle shift z = l16 % 8 and radial shifts a = l16 / 8
+    // and l16 / 8 + 2.  Tile u of the one-hot covers blocks 16 u .. 16 u + 15.
+    {
+      const int T = na * (na - 1) / 2;
+      aev_f32x4 c0[NT], c1[NT];
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        const float hot = blk == l16 + 16 * u ? 1.f : 0.f;
-        c0[u] = mfma4(b0, hot, c0[u]);
-        c1[u] = mfma4(b1, hot, c1[u]);
+        c0[u] = aev_f32x4{0.f, 0.f, 0.f, 0.f};
+        c1[u] = c0[u];
       }
-    }
-    wave_lds_sync();  // the next chunk overwrites the table
-    }
-    // column c of c0[u] is feature c of block 16 u + l16 (a = c / 8 for the
-    // low radial shifts, z = c % 8); c1[u] holds features 16 + c
-    OutT* ang = orow + S * kNR + l16 * 32 + 4 * kq;
+      for (int p0 = 0; p0 < T; p0 += kPairChunk) {
+        int tb = kQuadNbr * a;  // table slot of the chunk's first pair
+        if (!joint) {
+          tb = 0;
+          wave_lds_sync();  // the previous chunk's passes have read the table
+          if (p0 + lane < T) pair_geometry(p0 + lane, na, C, nda, nfa, nspa, pgeo, pblk, lane);
+          wave_lds_sync();
+        }
+        const int tn = T - p0 < kPairChunk ? T - p0 : kPairChunk;
+        for (int t0 = 0; t0 < tn; t0 += 4) {
+          const int t = t0 + kq;
+          float b0 = 0.f, b1 = 0.f;
+          int blk = -1;
+          if (t < tn) {
+            const float4 q = pgeo[tb + t];  // kappa cos, sine, mean distance, fc_j fc_k
+            blk = pblk[tb + t];
+            const float base_ = 0.5f + 0.5f * (q.x * cz + q.y * sz);
+            const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * q.w;
+            const float u0 = q.z - ra_lo, u1 = q.z - ra_hi;
+            b0 = wgt * fast_exp2(-C.eta_a_l2e * u0 * u0);
+            b1 = wgt * fast_exp2(-C.eta_a_l2e * u1 * u1);
+          }
+          // every tile's product runs on every pass: a tile without the pass's
+          // blocks adds zeros, which costs less than a branch that keeps the
+          // accumulators apart
 #pragma unroll
-    for (int u = 0; u < NT; ++u) {
-      if (l16 + 16 * u < nblk) {
-        Store<OutT>::put4(ang + 512 * u, make_float4(c0[u][0], c0[u][1], c0[u][2], c0[u][3]));
-        Store<OutT>::put4(ang + 512 * u + 16,
-                          make_float4(c1[u][0], c1[u][1], c1[u][2], c1[u][3]));
+          for (int u = 0; u < NT; ++u) {
+            const float hot = blk == l16 + 16 * u ? 1.f : 0.f;
+            c0[u] = mfma4(b0, hot, c0[u]);
+            c1[u] = mfma4(b1, hot, c1[u]);
+          }
+        }
+      }
+      // column c of c0[u] is feature c of block 16 u + l16 (a = c / 8 for the
+      // low radial shifts, z = c % 8); c1[u] holds features 16 + c
+      OutT* ang = orow + S * kNR + l16 * 32 + 4 * kq;
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        if (l16 + 16 * u < nblk) {
+          Store<OutT>::put4(ang + 512 * u, make_float4(c0[u][0], c0[u][1], c0[u][2], c0[u][3]));
+          Store<OutT>::put4(ang + 512 * u + 16,
+                            make_float4(c1[u][0], c1[u][1], c1[u][2], c1[u][3]));
+        }
       }
     }
+    for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
   }
-  for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
 }
 
 // Atoms per workgroup of the molecule adjoint.
@@ -282,47 +333,29 @@ constexpr int kMolBlock = 64;
 // forward pass measured no gain.
 constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 
-// The adjoint of one atom i, by one wave: dE/d(displacement) of every
-// neighbor entry into the wave's LDS region, then put(j, x, y, z) adds
-// -sign * dE/dv to neighbor j and (lane 0) +sign * sum to the centre i.
-// nd, nf, grad: cap float4 each; nsp: cap ints.
-template <typename GT, typename Put>
-__device__ __forceinline__ void adjoint_atom(int i, int n, const AevConst& C,
-                                             const float4* __restrict__ rec,
-                                             const int* __restrict__ nbr,
-                                             const int2* __restrict__ counts, int cap,
-                                             const int* __restrict__ row_of,
-                                             const GT* __restrict__ g, int ldg, float sign,
-                                             float4* nd, float4* nf, float4* grad, int* nsp,
-                                             Put&& put) {
-  const int lane = lane_id();
-  // records, counts, the dE/dG row and the neighbor indices of the scatter
-  // are all first-level loads
-  const int* nrow = nbr + (size_t)i * cap;
-  const float4* nrec = rec + (size_t)i * cap;
-  const float4 q0 = lane < kSpecRec && lane < cap ? nrec[lane] : make_float4(0.f, 0.f, 0.f, 0.f);
-  const int j0 = lane < kSpecRec && lane < cap ? nrow[lane] : 0;
-  const int2 cn = counts[i];
-  const GT* grow = g + (size_t)row_of[i] * ldg;
-  const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
-  const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
-  auto setup = [&](int e, const float4 q) __attribute__((always_inline)) {
-    const float r = fast_sqrt(dist2(q.x, q.y, q.z));
-    float dfr, dfa = 0.f;
-    const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
-    const float fa = e < na ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
-    nd[e] = make_float4(q.x, q.y, q.z, r);
-    nf[e] = make_float4(fr, fa, dfr, dfa);
-    nsp[e] = species_of(q);
-  };
-  if (nr <= kSpecRec) {  // wave-uniform
-    if (lane < nr) setup(lane, q0);
-  } else {
-    for (int e = lane; e < nr; e += kWave) setup(e, nrec[e]);
-  }
-  wave_lds_sync();
-  const int S = C.S;
+// One neighbor entry of the adjoint's LDS region: displacement and
+// distance, cutoff values and derivatives, species.
+__device__ __forceinline__ void adjoint_setup(int slot, const float4 q, bool ang,
+                                              const AevConst& C, float4* nd, float4* nf,
+                                              int* nsp) {
+  const float r = fast_sqrt(dist2(q.x, q.y, q.z));
+  float dfr, dfa = 0.f;
+  const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
+  const float fa = ang ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
+  nd[slot] = make_float4(q.x, q.y, q.z, r);
+  nf[slot] = make_float4(fr, fa, dfr, dfa);
+  nsp[slot] = species_of(q);
+}
 
+// The radial and angular passes of one atom (nr neighbors, the first na
+// angular, set up in nd, nf, nsp): dE/d(displacement) of every neighbor
+// entry into grad (the radial pass stores, the angular pass adds).
+template <typename GT>
+__device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C,
+                                               const GT* __restrict__ grow, const float4* nd,
+                                               const float4* nf, float4* grad, const int* nsp) {
+  const int lane = lane_id();
+  const int S = C.S;
   // ---- radial: dE/dr_ij per neighbor, reduced over the 16 shift lanes
   {
     const int gq = lane >> 4, m = lane & 15;
@@ -406,20 +439,208 @@ __device__ __forceinline__ void adjoint_atom(int i, int n, const AevConst& C,
     }
   }
   wave_lds_sync();
+}
 
-  // ---- scatter: neighbors get -sign * dE/dv, the centre gets +sign * sum
-  float sx = 0.f, sy = 0.f, sz2 = 0.f;
-  for (int e = lane; e < nr; e += kWave) {
-    const float4 gv = grad[e];
-    put(clampi(e < kSpecRec ? j0 : nrow[e], n), -sign * gv.x, -sign * gv.y, -sign * gv.z);
-    sx += gv.x;
-    sy += gv.y;
-    sz2 += gv.z;
+// Sixteen consecutive dE/dG values (one radial species block) as floats.
+template <typename GT> struct Load16;
+template <> struct Load16<float> {
+  __device__ __forceinline__ static void get(const float* p, float (&v)[16]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 u = reinterpret_cast<const float4*>(p)[q];
+      v[4 * q] = u.x;
+      v[4 * q + 1] = u.y;
+      v[4 * q + 2] = u.z;
+      v[4 * q + 3] = u.w;
+    }
   }
-  sx = wave_sum_rows(sx);
-  sy = wave_sum_rows(sy);
-  sz2 = wave_sum_rows(sz2);
-  if (lane == 0) put(i, sign * sx, sign * sy, sign * sz2);
+};
+template <> struct Load16<bf16_t> {
+  __device__ __forceinline__ static void get(const bf16_t* p, float (&v)[16]) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint4 u = reinterpret_cast<const uint4*>(p)[q];
+      const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[8 * q + 2 * k] = __uint_as_float(w[k] << 16);
+        v[8 * q + 2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+      }
+    }
+  }
+};
+
+// The adjoint of atoms i0 .. i0 + 3, by one wave: dE/d(displacement) of every
+// neighbor entry into the wave's LDS region (max(64, cap) entries of nd, nf,
+// grad, nsp), then put(j, x, y, z) adds -sign * dE/dv to neighbor j and
+// +sign * the sum to the centre atom.
+//
+// Quad waves (every atom with at most 16 neighbors) are built for latency:
+// the adjoint waits on its gathers of dE/dG, so it issues as few dependent
+// rounds of them as it can.  Lane (g, e) of group g sets up neighbor e of atom
+// i0 + g and computes that neighbor's whole radial derivative (its 16 shifts
+// against the 16 dE/dG values of its species block, two vector loads), so the
+// radial part of all four atoms is one round; the angular pairs of the four
+// atoms form one list that passes of eight pairs (eight lanes each) walk; the
+// scatter and the centre sums (16-lane reductions) again take all four atoms
+// at once.  Other waves take their atoms one at a time over the whole wave.
+template <typename GT, int Q, typename Put>
+__device__ __forceinline__ void adjoint_atoms(int i0, int n, const AevConst& C,
+                                              const float4* __restrict__ rec,
+                                              const int* __restrict__ nbr,
+                                              const int2* __restrict__ counts, int cap,
+                                              const int* __restrict__ row_of,
+                                              const GT* __restrict__ g, int ldg, float sign,
+                                              float4* nd, float4* nf, float4* grad, int* nsp,
+                                              Put&& put) {
+  const int lane = lane_id();
+  // records, neighbor indices and counts of all four atoms are first-level
+  // loads; group gq (lanes 16 gq .. 16 gq + 15) holds atom i0 + gq
+  const int gq = Q > 1 ? lane >> 4 : 0, l = lane & 15;
+  const int ig = i0 + gq;
+  const bool gin = ig < n;
+  const size_t gbase = (size_t)(gin ? ig : i0) * cap + l;
+  const float4 q0 = gin ? rec[gbase] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const int2 cn = gin ? counts[ig] : make_int2(0, 0);
+  const int nr_g = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
+  const int na_g = cn.y < 0 ? 0 : (cn.y > nr_g ? nr_g : cn.y);
+  const bool quad = Q > 1 && __ballot(nr_g > kQuadNbr) == 0;
+  const int S = C.S;
+  if (quad) {
+    const int row_g = gin ? row_of[ig] : 0;
+    // ---- setup and radial derivative, one lane per neighbor entry
+    if (l < nr_g) {
+      const float r = fast_sqrt(dist2(q0.x, q0.y, q0.z));
+      float dfr, dfa = 0.f;
+      const float fr = cutoff_val(r, C.inv_rc_r, dfr, C.pi_2rc_r);
+      const float fa = l < na_g ? cutoff_val(r, C.inv_rc_a, dfa, C.pi_2rc_a) : 0.f;
+      const int sp = species_of(q0);
+      const int slot = kQuadNbr * gq + l;
+      nd[slot] = make_float4(q0.x, q0.y, q0.z, r);
+      nf[slot] = make_float4(fr, fa, dfr, dfa);
+      nsp[slot] = sp;
+      float gv[16];
+      Load16<GT>::get(g + (size_t)row_g * ldg + sp * kNR, gv);
+      float acc = 0.f;
+#pragma unroll
+      for (int m = 0; m < kNR; ++m) {
+        const float u = r - C.shf_r[m];
+        acc += gv[m] * fast_exp2(-C.eta_r_l2e * u * u) * (dfr - C.eta_r2 * u * fr);
+      }
+      const float sc = C.cR * acc * fast_rcp(r);
+      grad[slot] = make_float4(q0.x * sc, q0.y * sc, q0.z * sc, 0.f);
+    }
+    wave_lds_sync();
+    // ---- angular: the four atoms' pair lists as one list (pairs of atom a
+    // from offset P_a), eight pairs per pass, lanes (pair tg, angle shift tz)
+    const int na0 = __builtin_amdgcn_readlane(na_g, 0);
+    const int na1 = __builtin_amdgcn_readlane(na_g, 16);
+    const int na2 = __builtin_amdgcn_readlane(na_g, 32);
+    const int na3 = __builtin_amdgcn_readlane(na_g, 48);
+    const int P1 = na0 * (na0 - 1) / 2;
+    const int P2 = P1 + na1 * (na1 - 1) / 2;
+    const int P3 = P2 + na2 * (na2 - 1) / 2;
+    const int Ttot = P3 + na3 * (na3 - 1) / 2;
+    const int r0 = __builtin_amdgcn_readlane(row_g, 0);
+    const int r1 = __builtin_amdgcn_readlane(row_g, 16);
+    const int r2 = __builtin_amdgcn_readlane(row_g, 32);
+    const int r3 = __builtin_amdgcn_readlane(row_g, 48);
+    const int tz = lane & 7, tg = lane >> 3;
+    const float cz = C.lane_tab[kNR + tz], sz = C.lane_tab[kNR + kNZ + tz];
+    const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
+    for (int t0 = 0; t0 < Ttot; t0 += 8) {
+      // lanes past the last pair recompute it and contribute zero
+      const int pt = t0 + tg;
+      const bool valid = pt < Ttot;
+      const int pc = valid ? pt : Ttot - 1;
+      const int a = (pc >= P1) + (pc >= P2) + (pc >= P3);
+      const int pa = a == 0 ? 0 : (a == 1 ? P1 : (a == 2 ? P2 : P3));
+      const int na = a == 0 ? na0 : (a == 1 ? na1 : (a == 2 ? na2 : na3));
+      const int ra = a == 0 ? r0 : (a == 1 ? r1 : (a == 2 ? r2 : r3));
+      int ej, ek;
+      decode_pair(pc - pa, na, ej, ek);
+      ej += kQuadNbr * a;
+      ek += kQuadNbr * a;
+      const float4 vj = nd[ej], vk = nd[ek];
+      const float4 cj = nf[ej], ck = nf[ek];
+      const float fj = cj.y, fk = ck.y, dfj = cj.w, dfk = ck.w;
+      const GT* gb = g + (size_t)ra * ldg + S * kNR + tz + pair_block(nsp[ej], nsp[ek], S) * 32;
+      const float g0 = Store<GT>::get(gb), g1 = Store<GT>::get(gb + 8),
+                  g2 = Store<GT>::get(gb + 16), g3 = Store<GT>::get(gb + 24);
+      const float rj = fast_rcp(vj.w), rk = fast_rcp(vk.w);
+      const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * (rj * rk);
+      const float kc = C.kappa * cs;
+      const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 1e-12f));
+      const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
+      const float pw = fast_exp2(C.zeta * fast_log2(base_));
+      const float f1 = 2.f * pw;
+      const float df1 = C.zeta * pw * fast_rcp(base_) * (C.kappa * (cz - kc * sz * fast_rcp(sn)));
+      const float dbar = 0.5f * (vj.w + vk.w);
+      float u, e2, A0 = 0.f, A1 = 0.f;
+      u = dbar - ra0; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g0 * e2; A1 -= g0 * u * e2;
+      u = dbar - ra1; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g1 * e2; A1 -= g1 * u * e2;
+      u = dbar - ra2; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g2 * e2; A1 -= g2 * u * e2;
+      u = dbar - ra3; e2 = fast_exp2(-C.eta_a_l2e * u * u); A0 += g3 * e2; A1 -= g3 * u * e2;
+      float X0 = valid ? f1 * A0 : 0.f;
+      float X1 = valid ? f1 * A1 * C.eta_a : 0.f;
+      float Xc = valid ? df1 * A0 : 0.f;
+      X0 = group8_sum(X0);
+      X1 = group8_sum(X1);
+      Xc = group8_sum(Xc);
+      if (valid && tz == 0) {
+        const float fcc = fj * fk;
+        const float dEdc = Xc * fcc;
+        const float dEdj = X1 * fcc + X0 * dfj * fk;
+        const float dEdk = X1 * fcc + X0 * fj * dfk;
+        const float aj = (dEdj - dEdc * cs * rj) * rj;
+        const float ak = (dEdk - dEdc * cs * rk) * rk;
+        const float bb = dEdc * rj * rk;
+        atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
+        atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
+        atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
+        atomicAdd(&grad[ek].x, ak * vk.x + bb * vj.x);
+        atomicAdd(&grad[ek].y, ak * vk.y + bb * vj.y);
+        atomicAdd(&grad[ek].z, ak * vk.z + bb * vj.z);
+      }
+    }
+    wave_lds_sync();
+    // ---- scatter of all four atoms: neighbors get -sign * dE/dv, each
+    // centre +sign * its group's sum
+    float4 gv = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (l < nr_g) {
+      gv = grad[kQuadNbr * gq + l];
+      put(clampi(nbr[gbase], n), -sign * gv.x, -sign * gv.y, -sign * gv.z);
+    }
+    const float sx = group16_sum(gv.x), sy = group16_sum(gv.y), sz2 = group16_sum(gv.z);
+    if (gin && l == 0) put(ig, sign * sx, sign * sy, sign * sz2);
+    return;
+  }
+  for (int a = 0; a < Q; ++a) {
+    const int i = i0 + a;
+    if (i >= n) break;  // wave-uniform
+    const int nr = __builtin_amdgcn_readlane(nr_g, kQuadNbr * a);
+    const int na = __builtin_amdgcn_readlane(na_g, kQuadNbr * a);
+    const GT* grow = g + (size_t)row_of[i] * ldg;
+    // this atom alone over the whole wave
+    const float4* arec = rec + (size_t)i * cap;
+    for (int e = lane; e < nr; e += kWave) adjoint_setup(e, arec[e], e < na, C, nd, nf, nsp);
+    wave_lds_sync();
+    adjoint_passes<GT>(nr, na, C, grow, nd, nf, grad, nsp);
+    const int* arow = nbr + (size_t)i * cap;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    for (int e = lane; e < nr; e += kWave) {
+      const float4 gv = grad[e];
+      put(clampi(arow[e], n), -sign * gv.x, -sign * gv.y, -sign * gv.z);
+      sx += gv.x;
+      sy += gv.y;
+      sz += gv.z;
+    }
+    sx = wave_sum_rows(sx);
+    sy = wave_sum_rows(sy);
+    sz = wave_sum_rows(sz);
+    if (lane == 0) put(i, sign * sx, sign * sy, sign * sz);
+    wave_lds_sync();  // the next atom reuses the region
+  }
 }
 
 // Adjoint: g (rows of type GT, stride ldg) -> scatter into out (float32 [n][3]).
@@ -429,7 +650,7 @@ __device__ __forceinline__ void adjoint_atom(int i, int n, const AevConst& C,
 // nb_adj on sum the molecular energies (one block per molecule), which need
 // only the atomic energies of the forward pass: they fill the tail of the
 // scatter instead of a launch of their own.
-template <typename GT>
+template <typename GT, int Q>
 __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C,
                                                  const float4* __restrict__ rec,
                                                  const int* __restrict__ nbr,
@@ -445,21 +666,22 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
     return;
   }
   const int n = dims[0];
-  const int w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 4 + w;
-  if (i >= n) return;
-  float4* nd = lds4 + (size_t)w * cap * 3;
-  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)4 * cap * 3) + w * cap;
-  adjoint_atom<GT>(i, n, C, rec, nbr, counts, cap, row_of, g, ldg, sign, nd, nd + cap,
-                   nd + 2 * cap, nsp, [&](int j, float x, float y, float z) {
-                     if (gidx) {
-                       j = gidx[j];
-                       if (j < 0 || j >= n_total) return;
-                     }
-                     unsafeAtomicAdd(out + 3 * j, x);
-                     unsafeAtomicAdd(out + 3 * j + 1, y);
-                     unsafeAtomicAdd(out + 3 * j + 2, z);
-                   });
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int i0 = ((int)blockIdx.x * 4 + w) * Q;
+  if (i0 >= n) return;
+  const int reg = aev_region(cap);
+  float4* nd = lds4 + (size_t)w * reg * 3;
+  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)4 * reg * 3) + w * reg;
+  adjoint_atoms<GT, Q>(i0, n, C, rec, nbr, counts, cap, row_of, g, ldg, sign, nd, nd + reg,
+                    nd + 2 * reg, nsp, [&](int j, float x, float y, float z) {
+                      if (gidx) {
+                        j = gidx[j];
+                        if (j < 0 || j >= n_total) return;
+                      }
+                      unsafeAtomicAdd(out + 3 * j, x);
+                      unsafeAtomicAdd(out + 3 * j + 1, y);
+                      unsafeAtomicAdd(out + 3 * j + 2, z);
+                    });
 }
 
 // Molecules (no box, no index map): a workgroup owns the kMolBlock atoms
@@ -472,8 +694,8 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
 // atoms (nothing else adds to it; staging zeroed the output), else with one
 // atomic add per component.  This replaces the contended per-entry global
 // atomics of the per-atom kernel (about nine adds per atom on the same lines).
-template <typename GT>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_aev_bwd_mol(const int* __restrict__ dims, AevConst C,
+template <typename GT, int Q>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_aev_bwd_mol(const int* __restrict__ dims, AevConst C,
                                                       const float4* __restrict__ rec,
                                                       const int* __restrict__ nbr,
                                                       const int2* __restrict__ counts, int cap,
@@ -491,29 +713,30 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
   const int n = dims[0];
   const int nw = (int)blockDim.x >> 6, w = (int)threadIdx.x >> 6;
   const int base = (int)blockIdx.x * kMolBlock, w0 = base - kMolBlock;
-  float4* nd = lds4 + (size_t)w * cap * 3;
-  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)nw * cap * 3) + w * cap;
-  float* win = reinterpret_cast<float*>(reinterpret_cast<int*>(lds4 + (size_t)nw * cap * 3) +
-                                        (size_t)nw * cap);
+  const int reg = aev_region(cap);
+  float4* nd = lds4 + (size_t)w * reg * 3;
+  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)nw * reg * 3) + w * reg;
+  float* win = reinterpret_cast<float*>(reinterpret_cast<int*>(lds4 + (size_t)nw * reg * 3) +
+                                        (size_t)nw * reg);
   for (int t = threadIdx.x; t < 3 * kWin; t += blockDim.x) win[t] = 0.f;
   __syncthreads();
-  for (int a = w; a < kMolBlock; a += nw) {
-    const int i = base + a;
-    if (i >= n) break;  // wave-uniform
-    adjoint_atom<GT>(i, n, C, rec, nbr, counts, cap, row_of, g, ldg, sign, nd, nd + cap,
-                     nd + 2 * cap, nsp, [&](int j, float x, float y, float z) {
-                       const int t = j - w0;
-                       if (t >= 0 && t < kWin) {
-                         atomicAdd(win + 3 * t, x);
-                         atomicAdd(win + 3 * t + 1, y);
-                         atomicAdd(win + 3 * t + 2, z);
-                       } else {
-                         unsafeAtomicAdd(out + 3 * j, x);
-                         unsafeAtomicAdd(out + 3 * j + 1, y);
-                         unsafeAtomicAdd(out + 3 * j + 2, z);
-                       }
-                     });
-    wave_lds_sync();  // the next atom reuses this wave's region
+  for (int a = Q * w; a < kMolBlock; a += Q * nw) {
+    const int i0 = base + a;
+    if (i0 >= n) break;  // wave-uniform
+    adjoint_atoms<GT, Q>(i0, n, C, rec, nbr, counts, cap, row_of, g, ldg, sign, nd, nd + reg,
+                      nd + 2 * reg, nsp, [&](int j, float x, float y, float z) {
+                        const int t = j - w0;
+                        if (t >= 0 && t < kWin) {
+                          atomicAdd(win + 3 * t, x);
+                          atomicAdd(win + 3 * t + 1, y);
+                          atomicAdd(win + 3 * t + 2, z);
+                        } else {
+                          unsafeAtomicAdd(out + 3 * j, x);
+                          unsafeAtomicAdd(out + 3 * j + 1, y);
+                          unsafeAtomicAdd(out + 3 * j + 2, z);
+                        }
+                      });
+    wave_lds_sync();  // the next atoms reuse this wave's region
   }
   __syncthreads();
   for (int t = threadIdx.x; t < kWin; t += blockDim.x) {
@@ -536,25 +759,67 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) vo
 
 // ----------------------------------------------------------------- launchers
 
+template <typename OutT, int Q>
+static void launch_aev_fwd_q(const int* dims, int n_cap, const AevConst& C, const float4* rec,
+                             const int2* counts, int cap, const int* row_of, OutT* out, int ld,
+                             hipStream_t st) {
+  const size_t lds = (size_t)4 * aev_region(cap) * kFwdBytesPerNbr +
+                     (size_t)4 * kPairChunk * kFwdPairBytes;
+  static const bool attr = (ensure_lds(k_aev_fwd<OutT, 1, Q>), ensure_lds(k_aev_fwd<OutT, 2, Q>),
+                            ensure_lds(k_aev_fwd<OutT, 3, Q>), true);
+  (void)attr;
+  const int nblk = C.S * (C.S + 1) / 2;
+  auto kern = nblk <= 16 ? k_aev_fwd<OutT, 1, Q>
+                         : (nblk <= 32 ? k_aev_fwd<OutT, 2, Q> : k_aev_fwd<OutT, 3, Q>);
+  const int per_block = 4 * Q;
+  hipLaunchKernelGGL(kern, dim3((n_cap + per_block - 1) / per_block), dim3(256), lds, st, dims, C,
+                     rec, counts, cap, row_of, out, ld);
+}
+
 template <typename OutT>
 void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int2* counts, int cap, const int* row_of, OutT* out, int ld,
                     hipStream_t st) {
   if (n_cap <= 0) return;
-  const size_t lds = (size_t)4 * cap * kFwdBytesPerNbr + (size_t)4 * kPairChunk * kFwdPairBytes;
-  static const bool attr = (ensure_lds(k_aev_fwd<OutT, 1>), ensure_lds(k_aev_fwd<OutT, 2>),
-                            ensure_lds(k_aev_fwd<OutT, 3>), true);
-  (void)attr;
-  const int nblk = C.S * (C.S + 1) / 2;
-  auto kern = nblk <= 16 ? k_aev_fwd<OutT, 1> : (nblk <= 32 ? k_aev_fwd<OutT, 2>
-                                                             : k_aev_fwd<OutT, 3>);
-  hipLaunchKernelGGL(kern, dim3((n_cap + 3) / 4), dim3(256), lds, st, dims, C, rec, counts, cap,
-                     row_of, out, ld);
+  if (aev_quads(cap))
+    launch_aev_fwd_q<OutT, 4>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, st);
+  else
+    launch_aev_fwd_q<OutT, 1>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, st);
 }
 template void launch_aev_fwd<float>(const int*, int, const AevConst&, const float4*, const int2*,
                                     int, const int*, float*, int, hipStream_t);
 template void launch_aev_fwd<bf16_t>(const int*, int, const AevConst&, const float4*,
                                      const int2*, int, const int*, bf16_t*, int, hipStream_t);
+
+template <typename GT, int Q>
+static void launch_aev_bwd_q(const int* dims, int n_cap, const AevConst& C, const float4* rec,
+                             const int* nbr, const int2* counts, int cap, const int* row_of,
+                             const GT* g, int ldg, float* out, float sign, const int* gidx,
+                             int n_total, const int2* mrange, const EnergyArgs* energy,
+                             int nmol_cap, hipStream_t st) {
+  const int nb_e = energy && energy->E && nmol_cap > 0 ? nmol_cap : 0;
+  const EnergyArgs ea = nb_e ? *energy : EnergyArgs{};
+  if (mrange && !gidx) {
+    // waves per workgroup: 8 while two workgroups fit a CU's LDS, else 4
+    const int nw = cap <= 128 ? 8 : 4;
+    const int nb_adj = n_cap > 0 ? (n_cap + kMolBlock - 1) / kMolBlock : 0;
+    if (nb_adj + nb_e == 0) return;
+    const size_t lds =
+        (size_t)nw * aev_region(cap) * kBwdBytesPerNbr + (size_t)3 * kMolBlock * 3 * 4;
+    static const bool attr = (ensure_lds(k_aev_bwd_mol<GT, Q>), true);
+    (void)attr;
+    hipLaunchKernelGGL((k_aev_bwd_mol<GT, Q>), dim3(nb_adj + nb_e), dim3(64 * nw), lds, st, dims,
+                       C, rec, nbr, counts, cap, row_of, g, ldg, out, sign, mrange, nb_adj, ea);
+    return;
+  }
+  const int nb_adj = n_cap > 0 ? (n_cap + 4 * Q - 1) / (4 * Q) : 0;
+  if (nb_adj + nb_e == 0) return;
+  const size_t lds = (size_t)4 * aev_region(cap) * kBwdBytesPerNbr;
+  static const bool attr = (ensure_lds(k_aev_bwd<GT, Q>), true);
+  (void)attr;
+  hipLaunchKernelGGL((k_aev_bwd<GT, Q>), dim3(nb_adj + nb_e), dim3(256), lds, st, dims, C, rec,
+                     nbr, counts, cap, row_of, g, ldg, out, sign, gidx, n_total, nb_adj, ea);
+}
 
 template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
@@ -562,27 +827,12 @@ void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4*
                     int ldg, float* out, float sign, const int* gidx, int n_total,
                     const int2* mrange, const EnergyArgs* energy, int nmol_cap,
                     hipStream_t st) {
-  const int nb_e = energy && energy->E && nmol_cap > 0 ? nmol_cap : 0;
-  const EnergyArgs ea = nb_e ? *energy : EnergyArgs{};
-  if (mrange && !gidx) {
-    // waves per workgroup: 16 while two workgroups fit a CU's LDS, else fewer
-    const int nw = cap <= 64 ? 16 : (cap <= 128 ? 8 : 4);
-    const int nb_adj = n_cap > 0 ? (n_cap + kMolBlock - 1) / kMolBlock : 0;
-    if (nb_adj + nb_e == 0) return;
-    const size_t lds = (size_t)nw * cap * kBwdBytesPerNbr + (size_t)3 * kMolBlock * 3 * 4;
-    static const bool attr = (ensure_lds(k_aev_bwd_mol<GT>), true);
-    (void)attr;
-    hipLaunchKernelGGL(k_aev_bwd_mol<GT>, dim3(nb_adj + nb_e), dim3(64 * nw), lds, st, dims, C,
-                       rec, nbr, counts, cap, row_of, g, ldg, out, sign, mrange, nb_adj, ea);
-    return;
-  }
-  const int nb_adj = n_cap > 0 ? (n_cap + 3) / 4 : 0;
-  if (nb_adj + nb_e == 0) return;
-  const size_t lds = (size_t)4 * cap * kBwdBytesPerNbr;
-  static const bool attr = (ensure_lds(k_aev_bwd<GT>), true);
-  (void)attr;
-  hipLaunchKernelGGL(k_aev_bwd<GT>, dim3(nb_adj + nb_e), dim3(256), lds, st, dims, C, rec, nbr,
-                     counts, cap, row_of, g, ldg, out, sign, gidx, n_total, nb_adj, ea);
+  if (aev_quads(cap))
+    launch_aev_bwd_q<GT, 4>(dims, n_cap, C, rec, nbr, counts, cap, row_of, g, ldg, out, sign,
+                            gidx, n_total, mrange, energy, nmol_cap, st);
+  else
+    launch_aev_bwd_q<GT, 1>(dims, n_cap, C, rec, nbr, counts, cap, row_of, g, ldg, out, sign,
+                            gidx, n_total, mrange, energy, nmol_cap, st);
 }
 template void launch_aev_bwd<float>(const int*, int, const AevConst&, const float4*, const int*,
                                     const int2*, int, const int*, const float*, int, float*, float,

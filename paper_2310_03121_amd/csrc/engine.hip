@@ -300,6 +300,7 @@ struct EvalIO {
   const int* gidx = nullptr;  // subset mode: rows of pos and out3 ([n_total][3]) per atom;
   int n_total = 0;            // forces are added to out3, not stored
   bool timed = true;          // stage events when profiling (they may create events)
+  bool keep_status = false;   // OR into the status word instead of clearing it first
 };
 
 template <typename T>
@@ -325,7 +326,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     StageTimer t(h, io.timed, ST_STAGE, st);
     launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.gidx, io.n_total,
                  io.species, io.off, S, xyzs, mol, mrange, io.gidx ? nullptr : io.out3, hist,
-                 status, st);
+                 status, !io.keep_status, st);
     if (P.nblk > kFusedSortBlocks) {
       launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
       launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
@@ -972,7 +973,7 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   float4* xyzs = at<float4>(ws, P.xyzs);
   int2* mrange = P.mrange ? at<int2>(ws, P.mrange) : nullptr;
   launch_stage(n, nmol, P.n, dims, pos, nullptr, nullptr, 0, species, off, h->S, xyzs,
-               at<int>(ws, P.mol), mrange, nullptr, at<int>(ws, P.hist), status, st);
+               at<int>(ws, P.mol), mrange, nullptr, at<int>(ws, P.hist), status, true, st);
   launch_groups(dims, P.n, h->S, at<int>(ws, P.hist), at<GroupTable>(ws, P.gt),
                 at<int>(ws, P.perm), P.rows_cap, off, kWChunk, status, st);
   if (P.B.periodic)
@@ -1078,6 +1079,7 @@ nnp_status nnp_md_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, doubl
     }
     launch_vv_kick_drift(dims, n, x, v, F, mass, dt, pos32, st);
     EvalIO io{n, nmol, pos32, nullptr, species, off, Etmp, F, 1.f, nullptr, nullptr};
+    io.keep_status = k > 0;  // the segment's device errors accumulate
     s = run(h, P, ws, io, st);
     if (s != NNP_OK) break;
     launch_vv_kick(dims, n, v, F, mass, dt, st);
@@ -1151,7 +1153,22 @@ struct Req {
   std::vector<int> sp;
   double t_submit = 0, t_admit = 0, t_done = 0;
   double e_pot = 0, e_kin = 0;
+  uint32_t status = 0;  // device status bits seen while the request was on the device
 };
+
+// Results of the requests that finished in one round, on their way to the
+// host: device-to-host copies into a pinned buffer behind an event, read on a
+// later round (or when the server runs dry), so no round waits for the GPU.
+struct RetireSlot {
+  hipEvent_t ev = nullptr;
+  double* h = nullptr;  // x, v per request, then the batch's E_pot, E_kin, then the status word
+  std::vector<std::pair<Req*, size_t>> reqs;  // finishing request, offset of its x in h
+  std::vector<int> mol;                       // its molecule index in the batch
+  std::vector<Req*> exposed;  // requests on the device while the status bits accumulated
+  size_t eo = 0;              // offset of the energies in h
+  int nact = 0;               // molecules in the batch
+};
+constexpr int kRetireSlots = 4;
 
 }  // namespace
 
@@ -1200,12 +1217,19 @@ struct nnp_server {
   std::map<int64_t, Req*> finished;
   std::deque<int64_t> done_q;
   int active_atoms = 0;
+  int undelivered = 0;  // admitted, result not yet handed to the host
+  RetireSlot slots[kRetireSlots];
+  std::deque<int> inflight;  // retire slots in flight, oldest first
+  // statistics (nnp_server_stats)
+  int64_t rounds = 0, mixed_rounds = 0, max_phases = 0, peak_atoms = 0, retire_waits = 0;
   ~nnp_server() {
-    // a request that finished in the last round is still listed as active;
-    // the finished map owns it
+    // a request whose last step has run is owned by its retire slot until its
+    // results arrive, then by the finished map
     for (Req* r : pending) delete r;
     for (Req* r : active)
       if (r->k <= r->n_steps) delete r;
+    for (int q : inflight)
+      for (auto& f : slots[q].reqs) delete f.first;
     for (auto& kv : finished) delete kv.second;
   }
 };
@@ -1226,6 +1250,59 @@ size_t server_state_bytes(int A, int M) {
   return b;
 }
 
+nnp_status status_from_bits(uint32_t word) {
+  if (word & kStOffsets) return NNP_E_INVALID;
+  if (word & kStSpecies) return NNP_E_SPECIES;
+  if (word & kStNonFinite) return NNP_E_NONFINITE;
+  if (word & kStCapacity) return NNP_E_CAPACITY;
+  return NNP_OK;
+}
+
+// Hands the results of retire slot q (whose copies have completed) to the
+// host side: status bits to the requests that were exposed to them, states
+// and energies to the finishing requests, which become pollable.
+void retire_deliver(nnp_server* s, int q) {
+  RetireSlot& sl = s->slots[q];
+  uint32_t word = 0;
+  std::memcpy(&word, sl.h + sl.eo + 2 * (size_t)sl.nact, 4);
+  if (word)
+    for (Req* r : sl.exposed) r->status |= word;
+  const double now = now_s();
+  for (size_t k = 0; k < sl.reqs.size(); ++k) {
+    Req* r = sl.reqs[k].first;
+    const double* hx = sl.h + sl.reqs[k].second;
+    r->x.assign(hx, hx + 3 * (size_t)r->n);
+    r->v.assign(hx + 3 * r->n, hx + 6 * (size_t)r->n);
+    r->e_pot = sl.h[sl.eo + sl.mol[k]];
+    r->e_kin = sl.h[sl.eo + sl.nact + sl.mol[k]];
+    r->t_done = now;
+    s->finished[r->id] = r;
+    s->done_q.push_back(r->id);
+    --s->undelivered;
+  }
+  sl.reqs.clear();
+  sl.mol.clear();
+  sl.exposed.clear();
+}
+
+// Delivers the in-flight retire slots in order: those whose copies have
+// completed, or (wait) all of them.
+nnp_status retire_drain(nnp_server* s, bool wait) {
+  while (!s->inflight.empty()) {
+    const int q = s->inflight.front();
+    if (wait) {
+      if (hipEventSynchronize(s->slots[q].ev) != hipSuccess) return NNP_E_HIP;
+    } else {
+      const hipError_t e = hipEventQuery(s->slots[q].ev);
+      if (e == hipErrorNotReady) break;
+      if (e != hipSuccess) return NNP_E_HIP;
+    }
+    retire_deliver(s, q);
+    s->inflight.pop_front();
+  }
+  return NNP_OK;
+}
+
 // One MD step of the packed batch: forces at x, integration by per-molecule
 // phase, kinetic energies, counters.  Every kernel reads the live atom and
 // molecule counts from the workspace, so the same launches (or their graph)
@@ -1235,6 +1312,7 @@ nnp_status server_enqueue_step(nnp_server* s) {
   const Plan& P = s->P;
   int* dims = at<int>(s->ws, P.dims);
   EvalIO io{-1, -1, nullptr, s->x, s->sp, s->off, s->epot, s->F, 1.f, nullptr, nullptr};
+  io.keep_status = true;  // cleared when the retire copies read it
   nnp_status r = run(h, P, s->ws, io, s->st);
   if (r != NNP_OK) return r;
   if (s->lfm)
@@ -1317,8 +1395,9 @@ nnp_status nnp_server_create(nnp_handle* h, size_t budget, int32_t max_atoms, in
   s->ws = s->dmem + align_up(sb, 256);
   // pinned host mirrors
   // src, in_sp | off, kdone, nsteps | dims | in_x, in_v, in_m | out (x, v, energies)
+  const size_t slot_bytes = align_up((size_t)A * 48 + (size_t)max_mols * 16 + 16, 64);
   const size_t hb = (size_t)A * 8 + (size_t)(max_mols + 1) * 12 + 64 + (size_t)A * 56 +
-                    (size_t)A * 48 + (size_t)max_mols * 24 + 4096;
+                    (size_t)A * 48 + (size_t)max_mols * 24 + 4096 + kRetireSlots * slot_bytes;
   if (hipHostMalloc((void**)&s->hmem, hb) != hipSuccess) {
     (void)hipFree(s->dmem);
     (void)hipStreamDestroy(s->st);
@@ -1342,11 +1421,20 @@ nnp_status nnp_server_create(nnp_handle* h, size_t budget, int32_t max_atoms, in
   s->h_in_m = (double*)htake((size_t)A * 8);
   s->h_out = (double*)htake((size_t)A * 48 + (size_t)max_mols * 16);
   s->h_seed = (uint64_t*)htake((size_t)max_mols * 8);
-  (void)hipEventCreateWithFlags(&s->ev_upload, hipEventDisableTiming);
+  bool evs = hip_ok(hipEventCreateWithFlags(&s->ev_upload, hipEventDisableTiming));
+  for (int q = 0; q < kRetireSlots; ++q) {
+    s->slots[q].h = (double*)htake(slot_bytes);
+    evs &= hip_ok(hipEventCreateWithFlags(&s->slots[q].ev, hipEventDisableTiming));
+  }
+  if (!evs) {
+    nnp_server_destroy(s);
+    return NNP_E_HIP;
+  }
   // empty batch: counts 0, offsets {0}
   s->h_dims[0] = 0;
   s->h_dims[1] = 0;
   s->h_off[0] = 0;
+  launch_fill_i32(reinterpret_cast<int*>(at<uint32_t>(s->ws, s->P.status)), 0, 1, s->st);
   bool ok = hip_ok(hipMemcpyAsync(at<int>(s->ws, s->P.dims), s->h_dims, 8, hipMemcpyHostToDevice,
                                   s->st)) &&
             hip_ok(hipMemcpyAsync(s->off, s->h_off, 4, hipMemcpyHostToDevice, s->st)) &&
@@ -1366,6 +1454,8 @@ void nnp_server_destroy(nnp_server* s) {
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
   if (s->ev_upload) (void)hipEventDestroy(s->ev_upload);
+  for (int q = 0; q < kRetireSlots; ++q)
+    if (s->slots[q].ev) (void)hipEventDestroy(s->slots[q].ev);
   if (s->hmem) (void)hipHostFree(s->hmem);
   if (s->dmem) (void)hipFree(s->dmem);
   if (s->st) (void)hipStreamDestroy(s->st);
@@ -1401,12 +1491,15 @@ nnp_status nnp_server_set_langevin(nnp_server* s, double temperature, double fri
   return NNP_OK;
 }
 
-int32_t nnp_server_active(const nnp_server* s) { return s ? (int32_t)s->active.size() : 0; }
+int32_t nnp_server_active(const nnp_server* s) { return s ? (int32_t)s->undelivered : 0; }
 int32_t nnp_server_pending(const nnp_server* s) { return s ? (int32_t)s->pending.size() : 0; }
 
 nnp_status nnp_server_step(nnp_server* s) {
   if (!s) return NNP_E_INVALID;
   if (hipSetDevice(s->h->device) != hipSuccess) return NNP_E_HIP;
+  // 0. results whose copies have arrived
+  nnp_status rs = retire_drain(s, false);
+  if (rs != NNP_OK) return rs;
   // 1. drop requests whose final step ran in the previous round
   std::vector<Req*> keep;
   bool changed = false;
@@ -1431,6 +1524,8 @@ nnp_status nnp_server_step(nnp_server* s) {
     ++mols;
   }
   if (!admit.empty()) changed = true;
+  if (!admit.empty() && !keep.empty()) ++s->mixed_rounds;
+  s->undelivered += (int)admit.size();
   // 3. repack on the device: survivors keep their state, admitted atoms come
   //    from staging
   if (changed) {
@@ -1508,7 +1603,17 @@ nnp_status nnp_server_step(nnp_server* s) {
     s->active.swap(next);
     s->active_atoms = atoms;
   }
-  if (s->active.empty()) return NNP_OK;
+  if (s->active.empty()) return retire_drain(s, true);  // nothing to run: wait for results
+  {
+    // statistics: atoms on the device, distinct step counters in one launch
+    std::vector<int> ks;
+    for (Req* q : s->active) ks.push_back(q->k);
+    std::sort(ks.begin(), ks.end());
+    const int64_t phases = std::unique(ks.begin(), ks.end()) - ks.begin();
+    s->max_phases = std::max(s->max_phases, phases);
+    s->peak_atoms = std::max<int64_t>(s->peak_atoms, s->active_atoms);
+    ++s->rounds;
+  }
   // 4. one step over the whole batch (graph replay after a first eager step)
   nnp_status r;
   if (!s->warmed) {
@@ -1529,57 +1634,67 @@ nnp_status nnp_server_step(nnp_server* s) {
     if (hipGraphLaunch(s->exec, s->st) != hipSuccess) return NNP_E_HIP;
   }
   for (Req* q : s->active) q->k += 1;
-  // 5. requests whose closing half kick ran: copy results out
-  std::vector<std::pair<Req*, int>> fin;
+  // 5. requests whose closing half kick ran: copy their results, the batch's
+  //    energies and the status word to a pinned retire slot behind an event;
+  //    a later round hands them over
+  std::vector<std::pair<Req*, int>> fin;  // request, first atom in the batch
+  std::vector<int> fin_mol;
   {
     int o = 0, mi = 0;
     for (Req* q : s->active) {
-      if (q->k > q->n_steps) fin.push_back({q, o});
+      if (q->k > q->n_steps) {
+        fin.push_back({q, o});
+        fin_mol.push_back(mi);
+      }
       o += q->n;
       ++mi;
     }
   }
   if (!fin.empty()) {
+    if ((int)s->inflight.size() == kRetireSlots) {  // every slot busy: wait for the oldest
+      const int q = s->inflight.front();
+      if (hipEventSynchronize(s->slots[q].ev) != hipSuccess) return NNP_E_HIP;
+      retire_deliver(s, q);
+      s->inflight.pop_front();
+      ++s->retire_waits;
+    }
+    int q = 0;
+    while (std::find(s->inflight.begin(), s->inflight.end(), q) != s->inflight.end()) ++q;
+    RetireSlot& sl = s->slots[q];
     size_t ho = 0;
-    std::vector<size_t> at_h;
     bool ok = true;
-    for (auto& f : fin) {
-      at_h.push_back(ho);
-      const size_t nb = (size_t)f.first->n * 24;
-      ok &= hip_ok(hipMemcpyAsync(s->h_out + ho, s->x + 3 * (size_t)f.second, nb,
+    for (size_t k = 0; k < fin.size(); ++k) {
+      Req* r = fin[k].first;
+      const size_t nb = (size_t)r->n * 24;
+      ok &= hip_ok(hipMemcpyAsync(sl.h + ho, s->x + 3 * (size_t)fin[k].second, nb,
                                   hipMemcpyDeviceToHost, s->st));
-      ok &= hip_ok(hipMemcpyAsync(s->h_out + ho + 3 * f.first->n, s->v + 3 * (size_t)f.second,
-                                  nb, hipMemcpyDeviceToHost, s->st));
-      ho += 6 * (size_t)f.first->n;
+      ok &= hip_ok(hipMemcpyAsync(sl.h + ho + 3 * r->n, s->v + 3 * (size_t)fin[k].second, nb,
+                                  hipMemcpyDeviceToHost, s->st));
+      sl.reqs.push_back({r, ho});
+      sl.mol.push_back(fin_mol[k]);
+      ho += 6 * (size_t)r->n;
     }
-    // molecule energies: index of each finishing molecule in the batch
-    const size_t eo = ho;
-    ok &= hip_ok(hipMemcpyAsync(s->h_out + eo, s->epot, s->active.size() * 8,
+    sl.nact = (int)s->active.size();
+    sl.eo = ho;
+    ok &= hip_ok(hipMemcpyAsync(sl.h + ho, s->epot, (size_t)sl.nact * 8, hipMemcpyDeviceToHost,
+                                s->st));
+    ok &= hip_ok(hipMemcpyAsync(sl.h + ho + sl.nact, s->ekin, (size_t)sl.nact * 8,
                                 hipMemcpyDeviceToHost, s->st));
-    ok &= hip_ok(hipMemcpyAsync(s->h_out + eo + s->active.size(), s->ekin,
-                                s->active.size() * 8, hipMemcpyDeviceToHost, s->st));
-    ok &= hip_ok(hipStreamSynchronize(s->st));
+    uint32_t* status = at<uint32_t>(s->ws, s->P.status);
+    ok &= hip_ok(hipMemcpyAsync(sl.h + ho + 2 * (size_t)sl.nact, status, 4,
+                                hipMemcpyDeviceToHost, s->st));
+    launch_fill_i32(reinterpret_cast<int*>(status), 0, 1, s->st);  // the next rounds' bits
+    sl.exposed = s->active;
+    ok &= hip_ok(hipEventRecord(sl.ev, s->st));
     if (!ok) return NNP_E_HIP;
-    const double now = now_s();
-    for (size_t q = 0; q < fin.size(); ++q) {
-      Req* r = fin[q].first;
-      const double* hx = s->h_out + at_h[q];
-      r->x.assign(hx, hx + 3 * (size_t)r->n);
-      r->v.assign(hx + 3 * r->n, hx + 6 * (size_t)r->n);
-      size_t mi = 0;
-      while (s->active[mi] != r) ++mi;
-      r->e_pot = s->h_out[eo + mi];
-      r->e_kin = s->h_out[eo + s->active.size() + mi];
-      r->t_done = now;
-      s->finished[r->id] = r;
-      s->done_q.push_back(r->id);
-    }
+    s->inflight.push_back(q);
   }
   return NNP_OK;
 }
 
 int32_t nnp_server_poll(nnp_server* s, int64_t* ids, int32_t max) {
   if (!s || !ids || max < 1) return 0;
+  (void)retire_drain(s, false);
   int32_t k = 0;
   while (k < max && !s->done_q.empty()) {
     ids[k++] = s->done_q.front();
@@ -1601,6 +1716,14 @@ nnp_status nnp_server_result(nnp_server* s, int64_t id, double* x, double* v, do
   if (t_submit) *t_submit = r->t_submit;
   if (t_admit) *t_admit = r->t_admit;
   if (t_done) *t_done = r->t_done;
+  return status_from_bits(r->status);
+}
+
+nnp_status nnp_server_stats(const nnp_server* s, int64_t* out, int32_t n) {
+  if (!s || !out || n < 1) return NNP_E_INVALID;
+  const int64_t v[8] = {s->max_atoms, s->max_mols, s->active_atoms, s->peak_atoms,
+                        s->rounds,    s->mixed_rounds, s->max_phases, s->retire_waits};
+  for (int32_t k = 0; k < n && k < 8; ++k) out[k] = v[k];
   return NNP_OK;
 }
 

@@ -96,7 +96,8 @@ __global__ void k_fill_f64(double* p, double v, int n);
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
                   const double* pos64, const int* gidx, int n_total, const int* species,
                   const int* off, int S, float4* xyzs, int* mol, int2* mrange, float* Fzero,
-                  int* hist, uint32_t* status, hipStream_t st);
+                  int* hist, uint32_t* status, bool clear_status,
+                  hipStream_t st);
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
                    int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
                    hipStream_t st);

@@ -14,7 +14,8 @@
 
 namespace nnp {
 
-__global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __restrict__ dims,
+__global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int clear_status,
+                                               int* __restrict__ dims,
                                                const float* __restrict__ pos,
                                                const double* __restrict__ pos64,
                                                const int* __restrict__ gidx, int n_total,
@@ -34,7 +35,9 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int* __r
       dims[0] = n;
       dims[1] = nmol;
     }
-    *status = 0u;  // later kernels of the evaluation only add bits
+    // later kernels only add bits; an MD segment clears the word once, so
+    // its bits accumulate over the steps
+    if (clear_status) *status = 0u;
   }
   if (threadIdx.x < kMaxS) h[threadIdx.x] = 0;
   if (threadIdx.x == 0) bits = 0;
@@ -256,9 +259,10 @@ __global__ void k_fill_f64(double* __restrict__ p, double v, int n) {
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
                   const double* pos64, const int* gidx, int n_total, const int* species,
                   const int* off, int S, float4* xyzs, int* mol, int2* mrange, float* Fzero,
-                  int* hist, uint32_t* status, hipStream_t st) {
+                  int* hist, uint32_t* status, bool clear_status, hipStream_t st) {
   const int nblk = stage_blocks(n_cap);
-  hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, dims, pos, pos64,
+  hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, clear_status ? 1 : 0,
+                     dims, pos, pos64,
                      gidx, n_total, species, off, S, xyzs, mol, mrange, Fzero, hist, status);
 }
 

@@ -106,7 +106,42 @@ def test_nve_energy_error_matches_oracle_integrator():
 
 
 def _requests(n, seed=3):
-    return w.poisson_requests(n, rate=1000.0, seed=seed, n_steps=30)
+    """n requests with step counts 20..40, so requests finish in different
+    rounds and survivors share launches with newly admitted ones."""
+    reqs = w.poisson_requests(n, rate=1000.0, seed=seed, n_steps=30)
+    for r in reqs:
+        r.n_steps = 20 + (7 * r.req_id) % 21
+    return reqs
+
+
+def _serve_staggered(srv, reqs, n_first=6, every=3):
+    """Submits the first n_first requests, then one more every `every`
+    rounds while the server runs; returns the delivered results and the
+    server statistics."""
+    def submit(r):
+        assert srv.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
+                          r.n_steps) == 0
+    for r in reqs[:n_first]:
+        submit(r)
+    nxt = n_first
+    done = {}
+    rounds = 0
+    while len(done) < len(reqs):
+        if nxt < len(reqs) and rounds % every == 0:
+            submit(reqs[nxt])
+            nxt += 1
+        srv.step()
+        rounds += 1
+        for i in srv.poll():
+            done[i] = srv.result(i, reqs[i].system.n_atoms)
+        assert rounds < 5000
+    st = srv.stats()
+    print(f"{rounds} rounds; stats {st}")
+    # survivors and new admissions in one repack, and requests at different
+    # steps of their trajectories in one launch
+    assert st["mixed_rounds"] >= 1
+    assert st["max_phases_per_launch"] >= 2
+    return done, st
 
 
 def test_serving_alone_equals_mix():
@@ -116,21 +151,7 @@ def test_serving_alone_equals_mix():
     reqs = _requests(24)
     srv = Server(pot, hbm_budget_bytes=8 << 30, max_atoms=900, max_mols=12, dt_fs=0.5,
                  mass_amu=w.MASS_AMU)
-    for r in reqs:
-        assert srv.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
-                          r.n_steps) == 0
-    done = {}
-    steps = 0
-    max_active = 0
-    while len(done) < len(reqs):
-        srv.step()
-        steps += 1
-        max_active = max(max_active, srv.active)
-        for i in srv.poll():
-            done[i] = srv.result(i, reqs[i].system.n_atoms)
-        assert steps < 5000
-    print(f"{steps} scheduling rounds, up to {max_active} requests in flight")
-    assert max_active > 1
+    done, st = _serve_staggered(srv, reqs)
     worst = 0.0
     for r in reqs[:10]:
         x, v, Ep, Ek = _md_gpu(pot, r.system, r.vel, 0.5, r.n_steps)
@@ -144,29 +165,88 @@ def test_serving_alone_equals_mix():
     print(f"alone vs mix: worst max|dx| {worst:.2e} A")
 
 
-def test_serving_respects_capacity_and_budget():
-    from paper_2310_03121_amd import Server
-    announce("server: tiny HBM budget admits fewer atoms at once")
-    pot, at, mt = potential(7, "fp32")
-    reqs = _requests(8, seed=9)
-    small = Server(pot, hbm_budget_bytes=24 << 20, max_atoms=4096, max_mols=64, dt_fs=0.5,
-                   mass_amu=w.MASS_AMU)
-    big = max(r.system.n_atoms for r in reqs)
+def _serve_all(srv, reqs):
     ids = []
     for r in reqs:
-        code = small.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
-                            r.n_steps)
-        assert code in (0, 9)
+        code = srv.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
+                          r.n_steps)
+        assert code in (0, 9)  # 9: larger than the server can ever hold
         if code == 0:
             ids.append(r.req_id)
     got = set()
     rounds = 0
     while len(got) < len(ids):
-        small.step()
+        srv.step()
         rounds += 1
-        got.update(small.poll())
+        got.update(srv.poll())
         assert rounds < 20000
-    print(f"{len(ids)} requests served under a 24 MiB budget in {rounds} rounds (largest {big} atoms)")
+    return ids, rounds, srv.stats()
+
+
+def test_serving_respects_capacity_and_budget():
+    from paper_2310_03121_amd import Server
+    announce("server: tiny HBM budget admits fewer atoms at once")
+    pot, at, mt = potential(7, "fp32")
+    reqs = _requests(8, seed=9)
+    big = max(r.system.n_atoms for r in reqs)
+    small = Server(pot, hbm_budget_bytes=24 << 20, max_atoms=4096, max_mols=64, dt_fs=0.5,
+                   mass_amu=w.MASS_AMU)
+    ids, rounds, st = _serve_all(small, reqs)
+    free = Server(pot, hbm_budget_bytes=8 << 30, max_atoms=4096, max_mols=64, dt_fs=0.5,
+                  mass_amu=w.MASS_AMU)
+    ids_f, rounds_f, st_f = _serve_all(free, reqs)
+    print(f"24 MiB budget: {len(ids)} requests, {rounds} rounds, {st}; "
+          f"8 GiB: {rounds_f} rounds, {st_f} (largest request {big} atoms)")
+    # the budget lowered the capacity, and with it the atoms on the device at
+    # once, which stretched the same work over more rounds
+    assert st["capacity_atoms"] < 4096 and st_f["capacity_atoms"] == 4096
+    assert st["peak_atoms"] <= st["capacity_atoms"]
+    assert st["peak_atoms"] < st_f["peak_atoms"]
+    assert rounds > rounds_f
+    # exactly the requests that fit the capacity were accepted
+    assert ids == [r.req_id for r in reqs if r.system.n_atoms <= st["capacity_atoms"]]
+
+
+def test_device_errors_reach_md_and_served_requests():
+    """A neighbor capacity of 16 with molecules denser than that: the
+    overflow bit raised during an MD segment is reported by nnp_check after
+    nnp_md_steps, and by nnp_server_result for every served request that was
+    on the device while it was raised."""
+    from paper_2310_03121_amd import NNPError, Server
+    announce("device status: capacity overflow in md_steps and in serving")
+    pot, at, mt = potential(7, "fp32", max_neighbors=16)
+    # a liquid-density cluster (atoms of the 1,500-water box within 6 A of its
+    # centre) as one molecule without a box: about 50 neighbors per atom
+    wb = w.config_system(2)
+    keep = np.nonzero(np.linalg.norm(wb.pos - wb.pos.mean(0), axis=1) < 6.0)[0]
+    s = w.System(wb.pos[keep].copy(), wb.species[keep].copy(),
+                 np.array([0, keep.size], np.int32), None, 7)
+    pos, sp, off = to_dev(s)
+    v0 = w.maxwell_boltzmann(s.species, 300.0, np.random.default_rng(1))
+    x = torch.from_numpy(s.pos.astype(np.float64)).cuda()
+    v = torch.from_numpy(v0).cuda()
+    m = torch.from_numpy(w.MASS_AMU[s.species]).cuda()
+    _, F = pot.energy_forces(pos, sp, off, None)
+    with pytest.raises(NNPError) as e:
+        pot.check()
+    assert e.value.code == 4
+    pot.md_steps(x, v, F, m, sp, off, 0.5, 5, None)
+    with pytest.raises(NNPError) as e:
+        pot.check()
+    assert e.value.code == 4
+    srv = Server(pot, hbm_budget_bytes=1 << 30, max_atoms=512, max_mols=8, dt_fs=0.5,
+                 mass_amu=w.MASS_AMU)
+    assert srv.submit(0, s.pos.astype(np.float64), v0, s.species, 4) == 0
+    got = []
+    rounds = 0
+    while not got:
+        srv.step()
+        got = srv.poll()
+        rounds += 1
+        assert rounds < 100
+    assert srv.result(0, s.n_atoms, check=False)["status"] == 4
+    with pytest.raises(NNPError):
+        srv.result(0, s.n_atoms)
 
 
 # ------------------------------------------------------- LF-Middle Langevin
@@ -252,20 +332,7 @@ def test_serving_langevin_alone_equals_mix():
     srv = Server(pot, hbm_budget_bytes=8 << 30, max_atoms=700, max_mols=10, dt_fs=0.5,
                  mass_amu=w.MASS_AMU)
     srv.set_langevin(300.0, 20.0)
-    for r in reqs:
-        assert srv.submit(r.req_id, r.system.pos.astype(np.float64), r.vel, r.system.species,
-                          r.n_steps) == 0
-    done = {}
-    steps = 0
-    max_active = 0
-    while len(done) < len(reqs):
-        srv.step()
-        steps += 1
-        max_active = max(max_active, srv.active)
-        for i in srv.poll():
-            done[i] = srv.result(i, reqs[i].system.n_atoms)
-        assert steps < 5000
-    assert max_active > 1
+    done, st = _serve_staggered(srv, reqs, n_first=4, every=4)
     worst = 0.0
     for r in reqs[:8]:
         s = r.system
