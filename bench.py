@@ -45,6 +45,7 @@ def stage_flops(widths, F):
     }
     d["mlp_mid_fused"] = (d["mlp_layer2"] + d["mlp_layer3_head"] + d["mlp_bwd_layer3"]
                           + d["mlp_bwd_layer2"])
+    d["mlp_net_fused"] = d["mlp_layer1"] + d["mlp_mid_fused"] + d["mlp_bwd_dEdG"]
     return d
 
 
@@ -204,6 +205,40 @@ def time_path(pot, pos, sp, off, box, steps, warmup):
     return dt, dt_graph, out, stages
 
 
+def backward_leg(pot, pos, sp, off, box, steps, warmup, mt):
+    """nnp_backward on the workload: the whole forward pass, dL/dpos (the
+    forces' adjoint) and every weight gradient for L = sum_m E_m, timed like
+    the evaluation, with the weight-gradient stage's own device time and its
+    algorithmic MFMA rate (2 FLOP per multiply-add of dW = delta^T h over all
+    atoms and layers)."""
+    import torch
+    n, nmol = pos.shape[0], off.shape[0] - 1
+    dLdE = torch.ones(nmol, dtype=torch.float64, device=pos.device)
+    for _ in range(warmup):
+        pot.backward(pos, sp, off, dLdE, box=box)
+    pot.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pot.backward(pos, sp, off, dLdE, box=box)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pot.check()
+    pot.profile(True)
+    for _ in range(steps):
+        pot.backward(pos, sp, off, dLdE, box=box)
+        pot.profile_collect()
+    stages = pot.profile_read()
+    pot.profile(False)
+    st = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
+    w = list(mt.widths)
+    wg_flop = 2 * n * sum(w[l] * w[l + 1] for l in range(len(w) - 1))
+    wg_ms = st.get("weight_grads")
+    return {"ms_per_call": 1e3 * dt / steps, "atoms_per_s": n * steps / dt,
+            "stages_ms": st, "weight_grad_flop": wg_flop,
+            "weight_grad_tflops": wg_flop / (wg_ms * 1e-3) / 1e12 if wg_ms else None}
+
+
 def latency_leg(pot, pos, sp, off, box, n_evals=1000, warmup=50):
     """Per-evaluation latency: each captured evaluation is launched and waited
     for on its own (median and p99 over n_evals, after warm-up)."""
@@ -223,8 +258,46 @@ def latency_leg(pot, pos, sp, off, box, n_evals=1000, warmup=50):
             "p99_us": float(np.percentile(lat, 99) * 1e6), "launch": "graph replay, synchronized"}
 
 
-def nve_leg(pot, s, n_steps=1000, dt=0.5, every=10, seed=4):
-    """NVE velocity Verlet from Maxwell-Boltzmann velocities at 300 K: total
+def relax(pot, x, sp, off, box, md, n_iter=400, dt=0.25, dt_max=1.0, max_step=0.05):
+    """FIRE energy minimization (Bitzek et al., PRL 97, 170201, 2006) of the
+    float64 positions x with the GPU forces: the random-weight potential is
+    far from equilibrium at the generated geometry, and NVE from there turns
+    that potential energy into heat.  Returns energy and largest force before
+    and after."""
+    import torch
+    acc = 9.648533e-3
+    v = torch.zeros_like(x)
+    alpha, n_pos = 0.1, 0
+    E, F = pot.energy_forces(x.float(), sp, off, box)
+    e0, f0 = E.sum().item(), F.norm(dim=1).max().item()
+    for _ in range(n_iter):
+        Fd = F.double()
+        p = float((Fd * v).sum())
+        if p > 0.0:
+            fn, vn = Fd.norm(), v.norm()
+            v = (1 - alpha) * v + alpha * vn * Fd / fn.clamp_min(1e-30)
+            n_pos += 1
+            if n_pos > 5:
+                dt, alpha = min(dt * 1.1, dt_max), alpha * 0.99
+        else:
+            v.zero_()
+            dt, alpha, n_pos = dt * 0.5, 0.1, 0
+        v += dt * acc * Fd / md[:, None]
+        step = dt * v
+        scale = (max_step / step.norm(dim=1).max().clamp_min(1e-30)).clamp(max=1.0)
+        x += step * scale
+        if box is not None:
+            L = torch.tensor(np.asarray(box, np.float64), device=x.device)
+            x -= L * torch.floor(x / L)
+        E, F = pot.energy_forces(x.float(), sp, off, box)
+    pot.check()
+    return {"iterations": n_iter, "E_eV_before_after": [e0, E.sum().item()],
+            "max_force_eV_per_A_before_after": [f0, F.norm(dim=1).max().item()]}
+
+
+def nve_leg(pot, s, n_steps=1000, dt=0.5, every=10, seed=4, relax_iters=0):
+    """NVE velocity Verlet from Maxwell-Boltzmann velocities at 300 K
+    (optionally after a FIRE relaxation of the generated geometry): total
     energy sampled every `every` steps; drift is the least-squares slope of
     E_tot(t), plus the largest excursion from the first sample, both per atom."""
     import torch
@@ -237,6 +310,7 @@ def nve_leg(pot, s, n_steps=1000, dt=0.5, every=10, seed=4):
     md = torch.from_numpy(m).to(dev)
     sp = torch.from_numpy(s.species).to(dev)
     off = torch.from_numpy(s.mol_offsets).to(dev)
+    relaxed = relax(pot, x, sp, off, s.box, md, n_iter=relax_iters) if relax_iters else None
     E0, F = pot.energy_forces(x.float(), sp, off, s.box)
     # E_tot as the integrator reports it (potential + kinetic after each
     # chunk of steps); the series starts after the first chunk
@@ -253,9 +327,10 @@ def nve_leg(pot, s, n_steps=1000, dt=0.5, every=10, seed=4):
     t = np.array(t) * 1e-3  # ps
     e = (np.array(tot) - tot[0]) * 1e3 / s.n_atoms  # meV per atom
     slope = float(np.polyfit(t, e, 1)[0])
-    return {"steps": n_steps, "dt_fs": dt, "sample_every": every,
+    return {"steps": n_steps, "dt_fs": dt, "sample_every": every, "relaxation": relaxed,
             "drift_meV_per_ps_per_atom": slope, "max_abs_dev_meV_per_atom": float(np.abs(e).max()),
             "kinetic_energy_eV_first_last_sample": [ek[0], ek[-1]],
+            "kinetic_energy_eV_max_sample": float(np.max(ek)),
             "ms_per_step": wall * 1e3 / n_steps}
 
 
@@ -333,39 +408,70 @@ def ceilings():
     return out
 
 
-def measured_peak(bound, prec):
-    """The ceiling measured on this device for the roofline's bound: a large
-    square library GEMM (hipBLASLt through torch) of the path's precision for
-    `mfma`, a 1 GiB device copy for `hbm`; none for `alu` (no VALU
-    microbenchmark here)."""
+CEILING_KINDS = {"mfma_bf16": 0, "mfma_fp32": 1, "valu_fma_fp32": 2, "valu_exp2_fp32": 3}
+
+
+def issue_ceilings():
+    """Compute ceilings measured on this device by the issue loops of
+    libnnp_ceilings.so (eight independent chains per wave, 8 waves per CU):
+    BF16 and FP32 MFMA (TFLOP/s), FP32 FMA (TFLOP/s, an FMA counting 2) and
+    v_exp_f32 (T transcendentals/s)."""
+    import ctypes as C
     import torch
-    if bound not in ("mfma", "hbm"):
-        return None
-    c = {}
-    if bound == "hbm":
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        fn, work, unit = (lambda: dst.copy_(src)), 2 * src.numel() / 1e9, "GB/s"
-    else:
-        n = 8192
-        dtype = torch.bfloat16 if prec == "bf16" else torch.float32
-        c["a"] = torch.randn(n, n, device="cuda", dtype=dtype)
-        c["b"] = torch.randn(n, n, device="cuda", dtype=dtype)
-        fn, work, unit = (lambda: c["a"] @ c["b"]), 2 * n ** 3 / 1e12, "TFLOP/s"
+    from paper_2310_03121_amd.build import CEIL_LIB
+    lib = C.CDLL(CEIL_LIB)
+    lib.nnp_ceiling_launch.restype = C.c_int
+    lib.nnp_ceiling_launch.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    lib.nnp_ceiling_work.restype = C.c_double
+    lib.nnp_ceiling_work.argtypes = [C.c_int, C.c_int, C.c_int]
+    blocks = 256 * 8 // 4 * 2  # two workgroups of 4 waves per CU
+    sink = torch.zeros(blocks, dtype=torch.float32, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    out = {}
+    for name, kind in CEILING_KINDS.items():
+        iters = {0: 100, 1: 50, 2: 100000, 3: 40000}[kind]  # 5-20 ms per launch
+        for _ in range(2):
+            assert lib.nnp_ceiling_launch(kind, blocks, iters, C.c_void_p(sink.data_ptr()),
+                                          stream) == 0
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            lib.nnp_ceiling_launch(kind, blocks, iters, C.c_void_p(sink.data_ptr()), stream)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 5 * 1e-3
+        out[name] = lib.nnp_ceiling_work(kind, blocks, iters) / sec / 1e12
+    out["units"] = "TFLOP/s (exp2: T/s)"
+    return out
+
+
+def measured_peak(bound, prec, issue):
+    """The ceiling measured on this device for the roofline's bound: the MFMA
+    issue loop of the path's precision for `mfma`, the FP32 FMA loop for
+    `alu`, a 1 GiB device copy for `hbm`."""
+    import torch
+    if bound == "mfma":
+        key = "mfma_bf16" if prec == "bf16" else "mfma_fp32"
+        return {"value": issue[key], "unit": "TFLOP/s", "what": f"{key} issue loop"}
+    if bound == "alu":
+        return {"value": issue["valu_fma_fp32"], "unit": "TFLOP/s",
+                "what": "fp32 FMA issue loop (an FMA counts 2)"}
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
     for _ in range(3):
-        fn()
+        dst.copy_(src)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(10):
-        fn()
+        dst.copy_(src)
     e1.record()
     torch.cuda.synchronize()
-    val = work / (e0.elapsed_time(e1) / 10 * 1e-3)
-    c.clear()
+    val = 2 * src.numel() / 1e9 / (e0.elapsed_time(e1) / 10 * 1e-3)
+    del src, dst
     torch.cuda.empty_cache()
-    return {"value": val, "unit": unit,
-            "what": "1 GiB device copy" if bound == "hbm" else f"{prec} 8192^3 library GEMM"}
+    return {"value": val, "unit": "GB/s", "what": "1 GiB device copy"}
 
 
 def serve_leg(srv, reqs, rate=None, id_base=0):
@@ -404,7 +510,7 @@ def serve_leg(srv, reqs, rate=None, id_base=0):
     L = np.array(sorted(lat.values())) * 1e3
     return {"requests": len(reqs), "wall_s": wall, "req_per_s": len(reqs) / wall,
             "atoms_evals_per_s": atom_evals / wall, "p50_ms": float(np.percentile(L, 50)),
-            "p99_ms": float(np.percentile(L, 99))}
+            "p99_ms": float(np.percentile(L, 99)), "server": srv.stats()}
 
 
 def serving(at, mt, n_req=2000, n_warm=200, n_steps=100):
@@ -432,7 +538,17 @@ def serving(at, mt, n_req=2000, n_warm=200, n_steps=100):
         for k, f in enumerate((0.5, 0.8)):
             r[f"open_loop_{f}mu"] = serve_leg(srv, reqs, rate=f * mu, id_base=(k + 2) << 20)
         out[prec] = r
-        del srv, pot
+        del srv
+        if prec == "bf16":
+            # admission by an HBM budget: a server asked for 262,144 atoms
+            # under a 1 GiB budget holds what fits, and the closed-loop stream
+            # (about 104k atoms in all) waits for room
+            srv = Server(pot, hbm_budget_bytes=1 << 30, max_atoms=262144, max_mols=4096,
+                         dt_fs=0.5, mass_amu=w.MASS_AMU)
+            serve_leg(srv, warm, id_base=0)
+            out["bf16_budget_1GiB"] = {"saturation": serve_leg(srv, reqs, id_base=1 << 20)}
+            del srv
+        del pot
     return out
 
 
@@ -503,6 +619,10 @@ def main():
     ap.add_argument("--nve", type=int, default=None,
                     help="NVE steps of the drift leg (default 1000 for water7667, else off)")
     ap.add_argument("--nve-dt", type=float, default=0.5, help="time step of the drift leg, fs")
+    ap.add_argument("--nve-scale", type=float, default=1.0,
+                    help="output-layer scale of the networks of the drift leg")
+    ap.add_argument("--nve-relax", type=int, default=0,
+                    help="FIRE iterations before the drift leg's velocities are drawn")
     ap.add_argument("--ensemble", type=int, default=0,
                     help="also time an ensemble of this many networks (BF16 and FP32)")
     ap.add_argument("--ceilings", action="store_true",
@@ -548,11 +668,28 @@ def main():
         forces[prec] = (E.cpu().numpy(), F.cpu().numpy().astype(np.float64))
         if prec == precs[0]:
             r["pairs"], r["triples"] = pair_counts(pot, s.n_atoms)
+        if args.workload == "batch":
+            r["backward"] = backward_leg(pot, pos, sp, off, box, max(args.steps // 5, 3),
+                                         max(args.warmup // 5, 2), mt)
+            bw = r["backward"]
+            if bw["weight_grad_tflops"] is not None:
+                bw["weight_grad_frac_of_peak"] = bw["weight_grad_tflops"] / PEAK_TFLOPS[prec]
         if args.workload == "mol24":
             r["latency"] = latency_leg(pot, pos, sp, off, box)
         n_nve = args.nve if args.nve is not None else (1000 if args.workload == "water7667" else 0)
         if n_nve:
-            r["nve"] = nve_leg(pot, s, n_steps=n_nve, dt=args.nve_dt)
+            if args.nve_scale != 1.0:
+                # the same networks with the output layer scaled: a gentler
+                # random potential for the energy-conservation leg
+                nve_pot = Potential.from_tables(at, mt.scaled_output(args.nve_scale),
+                                                precision=prec,
+                                                max_neighbors=MAX_NEIGHBORS[args.workload])
+            else:
+                nve_pot = pot
+            r["nve"] = nve_leg(nve_pot, s, n_steps=n_nve, dt=args.nve_dt,
+                               relax_iters=args.nve_relax)
+            r["nve"]["output_scale"] = args.nve_scale
+            del nve_pot
         results[prec] = r
         del pot
         torch.cuda.empty_cache()
@@ -593,7 +730,8 @@ def main():
     roof["profiled_avg_ms"] = profiled_kernel_ms(dom, WORKLOAD_KEYS[args.workload] + "_" +
                                                  main_prec)
     # the same achieved rate against the ceiling measured here
-    mp = measured_peak(roof["bound"], main_prec)
+    issue = issue_ceilings()
+    mp = measured_peak(roof["bound"], main_prec, issue)
     roof["measured_peak"] = mp
     roof["frac_of_measured"] = (roof["achieved"] / mp["value"]
                                 if mp and roof.get("achieved") is not None else None)
@@ -625,8 +763,9 @@ def main():
         "mlp_path_tflops": path_tflops,
         "mlp_path_frac_of_peak": path_tflops / PEAK_TFLOPS[main_prec],
         "roofline": roof,
+        "measured_ceilings": issue,
     }
-    for k in ("latency", "nve"):
+    for k in ("latency", "nve", "backward"):
         if k in main_r:
             out[k] = main_r[k]
     if not args.no_serve:

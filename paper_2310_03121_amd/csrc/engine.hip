@@ -102,12 +102,12 @@ __global__ void k_copy_status(const uint32_t* __restrict__ src, uint32_t* __rest
 
 enum Stage {
   ST_STAGE = 0, ST_PAIRS, ST_AEV, ST_L1, ST_L2, ST_HEAD, ST_ENERGY, ST_BWD3, ST_BWD2, ST_GRADG,
-  ST_AEVBWD, ST_WGRAD, ST_MID, ST_COUNT
+  ST_AEVBWD, ST_WGRAD, ST_MID, ST_NET, ST_COUNT
 };
 const char* kStageNames[ST_COUNT] = {
     "stage+sort", "neighbors", "aev_fwd", "mlp_layer1", "mlp_layer2", "mlp_layer3_head",
     "energy_sum", "mlp_bwd_layer3", "mlp_bwd_layer2", "mlp_bwd_dEdG", "aev_bwd_forces",
-    "weight_grads", "mlp_mid_fused"};
+    "weight_grads", "mlp_mid_fused", "mlp_net_fused"};
 
 hipEvent_t prof_event(nnp_handle* h) {
   if (h->ev_next == h->ev_pool.size()) {
@@ -246,7 +246,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B, bool wgr
   P.rec = take(N * P.cap * 16);
   if (B.periodic) {
     P.cell_of = take(N * 4);
-    P.cell_cnt = take((size_t)P.ncell * 4);
+    P.cell_cnt = take((size_t)(P.ncell + 1) * 4);  // counts, then the binning's done counter
     P.cell_start = take((size_t)(P.ncell + 1) * 4);
     P.cursor = take((size_t)P.ncell * 4);
     P.cell_atoms = take(N * 4);
@@ -326,7 +326,8 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     StageTimer t(h, io.timed, ST_STAGE, st);
     launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.gidx, io.n_total,
                  io.species, io.off, S, xyzs, mol, mrange, io.gidx ? nullptr : io.out3, hist,
-                 status, !io.keep_status, st);
+                 status, !io.keep_status, P.B.periodic ? at<int>(ws, P.cell_cnt) : nullptr,
+                 P.B.periodic ? P.ncell + 1 : 0, st);
     if (P.nblk > kFusedSortBlocks) {
       launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
       launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
@@ -381,6 +382,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   const float escale = 1.f / (float)M;
   const size_t esz = sizeof(T);
   bool ok = true;
+  bool net_fused = false;  // the whole network ran as one launch (dE/dG included)
   for (int k = 0; k < M; ++k) {
     // member k: weight slots k * S .. k * S + S - 1
     const int q0 = k * S;
@@ -402,6 +404,50 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     for (int l = 0; l < kLayers - 1; ++l) bias_k[l] = h->bias[l] + (size_t)q0 * h->width[l + 1];
     const float* wout_k = h->wout + (size_t)q0 * w3;
     const float* bout_k = h->bout + q0;
+    // BF16 with gradients, one network: layer 1, the fused middle and dE/dG
+    // in one launch per tile (H1 and D1 stay in LDS)
+    const bool can_net =
+        h->width[1] == 256 && h->width[2] == 192 && h->width[3] == 160 && Fp % 256 == 0;
+    if (bf && need_bwd && M == 1 && can_net) {
+      MidArgs ma{};
+      ma.gt = gt;
+      ma.W1 = static_cast<const bf16_t*>(Wqk[1]);
+      ma.W2 = static_cast<const bf16_t*>(Wqk[2]);
+      ma.W2T = static_cast<const bf16_t*>(WTqk[2]);
+      ma.W1T = static_cast<const bf16_t*>(WTqk[1]);
+      ma.b1 = bias_k[1];
+      ma.b2 = bias_k[2];
+      ma.wout = wout_k;
+      ma.bout = bout_k;
+      ma.erow = erow_k;
+      ma.D1 = io.dparams ? reinterpret_cast<bf16_t*>(D1k) : nullptr;  // the weight gradients' copy
+      ma.ld_d1 = ldd1;
+      ma.escale = escale;
+      if (io.dparams) {
+        ma.H2 = reinterpret_cast<bf16_t*>(H2);
+        ma.H3 = reinterpret_cast<bf16_t*>(H3);
+        ma.D3 = reinterpret_cast<bf16_t*>(D3);
+        ma.D2 = reinterpret_cast<bf16_t*>(D2);
+        ma.uprow = at<float>(ws, P.uprow);
+      }
+      ma.perm = perm;
+      ma.mol = mol;
+      ma.dLdE = io.dLdE;
+      ma.alpha = h->alpha;
+      ma.inv_alpha_l2e = (float)(1.4426950408889634 / h->alpha);
+      ma.X = reinterpret_cast<const bf16_t*>(X);
+      ma.ldx = Fp;
+      ma.W0 = static_cast<const bf16_t*>(Wqk[0]);
+      ma.b0 = bias_k[0];
+      ma.H1out = reinterpret_cast<bf16_t*>(H1);
+      ma.W0T = static_cast<const bf16_t*>(WTq[0]);
+      ma.G = io.out3 ? reinterpret_cast<bf16_t*>(G) : nullptr;
+      StageTimer t(h, io.timed, ST_NET, st);
+      if (launch_mlp_net(h->width, ma, P.rows_cap, st)) {
+        net_fused = true;
+        continue;
+      }
+    }
     GemmArgs g{};
     g.gt = gt;
     g.alpha = h->alpha;
@@ -510,7 +556,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     g.Bq = cat ? (bf ? (const void*)h->WT0cq : nullptr) : WTq[0];
     g.sB = (long)Fp * ldd1; g.ldb = ldd1;
     g.N = Fp; g.K = ldd1; g.C = G; g.ldc = Fp; g.H = nullptr;
-    {
+    if (!net_fused) {
       StageTimer t(h, io.timed, ST_GRADG, st);
       ok &= launch_gemm<T>(EPI_OUT, g, P.rows_cap, st);
     }
@@ -973,7 +1019,9 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   float4* xyzs = at<float4>(ws, P.xyzs);
   int2* mrange = P.mrange ? at<int2>(ws, P.mrange) : nullptr;
   launch_stage(n, nmol, P.n, dims, pos, nullptr, nullptr, 0, species, off, h->S, xyzs,
-               at<int>(ws, P.mol), mrange, nullptr, at<int>(ws, P.hist), status, true, st);
+               at<int>(ws, P.mol), mrange, nullptr, at<int>(ws, P.hist), status, true,
+               P.B.periodic ? at<int>(ws, P.cell_cnt) : nullptr, P.B.periodic ? P.ncell + 1 : 0,
+               st);
   launch_groups(dims, P.n, h->S, at<int>(ws, P.hist), at<GroupTable>(ws, P.gt),
                 at<int>(ws, P.perm), P.rows_cap, off, kWChunk, status, st);
   if (P.B.periodic)

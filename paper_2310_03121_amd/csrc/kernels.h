@@ -62,6 +62,14 @@ struct MidArgs {
   float inv_alpha_l2e;
   float escale = 1.f;             // factor on the upstream gradient (1 / ensemble size)
   int ld_d1 = 0;                  // row stride of D1 (0: W1)
+  // the whole network per tile (k_mlp_net): layer 1 from X, dE/dG into G
+  const bf16_t* X = nullptr;      // [rows][ldx] feature rows
+  int ldx = 0;                    // row stride of X and G, layer 1's K (a multiple of 256)
+  const bf16_t* W0 = nullptr;     // [S][W1][ldx], fragment order
+  const float* b0 = nullptr;      // [S][W1]
+  bf16_t* H1out = nullptr;        // [rows][W1]: H1, also read back for the last slopes
+  const bf16_t* W0T = nullptr;    // [S][ldx][W1], fragment order
+  bf16_t* G = nullptr;            // [rows][ldx] dE/dG, or null (no forces)
 };
 
 // Weight slots: member k of an ensemble, element s -> slot k * S + s.
@@ -97,7 +105,7 @@ void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* po
                   const double* pos64, const int* gidx, int n_total, const int* species,
                   const int* off, int S, float4* xyzs, int* mol, int2* mrange, float* Fzero,
                   int* hist, uint32_t* status, bool clear_status,
-                  hipStream_t st);
+                  int* zero, int nzero, hipStream_t st);
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,
                    int rows_cap, const int* off, int wchunk_rows, uint32_t* status,
                    hipStream_t st);
@@ -128,6 +136,8 @@ void launch_sort_pairs_mol(const int* dims, int n_cap, int S, const int* hist, G
                            const AevConst& C, const float4* xyzs, const int2* mrange, int cap,
                            int* nbr, float4* rec, int2* counts, uint32_t* status,
                            hipStream_t st);
+// Periodic boxes: cell_cnt holds ncell + 1 ints that staging zeroed (the
+// counts and the binning's done counter).
 void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                        const float4* xyzs, int* cell_of, int* cell_cnt, int* cell_start,
                        int* cursor, int* cell_atoms, float4* cell_xyzs, int cap, int* nbr,
@@ -156,6 +166,10 @@ void launch_pack(const PackArgs& p, int slots, hipStream_t st);
 
 // mlp_mid.hip
 bool launch_mlp_mid(const int* width, const MidArgs& a, int rows_cap, hipStream_t st);
+// Layer 1, the fused middle and dE/dG in one launch (one workgroup per
+// 128-row tile; H1 and D1 stay in LDS).  Widths 1008-256-192-160 with a
+// padded feature count that is a multiple of 256; returns false otherwise.
+bool launch_mlp_net(const int* width, const MidArgs& a, int rows_cap, hipStream_t st);
 
 // md.hip
 void launch_vv_kick_drift(const int* dims, int n_cap, double* x, double* v, const float* F,

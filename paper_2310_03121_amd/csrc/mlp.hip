@@ -16,6 +16,8 @@
 // v_mfma_f32_16x16x4f32; both accumulate in FP32.
 #include "mfma_tile.h"
 
+#include <type_traits>
+
 namespace nnp {
 
 // ------------------------------------------------------------- body layers
@@ -641,6 +643,206 @@ __global__ __launch_bounds__(256) void k_wgrad(const GroupTable* __restrict__ gt
   if (blockIdx.z == 0 && tid < 64 && o0 + tid < Nout) out[(size_t)Nout * Nin + o0 + tid] = bacc;
 }
 
+// The same partials on MFMA (layers whose width is at least 16): the chunk's
+// product dW = D^T H as C[i][o] = sum_r H[r][i] D[r][o], K = the chunk's
+// rows.  One workgroup per (chunk, 128 o, 128 i) tile, four waves of 64 x 64
+// (4 x 4 MFMA tiles).  Every stage reads BK rows of D and H with coalesced
+// loads (16 or 32 lanes per 256- or 512-byte row segment) while the previous
+// stage computes.
+//   FP32 (v_mfma_f32_16x16x4f32, one K element per lane): the rows stay
+//   row-major in LDS (144 floats per row, so the four K rows of a fragment
+//   fall in different banks), and a fragment is one 4-byte read per lane.
+//   BF16 (v_mfma_f32_16x16x32_bf16, eight consecutive K per lane): the tile is
+//   transposed on its way into LDS, one LDS row per output (or input) holding
+//   the stage's 64 atom rows, with the 16-byte granules of row c XOR-swizzled
+//   by (c / 8) % 8 and rows 160 bytes apart; lanes 16 apart hold atom rows r
+//   and r ^ 1 and swap them, so each 4-byte store writes an (r, r + 1) pair.
+//   Stores then meet at most two to a bank and the 16-byte fragment reads
+//   none (a CPU model of the layout checks every fragment).
+// The i-tile-0 workgroups also sum db from the staged D.  The accumulator
+// layout leaves each lane four consecutive i of one o, stored as one vector.
+constexpr int kWgBO = 128, kWgBI = 128;
+
+template <typename T> struct WgLayout;
+template <> struct WgLayout<bf16_t> {
+  static constexpr int BK = 64;                 // atom rows per stage
+  static constexpr int P = 80;                  // elements per LDS row (160 bytes)
+  static constexpr int TILE = 128 * P;          // elements per operand tile
+  static constexpr int ITEMS = BK * 16 / 256;   // 16-byte loads per thread and operand
+  __device__ __forceinline__ static int off(int c, int k) {
+    return c * P + 8 * ((k >> 3) ^ ((c >> 3) & 7)) + (k & 7);
+  }
+};
+template <> struct WgLayout<float> {
+  static constexpr int BK = 32;
+  static constexpr int RS = 144;                // floats per LDS row (one atom row)
+  static constexpr int TILE = BK * RS;
+  static constexpr int ITEMS = BK * 32 / 256;
+};
+
+template <typename T>
+constexpr size_t wgrad_lds_bytes() {
+  return (size_t)2 * 2 * WgLayout<T>::TILE * sizeof(T);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(const GroupTable* __restrict__ gt, int S,
+                                                    const T* __restrict__ D, int ldd, int Nout,
+                                                    const T* __restrict__ H, int ldh, int Nin,
+                                                    int chunk, float* __restrict__ partial) {
+  using L = WgLayout<T>;
+  constexpr bool BF = sizeof(T) == 2;
+  constexpr int BK = L::BK, ITEMS = L::ITEMS;
+  constexpr int CPL = 16 / sizeof(T);       // columns per 16-byte load
+  constexpr int LPR = 128 / CPL;            // loads per 128-column row segment
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+
+  const int c = blockIdx.x;
+  if (c >= gt->n_wchunks) return;
+  int s = 0;
+  for (int q = 1; q < S; ++q) s = (c >= gt->wchunk[q]) ? q : s;
+  const int r0 = gt->pstart[s] + (c - gt->wchunk[s]) * chunk;
+  const int rend = gt->pstart[s] + gt->cnt[s];
+  const int r1 = r0 + chunk < rend ? r0 + chunk : rend;
+  const int o0 = blockIdx.y * kWgBO, i0 = blockIdx.z * kWgBI;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wo = w >> 1, wi = w & 1;  // this wave's 64 x 64 tile
+
+  uint4 rd[ITEMS], rh[ITEMS];
+  // item k of this thread: atom row f / LPR of the stage, column group f % LPR
+  auto gload = [&](int rb) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int f = tid + 256 * k, r = f / LPR, g = f % LPR;
+      const int row = rb + r;
+      const bool rok = row < r1;
+      const int oc = o0 + g * CPL, ic = i0 + g * CPL;
+      rd[k] = rok && oc < Nout ? *reinterpret_cast<const uint4*>(D + (size_t)row * ldd + oc)
+                               : make_uint4(0u, 0u, 0u, 0u);
+      rh[k] = rok && ic < Nin ? *reinterpret_cast<const uint4*>(H + (size_t)row * ldh + ic)
+                              : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto lstore = [&](int buf) __attribute__((always_inline)) {
+    T* dt = lds + (size_t)buf * 2 * L::TILE;
+    T* ht = dt + L::TILE;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int f = tid + 256 * k, r = f / LPR, g = f % LPR;
+      if constexpr (BF) {
+        // lanes 16 apart hold rows r and r ^ 1 of the same columns
+        uint4 od, oh;
+        od.x = __shfl_xor(rd[k].x, 16, 64); od.y = __shfl_xor(rd[k].y, 16, 64);
+        od.z = __shfl_xor(rd[k].z, 16, 64); od.w = __shfl_xor(rd[k].w, 16, 64);
+        oh.x = __shfl_xor(rh[k].x, 16, 64); oh.y = __shfl_xor(rh[k].y, 16, 64);
+        oh.z = __shfl_xor(rh[k].z, 16, 64); oh.w = __shfl_xor(rh[k].w, 16, 64);
+        const bool odd = r & 1;
+        // even rows write columns 0..3 of the group, odd rows columns 4..7;
+        // lo = the even row's element, hi = the odd row's
+        const unsigned md[4] = {rd[k].x, rd[k].y, rd[k].z, rd[k].w};
+        const unsigned pd[4] = {od.x, od.y, od.z, od.w};
+        const unsigned mh[4] = {rh[k].x, rh[k].y, rh[k].z, rh[k].w};
+        const unsigned ph[4] = {oh.x, oh.y, oh.z, oh.w};
+        const int kr = r & ~1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int col = g * 8 + e + (odd ? 4 : 0);
+          const int wd = (e + (odd ? 4 : 0)) >> 1;  // dword of the element
+          const bool hi = (e & 1);                 // which half of it
+          const unsigned ev_d = odd ? pd[wd] : md[wd], od_d = odd ? md[wd] : pd[wd];
+          const unsigned ev_h = odd ? ph[wd] : mh[wd], od_h = odd ? mh[wd] : ph[wd];
+          const unsigned vd = hi ? ((ev_d >> 16) | (od_d & 0xffff0000u))
+                                 : ((ev_d & 0xffffu) | (od_d << 16));
+          const unsigned vh = hi ? ((ev_h >> 16) | (od_h & 0xffff0000u))
+                                 : ((ev_h & 0xffffu) | (od_h << 16));
+          *reinterpret_cast<unsigned*>(dt + L::off(col, kr)) = vd;
+          *reinterpret_cast<unsigned*>(ht + L::off(col, kr)) = vh;
+        }
+      } else {
+        *reinterpret_cast<uint4*>(dt + r * L::RS + g * 4) = rd[k];
+        *reinterpret_cast<uint4*>(ht + r * L::RS + g * 4) = rh[k];
+      }
+    }
+  };
+
+  f32x4_t acc[4][4];
+  zero_acc(acc);
+  float bacc = 0.f;
+  const int nst = (r1 - r0 + BK - 1) / BK;
+  if (nst > 0) {
+    gload(r0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) gload(r0 + (st + 1) * BK);
+    const T* dt = lds + (size_t)buf * 2 * L::TILE;
+    const T* ht = dt + L::TILE;
+    if constexpr (BF) {
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        const int j = kk * 4 + (lane >> 4);  // this lane's 8-row granule
+        uint4 fa[4], fb[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int ci = wi * 64 + x * 16 + (lane & 15);
+          fa[x] = *reinterpret_cast<const uint4*>(ht + ci * L::P + 8 * (j ^ ((ci >> 3) & 7)));
+        }
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int co = wo * 64 + y * 16 + (lane & 15);
+          fb[y] = *reinterpret_cast<const uint4*>(dt + co * L::P + 8 * (j ^ ((co >> 3) & 7)));
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) Mfma<bf16_t>::mma(fa[x], fb[y], acc[x][y]);
+      }
+      if (blockIdx.z == 0 && tid < kWgBO) {
+        for (int k = 0; k < BK; ++k) bacc += bf2f(dt[L::off(tid, k)]);
+      }
+    } else {
+#pragma unroll 2
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        float fa[4], fb[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) fa[x] = ht[kr * L::RS + wi * 64 + x * 16 + (lane & 15)];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) fb[y] = dt[kr * L::RS + wo * 64 + y * 16 + (lane & 15)];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[x], fb[y], acc[x][y], 0, 0, 0);
+      }
+      if (blockIdx.z == 0 && tid < kWgBO) {
+        for (int k = 0; k < BK; ++k) bacc += dt[k * L::RS + tid];
+      }
+    }
+    if (st + 1 < nst) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // acc[x][y][e]: i = i0 + wi 64 + x 16 + 4 (lane / 16) + e, o = o0 + wo 64 + y 16 + lane % 16
+  float* out = partial + (size_t)c * ((size_t)Nout * Nin + Nout);
+  const int iq = 4 * (lane >> 4);
+#pragma unroll
+  for (int y = 0; y < 4; ++y) {
+    const int o = o0 + wo * 64 + y * 16 + (lane & 15);
+    if (o >= Nout) continue;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = i0 + wi * 64 + x * 16 + iq;
+      if (i < Nin)
+        *reinterpret_cast<float4*>(out + (size_t)o * Nin + i) =
+            make_float4(acc[x][y][0], acc[x][y][1], acc[x][y][2], acc[x][y][3]);
+    }
+  }
+  if (blockIdx.z == 0 && tid < kWgBO && o0 + tid < Nout) out[(size_t)Nout * Nin + o0 + tid] = bacc;
+}
+
 // out[s] (W then b, Nout*Nin + Nout floats at param_off[s]) = sum of partials.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const GroupTable* __restrict__ gt, int S,
                                                       const float* __restrict__ partial, int len,
@@ -659,6 +861,19 @@ template <typename TD, typename TH>
 void launch_wgrad(const GroupTable* gt, int S, int n_chunks_cap, const TD* D, int ldd, int Nout,
                   const TH* H, int ldh, int Nin, int chunk, float* partial, float* dparams,
                   const long* param_off_dev, hipStream_t st) {
+  if constexpr (std::is_same<TD, TH>::value) {
+    if (Nout >= 16 && Nout % 4 == 0 && Nin % 4 == 0 && ldd % 8 == 0 && ldh % 8 == 0) {
+      static const bool attr = (ensure_lds(k_wgrad_mfma<TD>), true);
+      (void)attr;
+      dim3 grid(n_chunks_cap, (Nout + kWgBO - 1) / kWgBO, (Nin + kWgBI - 1) / kWgBI);
+      hipLaunchKernelGGL(k_wgrad_mfma<TD>, grid, dim3(256), wgrad_lds_bytes<TD>(), st, gt, S, D,
+                         ldd, Nout, H, ldh, Nin, chunk, partial);
+      const int len = Nout * Nin + Nout;
+      hipLaunchKernelGGL(k_wgrad_reduce, dim3((len + 255) / 256, S), dim3(256), 0, st, gt, S,
+                         partial, len, dparams, param_off_dev);
+      return;
+    }
+  }
   dim3 grid(n_chunks_cap, (Nout + 63) / 64, (Nin + 63) / 64);
   hipLaunchKernelGGL((k_wgrad<TD, TH>), grid, dim3(256), 0, st, gt, S, D, ldd, Nout, H, ldh, Nin,
                      chunk, partial);

@@ -79,55 +79,21 @@ __device__ __forceinline__ float4 lds_get4(const unsigned char* p) {
                      __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
 }
 
+// The four products of the fused middle, from H1 in X1 (LDS, row stride S1;
+// also in global a.H1 for the slopes of the last product) with the first
+// product's weight ring already started: H2 into X2, energies, D3 over H1,
+// D2 over H2, and D1 to global a.D1 (if set) and to LDS d1_lds (if set, row
+// stride S1, which may be X1: D3 is consumed by then).
 template <int W1, int W2, int W3>
-__global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
-  static_assert(W3 <= W1, "D3 is stored over H1");
-  constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;  // LDS row strides (bytes)
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  unsigned char* X1 = smem;                          // H1, then D3
-  unsigned char* X2 = X1 + kMidBM * S1;              // H2, then D2
-  float* epart = reinterpret_cast<float*>(X2 + kMidBM * S2);  // [WN][128]
-
-  const GroupTable* gt = a.gt;
-  // tiles holding rows (groups are padded to whole tiles); the grid covers
-  // the capacity, and blocks past the used tiles exit
-  const int nt = gt->total_rows / kMidBM;
-  if ((int)blockIdx.x >= nt) return;
-  const int row0 = xcd_tile(blockIdx.x, nt) * kMidBM;
-  const int s = tile_species(gt, row0);
-  const int row_end = gt->pstart[s] + gt->cnt[s];
-  if (row0 >= row_end) return;
+__device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2>& br1,
+                                             unsigned char* X1, unsigned char* X2, float* epart,
+                                             int row0, int row_end, int s,
+                                             unsigned char* d1_lds) {
+  constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;
+  (void)S2;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rl = lane & 15, cq = (lane >> 4) * 4;
   const float alpha = a.alpha, ia = 1.f / a.alpha, ial2e = a.inv_alpha_l2e;
-
-  // the first product's weights are requested before the H1 tile, so the
-  // two latencies overlap
-  MidRing<W2> br1;
-  mid_ring<W2, W1>(br1, a.W1 + (size_t)s * W2 * W1, lane, wv);
-
-  // H1 tile -> LDS (zero rows past the group): every load is issued before
-  // the first store
-  {
-    constexpr int V1 = W1 / 8;  // 16-byte vectors per row
-    constexpr int NV = kMidBM * V1 / 512;
-    static_assert(kMidBM * V1 % 512 == 0, "whole vectors per thread");
-    uint4 v[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const int idx = tid + q * 512, r = idx / V1, c = idx % V1;
-      v[q] = make_uint4(0, 0, 0, 0);
-      if (row0 + r < row_end)
-        v[q] = *reinterpret_cast<const uint4*>(a.H1 + (size_t)(row0 + r) * W1 + c * 8);
-    }
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const int idx = tid + q * 512, r = idx / V1, c = idx % V1;
-      *reinterpret_cast<uint4*>(X1 + r * S1 + c * 16) = v[q];
-    }
-  }
-  __syncthreads();
-
   // ---- H2 = CELU(H1 W1^T + b1)
   {
     using C = MidCfg<W2>;
@@ -267,7 +233,242 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
         float4 d = make_float4(acc[i][j][0] * celu_slope(h.x, ia), acc[i][j][1] * celu_slope(h.y, ia),
                                acc[i][j][2] * celu_slope(h.z, ia), acc[i][j][3] * celu_slope(h.w, ia));
         if (!rv) d = make_float4(0.f, 0.f, 0.f, 0.f);
-        Store<bf16_t>::put4(a.D1 + (size_t)row * ldd1 + c, d);
+        if (d1_lds) lds_put4(d1_lds + r * S1 + c * 2, d);
+        if (a.D1) Store<bf16_t>::put4(a.D1 + (size_t)row * ldd1 + c, d);
+      }
+    }
+  }
+}
+
+template <int W1, int W2, int W3>
+__global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
+  static_assert(W3 <= W1, "D3 is stored over H1");
+  constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;  // LDS row strides (bytes)
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned char* X1 = smem;                          // H1, then D3
+  unsigned char* X2 = X1 + kMidBM * S1;              // H2, then D2
+  float* epart = reinterpret_cast<float*>(X2 + kMidBM * S2);  // [WN][128]
+
+  const GroupTable* gt = a.gt;
+  // tiles holding rows (groups are padded to whole tiles); the grid covers
+  // the capacity, and blocks past the used tiles exit
+  const int nt = gt->total_rows / kMidBM;
+  if ((int)blockIdx.x >= nt) return;
+  const int row0 = xcd_tile(blockIdx.x, nt) * kMidBM;
+  const int s = tile_species(gt, row0);
+  const int row_end = gt->pstart[s] + gt->cnt[s];
+  if (row0 >= row_end) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+  // the first product's weights are requested before the H1 tile, so the
+  // two latencies overlap
+  MidRing<W2> br1;
+  mid_ring<W2, W1>(br1, a.W1 + (size_t)s * W2 * W1, lane, wv);
+
+  // H1 tile -> LDS (zero rows past the group): every load is issued before
+  // the first store
+  {
+    constexpr int V1 = W1 / 8;  // 16-byte vectors per row
+    constexpr int NV = kMidBM * V1 / 512;
+    static_assert(kMidBM * V1 % 512 == 0, "whole vectors per thread");
+    uint4 v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int idx = tid + q * 512, r = idx / V1, c = idx % V1;
+      v[q] = make_uint4(0, 0, 0, 0);
+      if (row0 + r < row_end)
+        v[q] = *reinterpret_cast<const uint4*>(a.H1 + (size_t)(row0 + r) * W1 + c * 8);
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int idx = tid + q * 512, r = idx / V1, c = idx % V1;
+      *reinterpret_cast<uint4*>(X1 + r * S1 + c * 16) = v[q];
+    }
+  }
+  __syncthreads();
+
+  mid_products<W1, W2, W3>(a, br1, X1, X2, epart, row0, row_end, s, nullptr);
+}
+
+// ------------------------------------------------------------ whole network
+//
+// Layer 1, the fused middle and dE/dG for one tile of 128 species-sorted
+// rows per workgroup, so H1 and D1 never make an HBM round trip and the
+// three stages share one launch:
+//   H1 = CELU(X W0^T + b0)      X streamed through two LDS chunk buffers
+//                               (region A), weights through the register
+//                               ring; H1 into LDS (X1) and to global memory
+//                               (the last slopes and the weight gradients)
+//   middle products             as k_mlp_mid, H2 / D2 in region A; D1 into X1
+//   G = D1 W0                   D1 resident in X1, four passes of 256
+//                               columns, staged per wave in region A for
+//                               whole-row-segment stores
+// LDS: region A (two chunk buffers, 69,632 bytes) + X1 (128 rows of 528
+// bytes) = 137,216 bytes.
+constexpr int kNetChunk = 256;                  // bytes of K per row and chunk
+constexpr int kNetChunkStride = kNetChunk + 16;
+
+template <int W1, int W2, int W3>
+constexpr size_t net_lds() {
+  return (size_t)2 * kMidBM * kNetChunkStride + (size_t)kMidBM * (W1 * 2 + 16);
+}
+
+template <int W1, int W2, int W3>
+__global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
+  static_assert(W3 <= W1, "D3 is stored over H1");
+  constexpr int BM = kMidBM;
+  constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;
+  constexpr int RA = 2 * BM * kNetChunkStride;
+  static_assert(BM * S2 + 4 * BM * 4 <= RA, "X2 and the energy partials fit region A");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned char* RAp = smem;
+  unsigned char* X1 = smem + RA;
+  unsigned char* X2 = RAp;
+  float* epart = reinterpret_cast<float*>(X2 + BM * S2);
+
+  const GroupTable* gt = a.gt;
+  const int nt = gt->total_rows / BM;
+  if ((int)blockIdx.x >= nt) return;
+  const int row0 = xcd_tile(blockIdx.x, nt) * BM;
+  const int s = tile_species(gt, row0);
+  const int row_end = gt->pstart[s] + gt->cnt[s];
+  if (row0 >= row_end) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rl = lane & 15, cq = (lane >> 4) * 4;
+  constexpr int WM = 2, WN = 4, TM = 4, TN = W1 / 64, P = 4;
+  static_assert(WM * TM * 16 == BM && WN * TN * 16 == W1, "one pass covers layer 1");
+  const int wm = wv / WN, wn = wv % WN;
+  const int K = a.ldx;
+
+  // ---- layer 1: H1 = CELU(X W0^T + b0)
+  {
+    constexpr int KC = kNetChunk / 2;           // bf16 per chunk row
+    constexpr int SPC = KC / Frag<bf16_t>::KS;  // k-steps per chunk
+    static_assert(SPC == P, "one ring cycle per chunk");
+    constexpr int VPR = kNetChunk / 16;
+    constexpr int NVA = BM * VPR / 512;
+    const __amdgpu_buffer_rsrc_t arsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<bf16_t*>(a.X + (size_t)row0 * K), (short)0, (row_end - row0) * K * 2,
+        kBufferRsrcWord3);
+    auto aload = [&](int c, uint4 (&ra)[NVA]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int v = 0; v < NVA; ++v) {
+        const int idx = tid + v * 512;
+        const int r = idx / VPR, k = c * KC + (idx % VPR) * 8;
+        const unsigned off = k < K ? (unsigned)((r * K + k) * 2) : kOutOfRange;
+        const u32x4_t val = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
+        ra[v] = make_uint4(val[0], val[1], val[2], val[3]);
+      }
+    };
+    auto astore = [&](int buf, const uint4 (&ra)[NVA]) __attribute__((always_inline)) {
+      unsigned char* base = RAp + buf * BM * kNetChunkStride;
+#pragma unroll
+      for (int v = 0; v < NVA; ++v) {
+        const int idx = tid + v * 512;
+        *reinterpret_cast<uint4*>(base + (idx / VPR) * kNetChunkStride + (idx % VPR) * 16) = ra[v];
+      }
+    };
+    const int nu = (K + KC - 1) / KC;
+    const int arow = (wm * TM * 16 + (lane & 15)) * kNetChunkStride + (lane >> 4) * 16;
+    f32x4_t acc[TM][TN];
+    zero_acc(acc);
+    BRing<bf16_t, TN, P> br;
+    br.init(a.W0 + (size_t)s * W1 * K, wn * TN * 16, -1, lane, K);
+    br.prologue();
+    uint4 ra0[NVA], ra1[NVA];
+    aload(0, ra0);
+    astore(0, ra0);
+    aload(1 % nu, ra1);
+    __syncthreads();
+    auto unit = [&](int u, uint4 (&r_next2)[NVA], const uint4 (&r_next1)[NVA])
+                    __attribute__((always_inline)) {
+      aload(u + 2 < nu ? u + 2 : nu - 1, r_next2);
+      kgroup<bf16_t, TM, TN, P>(RAp + (u & 1) * BM * kNetChunkStride + arow,
+                                16 * kNetChunkStride, br, u * SPC, acc);
+      astore((u + 1) & 1, r_next1);
+      __syncthreads();
+    };
+    for (int u = 0; u < nu; u += 2) {
+      unit(u, ra0, ra1);
+      if (u + 1 < nu) unit(u + 1, ra1, ra0);
+    }
+    const float alpha = a.alpha, ial2e = a.inv_alpha_l2e;
+    const float* b0 = a.b0 + (size_t)s * W1;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * TM * 16 + i * 16 + rl;
+      const bool rv = row0 + r < row_end;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int c = wn * TN * 16 + j * 16 + cq;
+        const float4 b = *reinterpret_cast<const float4*>(b0 + c);
+        float4 h = make_float4(celu_fwd(acc[i][j][0] + b.x, alpha, ial2e),
+                               celu_fwd(acc[i][j][1] + b.y, alpha, ial2e),
+                               celu_fwd(acc[i][j][2] + b.z, alpha, ial2e),
+                               celu_fwd(acc[i][j][3] + b.w, alpha, ial2e));
+        if (!rv) h = make_float4(0.f, 0.f, 0.f, 0.f);
+        lds_put4(X1 + r * S1 + c * 2, h);
+        if (rv) Store<bf16_t>::put4(a.H1out + (size_t)(row0 + r) * W1 + c, h);
+      }
+    }
+  }
+  __syncthreads();  // H1 in X1 (and in global memory); region A free
+
+  // ---- the middle: H2, energies, D3, D2, D1 (into X1)
+  {
+    MidRing<W2> br1;
+    mid_ring<W2, W1>(br1, a.W1 + (size_t)s * W2 * W1, lane, wv);
+    MidArgs am = a;
+    am.H1 = a.H1out;
+    mid_products<W1, W2, W3>(am, br1, X1, X2, epart, row0, row_end, s, X1);
+  }
+  if (!a.G) return;  // block-uniform: no forces asked for
+  __syncthreads();   // D1 in X1; region A free
+
+  // ---- dE/dG: G = D1 W0, passes of W1 columns of the ldx
+  {
+    constexpr int NP = WN * TN * 16;
+    constexpr int SS = TN * 16 * 2 + 16;        // staging row stride (bytes)
+    constexpr int WCOLB = TN * 16 * 2;          // bytes of a wave's tile row
+    const int npass = K / NP;
+    const int col_w = wn * TN * 16;
+    const bf16_t* B = a.W0T + (size_t)s * K * W1;
+    BRing<bf16_t, TN, P> br;
+    br.init(B, col_w, npass > 1 ? NP + col_w : -1, lane, W1);
+    br.prologue();
+    const int arow = (wm * TM * 16 + (lane & 15)) * S1 + (lane >> 4) * 16;
+    unsigned char* stg = RAp + wv * 16 * SS;
+    f32x4_t acc[TM][TN];
+    for (int p = 0; p < npass; ++p) {
+      zero_acc(acc);
+#pragma unroll
+      for (int c = 0; c < W1 / 128; ++c)
+        kgroup<bf16_t, TM, TN, P>(X1 + arow + c * 256, 16 * S1, br, c * P, acc);
+      br.next_pass(B, p + 2 < npass ? (p + 2) * NP + col_w : -1, lane);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int rloc = wm * TM * 16 + i * 16;
+        const bool rv = row0 + rloc + rl < row_end;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          float4 v = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+          if (!rv) v = make_float4(0.f, 0.f, 0.f, 0.f);
+          lds_put4(stg + rl * SS + (j * 16 + cq) * 2, v);
+        }
+        wave_lds_sync();
+        constexpr int VR = WCOLB / 16;
+#pragma unroll
+        for (int q = 0; q < (16 * VR + 63) / 64; ++q) {
+          const int idx = lane + q * 64;
+          if (16 * VR % 64 == 0 || idx < 16 * VR) {
+            const int r = idx / VR, cv = idx % VR;
+            const uint4 val = *reinterpret_cast<const uint4*>(stg + r * SS + cv * 16);
+            unsigned char* dst = reinterpret_cast<unsigned char*>(a.G) +
+                                 ((size_t)(row0 + rloc + r) * K + p * NP + col_w) * 2 + cv * 16;
+            *reinterpret_cast<uint4*>(dst) = val;
+          }
+        }
+        wave_lds_sync();
       }
     }
   }
@@ -284,6 +485,16 @@ static void launch_mid_t(const MidArgs& a, int rows_cap, hipStream_t st) {
   static const bool attr = (ensure_lds(k_mlp_mid<W1, W2, W3>), true);
   (void)attr;
   hipLaunchKernelGGL((k_mlp_mid<W1, W2, W3>), dim3(rows_cap / kMidBM), dim3(512), lds, st, a);
+}
+
+bool launch_mlp_net(const int* width, const MidArgs& a, int rows_cap, hipStream_t st) {
+  if (!(width[1] == 256 && width[2] == 192 && width[3] == 160)) return false;
+  if (a.ldx <= 0 || a.ldx % 256 != 0 || !a.X || !a.W0 || !a.W0T || !a.H1out) return false;
+  constexpr size_t lds = net_lds<256, 192, 160>();
+  static const bool attr = (ensure_lds(k_mlp_net<256, 192, 160>), true);
+  (void)attr;
+  hipLaunchKernelGGL((k_mlp_net<256, 192, 160>), dim3(rows_cap / kMidBM), dim3(512), lds, st, a);
+  return true;
 }
 
 // Widths with a fused kernel: 1008-256-192-160 (seven elements) and

@@ -16,9 +16,10 @@
 //
 // Molecules without a box: candidates are the atoms of the same molecule,
 // read as contiguous float4 records.  Periodic boxes (one system): atoms are
-// binned into cells no narrower than rc + 1e-3 A; a wave scans the
-// concatenation of the 27 surrounding cells (fewer when a dimension has fewer
-// than three cells) from a cell-ordered copy of the records.
+// binned into cells no narrower than rc + 1e-3 A; a workgroup per cell stages
+// the concatenation of the 27 surrounding cells (fewer when a dimension has
+// fewer than three cells) in LDS from a cell-ordered copy of the records, and
+// its waves scan it for the cell's atoms.
 #include "kernels.h"
 #include "sort_scatter.h"
 
@@ -138,47 +139,58 @@ __device__ __forceinline__ int cell_coord(float x, float L, float invL, float sc
   return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
+// Bins the atoms (cell counts by atomics; staging zeroed the counts and the
+// done counter cell_cnt[ncell]), and the last workgroup to finish turns the
+// counts into cell starts and fill cursors (an exclusive scan), so binning
+// needs no launch of its own for the scan.  Every workgroup takes part in the
+// done count, whatever its atoms.
 __global__ __launch_bounds__(256) void k_cell_count(const int* __restrict__ dims, BoxConst B,
                                                     const float4* __restrict__ xyzs,
                                                     int* __restrict__ cell_of,
-                                                    int* __restrict__ cell_cnt) {
-  const int n = dims[0];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float4 p = xyzs[i];
-  int cx, cy, cz;
-  if (B.periodic == 2) {
-    // fractional coordinates, wrapped into [0, 1), then binned
-    const float sz = p.z * B.inv_diag[2];
-    const float sy = (p.y - B.v[2][1] * sz) * B.inv_diag[1];
-    const float sx = (p.x - B.v[1][0] * sy - B.v[2][0] * sz) * B.inv_diag[0];
-    cx = cell_coord(sx, 1.f, 1.f, (float)B.nc[0], B.nc[0]);
-    cy = cell_coord(sy, 1.f, 1.f, (float)B.nc[1], B.nc[1]);
-    cz = cell_coord(sz, 1.f, 1.f, (float)B.nc[2], B.nc[2]);
-  } else {
-    cx = cell_coord(p.x, B.L[0], B.invL[0], B.cell_scale[0], B.nc[0]);
-    cy = cell_coord(p.y, B.L[1], B.invL[1], B.cell_scale[1], B.nc[1]);
-    cz = cell_coord(p.z, B.L[2], B.invL[2], B.cell_scale[2], B.nc[2]);
-  }
-  const int c = cx + B.nc[0] * (cy + B.nc[1] * cz);
-  cell_of[i] = c;
-  atomicAdd(&cell_cnt[c], 1);
-}
-
-// One block: exclusive scan of the cell counts into starts and cursors.
-__global__ __launch_bounds__(1024) void k_cell_scan(int ncell, const int* __restrict__ cnt,
+                                                    int* __restrict__ cell_cnt, int ncell,
                                                     int* __restrict__ start,
                                                     int* __restrict__ cursor) {
-  __shared__ int scan[1024];
+  __shared__ int scan[256];
+  __shared__ int is_last;
+  const int n = dims[0];
   const int t = threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + t;
+  if (i < n) {
+    const float4 p = xyzs[i];
+    int cx, cy, cz;
+    if (B.periodic == 2) {
+      // fractional coordinates, wrapped into [0, 1), then binned
+      const float sz = p.z * B.inv_diag[2];
+      const float sy = (p.y - B.v[2][1] * sz) * B.inv_diag[1];
+      const float sx = (p.x - B.v[1][0] * sy - B.v[2][0] * sz) * B.inv_diag[0];
+      cx = cell_coord(sx, 1.f, 1.f, (float)B.nc[0], B.nc[0]);
+      cy = cell_coord(sy, 1.f, 1.f, (float)B.nc[1], B.nc[1]);
+      cz = cell_coord(sz, 1.f, 1.f, (float)B.nc[2], B.nc[2]);
+    } else {
+      cx = cell_coord(p.x, B.L[0], B.invL[0], B.cell_scale[0], B.nc[0]);
+      cy = cell_coord(p.y, B.L[1], B.invL[1], B.cell_scale[1], B.nc[1]);
+      cz = cell_coord(p.z, B.L[2], B.invL[2], B.cell_scale[2], B.nc[2]);
+    }
+    const int c = cx + B.nc[0] * (cy + B.nc[1] * cz);
+    cell_of[i] = c;
+    atomicAdd(&cell_cnt[c], 1);
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) is_last = atomicAdd(&cell_cnt[ncell], 1) == (int)gridDim.x - 1;
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
   int carry = 0;
-  for (int c0 = 0; c0 < ncell; c0 += blockDim.x) {
+  for (int c0 = 0; c0 < ncell; c0 += 256) {
     const int c = c0 + t;
-    const int v = c < ncell ? cnt[c] : 0;
+    const int v = c < ncell ? __hip_atomic_load(&cell_cnt[c], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : 0;
     scan[t] = v;
     __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-      int u = t >= o ? scan[t - o] : 0;
+    for (int o = 1; o < 256; o <<= 1) {
+      const int u = t >= o ? scan[t - o] : 0;
       __syncthreads();
       scan[t] += u;
       __syncthreads();
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(1024) void k_cell_scan(int ncell, const int* __rest
       start[c] = carry + scan[t] - v;
       cursor[c] = carry + scan[t] - v;
     }
-    const int last = scan[blockDim.x - 1];
+    const int last = scan[255];
     __syncthreads();
     carry += last;
   }
@@ -208,107 +220,145 @@ __global__ __launch_bounds__(256) void k_cell_fill(const int* __restrict__ dims,
   cell_xyzs[slot] = xyzs[i];
 }
 
-// One wave per atom, visiting atoms in cell order (neighbouring waves share
-// their candidate cells).  Candidates are the concatenation of the stencil
-// cells; a lane maps its candidate number to (cell, slot) through a per-wave
-// prefix table of the stencil's cell sizes.
-__global__ __launch_bounds__(256) void k_pairs_cell(const int* __restrict__ dims, AevConst C,
-                                                    BoxConst B, const int* __restrict__ cell_of,
-                                                    const int* __restrict__ cell_start,
-                                                    const int* __restrict__ cell_atoms,
-                                                    const float4* __restrict__ cell_xyzs, int cap,
-                                                    int* __restrict__ nbr,
-                                                    float4* __restrict__ rec,
-                                                    int2* __restrict__ counts,
-                                                    uint32_t* __restrict__ status) {
+// Cell-centred neighbor search: one workgroup per cell.  The workgroup stages
+// the records and indices of its stencil cells (the concatenation of up to 27
+// cells, at most kCandLds of them) in LDS once; its waves then take the
+// cell's atoms in turn and scan the staged candidates 64 at a time, so the
+// ~460 candidates of a liquid-density cell are read from global memory once
+// per cell instead of once per atom.  A workgroup whose stencil holds more
+// candidates reads them from global memory (the same arithmetic).
+constexpr int kCandLds = 1024;
+
+// Waves per cell workgroup: about one per atom of a liquid-density cell
+// (17 at the large box's cells), as LDS allows.
+__host__ __device__ constexpr int pairs_cell_waves(int cap) {
+  return cap <= 128 ? 16 : (cap <= 256 ? 8 : 4);
+}
+
+__host__ __device__ constexpr size_t pairs_cell_lds_bytes(int cap) {
+  return (size_t)kCandLds * (sizeof(float4) + sizeof(int)) +
+         (size_t)pairs_cell_waves(cap) * cap * (sizeof(float4) + sizeof(int)) + 64 * sizeof(int);
+}
+
+__global__ __launch_bounds__(1024) void k_pairs_cell_lds(
+    const int* __restrict__ dims, AevConst C, BoxConst B, const int* __restrict__ cell_start,
+    const int* __restrict__ cell_atoms, const float4* __restrict__ cell_xyzs, int cap,
+    int* __restrict__ nbr, float4* __restrict__ rec, int2* __restrict__ counts,
+    uint32_t* __restrict__ status) {
   extern __shared__ float4 lds_cell[];
+  float4* cand = lds_cell;
+  int* cidx = reinterpret_cast<int*>(cand + kCandLds);
+  const int nw = (int)blockDim.x >> 6;
+  float4* lrec_all = reinterpret_cast<float4*>(cidx + kCandLds);
+  int* key_all = reinterpret_cast<int*>(lrec_all + (size_t)nw * cap);
+  int* pref = key_all + (size_t)nw * cap;  // 28 prefix entries
+  int* cst = pref + 28;                   // 27 cell starts
   const int n = dims[0];
-  const int w = threadIdx.x >> 6;
-  const int lane = lane_id();
-  const int slot_i = blockIdx.x * 4 + w;
-  if (slot_i >= n) return;
-  float4* lrec = lds_cell + (size_t)w * cap;
-  int* key = reinterpret_cast<int*>(lds_cell + (size_t)4 * cap) + w * (cap + 64);
-  int* pref = key + cap;  // 28 prefix entries + 27 cell starts
-  int* cst = pref + 28;
-  const int i = cell_atoms[slot_i];
-  const float4 pi = cell_xyzs[slot_i];
-  const int c = cell_of[i];
+  const int tid = threadIdx.x, lane = lane_id();
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  float4* lrec = lrec_all + (size_t)w * cap;
+  int* key = key_all + (size_t)w * cap;
+  const int c = blockIdx.x;
   const int cx = c % B.nc[0], cy = (c / B.nc[0]) % B.nc[1], cz = c / (B.nc[0] * B.nc[1]);
   // stencil: offsets -1..1 per binned dimension, only 0 where nc == 1
   const int rx = B.nc[0] >= 3 ? 1 : 0, ry = B.nc[1] >= 3 ? 1 : 0, rz = B.nc[2] >= 3 ? 1 : 0;
   const int sx = 2 * rx + 1, sy = 2 * ry + 1, sz = 2 * rz + 1;
   const int nst = sx * sy * sz;
-  int cnt = 0, st = 0;
-  if (lane < nst) {
-    const int ox = lane % sx - rx, oy = (lane / sx) % sy - ry, oz = lane / (sx * sy) - rz;
-    const int ncx = (cx + ox + B.nc[0]) % B.nc[0];
-    const int ncy = (cy + oy + B.nc[1]) % B.nc[1];
-    const int ncz = (cz + oz + B.nc[2]) % B.nc[2];
-    const int cc = ncx + B.nc[0] * (ncy + B.nc[1] * ncz);
-    st = cell_start[cc];
-    cnt = cell_start[cc + 1] - st;
-  }
-  // inclusive scan of cnt over lanes 0..nst-1
-  int incl = cnt;
+  if (w == 0) {
+    int cnt = 0, st = 0;
+    if (lane < nst) {
+      const int ox = lane % sx - rx, oy = (lane / sx) % sy - ry, oz = lane / (sx * sy) - rz;
+      const int ncx = (cx + ox + B.nc[0]) % B.nc[0];
+      const int ncy = (cy + oy + B.nc[1]) % B.nc[1];
+      const int ncz = (cz + oz + B.nc[2]) % B.nc[2];
+      const int cc = ncx + B.nc[0] * (ncy + B.nc[1] * ncz);
+      st = cell_start[cc];
+      cnt = cell_start[cc + 1] - st;
+    }
+    int incl = cnt;
 #pragma unroll
-  for (int o = 1; o < 32; o <<= 1) {
-    const int u = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += u;
+    for (int o = 1; o < 32; o <<= 1) {
+      const int u = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += u;
+    }
+    if (lane < nst) {
+      pref[lane + 1] = incl;
+      cst[lane] = st;
+    }
+    if (lane == 0) pref[0] = 0;
   }
-  if (lane < nst) {
-    pref[lane + 1] = incl;
-    cst[lane] = st;
+  __syncthreads();
+  const int total = pref[nst];
+  const bool staged = total <= kCandLds;  // block-uniform
+  // slot of candidate t: the largest q < nst with pref[q] <= t holds it
+  auto cand_slot = [&](int t) __attribute__((always_inline)) {
+    int q = 0, hi = nst;
+    while (hi - q > 1) {
+      const int mid = (q + hi) >> 1;
+      if (pref[mid] <= t) q = mid; else hi = mid;
+    }
+    return cst[q] + (t - pref[q]);
+  };
+  if (staged) {
+    for (int t = tid; t < total; t += (int)blockDim.x) {
+      const int slot = cand_slot(t);
+      cand[t] = cell_xyzs[slot];
+      cidx[t] = cell_atoms[slot];
+    }
   }
-  if (lane == 0) pref[0] = 0;
-  const int total = __shfl(incl, nst - 1, 64);
-  wave_lds_sync();
-  int nr = 0, na = 0;
-  for (int base = 0; base < total; base += kWave) {
-    const int t = base + lane;
-    bool inR = false, inA = false;
-    int j = 0, sj = 0;
-    float dx = 0.f, dy = 0.f, dz = 0.f;
-    if (t < total) {
-      // largest q < nst with pref[q] <= t (that cell is non-empty and holds t)
-      int q = 0, hi = nst;
-      while (hi - q > 1) {
-        const int mid = (q + hi) >> 1;
-        if (pref[mid] <= t) q = mid; else hi = mid;
-      }
-      const int slot = cst[q] + (t - pref[q]);
-      j = cell_atoms[slot];
-      if (j != i) {
-        const float4 pj = cell_xyzs[slot];
-        if (B.periodic == 2) {
-          tric_disp(pi, pj, B, dx, dy, dz);
+  __syncthreads();
+  const int c0 = cell_start[c], cn = cell_start[c + 1] - c0;
+  for (int a = w; a < cn; a += nw) {
+    const int i = cell_atoms[c0 + a];
+    const float4 pi = cell_xyzs[c0 + a];
+    int nr = 0, na = 0;
+    for (int base = 0; base < total; base += kWave) {
+      const int t = base + lane;
+      bool inR = false, inA = false;
+      int j = 0, sj = 0;
+      float dx = 0.f, dy = 0.f, dz = 0.f;
+      if (t < total) {
+        float4 pj;
+        if (staged) {
+          j = cidx[t];
+          pj = cand[t];
         } else {
-          dx = disp(pi.x, pj.x, B.L[0], B.invL[0], 1);
-          dy = disp(pi.y, pj.y, B.L[1], B.invL[1], 1);
-          dz = disp(pi.z, pj.z, B.L[2], B.invL[2], 1);
+          const int slot = cand_slot(t);
+          j = cell_atoms[slot];
+          pj = cell_xyzs[slot];
         }
-        const float d2 = dist2(dx, dy, dz);
-        inR = d2 < C.rc2_r;
-        inA = d2 < C.rc2_a;
-        sj = species_of(pj);
+        if (j != i) {
+          if (B.periodic == 2) {
+            tric_disp(pi, pj, B, dx, dy, dz);
+          } else {
+            dx = disp(pi.x, pj.x, B.L[0], B.invL[0], 1);
+            dy = disp(pi.y, pj.y, B.L[1], B.invL[1], 1);
+            dz = disp(pi.z, pj.z, B.L[2], B.invL[2], 1);
+          }
+          const float d2 = dist2(dx, dy, dz);
+          inR = d2 < C.rc2_r;
+          inA = d2 < C.rc2_a;
+          sj = species_of(pj);
+        }
       }
+      const uint64_t mr = ballot(inR);
+      const int p = nr + popc_below(mr);
+      if (inR && p < cap) {
+        key[p] = make_key(j, sj, inA);
+        lrec[p] = make_float4(dx, dy, dz, __int_as_float(sj));
+      }
+      nr += __popcll(mr);
+      na += __popcll(ballot(inA));
     }
-    const uint64_t mr = ballot(inR);
-    const int p = nr + popc_below(mr);
-    if (inR && p < cap) {
-      key[p] = make_key(j, sj, inA);
-      lrec[p] = make_float4(dx, dy, dz, __int_as_float(sj));
+    if (nr > cap) {
+      if (lane == 0) atomicOr(status, kStCapacity);
+      nr = cap;
+      na = na < nr ? na : nr;
     }
-    nr += __popcll(mr);
-    na += __popcll(ballot(inA));
+    wave_lds_sync();
+    if (i >= 0 && i < n) finish_list(key, lrec, nr, na, i, cap, nbr, rec, counts);
+    wave_lds_sync();  // the next atom reuses the wave's list
   }
-  if (nr > cap) {
-    if (lane == 0) atomicOr(status, kStCapacity);
-    nr = cap;
-    na = na < nr ? na : nr;
-  }
-  wave_lds_sync();
-  finish_list(key, lrec, nr, na, i, cap, nbr, rec, counts);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -341,16 +391,16 @@ void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxC
                        float4* rec, int2* counts, uint32_t* status, hipStream_t st) {
   if (n_cap <= 0) return;
   const int ncell = B.nc[0] * B.nc[1] * B.nc[2];
-  hipLaunchKernelGGL(k_fill_i32, dim3((ncell + 255) / 256), dim3(256), 0, st, cell_cnt, 0, ncell);
+  // staging zeroed cell_cnt[0 .. ncell]
   hipLaunchKernelGGL(k_cell_count, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, B, xyzs,
-                     cell_of, cell_cnt);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, ncell, cell_cnt, cell_start,
-                     cursor);
+                     cell_of, cell_cnt, ncell, cell_start, cursor);
   hipLaunchKernelGGL(k_cell_fill, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, xyzs,
                      cell_of, cursor, cell_atoms, cell_xyzs);
-  hipLaunchKernelGGL(k_pairs_cell, dim3((n_cap + 3) / 4), dim3(256),
-                     4 * (cap * sizeof(float4) + (cap + 64) * sizeof(int)), st, dims, C, B,
-                     cell_of, cell_start, cell_atoms, cell_xyzs, cap, nbr, rec, counts, status);
+  static const bool attr = (ensure_lds(k_pairs_cell_lds), true);
+  (void)attr;
+  hipLaunchKernelGGL(k_pairs_cell_lds, dim3(ncell), dim3(64 * pairs_cell_waves(cap)),
+                     pairs_cell_lds_bytes(cap), st, dims, C, B, cell_start, cell_atoms, cell_xyzs,
+                     cap, nbr, rec, counts, status);
 }
 
 }  // namespace nnp

@@ -24,8 +24,12 @@ __global__ __launch_bounds__(256) void k_stage(int n_arg, int nmol_arg, int clea
                                                float4* __restrict__ xyzs, int* __restrict__ mol,
                                                int2* __restrict__ mrange,
                                                float* __restrict__ Fzero, int* __restrict__ hist,
-                                               uint32_t* __restrict__ status) {
+                                               uint32_t* __restrict__ status,
+                                               int* __restrict__ zero, int nzero) {
   __shared__ int h[kMaxS];
+  // counters a later kernel of the evaluation accumulates into (the cell list)
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nzero; k += gridDim.x * blockDim.x)
+    zero[k] = 0;
   __shared__ uint32_t bits;
   __shared__ int smp[kOffSamples + 1];
   const int n = n_arg >= 0 ? n_arg : dims[0];
@@ -259,11 +263,12 @@ __global__ void k_fill_f64(double* __restrict__ p, double v, int n) {
 void launch_stage(int n_arg, int nmol_arg, int n_cap, int* dims, const float* pos,
                   const double* pos64, const int* gidx, int n_total, const int* species,
                   const int* off, int S, float4* xyzs, int* mol, int2* mrange, float* Fzero,
-                  int* hist, uint32_t* status, bool clear_status, hipStream_t st) {
+                  int* hist, uint32_t* status, bool clear_status, int* zero, int nzero,
+                  hipStream_t st) {
   const int nblk = stage_blocks(n_cap);
   hipLaunchKernelGGL(k_stage, dim3(nblk), dim3(256), 0, st, n_arg, nmol_arg, clear_status ? 1 : 0,
-                     dims, pos, pos64,
-                     gidx, n_total, species, off, S, xyzs, mol, mrange, Fzero, hist, status);
+                     dims, pos, pos64, gidx, n_total, species, off, S, xyzs, mol, mrange, Fzero,
+                     hist, status, zero, nzero);
 }
 
 void launch_groups(const int* dims, int n_cap, int S, int* hist, GroupTable* gt, int* perm,

@@ -560,6 +560,50 @@ def test_fp32_finite_difference_gradcheck():
     assert rel_rms(a[:, 0], a[:, 1]) <= 2e-2
 
 
+def test_water7667_weight_gradient_finite_differences():
+    """Weight gradients of the whole 23,001-atom water box (FP32 path,
+    nnp_backward) against central differences of the GPU energy: for each
+    element present (H, O) and each layer, the weight with the largest
+    gradient.  Bar 2e-3 relative: the energy is an FP64 sum of FP32 atomic
+    energies, so a difference of two evaluations carries ~1e-5 eV of rounding
+    noise, against g h of about 1e-2 eV or more here."""
+    s = w.config_system(4)
+    announce(f"weight-gradient finite differences, water box N={s.n_atoms}")
+    pot, at, mt = potential(7, "fp32")
+    pos, sp, off = to_dev(s)
+    dLdE = torch.ones(1, dtype=torch.float64, device="cuda")
+    _, gw, E0 = pot.backward(pos, sp, off, dLdE, box=s.box, want_pos=False)
+    pot.check()
+    gw = gw.cpu().numpy().astype(np.float64)
+    flat = mt.flat().astype(np.float32)
+    picks = []
+    o_ = 0
+    for sp_ in range(7):
+        for l in range(4):
+            nW, nb = mt.W[sp_][l].size, mt.b[sp_][l].size
+            if sp_ in (0, 3):
+                picks.append(o_ + int(np.argmax(np.abs(gw[o_:o_ + nW]))))
+            o_ += nW + nb
+    worst = 0.0
+    for idx in picks:
+        h = np.float32(1e-3)
+        pp, pm = flat.copy(), flat.copy()
+        pp[idx] += h
+        pm[idx] -= h
+        pot.set_params(torch.from_numpy(pp).cuda())
+        ep, _ = pot.energy_forces(pos, sp, off, s.box, forces=False)
+        pot.set_params(torch.from_numpy(pm).cuda())
+        em, _ = pot.energy_forces(pos, sp, off, s.box, forces=False)
+        pot.check()
+        fd = (ep.item() - em.item()) / (float(pp[idx]) - float(pm[idx]))
+        err = abs(fd - gw[idx]) / abs(gw[idx])
+        worst = max(worst, err)
+        print(f"param {idx}: backward {gw[idx]:.6e}  central difference {fd:.6e}  rel {err:.2e}")
+        assert err <= 2e-3, (idx, gw[idx], fd)
+    pot.set_params(torch.from_numpy(flat).cuda())
+    print(f"worst relative error {worst:.2e} over {len(picks)} weights")
+
+
 def test_device_errors_are_reported():
     from paper_2310_03121_amd import NNPError
     announce("device status: species, non-finite, capacity; host: box")

@@ -134,6 +134,16 @@ class MLPTable:
             W.append(ws); b.append(bs)
         return MLPTable(self.widths, W, b, self.self_energy.copy(), self.celu_alpha)
 
+    def scaled_output(self, factor: float) -> "MLPTable":
+        """The same networks with the output layer (W and b) times `factor`:
+        energies and forces scale by it."""
+        W = [[w.copy() for w in ws] for ws in self.W]
+        b = [[x.copy() for x in bs] for bs in self.b]
+        for s in range(self.n_species):
+            W[s][-1] = (W[s][-1] * np.float32(factor)).astype(np.float32)
+            b[s][-1] = (b[s][-1] * np.float32(factor)).astype(np.float32)
+        return MLPTable(self.widths, W, b, self.self_energy.copy(), self.celu_alpha)
+
 
 def default_widths(n_species: int) -> tuple:
     f = feature_count(n_species)
