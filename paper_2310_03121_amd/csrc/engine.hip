@@ -267,12 +267,12 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B, bool wgr
   P.G = take(R * h->Fp * esz);
   P.erow = take(R * 4 * h->n_models);
   P.uprow = take(R * 4);
-  size_t maxlen = 0;
+  size_t plen = 0;  // one element's parameters
   for (int l = 0; l < kLayers; ++l) {
     const size_t in = l == 0 ? h->F : h->width[l];
-    maxlen = std::max(maxlen, (size_t)h->width[l + 1] * in + h->width[l + 1]);
+    plen += (size_t)h->width[l + 1] * in + h->width[l + 1];
   }
-  P.wpart = wgrad ? take((size_t)P.nwchunks * maxlen * 4) : 0;
+  P.wpart = wgrad ? take((size_t)P.nwchunks * plen * 4) : 0;
   P.pos32 = take(N * 12);
   P.total = o;
   return P;
@@ -568,16 +568,14 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     StageTimer t(h, io.timed, ST_WGRAD, st);
     float* part = at<float>(ws, P.wpart);
     const float* up = at<float>(ws, P.uprow);
-    const long* po = h->param_off_dev;
-    // output layer: dW3 = sum up * h3, db3 = sum up
-    launch_wgrad<float, T>(gt, S, P.nwchunks, up, 1, 1, H3, w3, w3, kWChunk, part, io.dparams,
-                           po + 3 * S, st);
-    launch_wgrad<T, T>(gt, S, P.nwchunks, D3, w3, w3, H2, w2, w2, kWChunk, part, io.dparams,
-                       po + 2 * S, st);
-    launch_wgrad<T, T>(gt, S, P.nwchunks, D2, w2, w2, H1, w1, w1, kWChunk, part, io.dparams,
-                       po + 1 * S, st);
-    launch_wgrad<T, T>(gt, S, P.nwchunks, D1, w1, w1, X, Fp, h->F, kWChunk, part, io.dparams,
-                       po, st);
+    const WgradLayer layers[kLayers] = {
+        {D1, X, w1, Fp, w1, h->F, false},
+        {D2, H1, w2, w1, w2, w1, false},
+        {D3, H2, w3, w2, w3, w2, false},
+        {up, H3, 1, w3, 1, w3, true},
+    };
+    launch_wgrad_net<T>(gt, S, P.nwchunks, kWChunk, layers, kLayers, part, io.dparams,
+                        h->param_off_dev, st);
   }
   if (!ok) return NNP_E_INVALID;
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;

@@ -158,10 +158,21 @@ void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4*
 // mlp.hip
 template <typename T>
 bool launch_gemm(int epi, const GemmArgs& a, int rows_cap, hipStream_t st);
-template <typename TD, typename TH>
-void launch_wgrad(const GroupTable* gt, int S, int n_chunks_cap, const TD* D, int ldd, int Nout,
-                  const TH* H, int ldh, int Nin, int chunk, float* partial, float* dparams,
-                  const long* param_off_dev, hipStream_t st);
+// Weight gradients of all layers (input layer first): per-chunk partials in
+// one launch (plus one per layer whose widths the MFMA tiles do not take),
+// then the chunk-ordered sum into dparams[param_off_dev[s] + e], e over the
+// element's whole flat parameter vector.  partial holds n_chunks_cap times
+// that vector's length in floats.
+struct WgradLayer {
+  const void* D;  // [rows][ldd] adjoint of the layer's output
+  const void* H;  // [rows][ldh] the layer's input
+  int ldd, ldh, Nout, Nin;
+  bool d_fp32;    // D is FP32 (the output layer's), else the operand type
+};
+template <typename T>
+void launch_wgrad_net(const GroupTable* gt, int S, int n_chunks_cap, int chunk,
+                      const WgradLayer* layers, int n_layers, float* partial, float* dparams,
+                      const long* param_off_dev, hipStream_t st);
 void launch_pack(const PackArgs& p, int slots, hipStream_t st);
 
 // mlp_mid.hip

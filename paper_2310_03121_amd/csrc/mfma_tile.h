@@ -22,6 +22,7 @@ namespace nnp {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
 
 // Word 3 of a raw buffer resource on CDNA (32-bit data format, no swizzle):
 // buffer loads whose offset lies past the resource's byte range return zero.

@@ -581,15 +581,47 @@ bool launch_gemm<float>(int epi, const GemmArgs& a, int rows_cap, hipStream_t st
 // ------------------------------------------------------------ weight gradients
 //
 // dW[o][i] = sum over the element's rows of D[r][o] * H[r][i];  db[o] = sum D[r][o].
-// The rows of each element are cut into chunks of `chunk` rows; block
-// (chunk, o-tile, i-tile) writes its partial sums, and a second kernel adds
-// the partials of each element in chunk order (deterministic).
+// The rows of each element are cut into chunks of `chunk` rows.  One launch
+// writes every layer's partial sums per chunk, laid out like the element's
+// flat parameter vector (layer by layer: W row-major, then b); a second adds
+// the partials of each element in chunk order, so the result does not depend
+// on scheduling.
 
+constexpr int kWgVecMaxIn = 256;  // widest input of the vector output-layer path
+struct WgLayerArgs {
+  const void* D;
+  const void* H;
+  int ldd, ldh, Nout, Nin;
+  int n_o, n_i;   // 128-wide output and input tiles
+  int block0;     // first block of the layer after the output layer's
+  long part_off;  // the layer's W inside a chunk's partial vector
+};
+struct WgVecArgs {
+  const void* H;
+  int ldh, Nin;
+  long part_off;
+};
+struct WgNetArgs {
+  const GroupTable* gt;
+  int S, chunk;
+  float* partial;
+  long part_len;  // floats per chunk
+  const float* up;
+  WgVecArgs vec;
+  int vec_blocks;    // a multiple of 8
+  int tiled_blocks;  // MFMA tiles of all layers
+  int n_tiled;
+  WgLayerArgs L[kLayers];
+};
+
+// Any layer shape (VALU, 64 x 64 register outer products from 32-row LDS
+// tiles): the fallback for widths the MFMA tiles do not take.
 template <typename TD, typename TH>
 __global__ __launch_bounds__(256) void k_wgrad(const GroupTable* __restrict__ gt, int S,
                                                const TD* __restrict__ D, int ldd, int Nout,
                                                const TH* __restrict__ H, int ldh, int Nin,
-                                               int chunk, float* __restrict__ partial) {
+                                               int chunk, float* __restrict__ partial, long part_len,
+                                               long part_off) {
   __shared__ float sd[32][65];
   __shared__ float sh[32][65];
   const int c = blockIdx.x;
@@ -632,7 +664,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const GroupTable* __restrict__ gt
     }
     __syncthreads();
   }
-  float* out = partial + (size_t)c * ((size_t)Nout * Nin + Nout);
+  float* out = partial + (size_t)c * part_len + part_off;
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
@@ -643,24 +675,6 @@ __global__ __launch_bounds__(256) void k_wgrad(const GroupTable* __restrict__ gt
   if (blockIdx.z == 0 && tid < 64 && o0 + tid < Nout) out[(size_t)Nout * Nin + o0 + tid] = bacc;
 }
 
-// The same partials on MFMA (layers whose width is at least 16): the chunk's
-// product dW = D^T H as C[i][o] = sum_r H[r][i] D[r][o], K = the chunk's
-// rows.  One workgroup per (chunk, 128 o, 128 i) tile, four waves of 64 x 64
-// (4 x 4 MFMA tiles).  Every stage reads BK rows of D and H with coalesced
-// loads (16 or 32 lanes per 256- or 512-byte row segment) while the previous
-// stage computes.
-//   FP32 (v_mfma_f32_16x16x4f32, one K element per lane): the rows stay
-//   row-major in LDS (144 floats per row, so the four K rows of a fragment
-//   fall in different banks), and a fragment is one 4-byte read per lane.
-//   BF16 (v_mfma_f32_16x16x32_bf16, eight consecutive K per lane): the tile is
-//   transposed on its way into LDS, one LDS row per output (or input) holding
-//   the stage's 64 atom rows, with the 16-byte granules of row c XOR-swizzled
-//   by (c / 8) % 8 and rows 160 bytes apart; lanes 16 apart hold atom rows r
-//   and r ^ 1 and swap them, so each 4-byte store writes an (r, r + 1) pair.
-//   Stores then meet at most two to a bank and the 16-byte fragment reads
-//   none (a CPU model of the layout checks every fragment).
-// The i-tile-0 workgroups also sum db from the staged D.  The accumulator
-// layout leaves each lane four consecutive i of one o, stored as one vector.
 constexpr int kWgBO = 128, kWgBI = 128;
 
 template <typename T> struct WgLayout;
@@ -685,46 +699,92 @@ constexpr size_t wgrad_lds_bytes() {
   return (size_t)2 * 2 * WgLayout<T>::TILE * sizeof(T);
 }
 
+
+// The MFMA partials of one (chunk, 128 o, 128 i) tile, as C[i][o] = sum_r
+// H[r][i] D[r][o] with K = the chunk's rows; four waves of 64 x 64 (4 x 4
+// MFMA tiles).  Every stage reads BK rows of D and H with coalesced 16-byte
+// loads (16 or 32 lanes per 256- or 512-byte row segment) into registers two
+// stages ahead of the one being multiplied, so two stages' loads are in
+// flight behind each stage's products.
+//   FP32 (v_mfma_f32_16x16x4f32, one K element per lane): the rows stay
+//   row-major in LDS (144 floats per row, so the four K rows of a fragment
+//   fall in different banks), and a fragment is one 4-byte read per lane.
+//   BF16 (v_mfma_f32_16x16x32_bf16, eight consecutive K per lane): the tile is
+//   transposed on its way into LDS, one LDS row per output (or input) holding
+//   the stage's 64 atom rows, with the 16-byte granules of row c XOR-swizzled
+//   by (c / 8) % 8 and rows 160 bytes apart; lanes 16 apart hold atom rows r
+//   and r ^ 1 and swap them, so each 4-byte store writes an (r, r + 1) pair.
+//   Stores then meet at most two to a bank and the 16-byte fragment reads
+//   none (a CPU model of the layout checks every fragment).
+// Tiles at i = 0 also sum db: each thread adds the D columns it loads over
+// its rows in registers, and the sixteen (or eight) threads of a column group
+// are added in a fixed order at the end.  The accumulator layout leaves each
+// lane four consecutive i of one o, stored as one vector.
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_wgrad_mfma(const GroupTable* __restrict__ gt, int S,
-                                                    const T* __restrict__ D, int ldd, int Nout,
-                                                    const T* __restrict__ H, int ldh, int Nin,
-                                                    int chunk, float* __restrict__ partial) {
+__device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int Nout,
+                                           const T* __restrict__ H, int ldh, int Nin, int r0,
+                                           int r1, int o0, int i0, bool bias,
+                                           float* __restrict__ out, float* __restrict__ bout,
+                                           T* lds) {
   using L = WgLayout<T>;
   constexpr bool BF = sizeof(T) == 2;
   constexpr int BK = L::BK, ITEMS = L::ITEMS;
   constexpr int CPL = 16 / sizeof(T);       // columns per 16-byte load
   constexpr int LPR = 128 / CPL;            // loads per 128-column row segment
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  T* lds = reinterpret_cast<T*>(smem);
-
-  const int c = blockIdx.x;
-  if (c >= gt->n_wchunks) return;
-  int s = 0;
-  for (int q = 1; q < S; ++q) s = (c >= gt->wchunk[q]) ? q : s;
-  const int r0 = gt->pstart[s] + (c - gt->wchunk[s]) * chunk;
-  const int rend = gt->pstart[s] + gt->cnt[s];
-  const int r1 = r0 + chunk < rend ? r0 + chunk : rend;
-  const int o0 = blockIdx.y * kWgBO, i0 = blockIdx.z * kWgBI;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wo = w >> 1, wi = w & 1;  // this wave's 64 x 64 tile
 
-  uint4 rd[ITEMS], rh[ITEMS];
-  // item k of this thread: atom row f / LPR of the stage, column group f % LPR
-  auto gload = [&](int rb) __attribute__((always_inline)) {
+  uint4 rd0[ITEMS], rh0[ITEMS], rd1[ITEMS], rh1[ITEMS];
+  float bsum[CPL];
+#pragma unroll
+  for (int e = 0; e < CPL; ++e) bsum[e] = 0.f;
+  // Item k of this thread: atom row f / LPR of the stage, column group f % LPR
+  // (= tid % LPR for every k), at a byte offset that is the same in every
+  // stage.  Each stage reads through buffer resources that start at its first
+  // row and end at the chunk's last: rows past the chunk, and columns past
+  // the layer (sent out of range), load as zeros.
+  unsigned offd[ITEMS], offh[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int f = tid + 256 * k, r = f / LPR, g = f % LPR;
+    const int oc = o0 + g * CPL, ic = i0 + g * CPL;
+    offd[k] = oc < Nout ? (unsigned)((r * ldd + oc) * (int)sizeof(T)) : kOutOfRange;
+    offh[k] = ic < Nin ? (unsigned)((r * ldh + ic) * (int)sizeof(T)) : kOutOfRange;
+  }
+  auto gload = [&](uint4 (&rd)[ITEMS], uint4 (&rh)[ITEMS], int rb) __attribute__((always_inline)) {
+    // (uniform; read into a scalar register so that the resources are built
+    // there and the loads need no per-lane resource loop)
+    const int nr = __builtin_amdgcn_readfirstlane(r1 - rb < 0 ? 0 : (r1 - rb < BK ? r1 - rb : BK));
+    const __amdgpu_buffer_rsrc_t dsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(D + (size_t)rb * ldd), (short)0, nr * ldd * (int)sizeof(T),
+        kBufferRsrcWord3);
+    const __amdgpu_buffer_rsrc_t hsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(H + (size_t)rb * ldh), (short)0, nr * ldh * (int)sizeof(T),
+        kBufferRsrcWord3);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      const int f = tid + 256 * k, r = f / LPR, g = f % LPR;
-      const int row = rb + r;
-      const bool rok = row < r1;
-      const int oc = o0 + g * CPL, ic = i0 + g * CPL;
-      rd[k] = rok && oc < Nout ? *reinterpret_cast<const uint4*>(D + (size_t)row * ldd + oc)
-                               : make_uint4(0u, 0u, 0u, 0u);
-      rh[k] = rok && ic < Nin ? *reinterpret_cast<const uint4*>(H + (size_t)row * ldh + ic)
-                              : make_uint4(0u, 0u, 0u, 0u);
+      const u32x4_t vd = __builtin_amdgcn_raw_buffer_load_b128(dsrc, offd[k], 0, 0);
+      const u32x4_t vh = __builtin_amdgcn_raw_buffer_load_b128(hsrc, offh[k], 0, 0);
+      rd[k] = make_uint4(vd[0], vd[1], vd[2], vd[3]);
+      rh[k] = make_uint4(vh[0], vh[1], vh[2], vh[3]);
     }
   };
-  auto lstore = [&](int buf) __attribute__((always_inline)) {
+  auto addbias = [&](const uint4 (&rd)[ITEMS]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const unsigned u[4] = {rd[k].x, rd[k].y, rd[k].z, rd[k].w};
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        if constexpr (BF)
+          bsum[e] += __uint_as_float((e & 1) ? (u[e >> 1] & 0xffff0000u) : (u[e >> 1] << 16));
+        else
+          bsum[e] += __uint_as_float(u[e]);
+      }
+    }
+  };
+  auto lstore = [&](const uint4 (&rd)[ITEMS], const uint4 (&rh)[ITEMS], int buf)
+                    __attribute__((always_inline)) {
     T* dt = lds + (size_t)buf * 2 * L::TILE;
     T* ht = dt + L::TILE;
 #pragma unroll
@@ -748,10 +808,12 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const GroupTable* __restrict
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int col = g * 8 + e + (odd ? 4 : 0);
-          const int wd = (e + (odd ? 4 : 0)) >> 1;  // dword of the element
+          // dword (e + (odd ? 4 : 0)) / 2 of each operand, selected without
+          // a run-time array index (which would put the arrays in scratch)
+          const int lo = e >> 1, hi4 = lo + 2;
           const bool hi = (e & 1);                 // which half of it
-          const unsigned ev_d = odd ? pd[wd] : md[wd], od_d = odd ? md[wd] : pd[wd];
-          const unsigned ev_h = odd ? ph[wd] : mh[wd], od_h = odd ? mh[wd] : ph[wd];
+          const unsigned ev_d = odd ? pd[hi4] : md[lo], od_d = odd ? md[hi4] : pd[lo];
+          const unsigned ev_h = odd ? ph[hi4] : mh[lo], od_h = odd ? mh[hi4] : ph[lo];
           const unsigned vd = hi ? ((ev_d >> 16) | (od_d & 0xffff0000u))
                                  : ((ev_d & 0xffffu) | (od_d << 16));
           const unsigned vh = hi ? ((ev_h >> 16) | (od_h & 0xffff0000u))
@@ -765,23 +827,13 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const GroupTable* __restrict
       }
     }
   };
-
   f32x4_t acc[4][4];
   zero_acc(acc);
-  float bacc = 0.f;
-  const int nst = (r1 - r0 + BK - 1) / BK;
-  if (nst > 0) {
-    gload(r0);
-    lstore(0);
-  }
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < nst) gload(r0 + (st + 1) * BK);
+  auto compute = [&](int buf) __attribute__((always_inline)) {
     const T* dt = lds + (size_t)buf * 2 * L::TILE;
     const T* ht = dt + L::TILE;
     if constexpr (BF) {
-#pragma unroll
+#pragma unroll 1
       for (int kk = 0; kk < 2; ++kk) {
         const int j = kk * 4 + (lane >> 4);  // this lane's 8-row granule
         uint4 fa[4], fb[4];
@@ -800,9 +852,6 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const GroupTable* __restrict
 #pragma unroll
           for (int y = 0; y < 4; ++y) Mfma<bf16_t>::mma(fa[x], fb[y], acc[x][y]);
       }
-      if (blockIdx.z == 0 && tid < kWgBO) {
-        for (int k = 0; k < BK; ++k) bacc += bf2f(dt[L::off(tid, k)]);
-      }
     } else {
 #pragma unroll 2
       for (int ks = 0; ks < BK / 4; ++ks) {
@@ -818,15 +867,34 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const GroupTable* __restrict
           for (int y = 0; y < 4; ++y)
             acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[x], fb[y], acc[x][y], 0, 0, 0);
       }
-      if (blockIdx.z == 0 && tid < kWgBO) {
-        for (int k = 0; k < BK; ++k) bacc += dt[k * L::RS + tid];
-      }
     }
-    if (st + 1 < nst) lstore(buf ^ 1);
+  };
+
+  // Stage s is loaded into register set s % 2 two stages before it is
+  // multiplied and stored to LDS buffer s % 2 one stage before.  The stage
+  // count is rounded up to even and every load is issued: stages past the
+  // chunk read an empty range (zeros, which add nothing), so no load sits
+  // behind a branch and each wait covers exactly the set it needs.
+  const int nst = (r1 - r0 + 2 * BK - 1) / (2 * BK) * 2;
+  gload(rd0, rh0, r0);
+  gload(rd1, rh1, r0 + BK);
+  if (bias) addbias(rd0);
+  lstore(rd0, rh0, 0);
+  gload(rd0, rh0, r0 + 2 * BK);
+  __syncthreads();
+  for (int st = 0; st < nst; st += 2) {
+    compute(0);
+    if (bias) addbias(rd1);
+    lstore(rd1, rh1, 1);
+    gload(rd1, rh1, r0 + (st + 3) * BK);
+    __syncthreads();
+    compute(1);
+    if (bias) addbias(rd0);
+    lstore(rd0, rh0, 0);
+    gload(rd0, rh0, r0 + (st + 4) * BK);
     __syncthreads();
   }
   // acc[x][y][e]: i = i0 + wi 64 + x 16 + 4 (lane / 16) + e, o = o0 + wo 64 + y 16 + lane % 16
-  float* out = partial + (size_t)c * ((size_t)Nout * Nin + Nout);
   const int iq = 4 * (lane >> 4);
 #pragma unroll
   for (int y = 0; y < 4; ++y) {
@@ -840,56 +908,212 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const GroupTable* __restrict
             make_float4(acc[x][y][0], acc[x][y][1], acc[x][y][2], acc[x][y][3]);
     }
   }
-  if (blockIdx.z == 0 && tid < kWgBO && o0 + tid < Nout) out[(size_t)Nout * Nin + o0 + tid] = bacc;
+  if (bias) {
+    // the LDS tiles are free after the loop's last barrier
+    float* red = reinterpret_cast<float*>(lds);  // [256 / LPR][128]
+    const int g = tid % LPR;
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) red[(tid / LPR) * 128 + g * CPL + e] = bsum[e];
+    __syncthreads();
+    if (tid < 128 && o0 + tid < Nout) {
+      float v = 0.f;
+      for (int q = 0; q < 256 / LPR; ++q) v += red[q * 128 + tid];
+      bout[o0 + tid] = v;
+    }
+  }
+}
+
+// The output layer's partials (one output): dW[i] = sum_r up[r] H[r][i],
+// db = sum_r up[r].  Lane l takes columns 4l..4l+3 of every row (one 8- or
+// 16-byte load), the workgroup's four waves take 16-row blocks in turn, and
+// the 16 rows' loads are issued together through buffer resources spanning
+// the chunk (rows past it and columns past Nin load as zeros, so no load is
+// behind a branch).  The waves' sums are added in wave order.
+template <typename TH>
+__device__ __forceinline__ void wgrad_vec(const float* __restrict__ up,
+                                          const TH* __restrict__ H, int ldh, int Nin, int r0,
+                                          int r1, float* __restrict__ out, float* red) {
+  constexpr int U = 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nrow = __builtin_amdgcn_readfirstlane(r1 - r0);
+  const __amdgpu_buffer_rsrc_t hs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<TH*>(H + (size_t)r0 * ldh), (short)0, nrow * ldh * (int)sizeof(TH),
+      kBufferRsrcWord3);
+  const __amdgpu_buffer_rsrc_t us = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(up + r0), (short)0, nrow * 4, kBufferRsrcWord3);
+  const int c0 = 4 * lane;
+  const bool cok = c0 < Nin;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f}, bacc = 0.f;
+  for (int rb = w * U; rb < nrow; rb += 4 * U) {
+    float d[U], hv[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = rb + u;
+      d[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(us, r * 4, 0, 0));
+      const unsigned off = cok ? (unsigned)((r * ldh + c0) * (int)sizeof(TH)) : kOutOfRange;
+      if constexpr (sizeof(TH) == 2) {
+        const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(hs, off, 0, 0);
+        hv[u][0] = __uint_as_float(v[0] << 16);
+        hv[u][1] = __uint_as_float(v[0] & 0xffff0000u);
+        hv[u][2] = __uint_as_float(v[1] << 16);
+        hv[u][3] = __uint_as_float(v[1] & 0xffff0000u);
+      } else {
+        const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(hs, off, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hv[u][e] = __uint_as_float(v[e]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      bacc += d[u];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += d[u] * hv[u][e];
+    }
+  }
+  constexpr int RS = kWgVecMaxIn + 4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[w * RS + c0 + e] = acc[e];
+  if (lane == 0) red[w * RS + kWgVecMaxIn] = bacc;
+  __syncthreads();
+  for (int i = threadIdx.x; i <= Nin; i += 256) {
+    const int src = i < Nin ? i : kWgVecMaxIn;
+    out[i] = ((red[src] + red[RS + src]) + red[2 * RS + src]) + red[3 * RS + src];
+  }
+}
+
+// Which (element, row range) chunk c covers; false past the last chunk.
+__device__ __forceinline__ bool wgrad_chunk(const GroupTable* gt, int S, int chunk, int c,
+                                            int& r0, int& r1) {
+  if (c >= gt->n_wchunks) return false;
+  int s = 0;
+  for (int q = 1; q < S; ++q) s = (c >= gt->wchunk[q]) ? q : s;
+  r0 = gt->pstart[s] + (c - gt->wchunk[s]) * chunk;
+  const int rend = gt->pstart[s] + gt->cnt[s];
+  r1 = r0 + chunk < rend ? r0 + chunk : rend;
+  return true;
+}
+
+// Blocks [0, vec_blocks) take the output layer's chunks; then, layer by
+// layer, (chunk, o-tile, i-tile) MFMA tiles, chunk-major.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_wgrad_net(
+    WgNetArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  int b = blockIdx.x;
+  int r0 = 0, r1 = 0;
+  if (b < a.vec_blocks) {
+    if (!wgrad_chunk(a.gt, a.S, a.chunk, b, r0, r1)) return;
+    wgrad_vec<T>(a.up, static_cast<const T*>(a.vec.H), a.vec.ldh, a.vec.Nin, r0, r1,
+                 a.partial + (size_t)b * a.part_len + a.vec.part_off,
+                 reinterpret_cast<float*>(smem));
+    return;
+  }
+  // Tiles in XCD-major order: workgroups are dealt to the eight XCDs in
+  // turn, so physical block b (after the 8-aligned output-layer blocks) is
+  // slot b / 8 on XCD b % 8; XCD x takes the contiguous range of tiles
+  // [x, x + 1) * T / 8, which keeps the tiles of one chunk (reading the same
+  // rows of D and H) on one XCD and its L2.
+  b -= a.vec_blocks;
+  {
+    const int per_xcd = (a.tiled_blocks + 7) / 8;
+    b = (b % 8) * per_xcd + b / 8;
+    if (b >= a.tiled_blocks) return;
+  }
+  int l = 0;
+  for (int q = 1; q < a.n_tiled; ++q) l = b >= a.L[q].block0 ? q : l;
+  const WgLayerArgs& Ly = a.L[l];
+  b -= Ly.block0;
+  const int per = Ly.n_o * Ly.n_i;
+  const int c = b / per, t = b % per;
+  const int ot = t / Ly.n_i, it = t % Ly.n_i;
+  if (!wgrad_chunk(a.gt, a.S, a.chunk, c, r0, r1)) return;
+  float* out = a.partial + (size_t)c * a.part_len + Ly.part_off;
+  wgrad_tile<T>(static_cast<const T*>(Ly.D), Ly.ldd, Ly.Nout, static_cast<const T*>(Ly.H), Ly.ldh,
+                Ly.Nin, r0, r1, ot * kWgBO, it * kWgBI, it == 0, out,
+                out + (size_t)Ly.Nout * Ly.Nin, reinterpret_cast<T*>(smem));
 }
 
 // out[s] (W then b, Nout*Nin + Nout floats at param_off[s]) = sum of partials.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const GroupTable* __restrict__ gt, int S,
-                                                      const float* __restrict__ partial, int len,
+                                                      const float* __restrict__ partial, long len,
                                                       float* __restrict__ dparams,
                                                       const long* __restrict__ param_off) {
   const int s = blockIdx.y;
   if (s >= S) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= len) return;
   float v = 0.f;
   for (int c = gt->wchunk[s]; c < gt->wchunk[s + 1]; ++c) v += partial[(size_t)c * len + e];
   dparams[param_off[s] + e] = v;
 }
 
-template <typename TD, typename TH>
-void launch_wgrad(const GroupTable* gt, int S, int n_chunks_cap, const TD* D, int ldd, int Nout,
-                  const TH* H, int ldh, int Nin, int chunk, float* partial, float* dparams,
-                  const long* param_off_dev, hipStream_t st) {
-  if constexpr (std::is_same<TD, TH>::value) {
-    if (Nout >= 16 && Nout % 4 == 0 && Nin % 4 == 0 && ldd % 8 == 0 && ldh % 8 == 0) {
-      static const bool attr = (ensure_lds(k_wgrad_mfma<TD>), true);
-      (void)attr;
-      dim3 grid(n_chunks_cap, (Nout + kWgBO - 1) / kWgBO, (Nin + kWgBI - 1) / kWgBI);
-      hipLaunchKernelGGL(k_wgrad_mfma<TD>, grid, dim3(256), wgrad_lds_bytes<TD>(), st, gt, S, D,
-                         ldd, Nout, H, ldh, Nin, chunk, partial);
-      const int len = Nout * Nin + Nout;
-      hipLaunchKernelGGL(k_wgrad_reduce, dim3((len + 255) / 256, S), dim3(256), 0, st, gt, S,
-                         partial, len, dparams, param_off_dev);
-      return;
+template <typename T>
+void launch_wgrad_net(const GroupTable* gt, int S, int n_chunks_cap, int chunk,
+                      const WgradLayer* layers, int n_layers, float* partial, float* dparams,
+                      const long* param_off_dev, hipStream_t st) {
+  if (n_chunks_cap <= 0 || n_layers <= 0) return;
+  static const bool attr = (ensure_lds(k_wgrad_net<T>), true);
+  (void)attr;
+  long part_len = 0, off[kLayers] = {};
+  for (int l = 0; l < n_layers; ++l) {
+    off[l] = part_len;
+    part_len += (long)layers[l].Nout * layers[l].Nin + layers[l].Nout;
+  }
+  WgNetArgs a{};
+  a.gt = gt;
+  a.S = S;
+  a.chunk = chunk;
+  a.partial = partial;
+  a.part_len = part_len;
+  int blocks = 0;
+  // the output layer: the vector kernel when it has one output
+  const WgradLayer& lo = layers[n_layers - 1];
+  const bool vec = lo.Nout == 1 && lo.Nin <= kWgVecMaxIn && lo.Nin % 4 == 0 && lo.ldh % 4 == 0;
+  if (vec) {
+    a.up = static_cast<const float*>(lo.D);
+    a.vec.H = lo.H;
+    a.vec.ldh = lo.ldh;
+    a.vec.Nin = lo.Nin;
+    a.vec.part_off = off[n_layers - 1];
+    a.vec_blocks = (n_chunks_cap + 7) / 8 * 8;
+  }
+  for (int l = 0; l < n_layers; ++l) {
+    const WgradLayer& y = layers[l];
+    if (l == n_layers - 1 && vec) continue;
+    const bool tiled = y.Nout >= 16 && y.Nout % 4 == 0 && y.Nin % 4 == 0 && y.ldd % 8 == 0 &&
+                       y.ldh % 8 == 0 && !y.d_fp32;
+    if (tiled && a.n_tiled < kLayers) {
+      WgLayerArgs& t = a.L[a.n_tiled++];
+      t.D = y.D; t.H = y.H; t.ldd = y.ldd; t.ldh = y.ldh; t.Nout = y.Nout; t.Nin = y.Nin;
+      t.n_o = (y.Nout + kWgBO - 1) / kWgBO;
+      t.n_i = (y.Nin + kWgBI - 1) / kWgBI;
+      t.block0 = blocks;
+      t.part_off = off[l];
+      blocks += n_chunks_cap * t.n_o * t.n_i;
+    } else if (y.d_fp32) {
+      dim3 grid(n_chunks_cap, (y.Nout + 63) / 64, (y.Nin + 63) / 64);
+      hipLaunchKernelGGL((k_wgrad<float, T>), grid, dim3(256), 0, st, gt, S,
+                         static_cast<const float*>(y.D), y.ldd, y.Nout,
+                         static_cast<const T*>(y.H), y.ldh, y.Nin, chunk, partial, part_len,
+                         off[l]);
+    } else {
+      dim3 grid(n_chunks_cap, (y.Nout + 63) / 64, (y.Nin + 63) / 64);
+      hipLaunchKernelGGL((k_wgrad<T, T>), grid, dim3(256), 0, st, gt, S,
+                         static_cast<const T*>(y.D), y.ldd, y.Nout, static_cast<const T*>(y.H),
+                         y.ldh, y.Nin, chunk, partial, part_len, off[l]);
     }
   }
-  dim3 grid(n_chunks_cap, (Nout + 63) / 64, (Nin + 63) / 64);
-  hipLaunchKernelGGL((k_wgrad<TD, TH>), grid, dim3(256), 0, st, gt, S, D, ldd, Nout, H, ldh, Nin,
-                     chunk, partial);
-  const int len = Nout * Nin + Nout;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((len + 255) / 256, S), dim3(256), 0, st, gt, S, partial,
-                     len, dparams, param_off_dev);
+  a.tiled_blocks = blocks;
+  const int total = a.vec_blocks + (blocks + 7) / 8 * 8;
+  if (total > 0)
+    hipLaunchKernelGGL(k_wgrad_net<T>, dim3(total), dim3(256), wgrad_lds_bytes<T>(), st, a);
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((part_len + 255) / 256), S), dim3(256), 0,
+                     st, gt, S, partial, part_len, dparams, param_off_dev);
 }
-template void launch_wgrad<float, float>(const GroupTable*, int, int, const float*, int, int,
-                                         const float*, int, int, int, float*, float*, const long*,
-                                         hipStream_t);
-template void launch_wgrad<bf16_t, bf16_t>(const GroupTable*, int, int, const bf16_t*, int, int,
-                                           const bf16_t*, int, int, int, float*, float*,
-                                           const long*, hipStream_t);
-template void launch_wgrad<float, bf16_t>(const GroupTable*, int, int, const float*, int, int,
-                                          const bf16_t*, int, int, int, float*, float*,
-                                          const long*, hipStream_t);
+template void launch_wgrad_net<float>(const GroupTable*, int, int, int, const WgradLayer*, int,
+                                      float*, float*, const long*, hipStream_t);
+template void launch_wgrad_net<bf16_t>(const GroupTable*, int, int, int, const WgradLayer*, int,
+                                       float*, float*, const long*, hipStream_t);
 
 // ------------------------------------------------------------ weight packing
 //

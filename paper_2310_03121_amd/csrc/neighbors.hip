@@ -33,17 +33,33 @@ __device__ __forceinline__ int make_key(int j, int s, bool ang) {
 }
 
 // Sorts the wave's keys [0, nr) by rank (keys are distinct) and writes the
-// row: indices to nbr, the matching displacement records to rec.
+// row: indices to nbr, the matching displacement records to rec.  Lists of at
+// most 64 keep one key per lane and count smaller keys with lane reads (no
+// LDS round trip per comparison), in groups of 16 up to nr; longer lists
+// compare against the LDS copy.
 __device__ __forceinline__ void finish_list(const int* key, const float4* lrec, int nr, int na,
                                             int i, int cap, int* __restrict__ nbr,
                                             float4* __restrict__ rec, int2* __restrict__ counts) {
   const int lane = lane_id();
-  for (int e = lane; e < nr; e += kWave) {
-    const int k = key[e];
+  if (nr <= kWave) {
+    const int k = lane < nr ? key[lane] : 0x7fffffff;
     int rank = 0;
-    for (int q = 0; q < nr; ++q) rank += key[q] < k;
-    nbr[(size_t)i * cap + rank] = k & kKeyJMask;
-    rec[(size_t)i * cap + rank] = lrec[e];
+    for (int g = 0; g < nr; g += 16) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) rank += __builtin_amdgcn_readlane(k, g + q) < k ? 1 : 0;
+    }
+    if (lane < nr) {
+      nbr[(size_t)i * cap + rank] = k & kKeyJMask;
+      rec[(size_t)i * cap + rank] = lrec[lane];
+    }
+  } else {
+    for (int e = lane; e < nr; e += kWave) {
+      const int k = key[e];
+      int rank = 0;
+      for (int q = 0; q < nr; ++q) rank += key[q] < k;
+      nbr[(size_t)i * cap + rank] = k & kKeyJMask;
+      rec[(size_t)i * cap + rank] = lrec[e];
+    }
   }
   if (lane == 0) counts[i] = make_int2(nr, na);
 }
@@ -181,13 +197,23 @@ __global__ __launch_bounds__(256) void k_cell_count(const int* __restrict__ dims
   __syncthreads();
   if (!is_last) return;
   __threadfence();
+  // Exclusive scan of the counts, 2,048 cells per pass: each thread loads its
+  // eight consecutive counts at once (one memory latency per pass, not one per
+  // 256 cells), scans their sums across the block and writes eight starts.
+  constexpr int kPer = 8;
   int carry = 0;
-  for (int c0 = 0; c0 < ncell; c0 += 256) {
-    const int c = c0 + t;
-    const int v = c < ncell ? __hip_atomic_load(&cell_cnt[c], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT)
+  for (int c0 = 0; c0 < ncell; c0 += 256 * kPer) {
+    const int cb = c0 + t * kPer;
+    int v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      v[q] = cb + q < ncell ? __hip_atomic_load(&cell_cnt[cb + q], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
                             : 0;
-    scan[t] = v;
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) sum += v[q];
+    scan[t] = sum;
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
       const int u = t >= o ? scan[t - o] : 0;
@@ -195,9 +221,14 @@ __global__ __launch_bounds__(256) void k_cell_count(const int* __restrict__ dims
       scan[t] += u;
       __syncthreads();
     }
-    if (c < ncell) {
-      start[c] = carry + scan[t] - v;
-      cursor[c] = carry + scan[t] - v;
+    int run = carry + scan[t] - sum;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (cb + q < ncell) {
+        start[cb + q] = run;
+        cursor[cb + q] = run;
+      }
+      run += v[q];
     }
     const int last = scan[255];
     __syncthreads();
