@@ -680,11 +680,12 @@ constexpr int kWgBO = 128, kWgBI = 128;
 template <typename T> struct WgLayout;
 template <> struct WgLayout<bf16_t> {
   static constexpr int BK = 64;                 // atom rows per stage
-  static constexpr int P = 80;                  // elements per LDS row (160 bytes)
+  static constexpr int P = 72;                  // elements per LDS row (144 bytes)
   static constexpr int TILE = 128 * P;          // elements per operand tile
-  static constexpr int ITEMS = BK * 16 / 256;   // 16-byte loads per thread and operand
+  // element (c, k): row c of the transposed tile (an output or input), atom
+  // row k of the stage; 8-row granules XOR-swizzled by (c / 16) % 8
   __device__ __forceinline__ static int off(int c, int k) {
-    return c * P + 8 * ((k >> 3) ^ ((c >> 3) & 7)) + (k & 7);
+    return c * P + 8 * ((k >> 3) ^ ((c >> 4) & 7)) + (k & 7);
   }
 };
 template <> struct WgLayout<float> {
@@ -703,24 +704,27 @@ constexpr size_t wgrad_lds_bytes() {
 // The MFMA partials of one (chunk, 128 o, 128 i) tile, as C[i][o] = sum_r
 // H[r][i] D[r][o] with K = the chunk's rows; four waves of 64 x 64 (4 x 4
 // MFMA tiles).  Every stage reads BK rows of D and H with coalesced 16-byte
-// loads (16 or 32 lanes per 256- or 512-byte row segment) into registers two
-// stages ahead of the one being multiplied, so two stages' loads are in
-// flight behind each stage's products.
+// loads into registers two stages ahead of the one being multiplied, so two
+// stages' loads are in flight behind each stage's products.  The loads go
+// through buffer resources that start at the stage's first row and end at
+// the chunk's last: rows past the chunk, and columns past the layer (sent out
+// of range), load as zeros, and no load sits behind a branch.
 //   FP32 (v_mfma_f32_16x16x4f32, one K element per lane): the rows stay
 //   row-major in LDS (144 floats per row, so the four K rows of a fragment
 //   fall in different banks), and a fragment is one 4-byte read per lane.
-//   BF16 (v_mfma_f32_16x16x32_bf16, eight consecutive K per lane): the tile is
-//   transposed on its way into LDS, one LDS row per output (or input) holding
-//   the stage's 64 atom rows, with the 16-byte granules of row c XOR-swizzled
-//   by (c / 8) % 8 and rows 160 bytes apart; lanes 16 apart hold atom rows r
-//   and r ^ 1 and swap them, so each 4-byte store writes an (r, r + 1) pair.
-//   Stores then meet at most two to a bank and the 16-byte fragment reads
-//   none (a CPU model of the layout checks every fragment).
+//   BF16 (v_mfma_f32_16x16x32_bf16, eight consecutive K per lane): waves 0-1
+//   stage D and waves 2-3 H; each thread loads an 8-row x 8-column block
+//   (eight 16-byte row pieces), transposes it in registers (byte permutes)
+//   and stores eight 16-byte column pieces, each one MFMA K granule, into a
+//   transposed tile: one LDS row per output (or input) holding the stage's
+//   64 atom rows, rows 144 bytes apart, granules XOR-swizzled by (c / 16) % 8.
+//   Then neither the stores nor the fragment reads meet two to a bank
+//   (16 lanes per pass of a 16-byte access, 64 banks; a CPU model of the
+//   layout checks every instruction).
 // Tiles at i = 0 also sum db: each thread adds the D columns it loads over
-// its rows in registers, and the sixteen (or eight) threads of a column group
-// are added in a fixed order at the end.  The accumulator layout leaves each
-// lane four consecutive i of one o, stored as one vector.
-
+// its rows in registers, and the threads of a column group are added in a
+// fixed order at the end.  The accumulator layout leaves each lane four
+// consecutive i of one o, stored as one vector.
 template <typename T>
 __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int Nout,
                                            const T* __restrict__ H, int ldh, int Nin, int r0,
@@ -729,30 +733,37 @@ __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int
                                            T* lds) {
   using L = WgLayout<T>;
   constexpr bool BF = sizeof(T) == 2;
-  constexpr int BK = L::BK, ITEMS = L::ITEMS;
-  constexpr int CPL = 16 / sizeof(T);       // columns per 16-byte load
-  constexpr int LPR = 128 / CPL;            // loads per 128-column row segment
+  constexpr int BK = L::BK;
+  constexpr int NL = 8;  // 16-byte loads per thread and stage
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wo = w >> 1, wi = w & 1;  // this wave's 64 x 64 tile
 
-  uint4 rd0[ITEMS], rh0[ITEMS], rd1[ITEMS], rh1[ITEMS];
-  float bsum[CPL];
+  // BF16: this thread's block (operand op, column group g, row block blk);
+  // FP32: item k is atom row (tid + 256 k) / 32 (both operands), columns
+  // 4 (tid % 32) .. + 3.
+  const int op = __builtin_amdgcn_readfirstlane(w >> 1);  // BF16: 0 stages D, 1 H
+  const int bu = tid & 127, bg = bu & 15, blk = bu >> 4;
+  unsigned offs[NL];
+  constexpr int NB = BF ? 8 : 4;  // columns per thread summed for db
+  float bsum[NB];
 #pragma unroll
-  for (int e = 0; e < CPL; ++e) bsum[e] = 0.f;
-  // Item k of this thread: atom row f / LPR of the stage, column group f % LPR
-  // (= tid % LPR for every k), at a byte offset that is the same in every
-  // stage.  Each stage reads through buffer resources that start at its first
-  // row and end at the chunk's last: rows past the chunk, and columns past
-  // the layer (sent out of range), load as zeros.
-  unsigned offd[ITEMS], offh[ITEMS];
+  for (int e = 0; e < NB; ++e) bsum[e] = 0.f;
+  if constexpr (BF) {
+    const int ld = op ? ldh : ldd, N = op ? Nin : Nout, c = (op ? i0 : o0) + 8 * bg;
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const int f = tid + 256 * k, r = f / LPR, g = f % LPR;
-    const int oc = o0 + g * CPL, ic = i0 + g * CPL;
-    offd[k] = oc < Nout ? (unsigned)((r * ldd + oc) * (int)sizeof(T)) : kOutOfRange;
-    offh[k] = ic < Nin ? (unsigned)((r * ldh + ic) * (int)sizeof(T)) : kOutOfRange;
+    for (int e = 0; e < NL; ++e)
+      offs[e] = c < N ? (unsigned)(((8 * blk + e) * ld + c) * 2) : kOutOfRange;
+  } else {
+    const int g = tid & 31, oc = o0 + 4 * g, ic = i0 + 4 * g;
+#pragma unroll
+    for (int k = 0; k < NL / 2; ++k) {
+      const int r = (tid >> 5) + 8 * k;
+      offs[k] = oc < Nout ? (unsigned)((r * ldd + oc) * 4) : kOutOfRange;
+      offs[NL / 2 + k] = ic < Nin ? (unsigned)((r * ldh + ic) * 4) : kOutOfRange;
+    }
   }
-  auto gload = [&](uint4 (&rd)[ITEMS], uint4 (&rh)[ITEMS], int rb) __attribute__((always_inline)) {
+  uint4 ra0[NL], ra1[NL];
+  auto gload = [&](uint4 (&ra)[NL], int rb) __attribute__((always_inline)) {
     // (uniform; read into a scalar register so that the resources are built
     // there and the loads need no per-lane resource loop)
     const int nr = __builtin_amdgcn_readfirstlane(r1 - rb < 0 ? 0 : (r1 - rb < BK ? r1 - rb : BK));
@@ -763,67 +774,61 @@ __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int
         const_cast<T*>(H + (size_t)rb * ldh), (short)0, nr * ldh * (int)sizeof(T),
         kBufferRsrcWord3);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const u32x4_t vd = __builtin_amdgcn_raw_buffer_load_b128(dsrc, offd[k], 0, 0);
-      const u32x4_t vh = __builtin_amdgcn_raw_buffer_load_b128(hsrc, offh[k], 0, 0);
-      rd[k] = make_uint4(vd[0], vd[1], vd[2], vd[3]);
-      rh[k] = make_uint4(vh[0], vh[1], vh[2], vh[3]);
+    for (int e = 0; e < NL; ++e) {
+      u32x4_t v;
+      if constexpr (BF)
+        v = __builtin_amdgcn_raw_buffer_load_b128(op ? hsrc : dsrc, offs[e], 0, 0);
+      else
+        v = __builtin_amdgcn_raw_buffer_load_b128(e < NL / 2 ? dsrc : hsrc, offs[e], 0, 0);
+      ra[e] = make_uint4(v[0], v[1], v[2], v[3]);
     }
   };
-  auto addbias = [&](const uint4 (&rd)[ITEMS]) __attribute__((always_inline)) {
+  auto addbias = [&](const uint4 (&ra)[NL]) __attribute__((always_inline)) {
+    if constexpr (BF) {
+      if (op != 0) return;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const unsigned u[4] = {rd[k].x, rd[k].y, rd[k].z, rd[k].w};
+      for (int e = 0; e < NL; ++e) {
+        const unsigned u[4] = {ra[e].x, ra[e].y, ra[e].z, ra[e].w};
 #pragma unroll
-      for (int e = 0; e < CPL; ++e) {
-        if constexpr (BF)
-          bsum[e] += __uint_as_float((e & 1) ? (u[e >> 1] & 0xffff0000u) : (u[e >> 1] << 16));
-        else
-          bsum[e] += __uint_as_float(u[e]);
+        for (int c = 0; c < 8; ++c)
+          bsum[c] += __uint_as_float((c & 1) ? (u[c >> 1] & 0xffff0000u) : (u[c >> 1] << 16));
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < NL / 2; ++k) {
+        bsum[0] += __uint_as_float(ra[k].x);
+        bsum[1] += __uint_as_float(ra[k].y);
+        bsum[2] += __uint_as_float(ra[k].z);
+        bsum[3] += __uint_as_float(ra[k].w);
       }
     }
   };
-  auto lstore = [&](const uint4 (&rd)[ITEMS], const uint4 (&rh)[ITEMS], int buf)
-                    __attribute__((always_inline)) {
+  auto lstore = [&](const uint4 (&ra)[NL], int buf) __attribute__((always_inline)) {
     T* dt = lds + (size_t)buf * 2 * L::TILE;
-    T* ht = dt + L::TILE;
+    if constexpr (BF) {
+      // column c of the block: (row 2q, row 2q + 1) pairs from the low
+      // (c even) or high (c odd) halves of dword c / 2 of rows 2q and 2q + 1
+      T* tile = dt + op * L::TILE;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const int f = tid + 256 * k, r = f / LPR, g = f % LPR;
-      if constexpr (BF) {
-        // lanes 16 apart hold rows r and r ^ 1 of the same columns
-        uint4 od, oh;
-        od.x = __shfl_xor(rd[k].x, 16, 64); od.y = __shfl_xor(rd[k].y, 16, 64);
-        od.z = __shfl_xor(rd[k].z, 16, 64); od.w = __shfl_xor(rd[k].w, 16, 64);
-        oh.x = __shfl_xor(rh[k].x, 16, 64); oh.y = __shfl_xor(rh[k].y, 16, 64);
-        oh.z = __shfl_xor(rh[k].z, 16, 64); oh.w = __shfl_xor(rh[k].w, 16, 64);
-        const bool odd = r & 1;
-        // even rows write columns 0..3 of the group, odd rows columns 4..7;
-        // lo = the even row's element, hi = the odd row's
-        const unsigned md[4] = {rd[k].x, rd[k].y, rd[k].z, rd[k].w};
-        const unsigned pd[4] = {od.x, od.y, od.z, od.w};
-        const unsigned mh[4] = {rh[k].x, rh[k].y, rh[k].z, rh[k].w};
-        const unsigned ph[4] = {oh.x, oh.y, oh.z, oh.w};
-        const int kr = r & ~1;
+      for (int c = 0; c < 8; ++c) {
+        const unsigned sel = (c & 1) ? 0x07060302u : 0x05040100u;
+        unsigned q[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int col = g * 8 + e + (odd ? 4 : 0);
-          // dword (e + (odd ? 4 : 0)) / 2 of each operand, selected without
-          // a run-time array index (which would put the arrays in scratch)
-          const int lo = e >> 1, hi4 = lo + 2;
-          const bool hi = (e & 1);                 // which half of it
-          const unsigned ev_d = odd ? pd[hi4] : md[lo], od_d = odd ? md[hi4] : pd[lo];
-          const unsigned ev_h = odd ? ph[hi4] : mh[lo], od_h = odd ? mh[hi4] : ph[lo];
-          const unsigned vd = hi ? ((ev_d >> 16) | (od_d & 0xffff0000u))
-                                 : ((ev_d & 0xffffu) | (od_d << 16));
-          const unsigned vh = hi ? ((ev_h >> 16) | (od_h & 0xffff0000u))
-                                 : ((ev_h & 0xffffu) | (od_h << 16));
-          *reinterpret_cast<unsigned*>(dt + L::off(col, kr)) = vd;
-          *reinterpret_cast<unsigned*>(ht + L::off(col, kr)) = vh;
+        for (int h = 0; h < 4; ++h) {
+          const uint4 a = ra[2 * h], b = ra[2 * h + 1];
+          const unsigned ua[4] = {a.x, a.y, a.z, a.w}, ub[4] = {b.x, b.y, b.z, b.w};
+          q[h] = __builtin_amdgcn_perm(ub[c >> 1], ua[c >> 1], sel);
         }
-      } else {
-        *reinterpret_cast<uint4*>(dt + r * L::RS + g * 4) = rd[k];
-        *reinterpret_cast<uint4*>(ht + r * L::RS + g * 4) = rh[k];
+        *reinterpret_cast<uint4*>(tile + L::off(8 * bg + c, 8 * blk)) =
+            make_uint4(q[0], q[1], q[2], q[3]);
+      }
+    } else {
+      T* ht = dt + L::TILE;
+#pragma unroll
+      for (int k = 0; k < NL / 2; ++k) {
+        const int r = (tid >> 5) + 8 * k, g = tid & 31;
+        *reinterpret_cast<uint4*>(dt + r * L::RS + g * 4) = ra[k];
+        *reinterpret_cast<uint4*>(ht + r * L::RS + g * 4) = ra[NL / 2 + k];
       }
     }
   };
@@ -840,12 +845,12 @@ __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           const int ci = wi * 64 + x * 16 + (lane & 15);
-          fa[x] = *reinterpret_cast<const uint4*>(ht + ci * L::P + 8 * (j ^ ((ci >> 3) & 7)));
+          fa[x] = *reinterpret_cast<const uint4*>(ht + L::off(ci, 8 * j));
         }
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
           const int co = wo * 64 + y * 16 + (lane & 15);
-          fb[y] = *reinterpret_cast<const uint4*>(dt + co * L::P + 8 * (j ^ ((co >> 3) & 7)));
+          fb[y] = *reinterpret_cast<const uint4*>(dt + L::off(co, 8 * j));
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x)
@@ -876,22 +881,22 @@ __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int
   // chunk read an empty range (zeros, which add nothing), so no load sits
   // behind a branch and each wait covers exactly the set it needs.
   const int nst = (r1 - r0 + 2 * BK - 1) / (2 * BK) * 2;
-  gload(rd0, rh0, r0);
-  gload(rd1, rh1, r0 + BK);
-  if (bias) addbias(rd0);
-  lstore(rd0, rh0, 0);
-  gload(rd0, rh0, r0 + 2 * BK);
+  gload(ra0, r0);
+  gload(ra1, r0 + BK);
+  if (bias) addbias(ra0);
+  lstore(ra0, 0);
+  gload(ra0, r0 + 2 * BK);
   __syncthreads();
   for (int st = 0; st < nst; st += 2) {
     compute(0);
-    if (bias) addbias(rd1);
-    lstore(rd1, rh1, 1);
-    gload(rd1, rh1, r0 + (st + 3) * BK);
+    if (bias) addbias(ra1);
+    lstore(ra1, 1);
+    gload(ra1, r0 + (st + 3) * BK);
     __syncthreads();
     compute(1);
-    if (bias) addbias(rd0);
-    lstore(rd0, rh0, 0);
-    gload(rd0, rh0, r0 + (st + 4) * BK);
+    if (bias) addbias(ra0);
+    lstore(ra0, 0);
+    gload(ra0, r0 + (st + 4) * BK);
     __syncthreads();
   }
   // acc[x][y][e]: i = i0 + wi 64 + x 16 + 4 (lane / 16) + e, o = o0 + wo 64 + y 16 + lane % 16
@@ -909,15 +914,23 @@ __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int
     }
   }
   if (bias) {
-    // the LDS tiles are free after the loop's last barrier
-    float* red = reinterpret_cast<float*>(lds);  // [256 / LPR][128]
-    const int g = tid % LPR;
+    // the LDS tiles are free after the loop's last barrier; red[q][o] holds
+    // the column sums of the q-th group of threads covering output o
+    float* red = reinterpret_cast<float*>(lds);
+    constexpr int NG = BF ? 8 : 8;
+    if constexpr (BF) {
+      if (op == 0) {
 #pragma unroll
-    for (int e = 0; e < CPL; ++e) red[(tid / LPR) * 128 + g * CPL + e] = bsum[e];
+        for (int c = 0; c < 8; ++c) red[blk * 128 + 8 * bg + c] = bsum[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[(tid >> 5) * 128 + 4 * (tid & 31) + c] = bsum[c];
+    }
     __syncthreads();
     if (tid < 128 && o0 + tid < Nout) {
       float v = 0.f;
-      for (int q = 0; q < 256 / LPR; ++q) v += red[q * 128 + tid];
+      for (int q = 0; q < NG; ++q) v += red[q * 128 + tid];
       bout[o0 + tid] = v;
     }
   }
