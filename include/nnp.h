@@ -159,6 +159,22 @@ nnp_status nnp_set_max_neighbors(nnp_handle* h, int32_t max_neighbors);
  * a cell not in reduced form).  Atoms are binned in fractional coordinates. */
 nnp_status nnp_set_triclinic(nnp_handle* h, int32_t on);
 
+/* Force accumulation order of every later call on this handle.  Forces are
+ * the negative energy gradient (Methods, "PyTorch Model Support"); how the
+ * per-pair terms are summed is this library's choice.
+ * on == 0 (default): each atom's adjoint adds its neighbors' terms with
+ * floating-point atomics, so the last bits of a force depend on scheduling.
+ * on != 0 (deterministic gather mode): one atom per wave in the symmetry-
+ * function kernels; the adjoint writes each atom's dE_i/d(displacement) per
+ * neighbor entry to the workspace (n_atoms x capacity x 16 more bytes, in
+ * nnp_workspace_bytes), and a gather forms the force on atom a as the sum,
+ * in a's neighbor-list order, of its own entries minus the matching entries
+ * of its neighbors' lists.  Every energy and force is then a function of its
+ * molecule alone: the same bits in any batch, any position, any run.  It is
+ * slower and meant for debugging and reproducibility checks.  Graphs keep
+ * the mode they were captured with.  NNP_E_INVALID for a null handle. */
+nnp_status nnp_set_deterministic(nnp_handle* h, int32_t on);
+
 /* Bytes of workspace an evaluation of this shape needs.  `box` is host memory
  * (3 floats) or NULL, as for nnp_energy_forces.  Returns 0 for invalid shapes. */
 size_t nnp_workspace_bytes(const nnp_handle* h, int32_t n_atoms, int32_t n_mol,

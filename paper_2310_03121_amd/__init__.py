@@ -41,7 +41,8 @@ class Potential:
 
     def __init__(self, *, n_species, rc_rad, eta_r, shf_r, rc_ang, eta_a, zeta, shf_a, shf_z,
                  widths, params, celu_alpha=0.1, self_energy=None, radial_prefactor=0.25,
-                 angle_cos_scale=0.95, precision="fp32", max_neighbors=128, triclinic=False):
+                 angle_cos_scale=0.95, precision="fp32", max_neighbors=128, triclinic=False,
+                 deterministic=False):
         self._lib = capi.lib()
         self.n_species = int(n_species)
         self.widths = tuple(int(w) for w in widths)
@@ -83,6 +84,13 @@ class Potential:
         if self.triclinic:
             capi.check(self._lib.nnp_set_triclinic(h, 1), "set_triclinic")
         self._ws = None
+        self.set_deterministic(deterministic)
+
+    def set_deterministic(self, on: bool):
+        """Deterministic gather mode for the forces (nnp_set_deterministic)."""
+        self.deterministic = bool(on)
+        capi.check(self._lib.nnp_set_deterministic(self._h, int(self.deterministic)),
+                   "set_deterministic")
 
     @classmethod
     def from_tables(cls, aev, mlp, precision="fp32", **kw):

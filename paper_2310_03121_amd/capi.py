@@ -55,6 +55,7 @@ _SIGS = [
     ("nnp_set_params_device", C.c_int, [_P, _P, _P]),
     ("nnp_set_max_neighbors", C.c_int, [_P, _I]),
     ("nnp_set_triclinic", C.c_int, [_P, _I]),
+    ("nnp_set_deterministic", C.c_int, [_P, _I]),
     ("nnp_workspace_bytes", C.c_size_t, [_P, _I, _I, _P]),
     ("nnp_energy_forces", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     ("nnp_energy_forces_noalloc", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P]),

@@ -349,8 +349,10 @@ __device__ __forceinline__ void adjoint_setup(int slot, const float4 q, bool ang
 
 // The radial and angular passes of one atom (nr neighbors, the first na
 // angular, set up in nd, nf, nsp): dE/d(displacement) of every neighbor
-// entry into grad (the radial pass stores, the angular pass adds).
-template <typename GT>
+// entry into grad (the radial pass stores, the angular pass adds).  Det: the
+// angular pass adds its eight pairs' terms one pair after the other, in pair
+// order, instead of with LDS atomics, so every entry's sum has a fixed order.
+template <typename GT, bool Det = false>
 __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C,
                                                const GT* __restrict__ grow, const float4* nd,
                                                const float4* nf, float4* grad, const int* nsp) {
@@ -429,12 +431,30 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
         const float aj = (dEdj - dEdc * cs * rj) * rj;
         const float ak = (dEdk - dEdc * cs * rk) * rk;
         const float bb = dEdc * rj * rk;
-        atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
-        atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
-        atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
-        atomicAdd(&grad[ek].x, ak * vk.x + bb * vj.x);
-        atomicAdd(&grad[ek].y, ak * vk.y + bb * vj.y);
-        atomicAdd(&grad[ek].z, ak * vk.z + bb * vj.z);
+        if constexpr (!Det) {
+          atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
+          atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
+          atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
+          atomicAdd(&grad[ek].x, ak * vk.x + bb * vj.x);
+          atomicAdd(&grad[ek].y, ak * vk.y + bb * vj.y);
+          atomicAdd(&grad[ek].z, ak * vk.z + bb * vj.z);
+        } else {
+          for (int q = 0; q < 8; ++q) {
+            if (tg == q) {
+              float4 a = grad[ej];
+              a.x += aj * vj.x + bb * vk.x;
+              a.y += aj * vj.y + bb * vk.y;
+              a.z += aj * vj.z + bb * vk.z;
+              grad[ej] = a;
+              float4 b = grad[ek];
+              b.x += ak * vk.x + bb * vj.x;
+              b.y += ak * vk.y + bb * vj.y;
+              b.z += ak * vk.z + bb * vj.z;
+              grad[ek] = b;
+            }
+            wave_lds_sync();
+          }
+        }
       }
     }
   }
@@ -684,6 +704,43 @@ __global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, A
                     });
 }
 
+// Deterministic adjoint (gather mode): one atom per wave, as above, but the
+// atom's dE/d(displacement) of every neighbor entry goes to pgrad[i * cap +
+// e] instead of being scattered; a gather forms the forces from these rows
+// (neighbors.hip).  Blocks from nb_adj on sum the molecular energies.
+template <typename GT>
+__global__ __launch_bounds__(256) void k_aev_bwd_det(const int* __restrict__ dims, AevConst C,
+                                                     const float4* __restrict__ rec,
+                                                     const int2* __restrict__ counts, int cap,
+                                                     const int* __restrict__ row_of,
+                                                     const GT* __restrict__ g, int ldg,
+                                                     float4* __restrict__ pgrad, int nb_adj,
+                                                     EnergyArgs EA) {
+  extern __shared__ float4 lds4[];
+  if ((int)blockIdx.x >= nb_adj) {  // block-uniform: the molecular energy sums
+    energy_block((int)blockIdx.x - nb_adj, dims, EA);
+    return;
+  }
+  const int n = dims[0];
+  const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int i = (int)blockIdx.x * 4 + w;
+  if (i >= n) return;
+  const int lane = lane_id();
+  const int reg = aev_region(cap);
+  float4* nd = lds4 + (size_t)w * reg * 3;
+  float4* nf = nd + reg;
+  float4* grad = nd + 2 * reg;
+  int* nsp = reinterpret_cast<int*>(lds4 + (size_t)4 * reg * 3) + w * reg;
+  const int2 cn = counts[i];
+  const int nr = cn.x < 0 ? 0 : (cn.x > cap ? cap : cn.x);
+  const int na = cn.y < 0 ? 0 : (cn.y > nr ? nr : cn.y);
+  const float4* arec = rec + (size_t)i * cap;
+  for (int e = lane; e < nr; e += kWave) adjoint_setup(e, arec[e], e < na, C, nd, nf, nsp);
+  wave_lds_sync();
+  adjoint_passes<GT, true>(nr, na, C, g + (size_t)row_of[i] * ldg, nd, nf, grad, nsp);
+  for (int e = lane; e < nr; e += kWave) pgrad[(size_t)i * cap + e] = grad[e];
+}
+
 // Molecules (no box, no index map): a workgroup owns the kMolBlock atoms
 // [b * kMolBlock, (b + 1) * kMolBlock), its waves taking them in turn, and
 // adds every force into an LDS window over the atoms [b - 1, b + 2) *
@@ -778,18 +835,19 @@ static void launch_aev_fwd_q(const int* dims, int n_cap, const AevConst& C, cons
 
 template <typename OutT>
 void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
-                    const int2* counts, int cap, const int* row_of, OutT* out, int ld,
+                    const int2* counts, int cap, const int* row_of, OutT* out, int ld, bool det,
                     hipStream_t st) {
   if (n_cap <= 0) return;
-  if (aev_quads(cap))
+  if (aev_quads(cap) && !det)
     launch_aev_fwd_q<OutT, 4>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, st);
   else
     launch_aev_fwd_q<OutT, 1>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, st);
 }
 template void launch_aev_fwd<float>(const int*, int, const AevConst&, const float4*, const int2*,
-                                    int, const int*, float*, int, hipStream_t);
+                                    int, const int*, float*, int, bool, hipStream_t);
 template void launch_aev_fwd<bf16_t>(const int*, int, const AevConst&, const float4*,
-                                     const int2*, int, const int*, bf16_t*, int, hipStream_t);
+                                     const int2*, int, const int*, bf16_t*, int, bool,
+                                     hipStream_t);
 
 template <typename GT, int Q>
 static void launch_aev_bwd_q(const int* dims, int n_cap, const AevConst& C, const float4* rec,
@@ -825,8 +883,20 @@ template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
                     int ldg, float* out, float sign, const int* gidx, int n_total,
-                    const int2* mrange, const EnergyArgs* energy, int nmol_cap,
+                    const int2* mrange, const EnergyArgs* energy, int nmol_cap, float4* pgrad,
                     hipStream_t st) {
+  if (pgrad) {
+    const int nb_e = energy && energy->E && nmol_cap > 0 ? nmol_cap : 0;
+    const EnergyArgs ea = nb_e ? *energy : EnergyArgs{};
+    const int nb_adj = n_cap > 0 ? (n_cap + 3) / 4 : 0;
+    if (nb_adj + nb_e == 0) return;
+    const size_t lds = (size_t)4 * aev_region(cap) * kBwdBytesPerNbr;
+    static const bool attr = (ensure_lds(k_aev_bwd_det<GT>), true);
+    (void)attr;
+    hipLaunchKernelGGL((k_aev_bwd_det<GT>), dim3(nb_adj + nb_e), dim3(256), lds, st, dims, C,
+                       rec, counts, cap, row_of, g, ldg, pgrad, nb_adj, ea);
+    return;
+  }
   if (aev_quads(cap))
     launch_aev_bwd_q<GT, 4>(dims, n_cap, C, rec, nbr, counts, cap, row_of, g, ldg, out, sign,
                             gidx, n_total, mrange, energy, nmol_cap, st);
@@ -836,11 +906,11 @@ void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4*
 }
 template void launch_aev_bwd<float>(const int*, int, const AevConst&, const float4*, const int*,
                                     const int2*, int, const int*, const float*, int, float*, float,
-                                    const int*, int, const int2*, const EnergyArgs*, int,
+                                    const int*, int, const int2*, const EnergyArgs*, int, float4*,
                                     hipStream_t);
 template void launch_aev_bwd<bf16_t>(const int*, int, const AevConst&, const float4*, const int*,
                                      const int2*, int, const int*, const bf16_t*, int, float*,
                                      float, const int*, int, const int2*, const EnergyArgs*, int,
-                                     hipStream_t);
+                                     float4*, hipStream_t);
 
 }  // namespace nnp

@@ -34,6 +34,7 @@ struct nnp_handle {
   float alpha = 0.1f;
   int max_nbr = 128;
   bool triclinic = false;               // box arguments are 9 floats (cell rows)
+  bool deterministic = false;           // forces by gather (no floating-point atomics)
   int n_models = 1;                     // ensemble members (weight slot = member * S + element)
   size_t n_params = 0;                  // all members
   long param_off[kMaxModels * kMaxS][kLayers] = {};  // flat offset of W for (slot, layer)
@@ -146,6 +147,7 @@ struct Plan {
   size_t status, dims, gt, xyzs, mol, mrange, row, perm, hist, nbr, counts, rec;
   size_t cell_of, cell_cnt, cell_start, cursor, cell_atoms, cell_xyzs;
   size_t X, H1, H2, H3, D3, D2, D1, G, erow, uprow, wpart, pos32;
+  size_t pgrad;  // deterministic mode: per-entry adjoint rows [n][cap]
 };
 
 bool make_box(const nnp_handle* h, const float* box, BoxConst& B) {
@@ -244,6 +246,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B, bool wgr
   P.nbr = take(N * P.cap * 4);
   P.counts = take(N * 8);
   P.rec = take(N * P.cap * 16);
+  P.pgrad = h->deterministic ? take(N * P.cap * 16) : 0;
   if (B.periodic) {
     P.cell_of = take(N * 4);
     P.cell_cnt = take((size_t)(P.ncell + 1) * 4);  // counts, then the binning's done counter
@@ -354,7 +357,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
   T* X = at<T>(ws, P.X);
   {
     StageTimer t(h, io.timed, ST_AEV, st);
-    launch_aev_fwd<T>(dims, P.n, h->C, rec, counts, P.cap, row, X, Fp, st);
+    launch_aev_fwd<T>(dims, P.n, h->C, rec, counts, P.cap, row, X, Fp, h->deterministic, st);
   }
 
   T* H1 = at<T>(ws, P.H1);
@@ -561,8 +564,12 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       ok &= launch_gemm<T>(EPI_OUT, g, P.rows_cap, st);
     }
     StageTimer t(h, io.timed, ST_AEVBWD, st);
+    float4* pgrad = h->deterministic ? at<float4>(ws, P.pgrad) : nullptr;
     launch_aev_bwd<T>(dims, P.n, h->C, rec, nbr, counts, P.cap, row, G, Fp, io.out3, io.sign,
-                      io.gidx, io.n_total, mrange, &ea, P.nmol, st);
+                      io.gidx, io.n_total, mrange, &ea, P.nmol, pgrad, st);
+    if (pgrad)
+      launch_force_gather(dims, P.n, xyzs, rec, nbr, counts, P.cap, pgrad, io.out3, io.sign,
+                          io.gidx, io.n_total, st);
   }
   if (io.dparams) {
     StageTimer t(h, io.timed, ST_WGRAD, st);
@@ -878,6 +885,12 @@ nnp_status nnp_set_triclinic(nnp_handle* h, int32_t on) {
   return NNP_OK;
 }
 
+nnp_status nnp_set_deterministic(nnp_handle* h, int32_t on) {
+  if (!h) return NNP_E_INVALID;
+  h->deterministic = on != 0;
+  return NNP_OK;
+}
+
 nnp_status nnp_set_max_neighbors(nnp_handle* h, int32_t m) {
   if (!h || m < 16 || m > 512) return NNP_E_INVALID;
   h->max_nbr = (m + 15) / 16 * 16;  // keeps the per-wave LDS regions 16-byte aligned
@@ -1031,7 +1044,7 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
     launch_pairs_mol(dims, P.n, h->C, xyzs, mrange, P.cap, at<int>(ws, P.nbr),
                      at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
   launch_aev_fwd<float>(dims, P.n, h->C, at<float4>(ws, P.rec), at<int2>(ws, P.counts), P.cap,
-                        nullptr, aev, h->F, st);
+                        nullptr, aev, h->F, h->deterministic, st);
   return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
 }
 

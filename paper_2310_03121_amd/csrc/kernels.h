@@ -142,17 +142,30 @@ void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxC
                        const float4* xyzs, int* cell_of, int* cell_cnt, int* cell_start,
                        int* cursor, int* cell_atoms, float4* cell_xyzs, int cap, int* nbr,
                        float4* rec, int2* counts, uint32_t* status, hipStream_t st);
+// Deterministic forces from the adjoint's per-entry rows pgrad ([n][cap],
+// dE_i/d(displacement of entry e)): atom a's row out[gidx ? gidx[a] : a] +=
+// sign * sum over a's entries e, in list order, of pgrad[a][e] -
+// pgrad[j_e][slot of a in j_e's list] (the lists are symmetric; the slot is
+// found by binary search on the sort key).  One wave per atom; each row is
+// added to once (no atomics).
+void launch_force_gather(const int* dims, int n_cap, const float4* xyzs, const float4* rec,
+                         const int* nbr, const int2* counts, int cap, const float4* pgrad,
+                         float* out, float sign, const int* gidx, int n_total, hipStream_t st);
 
 // aev.hip
+// det: one atom per wave whatever the capacity (the order of every sum is
+// then a function of the atom's own list only)
 template <typename OutT>
 void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
-                    const int2* counts, int cap, const int* row_of, OutT* out, int ld,
+                    const int2* counts, int cap, const int* row_of, OutT* out, int ld, bool det,
                     hipStream_t st);
+// pgrad: the deterministic adjoint, writing per-entry rows to pgrad (the
+// caller then runs launch_force_gather) instead of scattering into out
 template <typename GT>
 void launch_aev_bwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int* nbr, const int2* counts, int cap, const int* row_of, const GT* g,
                     int ldg, float* out, float sign, const int* gidx, int n_total,
-                    const int2* mrange, const EnergyArgs* energy, int nmol_cap,
+                    const int2* mrange, const EnergyArgs* energy, int nmol_cap, float4* pgrad,
                     hipStream_t st);
 
 // mlp.hip

@@ -392,6 +392,75 @@ __global__ __launch_bounds__(1024) void k_pairs_cell_lds(
   }
 }
 
+// ------------------------------------------------------------ force gather
+
+// Sort key of entry q of atom j's list (the key its row was ordered by).
+__device__ __forceinline__ int entry_key(const int* __restrict__ nbr,
+                                         const float4* __restrict__ rec, int j, int q, int na,
+                                         int cap) {
+  const size_t o = (size_t)j * cap + q;
+  return make_key(nbr[o] & kKeyJMask, species_of(rec[o]), q < na);
+}
+
+__global__ __launch_bounds__(256) void k_force_gather(
+    const int* __restrict__ dims, const float4* __restrict__ xyzs, const float4* __restrict__ rec,
+    const int* __restrict__ nbr, const int2* __restrict__ counts, int cap,
+    const float4* __restrict__ pgrad, float* __restrict__ out, float sign,
+    const int* __restrict__ gidx, int n_total) {
+  const int n = dims[0];
+  const int a = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+  if (a >= n) return;
+  const int lane = lane_id();
+  const int2 ca = counts[a];
+  const int nr = ca.x < 0 ? 0 : (ca.x > cap ? cap : ca.x);
+  const int na = ca.y < 0 ? 0 : (ca.y > nr ? nr : ca.y);
+  const int sa = species_of(xyzs[a]);
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  for (int e = lane; e < nr; e += kWave) {
+    const int j = clampi(nbr[(size_t)a * cap + e], n);
+    // the same pair seen from j: same distance, so the same angular flag
+    const int key = make_key(a, sa, e < na);
+    const int2 cj = counts[j];
+    const int nrj = cj.x < 0 ? 0 : (cj.x > cap ? cap : cj.x);
+    const int naj = cj.y < 0 ? 0 : (cj.y > nrj ? nrj : cj.y);
+    int lo = 0, hi = nrj;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (entry_key(nbr, rec, j, mid, naj, cap) < key) lo = mid + 1; else hi = mid;
+    }
+    const float4 own = pgrad[(size_t)a * cap + e];
+    float4 oth = make_float4(0.f, 0.f, 0.f, 0.f);
+    // (absent only when a list was cut at capacity, which the status reports)
+    if (lo < nrj && entry_key(nbr, rec, j, lo, naj, cap) == key) oth = pgrad[(size_t)j * cap + lo];
+    fx += own.x - oth.x;
+    fy += own.y - oth.y;
+    fz += own.z - oth.z;
+  }
+  fx = wave_sum_rows(fx);
+  fy = wave_sum_rows(fy);
+  fz = wave_sum_rows(fz);
+  if (lane == 0) {
+    int row = a;
+    if (gidx) {
+      row = gidx[a];
+      if (row < 0 || row >= n_total) return;
+    }
+    // added, as the scatter adds (staging zeroed the rows of a whole-system
+    // call; a subset call adds to the caller's rows, each written once)
+    out[3 * (size_t)row] += sign * fx;
+    out[3 * (size_t)row + 1] += sign * fy;
+    out[3 * (size_t)row + 2] += sign * fz;
+  }
+}
+
+void launch_force_gather(const int* dims, int n_cap, const float4* xyzs, const float4* rec,
+                         const int* nbr, const int2* counts, int cap, const float4* pgrad,
+                         float* out, float sign, const int* gidx, int n_total, hipStream_t st) {
+  if (n_cap <= 0) return;
+  hipLaunchKernelGGL(k_force_gather, dim3((n_cap + 3) / 4), dim3(256), 0, st, dims, xyzs, rec,
+                     nbr, counts, cap, pgrad, out, sign, gidx, n_total);
+}
+
 // ----------------------------------------------------------------- launchers
 
 void launch_pairs_mol(const int* dims, int n_cap, const AevConst& C, const float4* xyzs,
