@@ -260,10 +260,12 @@ __global__ __launch_bounds__(256) void k_cell_fill(const int* __restrict__ dims,
 // candidates reads them from global memory (the same arithmetic).
 constexpr int kCandLds = 1024;
 
-// Waves per cell workgroup: about one per atom of a liquid-density cell
-// (17 at the large box's cells), as LDS allows.
+// Waves per cell workgroup: about two atoms each at liquid density (17 per
+// cell in the large box).  Measured there: 16 waves 55.8 us (most waves take
+// one atom, and the workgroup holds its LDS until its slowest wave ends),
+// 8 waves 47.4 us, 4 waves 58.9 us.
 __host__ __device__ constexpr int pairs_cell_waves(int cap) {
-  return cap <= 128 ? 16 : (cap <= 256 ? 8 : 4);
+  return cap <= 128 ? 8 : 4;
 }
 
 __host__ __device__ constexpr size_t pairs_cell_lds_bytes(int cap) {
