@@ -393,6 +393,8 @@ nnp_status nnp_server_create(nnp_handle* h, size_t hbm_budget_bytes,
                              int32_t max_atoms, int32_t max_mols, double dt_fs,
                              const double* mass_amu /* host, [n_species] */,
                              void* stream, nnp_server** out);
+/* The handle must outlive the server's calls; nnp_server_destroy does not
+ * read it (it may run after nnp_destroy of the handle). */
 void nnp_server_destroy(nnp_server* s);
 
 /* Switches the server from velocity Verlet to LF-Middle Langevin dynamics

@@ -333,6 +333,65 @@ constexpr int kMolBlock = 64;
 // forward pass measured no gain.
 constexpr int kBwdBytesPerNbr = 16 + 16 + 16 + 4;
 
+// Sixteen consecutive dE/dG values (one radial species block) as floats.
+template <typename GT> struct Load16;
+template <> struct Load16<float> {
+  __device__ __forceinline__ static void get(const float* p, float (&v)[16]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 u = reinterpret_cast<const float4*>(p)[q];
+      v[4 * q] = u.x;
+      v[4 * q + 1] = u.y;
+      v[4 * q + 2] = u.z;
+      v[4 * q + 3] = u.w;
+    }
+  }
+};
+template <> struct Load16<bf16_t> {
+  __device__ __forceinline__ static void get(const bf16_t* p, float (&v)[16]) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint4 u = reinterpret_cast<const uint4*>(p)[q];
+      const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[8 * q + 2 * k] = __uint_as_float(w[k] << 16);
+        v[8 * q + 2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+      }
+    }
+  }
+};
+
+// The 32 dE/dG values of one angular pair block (four distance shifts x
+// eight angle shifts, a-major) as floats.
+template <typename GT> struct Load32;
+template <> struct Load32<float> {
+  __device__ __forceinline__ static void get(const float* p, float (&v)[32]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float4 u = reinterpret_cast<const float4*>(p)[q];
+      v[4 * q] = u.x;
+      v[4 * q + 1] = u.y;
+      v[4 * q + 2] = u.z;
+      v[4 * q + 3] = u.w;
+    }
+  }
+};
+template <> struct Load32<bf16_t> {
+  __device__ __forceinline__ static void get(const bf16_t* p, float (&v)[32]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint4 u = reinterpret_cast<const uint4*>(p)[q];
+      const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[8 * q + 2 * k] = __uint_as_float(w[k] << 16);
+        v[8 * q + 2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+      }
+    }
+  }
+};
+
 // One neighbor entry of the adjoint's LDS region: displacement and
 // distance, cutoff values and derivatives, species.
 __device__ __forceinline__ void adjoint_setup(int slot, const float4 q, bool ang,
@@ -349,15 +408,41 @@ __device__ __forceinline__ void adjoint_setup(int slot, const float4 q, bool ang
 
 // The radial and angular passes of one atom (nr neighbors, the first na
 // angular, set up in nd, nf, nsp): dE/d(displacement) of every neighbor
-// entry into grad (the radial pass stores, the angular pass adds).  Det: the
-// angular pass adds its eight pairs' terms one pair after the other, in pair
-// order, instead of with LDS atomics, so every entry's sum has a fixed order.
-template <typename GT, bool Det = false>
+// entry into grad (the radial pass stores, the angular pass adds).  The
+// angular pass takes one of three forms (Mode):
+//   kAngPairLanes: one lane per pair, 64 pairs per pass (long lists: the
+//     pair's shared terms are computed once, not in eight lanes), and one
+//     lane per neighbor entry in the radial pass;
+//   kAngShiftLanes: eight lanes per pair (one per angle shift), eight pairs
+//     per pass, fewer registers (the fallback of the four-atom kernels);
+//   kAngShiftLanesOrdered: the same, adding the pass's eight pairs' terms one
+//     pair after the other instead of with LDS atomics, so that every
+//     entry's sum has a fixed order (deterministic mode).
+constexpr int kAngPairLanes = 0, kAngShiftLanes = 1, kAngShiftLanesOrdered = 2;
+template <typename GT, int Mode>
 __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C,
                                                const GT* __restrict__ grow, const float4* nd,
                                                const float4* nf, float4* grad, const int* nsp) {
   const int lane = lane_id();
   const int S = C.S;
+  if constexpr (Mode == kAngPairLanes) {
+    // ---- radial: one lane per neighbor entry, its 16 shifts against the 16
+    // dE/dG values of its species block (two vector loads)
+    for (int e = lane; e < nr; e += kWave) {
+      const float4 v = nd[e];
+      const float4 f = nf[e];
+      float gv[16];
+      Load16<GT>::get(grow + nsp[e] * kNR, gv);
+      float acc = 0.f;
+#pragma unroll
+      for (int m = 0; m < kNR; ++m) {
+        const float u = v.w - C.shf_r[m];
+        acc += gv[m] * fast_exp2(-C.eta_r_l2e * u * u) * (f.z - C.eta_r2 * u * f.x);
+      }
+      const float sc = C.cR * acc * fast_rcp(v.w);
+      grad[e] = make_float4(v.x * sc, v.y * sc, v.z * sc, 0.f);
+    }
+  } else
   // ---- radial: dE/dr_ij per neighbor, reduced over the 16 shift lanes
   {
     const int gq = lane >> 4, m = lane & 15;
@@ -382,6 +467,72 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
   }
   wave_lds_sync();
 
+  if constexpr (Mode == kAngPairLanes) {
+    // ---- angular: one lane per unordered pair (j, k), 64 pairs per pass.
+    // What the pair's 32 terms share (cosine, sine, the four distance
+    // Gaussians) is computed once; the lane walks the eight angle shifts and
+    // contracts each with the pair block's dE/dG values (one vector load).
+    const int T = na * (na - 1) / 2;
+    const GT* gang = grow + S * kNR;
+    for (int t0 = 0; t0 < T; t0 += kWave) {
+      // lanes past the last pair recompute it and add nothing
+      const int t = t0 + lane;
+      const bool valid = t < T;
+      int ej, ek;
+      decode_pair(valid ? t : T - 1, na, ej, ek);
+      const float4 vj = nd[ej], vk = nd[ek];
+      const float4 cj = nf[ej], ck = nf[ek];
+      float gv[32];
+      Load32<GT>::get(gang + pair_block(nsp[ej], nsp[ek], S) * 32, gv);
+      const float fj = cj.y, fk = ck.y, dfj = cj.w, dfk = ck.w;
+      const float rj = fast_rcp(vj.w), rk = fast_rcp(vk.w);
+      const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * (rj * rk);
+      const float kc = C.kappa * cs;
+      const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 1e-12f));
+      const float isn = fast_rcp(sn);
+      const float dbar = 0.5f * (vj.w + vk.w);
+      float e2[kNA], ue2[kNA];
+#pragma unroll
+      for (int a = 0; a < kNA; ++a) {
+        const float u = dbar - C.shf_a[a];
+        e2[a] = fast_exp2(-C.eta_a_l2e * u * u);
+        ue2[a] = u * e2[a];
+      }
+      float X0 = 0.f, X1 = 0.f, Xc = 0.f;
+#pragma unroll
+      for (int z = 0; z < kNZ; ++z) {
+        const float cz = C.lane_tab[kNR + z], sz = C.lane_tab[kNR + kNZ + z];
+        float A0 = 0.f, A1 = 0.f;
+#pragma unroll
+        for (int a = 0; a < kNA; ++a) {
+          A0 += gv[a * kNZ + z] * e2[a];
+          A1 -= gv[a * kNZ + z] * ue2[a];
+        }
+        const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
+        const float pw = fast_exp2(C.zeta * fast_log2(base_));
+        const float df1 = C.zeta * pw * fast_rcp(base_) * (C.kappa * (cz - kc * sz * isn));
+        X0 += 2.f * pw * A0;
+        X1 += 2.f * pw * A1;
+        Xc += df1 * A0;
+      }
+      X1 *= C.eta_a;
+      if (valid) {
+        const float fcc = fj * fk;
+        const float dEdc = Xc * fcc;
+        const float dEdj = X1 * fcc + X0 * dfj * fk;
+        const float dEdk = X1 * fcc + X0 * fj * dfk;
+        const float aj = (dEdj - dEdc * cs * rj) * rj;
+        const float ak = (dEdk - dEdc * cs * rk) * rk;
+        const float bb = dEdc * rj * rk;
+        atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
+        atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
+        atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
+        atomicAdd(&grad[ek].x, ak * vk.x + bb * vj.x);
+        atomicAdd(&grad[ek].y, ak * vk.y + bb * vj.y);
+        atomicAdd(&grad[ek].z, ak * vk.z + bb * vj.z);
+      }
+    }
+  } else
   // ---- angular: lanes (t, z), eight unordered pairs per pass
   {
     const int tz = lane & 7, tg = lane >> 3;
@@ -431,7 +582,7 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
         const float aj = (dEdj - dEdc * cs * rj) * rj;
         const float ak = (dEdk - dEdc * cs * rk) * rk;
         const float bb = dEdc * rj * rk;
-        if constexpr (!Det) {
+        if constexpr (Mode == kAngShiftLanes) {
           atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
           atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
           atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
@@ -460,35 +611,6 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
   }
   wave_lds_sync();
 }
-
-// Sixteen consecutive dE/dG values (one radial species block) as floats.
-template <typename GT> struct Load16;
-template <> struct Load16<float> {
-  __device__ __forceinline__ static void get(const float* p, float (&v)[16]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 u = reinterpret_cast<const float4*>(p)[q];
-      v[4 * q] = u.x;
-      v[4 * q + 1] = u.y;
-      v[4 * q + 2] = u.z;
-      v[4 * q + 3] = u.w;
-    }
-  }
-};
-template <> struct Load16<bf16_t> {
-  __device__ __forceinline__ static void get(const bf16_t* p, float (&v)[16]) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const uint4 u = reinterpret_cast<const uint4*>(p)[q];
-      const unsigned w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        v[8 * q + 2 * k] = __uint_as_float(w[k] << 16);
-        v[8 * q + 2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
-      }
-    }
-  }
-};
 
 // The adjoint of atoms i0 .. i0 + 3, by one wave: dE/d(displacement) of every
 // neighbor entry into the wave's LDS region (max(64, cap) entries of nd, nf,
@@ -645,7 +767,8 @@ __device__ __forceinline__ void adjoint_atoms(int i0, int n, const AevConst& C,
     const float4* arec = rec + (size_t)i * cap;
     for (int e = lane; e < nr; e += kWave) adjoint_setup(e, arec[e], e < na, C, nd, nf, nsp);
     wave_lds_sync();
-    adjoint_passes<GT>(nr, na, C, grow, nd, nf, grad, nsp);
+    adjoint_passes<GT, Q == 1 ? kAngPairLanes : kAngShiftLanes>(nr, na, C, grow, nd, nf, grad,
+                                                                nsp);
     const int* arow = nbr + (size_t)i * cap;
     float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int e = lane; e < nr; e += kWave) {
@@ -737,7 +860,8 @@ __global__ __launch_bounds__(256) void k_aev_bwd_det(const int* __restrict__ dim
   const float4* arec = rec + (size_t)i * cap;
   for (int e = lane; e < nr; e += kWave) adjoint_setup(e, arec[e], e < na, C, nd, nf, nsp);
   wave_lds_sync();
-  adjoint_passes<GT, true>(nr, na, C, g + (size_t)row_of[i] * ldg, nd, nf, grad, nsp);
+  adjoint_passes<GT, kAngShiftLanesOrdered>(nr, na, C, g + (size_t)row_of[i] * ldg, nd, nf, grad,
+                                            nsp);
   for (int e = lane; e < nr; e += kWave) pgrad[(size_t)i * cap + e] = grad[e];
 }
 

@@ -287,6 +287,15 @@ template <typename T> T* at(void* ws, size_t off) {
 
 bool hip_ok(hipError_t e) { return e == hipSuccess; }
 
+// The launches of this call succeeded: the runtime's last error is clear.
+// hipErrorNotReady is no failure: the runtime also records it as the last
+// error when an event or stream query (the serving loop's, or the caller's)
+// finds work still running, and it would otherwise fail the next call.
+bool launches_ok() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess || e == hipErrorNotReady;
+}
+
 // ---------------------------------------------------------------- the path
 
 struct EvalIO {
@@ -585,7 +594,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
                         h->param_off_dev, st);
   }
   if (!ok) return NNP_E_INVALID;
-  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+  return launches_ok() ? NNP_OK : NNP_E_HIP;
 }
 
 nnp_status run(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hipStream_t st) {
@@ -835,7 +844,7 @@ nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* s
   p.wout = h->wout;
   p.bout = h->bout;
   launch_pack(p, Q, st);
-  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+  return launches_ok() ? NNP_OK : NNP_E_HIP;
 }
 
 nnp_status nnp_profile_enable(nnp_handle* h, int on) {
@@ -937,7 +946,7 @@ nnp_status nnp_energy_forces_noalloc(nnp_handle* h, int32_t n, int32_t nmol, con
   if (status) {
     hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, st,
                        static_cast<const uint32_t*>(at<uint32_t>(ws, P.status)), status);
-    if (hipGetLastError() != hipSuccess) return NNP_E_HIP;
+    if (!launches_ok()) return NNP_E_HIP;
   }
   return NNP_OK;
 }
@@ -1045,7 +1054,7 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
                      at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
   launch_aev_fwd<float>(dims, P.n, h->C, at<float4>(ws, P.rec), at<int2>(ws, P.counts), P.cap,
                         nullptr, aev, h->F, h->deterministic, st);
-  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+  return launches_ok() ? NNP_OK : NNP_E_HIP;
 }
 
 // ------------------------------------------------------------- graph replay
@@ -1151,7 +1160,7 @@ nnp_status nnp_md_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, doubl
     launch_kinetic(dims, nmol, off, v, mass, E_kin, nullptr, st);
   }
   if (s != NNP_OK) return s;
-  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+  return launches_ok() ? NNP_OK : NNP_E_HIP;
 }
 
 nnp_status nnp_langevin_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x, double* v,
@@ -1189,7 +1198,7 @@ nnp_status nnp_langevin_steps(nnp_handle* h, int32_t n, int32_t nmol, double* x,
   }
   if (s == NNP_OK && E_kin) launch_kinetic(dims, nmol, off, v, mass, E_kin, nullptr, st);
   if (s != NNP_OK) return s;
-  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+  return launches_ok() ? NNP_OK : NNP_E_HIP;
 }
 
 }  // extern "C"
@@ -1233,6 +1242,7 @@ constexpr int kRetireSlots = 4;
 
 struct nnp_server {
   nnp_handle* h = nullptr;
+  int device = 0;  // the handle's device, kept so destruction never reads the handle
   hipStream_t st = nullptr;
   double dt = 0.5;
   // integrator: velocity Verlet, or LF-Middle Langevin after nnp_server_set_langevin
@@ -1353,7 +1363,10 @@ nnp_status retire_drain(nnp_server* s, bool wait) {
       if (hipEventSynchronize(s->slots[q].ev) != hipSuccess) return NNP_E_HIP;
     } else {
       const hipError_t e = hipEventQuery(s->slots[q].ev);
-      if (e == hipErrorNotReady) break;
+      if (e == hipErrorNotReady) {
+        (void)hipGetLastError();  // the runtime records it as the last error
+        break;
+      }
       if (e != hipSuccess) return NNP_E_HIP;
     }
     retire_deliver(s, q);
@@ -1381,7 +1394,7 @@ nnp_status server_enqueue_step(nnp_server* s) {
     launch_serve_integrate(dims, s->max_atoms, at<int>(s->ws, P.mol), s->kdone, s->nsteps, s->x,
                            s->v, s->F, s->m, s->dt, s->st);
   launch_kinetic(dims, s->max_mols, s->off, s->v, s->m, s->ekin, s->kdone, s->st);
-  return hip_ok(hipGetLastError()) ? NNP_OK : NNP_E_HIP;
+  return launches_ok() ? NNP_OK : NNP_E_HIP;
 }
 
 }  // namespace
@@ -1410,6 +1423,7 @@ nnp_status nnp_server_create(nnp_handle* h, size_t budget, int32_t max_atoms, in
   nnp_server* s = new (std::nothrow) nnp_server();
   if (!s) return NNP_E_OOM;
   s->h = h;
+  s->device = h->device;
   s->dt = dt_fs;
   for (int q = 0; q < h->S; ++q) s->mass_tab[q] = mass_amu[q];
   s->max_atoms = A;
@@ -1508,7 +1522,7 @@ nnp_status nnp_server_create(nnp_handle* h, size_t budget, int32_t max_atoms, in
 
 void nnp_server_destroy(nnp_server* s) {
   if (!s) return;
-  (void)hipSetDevice(s->h->device);
+  (void)hipSetDevice(s->device);
   if (s->st) (void)hipStreamSynchronize(s->st);
   if (s->exec) (void)hipGraphExecDestroy(s->exec);
   if (s->graph) (void)hipGraphDestroy(s->graph);
