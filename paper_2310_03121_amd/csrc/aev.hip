@@ -103,11 +103,12 @@ __device__ __forceinline__ int pair_block(int p, int q, int S) {
 constexpr int kPairChunk = 64;
 
 // LDS per wave (forward): per neighbor float4 (dx, dy, dz, r), float2
-// (fc_rad, fc_ang), int species; a 64-entry table of angular pairs (float4
-// geometry and int block each).  The feature row is accumulated in registers
-// and stored block by block, so no LDS row is needed.
+// (fc_rad, fc_ang), int species; a 64-entry table of angular pairs (eight
+// angle-shift weights, four distance Gaussians and the block of each).  The
+// feature row is accumulated in registers and stored block by block, so no
+// LDS row is needed.
 constexpr int kFwdBytesPerNbr = 16 + 8 + 4;
-constexpr int kFwdPairBytes = 16 + 4;
+constexpr int kFwdPairBytes = 32 + 16 + 4;
 
 typedef float aev_f32x4 __attribute__((ext_vector_type(4)));
 
@@ -120,19 +121,37 @@ __device__ __forceinline__ aev_f32x4 mfma4(float a, float b, aev_f32x4 acc) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
 }
 
-// The angular pair t of atom-local list prefix [0, na), one per lane: what
-// a pair's 32 terms share, computed once instead of in each of the 16 lanes
-// of its pass, written to table slot `slot`.
+// The angular pair t of atom-local list prefix [0, na), one per lane: the
+// factors of its 32 terms, computed once instead of in each of the 16 lanes
+// of its pass, written to table slot `slot`: the angle-shift weights
+// w[z] = 2 ((1 + cos(theta - theta_z)) / 2)^zeta fc_j fc_k and the distance
+// Gaussians g[a] = exp(-eta_A ((r_j + r_k) / 2 - R_a)^2); term (a, z) = w[z] g[a].
 __device__ __forceinline__ void pair_geometry(int t, int na, const AevConst& C, const float4* nd,
-                                              const float2* nf, const int* nsp, float4* pgeo,
-                                              int* pblk, int slot) {
+                                              const float2* nf, const int* nsp, float* pw,
+                                              float* pg, int* pblk, int slot) {
   int a, b;
   decode_pair(t, na, a, b);
   const float4 vj = nd[a], vk = nd[b];
   const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * fast_rcp(vj.w * vk.w);
   const float kc = C.kappa * cs;
-  pgeo[slot] = make_float4(kc, fast_sqrt(fmaxf(1.f - kc * kc, 0.f)), 0.5f * (vj.w + vk.w),
-                           nf[a].y * nf[b].y);
+  const float sn = fast_sqrt(fmaxf(1.f - kc * kc, 0.f));
+  const float dbar = 0.5f * (vj.w + vk.w);
+  const float fcc = nf[a].y * nf[b].y;
+  float w[kNZ];
+#pragma unroll
+  for (int z = 0; z < kNZ; ++z) {
+    const float base_ = 0.5f + 0.5f * (kc * C.lane_tab[kNR + z] + sn * C.lane_tab[kNR + kNZ + z]);
+    w[z] = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * fcc;
+  }
+  float g[kNA];
+#pragma unroll
+  for (int q = 0; q < kNA; ++q) {
+    const float u = dbar - C.shf_a[q];
+    g[q] = fast_exp2(-C.eta_a_l2e * u * u);
+  }
+  reinterpret_cast<float4*>(pw)[2 * slot] = make_float4(w[0], w[1], w[2], w[3]);
+  reinterpret_cast<float4*>(pw)[2 * slot + 1] = make_float4(w[4], w[5], w[6], w[7]);
+  reinterpret_cast<float4*>(pg)[slot] = make_float4(g[0], g[1], g[2], g[3]);
   pblk[slot] = pair_block(nsp[a], nsp[b], C.S);
 }
 
@@ -159,7 +178,7 @@ __host__ __device__ constexpr bool aev_quads(int cap) { return cap <= 64; }
 // NT: 16-block tiles of the angular one-hot (ceil(S (S + 1) / 2 / 16): one
 // for up to five elements, two for six or seven, three for eight).
 template <typename OutT, int NT, int Q>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_aev_fwd(const int* __restrict__ dims, AevConst C,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 : 8, 8))) void k_aev_fwd(const int* __restrict__ dims, AevConst C,
                                                  const float4* __restrict__ rec,
                                                  const int2* __restrict__ counts, int cap,
                                                  const int* __restrict__ row_of,
@@ -176,9 +195,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   float2* nf = nf0 + (size_t)w * reg;
   int* nsp0 = reinterpret_cast<int*>(nf0 + (size_t)4 * reg);
   int* nsp = nsp0 + (size_t)w * reg;
-  float4* pgeo0 = reinterpret_cast<float4*>(nsp0 + (size_t)4 * reg);
-  float4* pgeo = pgeo0 + w * kPairChunk;
-  int* pblk = reinterpret_cast<int*>(pgeo0 + 4 * kPairChunk) + w * kPairChunk;
+  float* pw0 = reinterpret_cast<float*>(nsp0 + (size_t)4 * reg);  // [4][kPairChunk][8]
+  float* pw = pw0 + w * kPairChunk * kNZ;
+  float* pg0 = pw0 + 4 * kPairChunk * kNZ;                          // [4][kPairChunk][4]
+  float* pg = pg0 + w * kPairChunk * kNA;
+  int* pblk = reinterpret_cast<int*>(pg0 + 4 * kPairChunk * kNA) + w * kPairChunk;
 
   auto setup = [&](int slot, const float4 q, bool ang) __attribute__((always_inline)) {
     const float r = fast_sqrt(dist2(q.x, q.y, q.z));
@@ -208,7 +229,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     wave_lds_sync();
     if (joint) {
       if (l < T_g)
-        pair_geometry(l, na_g, C, nd + kQuadNbr * g, nf + kQuadNbr * g, nsp + kQuadNbr * g, pgeo,
+        pair_geometry(l, na_g, C, nd + kQuadNbr * g, nf + kQuadNbr * g, nsp + kQuadNbr * g, pw, pg,
                       pblk, lane);
       wave_lds_sync();
     }
@@ -217,9 +238,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const int l16 = lane & 15, kq = lane >> 4;
   const float Rm = C.lane_tab[l16];
   const int z = l16 & 7, ah = l16 >> 3;
-  const float cz = C.lane_tab[kNR + z], sz = C.lane_tab[kNR + kNZ + z];
-  const float ra_lo = ah ? C.shf_a[1] : C.shf_a[0];
-  const float ra_hi = ah ? C.shf_a[3] : C.shf_a[2];
   const int nblk = S * (S + 1) / 2;
 
   for (int a = 0; a < Q; ++a) {
@@ -278,7 +296,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         if (!joint) {
           tb = 0;
           wave_lds_sync();  // the previous chunk's passes have read the table
-          if (p0 + lane < T) pair_geometry(p0 + lane, na, C, nda, nfa, nspa, pgeo, pblk, lane);
+          if (p0 + lane < T) pair_geometry(p0 + lane, na, C, nda, nfa, nspa, pw, pg, pblk, lane);
           wave_lds_sync();
         }
         const int tn = T - p0 < kPairChunk ? T - p0 : kPairChunk;
@@ -287,22 +305,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
           float b0 = 0.f, b1 = 0.f;
           int blk = -1;
           if (t < tn) {
-            const float4 q = pgeo[tb + t];  // kappa cos, sine, mean distance, fc_j fc_k
-            blk = pblk[tb + t];
-            const float base_ = 0.5f + 0.5f * (q.x * cz + q.y * sz);
-            const float wgt = 2.f * fast_exp2(C.zeta * fast_log2(base_)) * q.w;
-            const float u0 = q.z - ra_lo, u1 = q.z - ra_hi;
-            b0 = wgt * fast_exp2(-C.eta_a_l2e * u0 * u0);
-            b1 = wgt * fast_exp2(-C.eta_a_l2e * u1 * u1);
+            const int sl = tb + t;
+            blk = pblk[sl];
+            const float wz = pw[sl * kNZ + z];
+            b0 = wz * pg[sl * kNA + ah];
+            b1 = wz * pg[sl * kNA + ah + 2];
           }
-          // every tile's product runs on every pass: a tile without the pass's
-          // blocks adds zeros, which costs less than a branch that keeps the
-          // accumulators apart
+          // a tile's products run only on passes that hold one of its blocks
+          // (pairs come in species order, so most passes touch one tile)
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            const float hot = blk == l16 + 16 * u ? 1.f : 0.f;
-            c0[u] = mfma4(b0, hot, c0[u]);
-            c1[u] = mfma4(b1, hot, c1[u]);
+            if (NT == 1 || __ballot(blk >= 16 * u && blk < 16 * u + 16) != 0) {
+              const float hot = blk == l16 + 16 * u ? 1.f : 0.f;
+              c0[u] = mfma4(b0, hot, c0[u]);
+              c1[u] = mfma4(b1, hot, c1[u]);
+            }
           }
         }
       }
