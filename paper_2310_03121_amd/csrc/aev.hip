@@ -380,10 +380,12 @@ template <> struct Load16<bf16_t> {
 };
 
 // The 32 dE/dG values of one angular pair block (four distance shifts x
-// eight angle shifts, a-major) as floats.
-template <typename GT> struct Load32;
-template <> struct Load32<float> {
-  __device__ __forceinline__ static void get(const float* p, float (&v)[32]) {
+// eight angle shifts, a-major), kept as loaded (BF16: two per register) and
+// converted where used.
+template <typename GT> struct Block32;
+template <> struct Block32<float> {
+  float v[32];
+  __device__ __forceinline__ void load(const float* p) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const float4 u = reinterpret_cast<const float4*>(p)[q];
@@ -393,19 +395,22 @@ template <> struct Load32<float> {
       v[4 * q + 3] = u.w;
     }
   }
+  __device__ __forceinline__ float at(int k) const { return v[k]; }
 };
-template <> struct Load32<bf16_t> {
-  __device__ __forceinline__ static void get(const bf16_t* p, float (&v)[32]) {
+template <> struct Block32<bf16_t> {
+  unsigned w[16];
+  __device__ __forceinline__ void load(const bf16_t* p) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint4 u = reinterpret_cast<const uint4*>(p)[q];
-      const unsigned w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        v[8 * q + 2 * k] = __uint_as_float(w[k] << 16);
-        v[8 * q + 2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
-      }
+      w[4 * q] = u.x;
+      w[4 * q + 1] = u.y;
+      w[4 * q + 2] = u.z;
+      w[4 * q + 3] = u.w;
     }
+  }
+  __device__ __forceinline__ float at(int k) const {
+    return __uint_as_float((k & 1) ? (w[k >> 1] & 0xffff0000u) : (w[k >> 1] << 16));
   }
 };
 
@@ -499,8 +504,8 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
       decode_pair(valid ? t : T - 1, na, ej, ek);
       const float4 vj = nd[ej], vk = nd[ek];
       const float4 cj = nf[ej], ck = nf[ek];
-      float gv[32];
-      Load32<GT>::get(gang + pair_block(nsp[ej], nsp[ek], S) * 32, gv);
+      Block32<GT> gb;
+      gb.load(gang + pair_block(nsp[ej], nsp[ek], S) * 32);
       const float fj = cj.y, fk = ck.y, dfj = cj.w, dfk = ck.w;
       const float rj = fast_rcp(vj.w), rk = fast_rcp(vk.w);
       const float cs = (vj.x * vk.x + vj.y * vk.y + vj.z * vk.z) * (rj * rk);
@@ -522,8 +527,8 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
         float A0 = 0.f, A1 = 0.f;
 #pragma unroll
         for (int a = 0; a < kNA; ++a) {
-          A0 += gv[a * kNZ + z] * e2[a];
-          A1 -= gv[a * kNZ + z] * ue2[a];
+          A0 += gb.at(a * kNZ + z) * e2[a];
+          A1 -= gb.at(a * kNZ + z) * ue2[a];
         }
         const float base_ = 0.5f + 0.5f * (kc * cz + sn * sz);
         const float pw = fast_exp2(C.zeta * fast_log2(base_));
@@ -533,17 +538,39 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
         Xc += df1 * A0;
       }
       X1 *= C.eta_a;
+      const float fcc = fj * fk;
+      const float dEdc = Xc * fcc;
+      const float dEdj = X1 * fcc + X0 * dfj * fk;
+      const float dEdk = X1 * fcc + X0 * fj * dfk;
+      const float aj = (dEdj - dEdc * cs * rj) * rj;
+      const float ak = (dEdk - dEdc * cs * rk) * rk;
+      const float bb = dEdc * rj * rk;
+      // Entry j's terms: the pass's pairs of row j are consecutive lanes, so
+      // a segmented sum over that run leaves the row's total in its last lane,
+      // which adds it alone (LDS atomics on one address from up to 16 lanes
+      // would serialize).  Lanes past the last pair lie after it.
+      float sx = aj * vj.x + bb * vk.x, sy = aj * vj.y + bb * vk.y, sz = aj * vj.z + bb * vk.z;
+      const int rs = (ej * (2 * na - ej - 1)) >> 1;  // the row's first pair
+      const int s_lane = (rs > t0 ? rs : t0) - t0;
+      const int re = rs + na - 2 - ej;               // and its last
+      const int e_lane = (re < t0 + kWave - 1 ? re : t0 + kWave - 1) - t0;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const float ox = __shfl_up(sx, d, kWave), oy = __shfl_up(sy, d, kWave),
+                    oz = __shfl_up(sz, d, kWave);
+        if (lane - d >= s_lane) {
+          sx += ox;
+          sy += oy;
+          sz += oz;
+        }
+      }
+      if (lane == e_lane) {
+        atomicAdd(&grad[ej].x, sx);
+        atomicAdd(&grad[ej].y, sy);
+        atomicAdd(&grad[ej].z, sz);
+      }
+      // entry k's terms: at most one per row, so few lanes share an entry
       if (valid) {
-        const float fcc = fj * fk;
-        const float dEdc = Xc * fcc;
-        const float dEdj = X1 * fcc + X0 * dfj * fk;
-        const float dEdk = X1 * fcc + X0 * fj * dfk;
-        const float aj = (dEdj - dEdc * cs * rj) * rj;
-        const float ak = (dEdk - dEdc * cs * rk) * rk;
-        const float bb = dEdc * rj * rk;
-        atomicAdd(&grad[ej].x, aj * vj.x + bb * vk.x);
-        atomicAdd(&grad[ej].y, aj * vj.y + bb * vk.y);
-        atomicAdd(&grad[ej].z, aj * vj.z + bb * vk.z);
         atomicAdd(&grad[ek].x, ak * vk.x + bb * vj.x);
         atomicAdd(&grad[ek].y, ak * vk.y + bb * vj.y);
         atomicAdd(&grad[ek].z, ak * vk.z + bb * vj.z);
@@ -811,7 +838,8 @@ __device__ __forceinline__ void adjoint_atoms(int i0, int n, const AevConst& C,
 // only the atomic energies of the forward pass: they fill the tail of the
 // scatter instead of a launch of their own.
 template <typename GT, int Q>
-__global__ __launch_bounds__(256) void k_aev_bwd(const int* __restrict__ dims, AevConst C,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q == 1 ? 6 : 4, 8))) void k_aev_bwd(
+    const int* __restrict__ dims, AevConst C,
                                                  const float4* __restrict__ rec,
                                                  const int* __restrict__ nbr,
                                                  const int2* __restrict__ counts, int cap,
