@@ -625,11 +625,15 @@ def main():
                          "at 0.1, x1.4 at 0.05)")
     ap.add_argument("--nve-relax", type=int, default=0,
                     help="FIRE iterations before the drift leg's velocities are drawn")
+    ap.add_argument("--max-neighbors", type=int, default=None,
+                    help="neighbor-list capacity of the handles (default per workload)")
     ap.add_argument("--ensemble", type=int, default=0,
                     help="also time an ensemble of this many networks (BF16 and FP32)")
     ap.add_argument("--ceilings", action="store_true",
                     help="also measure copy bandwidth and library GEMM rates on this device")
     args = ap.parse_args()
+    if args.max_neighbors is not None:
+        MAX_NEIGHBORS[args.workload] = args.max_neighbors
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is measured on one GPU's share "
               "(multi-GPU sharding is a design note, not implemented)", file=sys.stderr)

@@ -809,15 +809,20 @@ __device__ __forceinline__ void adjoint_atoms(int i0, int n, const AevConst& C,
     const GT* grow = g + (size_t)row_of[i] * ldg;
     // this atom alone over the whole wave
     const float4* arec = rec + (size_t)i * cap;
+    const int* arow = nbr + (size_t)i * cap;
+    // the scatter's first two rounds of neighbor indices, loaded now so that
+    // their latency hides behind the passes
+    const int j0 = lane < nr ? arow[lane] : 0;
+    const int j1 = lane + kWave < nr ? arow[lane + kWave] : 0;
     for (int e = lane; e < nr; e += kWave) adjoint_setup(e, arec[e], e < na, C, nd, nf, nsp);
     wave_lds_sync();
     adjoint_passes<GT, Q == 1 ? kAngPairLanes : kAngShiftLanes>(nr, na, C, grow, nd, nf, grad,
                                                                 nsp);
-    const int* arow = nbr + (size_t)i * cap;
     float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int e = lane; e < nr; e += kWave) {
       const float4 gv = grad[e];
-      put(clampi(arow[e], n), -sign * gv.x, -sign * gv.y, -sign * gv.z);
+      const int j = e < kWave ? j0 : (e < 2 * kWave ? j1 : arow[e]);
+      put(clampi(j, n), -sign * gv.x, -sign * gv.y, -sign * gv.z);
       sx += gv.x;
       sy += gv.y;
       sz += gv.z;
