@@ -245,6 +245,30 @@ nnp_status nnp_energy_forces_subset(nnp_handle* h, int32_t n_sub, int32_t n_mol,
                                     const float* box, double* E, float* F_all, void* workspace,
                                     size_t ws_bytes, void* stream);
 
+/* One spatial shard of a larger periodic system: the evaluation a GPU would
+ * run in a slab (or brick) decomposition of one big box over several GPUs,
+ * where each GPU owns the atoms of its region and holds copies ("ghosts")
+ * of the atoms within the radial cutoff of its faces.  The paper's large
+ * periodic simulations run one system over several GPUs (Results,
+ * "Performance"); how a potential is split is this library's design.
+ *   atoms [0, n_owned) are owned, [n_owned, n_atoms) ghosts; all interact
+ *   (neighbor pairs ignore the split); positions in the full system's box;
+ *   E  device float64 [2]: sum of E_i over the owned atoms, then over the
+ *      ghosts (whose owners count them: a multi-GPU run adds up E[0] only);
+ *   F  device float32 [n_atoms][3] = -dE[0]/dx for every atom: the owned
+ *      atoms' forces from this shard's energy, and on the ghosts the parts
+ *      that a run would send back to their owners and add there.
+ * An owned atom's energy and force are exact when every atom within the
+ * radial cutoff of it is present (owned or ghost); a ghost's own energy
+ * needs no complete neighborhood since it is not counted.  box is required
+ * (3 or 9 floats as set by nnp_set_triclinic).  Workspace:
+ * nnp_workspace_bytes(h, n_atoms, 2, box).  NNP_E_INVALID for n_owned
+ * outside [0, n_atoms], n_atoms < 1 or a null pointer. */
+nnp_status nnp_energy_forces_owned(nnp_handle* h, int32_t n_atoms, int32_t n_owned,
+                                   const float* pos, const int32_t* species, const float* box,
+                                   double* E, float* F, void* workspace, size_t ws_bytes,
+                                   void* stream);
+
 /* Adjoint for L = sum_m dL_dE[m] * E_m.  Recomputes the forward pass (the
  * symmetry functions are recomputed, not stored between calls), then writes
  *   dL_dpos    device, float32 [n_atoms][3] = sum_m dL_dE[m] dE_m/dpos, or NULL;

@@ -202,6 +202,21 @@ class Potential:
             "nnp_energy_forces_subset")
         return E
 
+    def energy_forces_owned(self, pos, species, n_owned, box):
+        """One shard of a larger periodic system (nnp_energy_forces_owned):
+        atoms [0, n_owned) owned, the rest ghosts.  Returns (E float64 [2]:
+        owned and ghost energy sums, F float32 [N, 3] = -dE[0]/dpos)."""
+        pos = pos.contiguous()
+        n = pos.shape[0]
+        E = torch.empty(2, dtype=torch.float64, device=pos.device)
+        F = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+        ws = self.workspace(n, 2, box, pos.device)
+        b, bp = self._box_arg(box)
+        capi.check(self._lib.nnp_energy_forces_owned(
+            self._h, n, int(n_owned), _ptr(pos), _ptr(species), bp, _ptr(E), _ptr(F), _ptr(ws),
+            ws.numel(), _stream()), "nnp_energy_forces_owned")
+        return E, F
+
     def backward(self, pos, species, mol_offsets, dL_dE, box=None, want_pos=True,
                  want_params=True):
         """(dL/dpos float32 [N,3] or None, dL/dparams float32 [P] or None, E)."""

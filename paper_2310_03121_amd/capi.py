@@ -62,6 +62,7 @@ _SIGS = [
     ("nnp_energy_forces_subset", C.c_int, [_P, _I, _I, _P, _I, _P, _P, _P, _P, _P, _P, _P,
                                             C.c_size_t, _P]),
     ("nnp_backward", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    ("nnp_energy_forces_owned", C.c_int, [_P, _I, _I, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     ("nnp_check", C.c_int, [_P, _P, _P]),
     ("nnp_status_string", C.c_char_p, [C.c_int]),
     ("nnp_debug_neighbors", C.c_int, [_P, _I, _P, C.c_size_t, _P, _P, _P]),

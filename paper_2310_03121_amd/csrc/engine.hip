@@ -96,6 +96,18 @@ void* scratch_ptr(int dev) {
   return g_scratch[dev];
 }
 
+// Owned/ghost evaluation: group offsets {0, n_owned, n} and upstream {1, 0}.
+__global__ void k_owned_groups(int n, int n_owned, int* __restrict__ off,
+                               double* __restrict__ up) {
+  if (threadIdx.x == 0) {
+    off[0] = 0;
+    off[1] = n_owned;
+    off[2] = n;
+    up[0] = 1.0;
+    up[1] = 0.0;
+  }
+}
+
 // Copies the evaluation's status word to the caller (one thread).
 __global__ void k_copy_status(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
   if (threadIdx.x == 0) *dst = *src;
@@ -148,6 +160,7 @@ struct Plan {
   size_t cell_of, cell_cnt, cell_start, cursor, cell_atoms, cell_xyzs;
   size_t X, H1, H2, H3, D3, D2, D1, G, erow, uprow, wpart, pos32;
   size_t pgrad;  // deterministic mode: per-entry adjoint rows [n][cap]
+  size_t grp;    // owned/ghost evaluation: group offsets (3 int) and upstream (2 double)
 };
 
 bool make_box(const nnp_handle* h, const float* box, BoxConst& B) {
@@ -247,6 +260,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B, bool wgr
   P.counts = take(N * 8);
   P.rec = take(N * P.cap * 16);
   P.pgrad = h->deterministic ? take(N * P.cap * 16) : 0;
+  P.grp = take(64);
   if (B.periodic) {
     P.cell_of = take(N * 4);
     P.cell_cnt = take((size_t)(P.ncell + 1) * 4);  // counts, then the binning's done counter
@@ -602,13 +616,16 @@ nnp_status run(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hipStre
   return run_path<float>(h, P, ws, io, st);
 }
 
+// groups: with a box, mol_offsets may split the atoms into energy groups
+// (all atoms still interact); only the owned/ghost entry point does that.
 nnp_status check_common(nnp_handle* h, int n, int nmol, const float* pos, const int* species,
-                        const int* off, const float* box, void* ws, size_t ws_bytes, Plan& P) {
+                        const int* off, const float* box, void* ws, size_t ws_bytes, Plan& P,
+                        bool groups = false) {
   if (!h || n < 0 || nmol < 1) return NNP_E_INVALID;
   if (n > 0 && (!pos || !species)) return NNP_E_INVALID;
   if (!off) return NNP_E_INVALID;
   if (n >= (1 << 27)) return NNP_E_INVALID;
-  if (box && nmol != 1) return NNP_E_INVALID;
+  if (box && nmol != 1 && !groups) return NNP_E_INVALID;
   BoxConst B;
   if (!make_box(h, box, B)) return NNP_E_BOX;
   P = make_plan(h, n, nmol, B);
@@ -978,6 +995,29 @@ nnp_status nnp_backward(nnp_handle* h, int32_t n, int32_t nmol, const float* pos
   if (dL_dparams && h && h->n_models > 1) return NNP_E_INVALID;  // weight gradients: one network
   EvalIO io{n, nmol, pos, nullptr, species, off, E, dL_dpos, -1.f, dLdE, dL_dparams};
   return run(h, P, ws, io, static_cast<hipStream_t>(stream));
+}
+
+nnp_status nnp_energy_forces_owned(nnp_handle* h, int32_t n, int32_t n_owned, const float* pos,
+                                   const int32_t* species, const float* box, double* E, float* F,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  if (!h || n < 1 || n_owned < 0 || n_owned > n || !box || !E || !F || !ws) return NNP_E_INVALID;
+  // the group arrays live in the workspace: plan once to find them, then
+  // check everything with them in place
+  BoxConst B;
+  if (!make_box(h, box, B)) return NNP_E_BOX;
+  const Plan P0 = make_plan(h, n, 2, B);
+  if (ws_bytes < P0.total) return NNP_E_WORKSPACE;
+  int* off = at<int>(ws, P0.grp);
+  double* up = reinterpret_cast<double*>(static_cast<char*>(ws) + P0.grp + 16);
+  Plan P;
+  nnp_status s = check_common(h, n, 2, pos, species, off, box, ws, ws_bytes, P, true);
+  if (s != NNP_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_owned_groups, dim3(1), dim3(64), 0, st, n, n_owned, off, up);
+  // forces of the owned energy: the adjoint with upstream 1 for group 0 and 0
+  // for the ghosts, written as forces (sign +1)
+  EvalIO io{n, 2, pos, nullptr, species, off, E, F, 1.f, up, nullptr};
+  return run(h, P, ws, io, st);
 }
 
 nnp_status nnp_check(const nnp_handle* h, void* ws, void* stream) {
