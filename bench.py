@@ -28,6 +28,14 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}   # MI355X dense MFMA
 PEAK_HBM_GBS = 8000.0
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line per finished leg on stderr (stdout carries only the result)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def mlp_flops_per_atom(widths, F):
     w = list(widths)
     w[0] = F
@@ -49,8 +57,9 @@ def stage_flops(widths, F):
     return d
 
 
-# Algorithmic fp32 operations of the symmetry-function kernels (add, mul and
-# each transcendental counted as one), from the radial and angular terms as
+# Algorithmic fp32 operations of the symmetry-function kernels (add, mul, FMA
+# and each transcendental counted as one lane operation), from the radial and
+# angular terms as
 # defined: per radial neighbor pair 16 shifts x 6 (difference, square, scale,
 # exp, cutoff product, sum) + 11 (distance, cutoff); per angular triple 151
 # (cosine 7, kappa and sine 4, 8 angle shifts x 7, 4 distance shifts x 4 + 2,
@@ -58,7 +67,11 @@ def stage_flops(widths, F):
 # terms and adds their derivatives and the scatter: 199 per radial pair, 280
 # per angular triple.
 AEV_OPS = {"aev_fwd": (107, 151), "aev_bwd_forces": (199, 280)}
-PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, unpacked fp32
+# Lane operations per second of the FP32 vector units: 1,024 SIMDs x 32 lanes
+# per clock x 2.4 GHz (one add, multiply, FMA or transcendental per lane and
+# clock); the same rate is the 157.3 TFLOP/s FP32 vector peak with an FMA
+# counted as 2.  The FMA issue loop measures about 61 % of it.
+PEAK_VALU_TOPS = 78.6
 
 
 def pair_counts(pot, n_atoms):
@@ -340,9 +353,11 @@ def ensemble_leg(s, at, S, args, single):
     one symmetry-function pass per evaluation.  Reports the time per
     evaluation and its ratio to the single network measured above (the
     ensemble's parity with the FP64 oracle is a GPU test)."""
+    progress("importing torch")
     import torch
     import workloads as w
     from paper_2310_03121_amd import Potential
+    progress("imports done")
     M = args.ensemble
     base = 101 if S == 7 else 100
     members = [w.mlp_table(S, seed=base + k) for k in range(M)]
@@ -455,8 +470,8 @@ def measured_peak(bound, prec, issue):
         key = "mfma_bf16" if prec == "bf16" else "mfma_fp32"
         return {"value": issue[key], "unit": "TFLOP/s", "what": f"{key} issue loop"}
     if bound == "alu":
-        return {"value": issue["valu_fma_fp32"], "unit": "TFLOP/s",
-                "what": "fp32 FMA issue loop (an FMA counts 2)"}
+        return {"value": issue["valu_fma_fp32"] / 2, "unit": "Tops/s",
+                "what": "fp32 FMA issue loop (one operation per FMA)"}
     src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -488,8 +503,13 @@ def serve_leg(srv, reqs, rate=None, id_base=0):
     nxt = 0
     lat = {}
     t0 = time.perf_counter()
+    t_report = 10.0
     while len(lat) < len(reqs):
         now = time.perf_counter() - t0
+        if now > t_report:  # a long leg still reports every 10 s
+            progress(f"  {len(lat)} of {len(reqs)} requests done, {srv.active} on the server, "
+                     f"{srv.pending} pending")
+            t_report += 10.0
         while nxt < len(reqs) and arrive[nxt] <= now:
             r = reqs[nxt]
             code = srv.submit(id_base + nxt, r.system.pos.astype(np.float64), r.vel,
@@ -532,10 +552,12 @@ def serving(at, mt, n_req=2000, n_warm=200, n_steps=100):
         srv = Server(pot, hbm_budget_bytes=16 << 30, max_atoms=8192, max_mols=256, dt_fs=0.5,
                      mass_amu=w.MASS_AMU)
         serve_leg(srv, warm, id_base=0)  # warm-up: graph capture, kernel attributes, pages
+        progress(f"serving {prec}: saturation")
         sat = serve_leg(srv, reqs, id_base=1 << 20)
         mu = sat["req_per_s"]
         r = {"saturation": sat}
         for k, f in enumerate((0.5, 0.8)):
+            progress(f"serving {prec}: open loop at {f} of saturation")
             r[f"open_loop_{f}mu"] = serve_leg(srv, reqs, rate=f * mu, id_base=(k + 2) << 20)
         out[prec] = r
         del srv
@@ -546,6 +568,7 @@ def serving(at, mt, n_req=2000, n_warm=200, n_steps=100):
             srv = Server(pot, hbm_budget_bytes=1 << 30, max_atoms=262144, max_mols=4096,
                          dt_fs=0.5, mass_amu=w.MASS_AMU)
             serve_leg(srv, warm, id_base=0)
+            progress("serving bf16: 1 GiB budget")
             out["bf16_budget_1GiB"] = {"saturation": serve_leg(srv, reqs, id_base=1 << 20)}
             del srv
         del pot
@@ -663,6 +686,7 @@ def main():
     for prec in precs:
         pot = Potential.from_tables(at, mt, precision=prec,
                                     max_neighbors=MAX_NEIGHBORS[args.workload])
+        progress(f"{prec}: timing {args.steps} evaluations")
         dt_eager, dt_graph, (E, F), stages = time_path(pot, pos, sp, off, box, args.steps,
                                                        args.warmup)
         dt = min(dt_eager, dt_graph)
@@ -675,12 +699,14 @@ def main():
         if prec == precs[0]:
             r["pairs"], r["triples"] = pair_counts(pot, s.n_atoms)
         if args.workload == "batch":
+            progress(f"{prec}: nnp_backward leg")
             r["backward"] = backward_leg(pot, pos, sp, off, box, max(args.steps // 5, 3),
                                          max(args.warmup // 5, 2), mt)
             bw = r["backward"]
             if bw["weight_grad_tflops"] is not None:
                 bw["weight_grad_frac_of_peak"] = bw["weight_grad_tflops"] / PEAK_TFLOPS[prec]
         if args.workload == "mol24":
+            progress(f"{prec}: latency leg")
             r["latency"] = latency_leg(pot, pos, sp, off, box)
         n_nve = args.nve if args.nve is not None else (1000 if args.workload == "water7667" else 0)
         if n_nve:
@@ -692,6 +718,7 @@ def main():
                                                 max_neighbors=MAX_NEIGHBORS[args.workload])
             else:
                 nve_pot = pot
+            progress(f"{prec}: NVE leg, {n_nve} steps")
             r["nve"] = nve_leg(nve_pot, s, n_steps=n_nve, dt=args.nve_dt,
                                relax_iters=args.nve_relax)
             r["nve"]["output_scale"] = args.nve_scale
@@ -717,17 +744,18 @@ def main():
         op_pair, op_trip = AEV_OPS[dom]
         ops = op_pair * main_r["pairs"] + op_trip * main_r["triples"]
         achieved = ops / (st[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic,
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS,
+                "unit": "Tops/s (FP32 lane operations)", "frac": achieved / PEAK_VALU_TOPS,
+                "traffic": traffic,
                 "flop_per_launch": ops, "avg_launch_ms": st[dom],
                 "pairs": main_r["pairs"], "triples": main_r["triples"]}
         pv = profiled_valu(dom, WORKLOAD_KEYS[args.workload] + "_" + main_prec)
         if pv is not None:
-            # issue-slot use: a wave64 VALU instruction occupies a 16-lane
-            # SIMD for 4 cycles; 1024 SIMDs at 2.4 GHz
+            # issue-slot use: a wave64 FP32 VALU instruction occupies a
+            # SIMD for 2 cycles (32 lanes per clock); 1024 SIMDs at 2.4 GHz
             per_wave, waves = pv
             roof["valu_instr_per_wave"] = per_wave
-            roof["valu_issue_frac"] = per_wave * waves * 4 / (1024 * 2.4e9 * st[dom] * 1e-3)
+            roof["valu_issue_frac"] = per_wave * waves * 2 / (1024 * 2.4e9 * st[dom] * 1e-3)
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": None, "traffic": traffic, "avg_launch_ms": st[dom]}
@@ -736,6 +764,7 @@ def main():
     roof["profiled_avg_ms"] = profiled_kernel_ms(dom, WORKLOAD_KEYS[args.workload] + "_" +
                                                  main_prec)
     # the same achieved rate against the ceiling measured here
+    progress("issue-loop ceilings")
     issue = issue_ceilings()
     mp = measured_peak(roof["bound"], main_prec, issue)
     roof["measured_peak"] = mp
@@ -775,16 +804,19 @@ def main():
         if k in main_r:
             out[k] = main_r[k]
     if not args.no_serve:
+        progress("serving legs")
         sv = serving(w.aev_table(7), w.mlp_table(7))
         out["serving"] = sv
         out["p99_latency_ms_bf16_0.8mu"] = sv["bf16"]["open_loop_0.8mu"]["p99_ms"]
     if args.ensemble > 1:
+        progress("ensemble leg")
         out["ensemble"] = ensemble_leg(s, at, S, args, results)
     if args.ceilings:
         out["ceilings"] = ceilings()
     if not args.no_cpu:
         # the oracle runs only here: the CPU baseline, whose last evaluation
         # of its sample also gives each path's force error
+        progress("CPU baseline (oracle)")
         out["cpu_baseline"], errs = cpu_baseline(s, S, gpu=forces)
         for prec, e in errs.items():
             target = out if prec == main_prec else out.get("fp32_path")

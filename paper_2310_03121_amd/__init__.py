@@ -455,9 +455,15 @@ class Server:
         return int(self._lib.nnp_server_pending(self._s))
 
     def poll(self, max_n=1024):
+        """Every delivered request id not reported before (the library hands
+        them out max_n per call; this drains the queue)."""
+        out = []
         ids = np.zeros(max_n, np.int64)
-        k = self._lib.nnp_server_poll(self._s, C.c_void_p(ids.ctypes.data), max_n)
-        return ids[:k].tolist()
+        while True:
+            k = self._lib.nnp_server_poll(self._s, C.c_void_p(ids.ctypes.data), max_n)
+            out += ids[:k].tolist()
+            if k < max_n:
+                return out
 
     def result(self, req_id, n_atoms, check=True):
         """Final state, energies and times of a delivered request.  With
