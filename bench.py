@@ -151,7 +151,8 @@ def profiled_valu(stage, workload_key):
             digest = line.split(":", 1)[1].strip()
         elif line.startswith("|") and not line.startswith("|--"):
             cells = [c.strip() for c in line.strip().strip("|").split("|")]
-            if len(cells) >= 4 and cells[0] == stage:
+            # the first table's row (a later table of the file holds MFMA counts)
+            if len(cells) >= 4 and cells[0] == stage and hit is None:
                 try:
                     hit = (float(cells[3]), float(cells[2]))
                 except ValueError:

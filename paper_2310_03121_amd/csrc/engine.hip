@@ -263,7 +263,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B, bool wgr
   P.grp = take(64);
   if (B.periodic) {
     P.cell_of = take(N * 4);
-    P.cell_cnt = take((size_t)(P.ncell + 1) * 4);  // counts, then the binning's done counter
+    P.cell_cnt = take(cell_zero_ints(P.ncell) * 4);  // counts and binning counters (zeroed)
     P.cell_start = take((size_t)(P.ncell + 1) * 4);
     P.cursor = take((size_t)P.ncell * 4);
     P.cell_atoms = take(N * 4);
@@ -353,7 +353,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     launch_stage(io.n_arg, io.nmol_arg, P.n, dims, io.pos, io.pos64, io.gidx, io.n_total,
                  io.species, io.off, S, xyzs, mol, mrange, io.gidx ? nullptr : io.out3, hist,
                  status, !io.keep_status, P.B.periodic ? at<int>(ws, P.cell_cnt) : nullptr,
-                 P.B.periodic ? P.ncell + 1 : 0, st);
+                 P.B.periodic ? cell_zero_ints(P.ncell) : 0, st);
     if (P.nblk > kFusedSortBlocks) {
       launch_groups(dims, P.n, S, hist, gt, perm, P.rows_cap, io.off, kWChunk, status, st);
       launch_scatter(dims, P.n, S, xyzs, hist, row, perm, st);
@@ -1080,7 +1080,7 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   int2* mrange = P.mrange ? at<int2>(ws, P.mrange) : nullptr;
   launch_stage(n, nmol, P.n, dims, pos, nullptr, nullptr, 0, species, off, h->S, xyzs,
                at<int>(ws, P.mol), mrange, nullptr, at<int>(ws, P.hist), status, true,
-               P.B.periodic ? at<int>(ws, P.cell_cnt) : nullptr, P.B.periodic ? P.ncell + 1 : 0,
+               P.B.periodic ? at<int>(ws, P.cell_cnt) : nullptr, P.B.periodic ? cell_zero_ints(P.ncell) : 0,
                st);
   launch_groups(dims, P.n, h->S, at<int>(ws, P.hist), at<GroupTable>(ws, P.gt),
                 at<int>(ws, P.perm), P.rows_cap, off, kWChunk, status, st);

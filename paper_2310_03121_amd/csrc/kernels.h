@@ -136,8 +136,13 @@ void launch_sort_pairs_mol(const int* dims, int n_cap, int S, const int* hist, G
                            const AevConst& C, const float4* xyzs, const int2* mrange, int cap,
                            int* nbr, float4* rec, int2* counts, uint32_t* status,
                            hipStream_t st);
-// Periodic boxes: cell_cnt holds ncell + 1 ints that staging zeroed (the
-// counts and the binning's done counter).
+// Periodic boxes: cell_cnt holds cell_zero_ints(ncell) ints that staging
+// zeroed: the per-cell counts, then (up to kCellScanLds cells) the fill
+// counters, or (more cells) the counting launch's done counter.
+constexpr int kCellScanLds = 8192;
+inline size_t cell_zero_ints(int ncell) {
+  return ncell <= kCellScanLds ? 2 * (size_t)ncell : (size_t)ncell + 1;
+}
 void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxConst& B,
                        const float4* xyzs, int* cell_of, int* cell_cnt, int* cell_start,
                        int* cursor, int* cell_atoms, float4* cell_xyzs, int cap, int* nbr,

@@ -160,6 +160,9 @@ __device__ __forceinline__ int cell_coord(float x, float L, float invL, float sc
 // counts into cell starts and fill cursors (an exclusive scan), so binning
 // needs no launch of its own for the scan.  Every workgroup takes part in the
 // done count, whatever its atoms.
+// Scan: the workgroup that finishes last also turns the counts into cell
+// starts (boxes with more cells than k_cell_fill_scan's LDS holds).
+template <bool Scan>
 __global__ __launch_bounds__(256) void k_cell_count(const int* __restrict__ dims, BoxConst B,
                                                     const float4* __restrict__ xyzs,
                                                     int* __restrict__ cell_of,
@@ -191,6 +194,7 @@ __global__ __launch_bounds__(256) void k_cell_count(const int* __restrict__ dims
     cell_of[i] = c;
     atomicAdd(&cell_cnt[c], 1);
   }
+  if constexpr (!Scan) return;
   __threadfence();
   __syncthreads();
   if (t == 0) is_last = atomicAdd(&cell_cnt[ncell], 1) == (int)gridDim.x - 1;
@@ -251,6 +255,54 @@ __global__ __launch_bounds__(256) void k_cell_fill(const int* __restrict__ dims,
   cell_xyzs[slot] = xyzs[i];
 }
 
+// Up to kCellScanLds cells: every workgroup scans the cell counts into LDS
+// itself (they are few: one pass of loads, no done counter and no
+// single-workgroup tail), workgroup 0 writes the starts for the pair search,
+// and each atom takes its slot from a per-cell fill counter.
+__global__ __launch_bounds__(256) void k_cell_fill_scan(
+    const int* __restrict__ dims, const float4* __restrict__ xyzs,
+    const int* __restrict__ cell_of, const int* __restrict__ cnt, int* __restrict__ fillc,
+    int ncell, int* __restrict__ start_out, int* __restrict__ cell_atoms,
+    float4* __restrict__ cell_xyzs) {
+  __shared__ int st[kCellScanLds + 1];
+  __shared__ int scan[256];
+  const int t = threadIdx.x;
+  constexpr int kPer = kCellScanLds / 256;
+  const int cb = t * kPer;
+  int v[kPer];
+  int sum = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    v[q] = cb + q < ncell ? cnt[cb + q] : 0;
+    sum += v[q];
+  }
+  scan[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int u = t >= o ? scan[t - o] : 0;
+    __syncthreads();
+    scan[t] += u;
+    __syncthreads();
+  }
+  int run = scan[t] - sum;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (cb + q < ncell) st[cb + q] = run;
+    run += v[q];
+  }
+  if (t == 255) st[ncell < kCellScanLds ? ncell : kCellScanLds] = scan[255];
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int c = t; c <= ncell; c += 256) start_out[c] = st[c];
+  const int n = dims[0];
+  const int i = blockIdx.x * blockDim.x + t;
+  if (i >= n) return;
+  const int c = cell_of[i];
+  const int slot = st[c] + atomicAdd(&fillc[c], 1);
+  cell_atoms[slot] = i;
+  cell_xyzs[slot] = xyzs[i];
+}
+
 // Cell-centred neighbor search: one workgroup per cell.  The workgroup stages
 // the records and indices of its stencil cells (the concatenation of up to 27
 // cells, at most kCandLds of them) in LDS once; its waves then take the
@@ -277,7 +329,7 @@ __global__ __launch_bounds__(1024) void k_pairs_cell_lds(
     const int* __restrict__ dims, AevConst C, BoxConst B, const int* __restrict__ cell_start,
     const int* __restrict__ cell_atoms, const float4* __restrict__ cell_xyzs, int cap,
     int* __restrict__ nbr, float4* __restrict__ rec, int2* __restrict__ counts,
-    uint32_t* __restrict__ status) {
+    uint32_t* __restrict__ status, int splits) {
   extern __shared__ float4 lds_cell[];
   float4* cand = lds_cell;
   int* cidx = reinterpret_cast<int*>(cand + kCandLds);
@@ -291,7 +343,9 @@ __global__ __launch_bounds__(1024) void k_pairs_cell_lds(
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   float4* lrec = lrec_all + (size_t)w * cap;
   int* key = key_all + (size_t)w * cap;
-  const int c = blockIdx.x;
+  // workgroups (c, part): with few cells, `splits` workgroups share a cell's
+  // atoms (each stages the cell's candidates)
+  const int c = (int)blockIdx.x / splits, part = (int)blockIdx.x % splits;
   const int cx = c % B.nc[0], cy = (c / B.nc[0]) % B.nc[1], cz = c / (B.nc[0] * B.nc[1]);
   // stencil: offsets -1..1 per binned dimension, only 0 where nc == 1
   const int rx = B.nc[0] >= 3 ? 1 : 0, ry = B.nc[1] >= 3 ? 1 : 0, rz = B.nc[2] >= 3 ? 1 : 0;
@@ -341,7 +395,7 @@ __global__ __launch_bounds__(1024) void k_pairs_cell_lds(
   }
   __syncthreads();
   const int c0 = cell_start[c], cn = cell_start[c + 1] - c0;
-  for (int a = w; a < cn; a += nw) {
+  for (int a = part * nw + w; a < cn; a += nw * splits) {
     const int i = cell_atoms[c0 + a];
     const float4 pi = cell_xyzs[c0 + a];
     int nr = 0, na = 0;
@@ -493,16 +547,26 @@ void launch_pairs_cell(const int* dims, int n_cap, const AevConst& C, const BoxC
                        float4* rec, int2* counts, uint32_t* status, hipStream_t st) {
   if (n_cap <= 0) return;
   const int ncell = B.nc[0] * B.nc[1] * B.nc[2];
-  // staging zeroed cell_cnt[0 .. ncell]
-  hipLaunchKernelGGL(k_cell_count, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, B, xyzs,
-                     cell_of, cell_cnt, ncell, cell_start, cursor);
-  hipLaunchKernelGGL(k_cell_fill, dim3((n_cap + 255) / 256), dim3(256), 0, st, dims, xyzs,
-                     cell_of, cursor, cell_atoms, cell_xyzs);
+  // staging zeroed cell_cnt[0 .. cell_zero_ints(ncell))
+  const dim3 grid((n_cap + 255) / 256);
+  if (ncell <= kCellScanLds) {
+    hipLaunchKernelGGL(k_cell_count<false>, grid, dim3(256), 0, st, dims, B, xyzs, cell_of,
+                       cell_cnt, ncell, cell_start, cursor);
+    hipLaunchKernelGGL(k_cell_fill_scan, grid, dim3(256), 0, st, dims, xyzs, cell_of, cell_cnt,
+                       cell_cnt + ncell, ncell, cell_start, cell_atoms, cell_xyzs);
+  } else {
+    hipLaunchKernelGGL(k_cell_count<true>, grid, dim3(256), 0, st, dims, B, xyzs, cell_of,
+                       cell_cnt, ncell, cell_start, cursor);
+    hipLaunchKernelGGL(k_cell_fill, grid, dim3(256), 0, st, dims, xyzs, cell_of, cursor,
+                       cell_atoms, cell_xyzs);
+  }
   static const bool attr = (ensure_lds(k_pairs_cell_lds), true);
   (void)attr;
-  hipLaunchKernelGGL(k_pairs_cell_lds, dim3(ncell), dim3(64 * pairs_cell_waves(cap)),
+  // at least about four workgroups per CU: boxes with few cells split them
+  const int splits = ncell >= 1024 ? 1 : (ncell >= 512 ? 2 : 4);
+  hipLaunchKernelGGL(k_pairs_cell_lds, dim3(ncell * splits), dim3(64 * pairs_cell_waves(cap)),
                      pairs_cell_lds_bytes(cap), st, dims, C, B, cell_start, cell_atoms, cell_xyzs,
-                     cap, nbr, rec, counts, status);
+                     cap, nbr, rec, counts, status, splits);
 }
 
 }  // namespace nnp
