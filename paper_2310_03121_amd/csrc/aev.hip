@@ -182,7 +182,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
                                                  const float4* __restrict__ rec,
                                                  const int2* __restrict__ counts, int cap,
                                                  const int* __restrict__ row_of,
-                                                 OutT* __restrict__ out, int ld) {
+                                                 OutT* __restrict__ out, int ld,
+                                                 unsigned long long* __restrict__ kmask,
+                                                 int sparse) {
   extern __shared__ float4 lds4[];
   const int n = dims[0];
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -257,13 +259,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
     const float4* nda = nd + base;
     const float2* nfa = nf + base;
     const int* nspa = nsp + base;
-    OutT* orow = out + (size_t)(row_of ? row_of[i] : i) * ld;
-
+    const int orow_i = row_of ? row_of[i] : i;
+    OutT* orow = out + (size_t)orow_i * ld;
     // ---- radial: G[s][m] = sum over neighbors e of [species(e) == s] * term(e, m)
     // as MFMA products of a one-hot (species x 4 neighbors) with the terms
     // (4 neighbors x 16 shifts); lane (kq, l16) computes neighbor kq, shift l16.
+    // With kmask, the same products also count each element's neighbors
+    // (all, and angular ones), which fixes the k-steps (32 feature columns)
+    // holding a block this atom touches: the radial blocks of the elements
+    // among its neighbors, the angular blocks of the element pairs among its
+    // angular neighbors (a pair (a, a) needs two of them).  Every other
+    // feature is zero, and the adjoint reads no dE/dG column outside them.
+    unsigned long long kbits = ~0ull;
+    unsigned sput = ~0u;
     {
       aev_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      aev_f32x4 cnt = acc;
       for (int e0 = 0; e0 < nr; e0 += 4) {
         const int e = e0 + kq;
         float term = 0.f, hot = 0.f;
@@ -273,8 +284,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
           hot = nspa[e] == l16 ? 1.f : 0.f;
         }
         acc = mfma4(term, hot, acc);
+        // (neighbors + 4096 x angular neighbors: exact, lists hold <= 512)
+        if (kmask) cnt = mfma4(e < na ? 4097.f : 1.f, hot, cnt);
       }
-      if (l16 < S)
+      if (kmask) {
+        // lane l16 < S (of the first 16) holds element l16's counts
+        const unsigned lm = (1u << S) - 1u;
+        const unsigned rp = (unsigned)__ballot(cnt[0] > 0.5f) & lm;
+        const unsigned ap = (unsigned)__ballot(cnt[0] > 4095.5f) & lm;
+        const unsigned ad = (unsigned)__ballot(cnt[0] > 8191.5f) & lm;
+        // element x's row of the angular triangle, blocks (x, x + k), starts
+        // at block x S - x (x - 1) / 2; (x, y > x) is touched when both
+        // elements are among the angular neighbors, (x, x) when x is twice
+        unsigned long long bm = 0;
+        for (unsigned r = ap; r; r &= r - 1u) {
+          const int x = __builtin_ctz(r);
+          const unsigned row = (((ap >> x) & ~1u) | ((ad >> x) & 1u)) & ((1u << (S - x)) - 1u);
+          bm |= (unsigned long long)row << (x * S - x * (x - 1) / 2);
+        }
+        const unsigned r2 = rp | (rp >> 1);  // k-step j holds elements 2j and 2j + 1
+        kbits = (unsigned long long)((r2 & 1u) | ((r2 >> 1) & 2u) | ((r2 >> 2) & 4u) |
+                                     ((r2 >> 3) & 8u)) |
+                (bm << (S >> 1)) | ((S & 1) ? bm << ((S >> 1) + 1) : 0ull);
+        if (lane == 0) kmask[orow_i] = kbits;
+        if (sparse) {
+          // this lane's stores: bit 0 radial, bits 1 + 2 u and 2 + 2 u the
+          // two halves of angular tile u
+          sput = (unsigned)(kbits >> (l16 >> 1)) & 1u;
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            const int c = S * kNR + l16 * 32 + 4 * kq + 512 * u;
+            sput |= ((unsigned)(kbits >> (c >> 5)) & 1u) << (1 + 2 * u);
+            sput |= ((unsigned)(kbits >> ((c + 16) >> 5)) & 1u) << (2 + 2 * u);
+          }
+        }
+      }
+      if (l16 < S && (sput & 1u))
         Store<OutT>::put4(orow + l16 * kNR + 4 * kq, make_float4(acc[0], acc[1], acc[2], acc[3]));
     }
 
@@ -329,9 +374,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
         if (l16 + 16 * u < nblk) {
-          Store<OutT>::put4(ang + 512 * u, make_float4(c0[u][0], c0[u][1], c0[u][2], c0[u][3]));
-          Store<OutT>::put4(ang + 512 * u + 16,
-                            make_float4(c1[u][0], c1[u][1], c1[u][2], c1[u][3]));
+          if (sput & (2u << (2 * u)))
+            Store<OutT>::put4(ang + 512 * u, make_float4(c0[u][0], c0[u][1], c0[u][2], c0[u][3]));
+          if (sput & (4u << (2 * u)))
+            Store<OutT>::put4(ang + 512 * u + 16,
+                              make_float4(c1[u][0], c1[u][1], c1[u][2], c1[u][3]));
         }
       }
     }
@@ -993,7 +1040,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 template <typename OutT, int Q>
 static void launch_aev_fwd_q(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                              const int2* counts, int cap, const int* row_of, OutT* out, int ld,
-                             hipStream_t st) {
+                             unsigned long long* kmask, bool sparse, hipStream_t st) {
   const size_t lds = (size_t)4 * aev_region(cap) * kFwdBytesPerNbr +
                      (size_t)4 * kPairChunk * kFwdPairBytes;
   static const bool attr = (ensure_lds(k_aev_fwd<OutT, 1, Q>), ensure_lds(k_aev_fwd<OutT, 2, Q>),
@@ -1004,24 +1051,28 @@ static void launch_aev_fwd_q(const int* dims, int n_cap, const AevConst& C, cons
                          : (nblk <= 32 ? k_aev_fwd<OutT, 2, Q> : k_aev_fwd<OutT, 3, Q>);
   const int per_block = 4 * Q;
   hipLaunchKernelGGL(kern, dim3((n_cap + per_block - 1) / per_block), dim3(256), lds, st, dims, C,
-                     rec, counts, cap, row_of, out, ld);
+                     rec, counts, cap, row_of, out, ld, kmask, sparse ? 1 : 0);
 }
 
 template <typename OutT>
 void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int2* counts, int cap, const int* row_of, OutT* out, int ld, bool det,
-                    hipStream_t st) {
+                    unsigned long long* kmask, bool sparse, hipStream_t st) {
   if (n_cap <= 0) return;
+  sparse = sparse && kmask && ld <= 64 * 32;
   if (aev_quads(cap) && !det)
-    launch_aev_fwd_q<OutT, 4>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, st);
+    launch_aev_fwd_q<OutT, 4>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, kmask, sparse,
+                              st);
   else
-    launch_aev_fwd_q<OutT, 1>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, st);
+    launch_aev_fwd_q<OutT, 1>(dims, n_cap, C, rec, counts, cap, row_of, out, ld, kmask, sparse,
+                              st);
 }
 template void launch_aev_fwd<float>(const int*, int, const AevConst&, const float4*, const int2*,
-                                    int, const int*, float*, int, bool, hipStream_t);
+                                    int, const int*, float*, int, bool, unsigned long long*, bool,
+                                    hipStream_t);
 template void launch_aev_fwd<bf16_t>(const int*, int, const AevConst&, const float4*,
                                      const int2*, int, const int*, bf16_t*, int, bool,
-                                     hipStream_t);
+                                     unsigned long long*, bool, hipStream_t);
 
 template <typename GT, int Q>
 static void launch_aev_bwd_q(const int* dims, int n_cap, const AevConst& C, const float4* rec,

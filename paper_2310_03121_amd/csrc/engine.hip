@@ -159,6 +159,7 @@ struct Plan {
   size_t status, dims, gt, xyzs, mol, mrange, row, perm, hist, nbr, counts, rec;
   size_t cell_of, cell_cnt, cell_start, cursor, cell_atoms, cell_xyzs;
   size_t X, H1, H2, H3, D3, D2, D1, G, erow, uprow, wpart, pos32;
+  size_t kmask;  // per feature row: the k-steps that may be nonzero
   size_t pgrad;  // deterministic mode: per-entry adjoint rows [n][cap]
   size_t grp;    // owned/ghost evaluation: group offsets (3 int) and upstream (2 double)
 };
@@ -275,6 +276,7 @@ Plan make_plan(const nnp_handle* h, int n, int nmol, const BoxConst& B, bool wgr
   }
   const int w1 = h->width[1], w2 = h->width[2], w3 = h->width[3];
   P.X = take(R * h->Fp * esz);
+  P.kmask = take(R * 8);
   P.H1 = take(R * w1 * esz);
   P.H2 = take(R * w2 * esz);
   P.H3 = take(R * w3 * esz);
@@ -378,9 +380,18 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     }
   }
   T* X = at<T>(ws, P.X);
+  unsigned long long* kmask = at<unsigned long long>(ws, P.kmask);
+  // BF16 with gradients, one network: layer 1, the fused middle and dE/dG
+  // in one launch per tile (H1 and D1 stay in LDS)
+  const bool net_path = bf && need_bwd && h->n_models == 1 && h->width[1] == 256 &&
+                        h->width[2] == 192 && h->width[3] == 160 && Fp % 256 == 0 &&
+                        Fp <= 2048;
   {
     StageTimer t(h, io.timed, ST_AEV, st);
-    launch_aev_fwd<T>(dims, P.n, h->C, rec, counts, P.cap, row, X, Fp, h->deterministic, st);
+    // the whole-network kernel reads each row's own k-steps only; the weight
+    // gradients and the layer kernels read whole rows
+    launch_aev_fwd<T>(dims, P.n, h->C, rec, counts, P.cap, row, X, Fp, h->deterministic, kmask,
+                      net_path && !io.dparams, st);
   }
 
   T* H1 = at<T>(ws, P.H1);
@@ -430,11 +441,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     for (int l = 0; l < kLayers - 1; ++l) bias_k[l] = h->bias[l] + (size_t)q0 * h->width[l + 1];
     const float* wout_k = h->wout + (size_t)q0 * w3;
     const float* bout_k = h->bout + q0;
-    // BF16 with gradients, one network: layer 1, the fused middle and dE/dG
-    // in one launch per tile (H1 and D1 stay in LDS)
-    const bool can_net =
-        h->width[1] == 256 && h->width[2] == 192 && h->width[3] == 160 && Fp % 256 == 0;
-    if (bf && need_bwd && M == 1 && can_net) {
+    if (net_path) {
       MidArgs ma{};
       ma.gt = gt;
       ma.W1 = static_cast<const bf16_t*>(Wqk[1]);
@@ -468,11 +475,12 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
       ma.H1out = reinterpret_cast<bf16_t*>(H1);
       ma.W0T = static_cast<const bf16_t*>(WTq[0]);
       ma.G = io.out3 ? reinterpret_cast<bf16_t*>(G) : nullptr;
+      ma.kmask = kmask;
       StageTimer t(h, io.timed, ST_NET, st);
-      if (launch_mlp_net(h->width, ma, P.rows_cap, st)) {
-        net_fused = true;
-        continue;
-      }
+      // (the feature rows may be stored sparse: no other kernel may take over)
+      ok &= launch_mlp_net(h->width, ma, P.rows_cap, st);
+      net_fused = true;
+      continue;
     }
     GemmArgs g{};
     g.gt = gt;
@@ -1093,7 +1101,7 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
     launch_pairs_mol(dims, P.n, h->C, xyzs, mrange, P.cap, at<int>(ws, P.nbr),
                      at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
   launch_aev_fwd<float>(dims, P.n, h->C, at<float4>(ws, P.rec), at<int2>(ws, P.counts), P.cap,
-                        nullptr, aev, h->F, h->deterministic, st);
+                        nullptr, aev, h->F, h->deterministic, nullptr, false, st);
   return launches_ok() ? NNP_OK : NNP_E_HIP;
 }
 

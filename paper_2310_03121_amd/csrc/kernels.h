@@ -70,6 +70,10 @@ struct MidArgs {
   bf16_t* H1out = nullptr;        // [rows][W1]: H1, also read back for the last slopes
   const bf16_t* W0T = nullptr;    // [S][ldx][W1], fragment order
   bf16_t* G = nullptr;            // [rows][ldx] dE/dG, or null (no forces)
+  // optional [rows]: per row, the k-steps (32 columns of X) that may be
+  // nonzero (launch_aev_fwd's kmask); X is read, and G written, only there.
+  // Null: every k-step (ldx <= 2048 either way).
+  const unsigned long long* kmask = nullptr;
 };
 
 // Weight slots: member k of an ensemble, element s -> slot k * S + s.
@@ -159,11 +163,14 @@ void launch_force_gather(const int* dims, int n_cap, const float4* xyzs, const f
 
 // aev.hip
 // det: one atom per wave whatever the capacity (the order of every sum is
-// then a function of the atom's own list only)
+// then a function of the atom's own list only).  kmask (optional, [rows]):
+// per row, bit q set when k-step q (feature columns 32 q .. 32 q + 31) holds
+// a block the atom touches; sparse (needs kmask and ld <= 2048): only those
+// k-steps of the row are stored (the rest of the row is left as it was).
 template <typename OutT>
 void launch_aev_fwd(const int* dims, int n_cap, const AevConst& C, const float4* rec,
                     const int2* counts, int cap, const int* row_of, OutT* out, int ld, bool det,
-                    hipStream_t st);
+                    unsigned long long* kmask, bool sparse, hipStream_t st);
 // pgrad: the deterministic adjoint, writing per-entry rows to pgrad (the
 // caller then runs launch_force_gather) instead of scattering into out
 template <typename GT>

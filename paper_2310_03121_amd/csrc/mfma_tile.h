@@ -87,6 +87,93 @@ struct BRing {
   }
 };
 
+// A ring over a compacted list of k-steps: position s of the product is
+// k-step `qlist` of lane s (qlist holds the tile's active k-steps in order,
+// one per lane), so steps whose A columns are zero for the whole tile are
+// never issued.  Positions from ns on re-read the last active step (k-step 0
+// when there is none), which keeps every access inside B.
+template <typename T, int TN, int P>
+struct BRingQ {
+  static constexpr int FE = 64 * Frag<T>::EL;
+  uint4 r[P][TN];
+  const T* base;  // fragment (n_first / 16, 0) + this lane
+  size_t tile;
+  int ns;         // active k-steps (uniform)
+  int qlist;      // lane l: the k-step of position l
+  __device__ __forceinline__ void init(const T* B, int n_first, int lane, int K, int ns_,
+                                       int qlist_) {
+    tile = (size_t)(K / Frag<T>::KS) * FE;
+    base = B + (size_t)(n_first / 16) * tile + lane * Frag<T>::EL;
+    ns = ns_;
+    qlist = qlist_;
+  }
+  template <int U>
+  __device__ __forceinline__ void load(int s) {
+    const int pc = s < ns ? s : (ns > 0 ? ns - 1 : 0);
+    const int q = __builtin_amdgcn_readlane(qlist, pc);
+    const T* p = base + (size_t)q * FE;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) r[U][j] = *reinterpret_cast<const uint4*>(p + j * tile);
+  }
+  template <int U = 0>
+  __device__ __forceinline__ void prologue() {
+    if constexpr (U < P) {
+      load<U>(U);
+      prologue<U + 1>();
+    }
+  }
+};
+
+// A ring for a product whose four 16-column tiles come in two pairs at
+// arbitrary places: tiles (2 c0, 2 c0 + 1, 2 c1, 2 c1 + 1) of B (K dense,
+// ns = K / KS steps, a multiple of P).  Steps from ns on read the next
+// pass's pair of pairs, as BRing does.
+template <typename T, int P>
+struct BRingPair {
+  static constexpr int FE = 64 * Frag<T>::EL;
+  uint4 r[P][4];
+  const T* b0;
+  const T* b1;   // this pass
+  const T* n0;
+  const T* n1;   // the next one
+  size_t tile;
+  int ns;
+  __device__ __forceinline__ const T* at(const T* B, int c, int lane) const {
+    return B + (size_t)(2 * c) * tile + lane * Frag<T>::EL;
+  }
+  __device__ __forceinline__ void init(const T* B, int K, int lane, int c0, int c1, int d0,
+                                       int d1) {
+    ns = K / Frag<T>::KS;
+    tile = (size_t)ns * FE;
+    b0 = at(B, c0, lane);
+    b1 = at(B, c1, lane);
+    n0 = at(B, d0, lane);
+    n1 = at(B, d1, lane);
+  }
+  __device__ __forceinline__ void next_pass(const T* B, int d0, int d1, int lane) {
+    b0 = n0;
+    b1 = n1;
+    n0 = at(B, d0, lane);
+    n1 = at(B, d1, lane);
+  }
+  template <int U>
+  __device__ __forceinline__ void load(int s) {
+    const T* p0 = s < ns ? b0 + (size_t)s * FE : n0 + (size_t)(s - ns) * FE;
+    const T* p1 = s < ns ? b1 + (size_t)s * FE : n1 + (size_t)(s - ns) * FE;
+    r[U][0] = *reinterpret_cast<const uint4*>(p0);
+    r[U][1] = *reinterpret_cast<const uint4*>(p0 + tile);
+    r[U][2] = *reinterpret_cast<const uint4*>(p1);
+    r[U][3] = *reinterpret_cast<const uint4*>(p1 + tile);
+  }
+  template <int U = 0>
+  __device__ __forceinline__ void prologue() {
+    if constexpr (U < P) {
+      load<U>(U);
+      prologue<U + 1>();
+    }
+  }
+};
+
 template <int TM>
 __device__ __forceinline__ void load_a(const unsigned char* arow, int astride16, uint4 (&fa)[TM]) {
 #pragma unroll
@@ -99,9 +186,9 @@ __device__ __forceinline__ void load_a(const unsigned char* arow, int astride16,
 // then (if REFILL) the slot is refilled with step s_next.  The scheduling
 // barrier keeps the refill right behind the step: left alone, the compiler
 // sinks all refills of a group to its end, which removes the prefetch.
-template <typename T, int TM, int TN, int P, int U, bool REFILL, bool PREF>
+template <typename T, int TM, int TN, int P, int U, bool REFILL, bool PREF, typename Ring>
 __device__ __forceinline__ void kstep(const unsigned char* anext, int astride16,
-                                      BRing<T, TN, P>& br, int s_next, f32x4_t (&acc)[TM][TN],
+                                      Ring& br, int s_next, f32x4_t (&acc)[TM][TN],
                                       const uint4 (&fa)[TM], uint4 (&fn)[TM]) {
   if constexpr (PREF) load_a<TM>(anext, astride16, fn);
 #pragma unroll
@@ -114,8 +201,8 @@ __device__ __forceinline__ void kstep(const unsigned char* anext, int astride16,
 
 // A group of P consecutive k-steps s0 .. s0+P-1 (s0 a multiple of P), A
 // starting at `ap` for step s0; every step refills its slot with step + P.
-template <typename T, int TM, int TN, int P>
-__device__ __forceinline__ void kgroup(const unsigned char* ap, int astride16, BRing<T, TN, P>& br,
+template <typename T, int TM, int TN, int P, typename Ring>
+__device__ __forceinline__ void kgroup(const unsigned char* ap, int astride16, Ring& br,
                                        int s0, f32x4_t (&acc)[TM][TN]) {
   static_assert(P == 4, "four steps per group");
   constexpr int SB = Frag<T>::KS * sizeof(T);

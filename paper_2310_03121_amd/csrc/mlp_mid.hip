@@ -303,14 +303,35 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
 //   G = D1 W0                   D1 resident in X1, four passes of 256
 //                               columns, staged per wave in region A for
 //                               whole-row-segment stores
+// Feature rows are sparse: an atom touches the blocks of the elements
+// around it only (about an eighth of the row in the 64-atom conformations,
+// the element pairs of water in a box).  With per-row masks of the k-steps
+// (32 columns) that may be nonzero, a tile runs layer 1 and dE/dG over the
+// union of its rows' k-steps only (a compacted k-step list, one entry per
+// lane: about half the steps for the conformations), each row reads its own
+// k-steps of X (the rest load as zero), and each row's dE/dG is written on
+// its own k-steps only, which are all the symmetry-function adjoint reads.
+// The skipped steps would add exact zeros, so the results do not change.
 // LDS: region A (two chunk buffers, 69,632 bytes) + X1 (128 rows of 528
-// bytes) = 137,216 bytes.
+// bytes) + the rows' masks (1,024 bytes) = 138,240 bytes.
 constexpr int kNetChunk = 256;                  // bytes of K per row and chunk
 constexpr int kNetChunkStride = kNetChunk + 16;
 
 template <int W1, int W2, int W3>
 constexpr size_t net_lds() {
-  return (size_t)2 * kMidBM * kNetChunkStride + (size_t)kMidBM * (W1 * 2 + 16);
+  return (size_t)2 * kMidBM * kNetChunkStride + (size_t)kMidBM * (W1 * 2 + 16) +
+         (size_t)kMidBM * 8;
+}
+
+// Lane l: the l-th set bit of m (0 when m has at most l set bits).
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int l) {
+  int q = 0;
+#pragma unroll
+  for (int w = 32; w; w >>= 1) {
+    const int t = q + w;
+    if (__popcll(m & ((1ull << t) - 1ull)) <= l) q = t;
+  }
+  return l < __popcll(m) ? q : 0;
 }
 
 template <int W1, int W2, int W3>
@@ -323,6 +344,7 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned char* RAp = smem;
   unsigned char* X1 = smem + RA;
+  unsigned long long* rmask = reinterpret_cast<unsigned long long*>(X1 + BM * S1);
   unsigned char* X2 = RAp;
   float* epart = reinterpret_cast<float*>(X2 + BM * S2);
 
@@ -333,29 +355,63 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
   const int s = tile_species(gt, row0);
   const int row_end = gt->pstart[s] + gt->cnt[s];
   if (row0 >= row_end) return;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int rl = lane & 15, cq = (lane >> 4) * 4;
   constexpr int WM = 2, WN = 4, TM = 4, TN = W1 / 64, P = 4;
   static_assert(WM * TM * 16 == BM && WN * TN * 16 == W1, "one pass covers layer 1");
   const int wm = wv / WN, wn = wv % WN;
   const int K = a.ldx;
 
-  // ---- layer 1: H1 = CELU(X W0^T + b0)
+  // ---- the tile's k-steps: the union of its rows' masks, compacted into
+  // qlist (lane l: the l-th active k-step); rows past the group have none
+  const int nks = K / Frag<bf16_t>::KS;
+  const unsigned long long all = nks >= 64 ? ~0ull : (1ull << nks) - 1ull;
+  auto row_mask = [&](int r) -> unsigned long long {
+    if (!a.kmask) return all;
+    return row0 + r < row_end ? a.kmask[row0 + r] & all : 0ull;
+  };
+  unsigned long long U;
+  {
+    const unsigned long long m0 = row_mask(lane), m1 = row_mask(lane + 64);
+    if (tid < BM) rmask[tid] = wv == 0 ? m0 : m1;
+    unsigned lo = (unsigned)(m0 | m1), hi = (unsigned)((m0 | m1) >> 32);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      lo |= __shfl_xor(lo, d, 64);
+      hi |= __shfl_xor(hi, d, 64);
+    }
+    U = ((unsigned long long)__builtin_amdgcn_readfirstlane(hi) << 32) |
+        (unsigned)__builtin_amdgcn_readfirstlane(lo);
+  }
+  const int nact = __popcll(U);
+  const int qlist = nth_set_bit(U, lane);
+
+  // ---- layer 1: H1 = CELU(X W0^T + b0), over the active k-steps, four per
+  // chunk; thread t loads 16-byte piece t % 4 of chunk slot (t / 4) % 4 of
+  // rows t / 16 + 32 v
   {
     constexpr int KC = kNetChunk / 2;           // bf16 per chunk row
     constexpr int SPC = KC / Frag<bf16_t>::KS;  // k-steps per chunk
     static_assert(SPC == P, "one ring cycle per chunk");
     constexpr int VPR = kNetChunk / 16;
     constexpr int NVA = BM * VPR / 512;
+    static_assert(VPR == 16 && NVA == 4, "four rows per thread, a fixed piece of each");
     const __amdgpu_buffer_rsrc_t arsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<bf16_t*>(a.X + (size_t)row0 * K), (short)0, (row_end - row0) * K * 2,
         kBufferRsrcWord3);
+    const int slot = (tid >> 2) & 3, piece = tid & 3;
+    unsigned long long rm[NVA];
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) rm[v] = row_mask((tid >> 4) + 32 * v);
     auto aload = [&](int c, uint4 (&ra)[NVA]) __attribute__((always_inline)) {
+      const int pos = c * SPC + slot;
+      const int q = __shfl(qlist, pos & 63, 64);
 #pragma unroll
       for (int v = 0; v < NVA; ++v) {
-        const int idx = tid + v * 512;
-        const int r = idx / VPR, k = c * KC + (idx % VPR) * 8;
-        const unsigned off = k < K ? (unsigned)((r * K + k) * 2) : kOutOfRange;
+        const int r = (tid >> 4) + 32 * v;
+        const bool on = pos < nact && ((rm[v] >> q) & 1ull);
+        const unsigned off = on ? (unsigned)((r * K + q * 32 + piece * 8) * 2) : kOutOfRange;
         const u32x4_t val = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
         ra[v] = make_uint4(val[0], val[1], val[2], val[3]);
       }
@@ -368,12 +424,12 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
         *reinterpret_cast<uint4*>(base + (idx / VPR) * kNetChunkStride + (idx % VPR) * 16) = ra[v];
       }
     };
-    const int nu = (K + KC - 1) / KC;
+    const int nu = nact > SPC ? (nact + SPC - 1) / SPC : 1;
     const int arow = (wm * TM * 16 + (lane & 15)) * kNetChunkStride + (lane >> 4) * 16;
     f32x4_t acc[TM][TN];
     zero_acc(acc);
-    BRing<bf16_t, TN, P> br;
-    br.init(a.W0 + (size_t)s * W1 * K, wn * TN * 16, -1, lane, K);
+    BRingQ<bf16_t, TN, P> br;
+    br.init(a.W0 + (size_t)s * W1 * K, wn * TN * 16, lane, K, nact, qlist);
     br.prologue();
     uint4 ra0[NVA], ra1[NVA];
     aload(0, ra0);
@@ -425,46 +481,51 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
   if (!a.G) return;  // block-uniform: no forces asked for
   __syncthreads();   // D1 in X1; region A free
 
-  // ---- dE/dG: G = D1 W0, passes of W1 columns of the ldx
+  // ---- dE/dG: G = D1 W0 over the tile's active k-steps, eight per pass:
+  // wave (wm, wn) takes positions 8 p + 2 wn and 8 p + 2 wn + 1 (column
+  // tiles 2 q0, 2 q0 + 1, 2 q1, 2 q1 + 1) for rows wm * 64 .. + 63
   {
-    constexpr int NP = WN * TN * 16;
+    static_assert(TN == 4, "two k-steps of 32 columns per wave and pass");
     constexpr int SS = TN * 16 * 2 + 16;        // staging row stride (bytes)
-    constexpr int WCOLB = TN * 16 * 2;          // bytes of a wave's tile row
-    const int npass = K / NP;
-    const int col_w = wn * TN * 16;
+    constexpr int VR = TN * 16 * 2 / 16;        // 16-byte vectors of a wave's tile row
+    const int npw = nact > 2 * wn ? (nact - 2 * wn + 7) / 8 : 0;  // this wave's passes
+    auto qat = [&](int pos) -> int {
+      return __builtin_amdgcn_readlane(qlist, pos < nact ? pos : (nact > 0 ? nact - 1 : 0));
+    };
     const bf16_t* B = a.W0T + (size_t)s * K * W1;
-    BRing<bf16_t, TN, P> br;
-    br.init(B, col_w, npass > 1 ? NP + col_w : -1, lane, W1);
-    br.prologue();
+    BRingPair<bf16_t, P> br;
+    br.init(B, W1, lane, qat(2 * wn), qat(2 * wn + 1), qat(8 + 2 * wn), qat(8 + 2 * wn + 1));
+    if (npw > 0) br.prologue();
     const int arow = (wm * TM * 16 + (lane & 15)) * S1 + (lane >> 4) * 16;
     unsigned char* stg = RAp + wv * 16 * SS;
     f32x4_t acc[TM][TN];
-    for (int p = 0; p < npass; ++p) {
+    for (int p = 0; p < npw; ++p) {
+      const int pos0 = 8 * p + 2 * wn;
+      const bool two = pos0 + 1 < nact;
+      const int q0 = qat(pos0), q1 = qat(pos0 + 1);
       zero_acc(acc);
 #pragma unroll
       for (int c = 0; c < W1 / 128; ++c)
         kgroup<bf16_t, TM, TN, P>(X1 + arow + c * 256, 16 * S1, br, c * P, acc);
-      br.next_pass(B, p + 2 < npass ? (p + 2) * NP + col_w : -1, lane);
+      br.next_pass(B, qat(pos0 + 16), qat(pos0 + 17), lane);
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int rloc = wm * TM * 16 + i * 16;
-        const bool rv = row0 + rloc + rl < row_end;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          float4 v = make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
-          if (!rv) v = make_float4(0.f, 0.f, 0.f, 0.f);
-          lds_put4(stg + rl * SS + (j * 16 + cq) * 2, v);
-        }
+        for (int j = 0; j < TN; ++j)
+          lds_put4(stg + rl * SS + (j * 16 + cq) * 2,
+                   make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]));
         wave_lds_sync();
-        constexpr int VR = WCOLB / 16;
+        static_assert(16 * VR % 64 == 0, "whole store rounds");
 #pragma unroll
-        for (int q = 0; q < (16 * VR + 63) / 64; ++q) {
-          const int idx = lane + q * 64;
-          if (16 * VR % 64 == 0 || idx < 16 * VR) {
-            const int r = idx / VR, cv = idx % VR;
+        for (int u = 0; u < 16 * VR / 64; ++u) {
+          const int idx = lane + u * 64;
+          const int r = idx / VR, cv = idx % VR, h = cv >> 2;
+          const int q = h ? q1 : q0;
+          if ((h == 0 || two) && row0 + rloc + r < row_end && ((rmask[rloc + r] >> q) & 1ull)) {
             const uint4 val = *reinterpret_cast<const uint4*>(stg + r * SS + cv * 16);
             unsigned char* dst = reinterpret_cast<unsigned char*>(a.G) +
-                                 ((size_t)(row0 + rloc + r) * K + p * NP + col_w) * 2 + cv * 16;
+                                 ((size_t)(row0 + rloc + r) * K + q * 32 + (cv & 3) * 8) * 2;
             *reinterpret_cast<uint4*>(dst) = val;
           }
         }
@@ -489,7 +550,8 @@ static void launch_mid_t(const MidArgs& a, int rows_cap, hipStream_t st) {
 
 bool launch_mlp_net(const int* width, const MidArgs& a, int rows_cap, hipStream_t st) {
   if (!(width[1] == 256 && width[2] == 192 && width[3] == 160)) return false;
-  if (a.ldx <= 0 || a.ldx % 256 != 0 || !a.X || !a.W0 || !a.W0T || !a.H1out) return false;
+  if (a.ldx <= 0 || a.ldx % 256 != 0 || a.ldx > 2048 || !a.X || !a.W0 || !a.W0T || !a.H1out)
+    return false;
   constexpr size_t lds = net_lds<256, 192, 160>();
   static const bool attr = (ensure_lds(k_mlp_net<256, 192, 160>), true);
   (void)attr;
