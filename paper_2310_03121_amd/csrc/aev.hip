@@ -264,8 +264,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
     // ---- radial: G[s][m] = sum over neighbors e of [species(e) == s] * term(e, m)
     // as MFMA products of a one-hot (species x 4 neighbors) with the terms
     // (4 neighbors x 16 shifts); lane (kq, l16) computes neighbor kq, shift l16.
-    // With kmask, the same products also count each element's neighbors
-    // (all, and angular ones), which fixes the k-steps (32 feature columns)
+    // With kmask, the lanes also count each element's neighbors (all, and
+    // angular ones), which fixes the k-steps (32 feature columns)
     // holding a block this atom touches: the radial blocks of the elements
     // among its neighbors, the angular blocks of the element pairs among its
     // angular neighbors (a pair (a, a) needs two of them).  Every other
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
     unsigned sput = ~0u;
     {
       aev_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      aev_f32x4 cnt = acc;
+      float cnt = 0.f;  // lane (kq, l16): element l16 among entries kq, kq + 4, ...
       for (int e0 = 0; e0 < nr; e0 += 4) {
         const int e = e0 + kq;
         float term = 0.f, hot = 0.f;
@@ -285,14 +285,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
         }
         acc = mfma4(term, hot, acc);
         // (neighbors + 4096 x angular neighbors: exact, lists hold <= 512)
-        if (kmask) cnt = mfma4(e < na ? 4097.f : 1.f, hot, cnt);
+        if (kmask) cnt += (e < na ? 4097.f : 1.f) * hot;
       }
       if (kmask) {
-        // lane l16 < S (of the first 16) holds element l16's counts
+        // the four entry groups' counts: lane l16 < S then holds element l16's
+        cnt += __shfl_xor(cnt, 16, kWave);
+        cnt += __shfl_xor(cnt, 32, kWave);
         const unsigned lm = (1u << S) - 1u;
-        const unsigned rp = (unsigned)__ballot(cnt[0] > 0.5f) & lm;
-        const unsigned ap = (unsigned)__ballot(cnt[0] > 4095.5f) & lm;
-        const unsigned ad = (unsigned)__ballot(cnt[0] > 8191.5f) & lm;
+        const unsigned rp = (unsigned)__ballot(cnt > 0.5f) & lm;
+        const unsigned ap = (unsigned)__ballot(cnt > 4095.5f) & lm;
+        const unsigned ad = (unsigned)__ballot(cnt > 8191.5f) & lm;
         // element x's row of the angular triangle, blocks (x, x + k), starts
         // at block x S - x (x - 1) / 2; (x, y > x) is touched when both
         // elements are among the angular neighbors, (x, x) when x is twice

@@ -23,50 +23,44 @@ namespace nnp {
 
 constexpr int kMidBM = 128;
 
-// Wave layout of a product with N columns in one pass: 2 x 4 waves of
-// 64 x (N/4) when N is a multiple of 64, else 4 x 2 waves of 32 x (N/2).
-template <int N>
+// Wave layout of a product with N columns over a tile of BM rows in one
+// pass: BM/64 x 4 waves of 64 x (N/4) when N is a multiple of 64, else
+// BM/32 x 2 waves of 32 x (N/2) (eight waves for 128 rows, four for 64).
+template <int N, int BM = kMidBM>
 struct MidCfg {
   static constexpr bool wide = N % 64 == 0;
-  static constexpr int WM = wide ? 2 : 4;
   static constexpr int WN = wide ? 4 : 2;
   static constexpr int TM = wide ? 4 : 2;
+  static constexpr int WM = BM / (16 * TM);
   static constexpr int TN = wide ? N / 64 : N / 32;
   static constexpr int P = 4;  // weight ring depth (k-steps)
-  static_assert(WM * TM * 16 == kMidBM && WN * TN * 16 == N, "one pass covers N");
+  static_assert(WM * TM * 16 == BM && WN * TN * 16 == N, "one pass covers N");
+  static_assert(WM * WN * 64 == BM * 4, "the same waves for every product");
 };
 
-template <int N>
-using MidRing = BRing<bf16_t, MidCfg<N>::TN, MidCfg<N>::P>;
+template <int N, int BM = kMidBM>
+using MidRing = BRing<bf16_t, MidCfg<N, BM>::TN, MidCfg<N, BM>::P>;
 
 // Starts the weight ring of a product with N columns and K inner (the
 // weights do not depend on the activations, so this can run early).
-template <int N, int K>
-__device__ __forceinline__ void mid_ring(MidRing<N>& br, const bf16_t* B, int lane, int wv) {
+template <int N, int K, int BM = kMidBM>
+__device__ __forceinline__ void mid_ring(MidRing<N, BM>& br, const bf16_t* B, int lane, int wv) {
   static_assert(K % Frag<bf16_t>::KS == 0, "whole k-steps");
-  br.init(B, (wv % MidCfg<N>::WN) * MidCfg<N>::TN * 16, -1, lane, K);
+  br.init(B, (wv % MidCfg<N, BM>::WN) * MidCfg<N, BM>::TN * 16, -1, lane, K);
   br.prologue();
 }
 
 // acc = A (LDS, row stride sa bytes, K columns) * B^T, B from a started ring.
-template <int N, int K>
-__device__ __forceinline__ void mid_steps(const unsigned char* As, int sa, MidRing<N>& br, int lane,
-                                          int wv, f32x4_t (&acc)[MidCfg<N>::TM][MidCfg<N>::TN]) {
-  using C = MidCfg<N>;
+template <int N, int K, int BM = kMidBM>
+__device__ __forceinline__ void mid_steps(const unsigned char* As, int sa, MidRing<N, BM>& br,
+                                          int lane, int wv,
+                                          f32x4_t (&acc)[MidCfg<N, BM>::TM][MidCfg<N, BM>::TN]) {
+  using C = MidCfg<N, BM>;
   const int wm = wv / C::WN;
   zero_acc(acc);
   const unsigned char* a0 = As + (wm * C::TM * 16 + (lane & 15)) * sa + (lane >> 4) * 16;
   uint4 fe[C::TM], fo[C::TM];
   ksteps_ct<bf16_t, C::TM, C::TN, C::P, K / Frag<bf16_t>::KS>(a0, 16 * sa, br, acc, fe, fo);
-}
-
-template <int N, int K>
-__device__ __forceinline__ void mid_product(const unsigned char* As, int sa, const bf16_t* B,
-                                            int lane, int wv,
-                                            f32x4_t (&acc)[MidCfg<N>::TM][MidCfg<N>::TN]) {
-  MidRing<N> br;
-  mid_ring<N, K>(br, B, lane, wv);
-  mid_steps<N, K>(As, sa, br, lane, wv, acc);
 }
 
 __device__ __forceinline__ void lds_put4(unsigned char* p, float4 v) {
@@ -83,22 +77,29 @@ __device__ __forceinline__ float4 lds_get4(const unsigned char* p) {
 // also in global a.H1 for the slopes of the last product) with the first
 // product's weight ring already started: H2 into X2, energies, D3 over H1,
 // D2 over H2, and D1 to global a.D1 (if set) and to LDS d1_lds (if set, row
-// stride S1, which may be X1: D3 is consumed by then).
-template <int W1, int W2, int W3>
-__device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2>& br1,
+// stride S1, which may be X1: D3 is consumed by then).  after_last() runs
+// right after the last product's steps (a following product can start its
+// weight ring there).
+template <int W1, int W2, int W3, int BM, typename AfterLast>
+__device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2, BM>& br1,
                                              unsigned char* X1, unsigned char* X2, float* epart,
                                              int row0, int row_end, int s,
-                                             unsigned char* d1_lds) {
+                                             unsigned char* d1_lds, AfterLast&& after_last) {
   constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;
   (void)S2;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int rl = lane & 15, cq = (lane >> 4) * 4;
   const float alpha = a.alpha, ia = 1.f / a.alpha, ial2e = a.inv_alpha_l2e;
+  // (each product's weight ring starts right after the previous product's
+  // last step, so its first fragments arrive during that epilogue and
+  // barrier instead of after them)
+  MidRing<W3, BM> br2;
   // ---- H2 = CELU(H1 W1^T + b1)
   {
-    using C = MidCfg<W2>;
+    using C = MidCfg<W2, BM>;
     f32x4_t acc[C::TM][C::TN];
-    mid_steps<W2, W1>(X1, S1, br1, lane, wv, acc);
+    mid_steps<W2, W1, BM>(X1, S1, br1, lane, wv, acc);
+    mid_ring<W3, W2, BM>(br2, a.W2 + (size_t)s * W3 * W2, lane, wv);
     const int wm = wv / C::WN, wn = wv % C::WN;
     const float* b1 = a.b1 + (size_t)s * W2;
 #pragma unroll
@@ -122,10 +123,12 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2>& br1,
   __syncthreads();
 
   // ---- z3 = H2 W2^T + b2: energies and D3 (over H1)
+  MidRing<W2, BM> br3;
   {
-    using C = MidCfg<W3>;
+    using C = MidCfg<W3, BM>;
     f32x4_t acc[C::TM][C::TN];
-    mid_product<W3, W2>(X2, S2, a.W2 + (size_t)s * W3 * W2, lane, wv, acc);
+    mid_steps<W3, W2, BM>(X2, S2, br2, lane, wv, acc);
+    mid_ring<W2, W3, BM>(br3, a.W2T + (size_t)s * W2 * W3, lane, wv);
     const int wm = wv / C::WN, wn = wv % C::WN;
     const float* b2 = a.b2 + (size_t)s * W3;
     const float* wo = a.wout + (size_t)s * W3;
@@ -159,15 +162,15 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2>& br1,
       }
       ep += __shfl_xor(ep, 16, 64);
       ep += __shfl_xor(ep, 32, 64);
-      if (lane < 16) epart[wn * kMidBM + r] = ep;
+      if (lane < 16) epart[wn * BM + r] = ep;
     }
   }
   __syncthreads();
-  if (tid < kMidBM) {
+  if (tid < BM) {
     const int row = row0 + tid;
     float e = a.bout[s];
 #pragma unroll
-    for (int q = 0; q < MidCfg<W3>::WN; ++q) e += epart[q * kMidBM + tid];
+    for (int q = 0; q < MidCfg<W3, BM>::WN; ++q) e += epart[q * BM + tid];
     if (row < row_end) a.erow[a.perm[row]] = e;  // input atom order
     if (a.uprow) {
       float up = 0.f;
@@ -177,10 +180,12 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2>& br1,
   }
 
   // ---- D2 = (D3 W2) * CELU'(z2), written over H2
+  MidRing<W1, BM> br4;
   {
-    using C = MidCfg<W2>;
+    using C = MidCfg<W2, BM>;
     f32x4_t acc[C::TM][C::TN];
-    mid_product<W2, W3>(X1, S1, a.W2T + (size_t)s * W2 * W3, lane, wv, acc);
+    mid_steps<W2, W3, BM>(X1, S1, br3, lane, wv, acc);
+    mid_ring<W1, W2, BM>(br4, a.W1T + (size_t)s * W1 * W2, lane, wv);
     const int wm = wv / C::WN, wn = wv % C::WN;
 #pragma unroll
     for (int i = 0; i < C::TM; ++i) {
@@ -202,7 +207,7 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2>& br1,
 
   // ---- D1 = (D2 W1) * CELU'(z1) -> global
   {
-    using C = MidCfg<W1>;
+    using C = MidCfg<W1, BM>;
     const int wm = wv / C::WN, wn = wv % C::WN;
     const int ldd1 = a.ld_d1 ? a.ld_d1 : W1;
     // H1 for the slopes is fetched before the product (4 bf16 per tile)
@@ -218,7 +223,8 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2>& br1,
       }
     }
     f32x4_t acc[C::TM][C::TN];
-    mid_product<W1, W2>(X2, S2, a.W1T + (size_t)s * W1 * W2, lane, wv, acc);
+    mid_steps<W1, W2, BM>(X2, S2, br4, lane, wv, acc);
+    after_last();
 #pragma unroll
     for (int i = 0; i < C::TM; ++i) {
       const int r = wm * C::TM * 16 + i * 16 + rl;
@@ -287,40 +293,44 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
   }
   __syncthreads();
 
-  mid_products<W1, W2, W3>(a, br1, X1, X2, epart, row0, row_end, s, nullptr);
+  mid_products<W1, W2, W3, kMidBM>(a, br1, X1, X2, epart, row0, row_end, s, nullptr, [] {});
 }
 
 // ------------------------------------------------------------ whole network
 //
-// Layer 1, the fused middle and dE/dG for one tile of 128 species-sorted
-// rows per workgroup, so H1 and D1 never make an HBM round trip and the
-// three stages share one launch:
+// Layer 1, the fused middle and dE/dG for one tile of 64 species-sorted
+// rows per workgroup of four waves, so H1 and D1 never make an HBM round
+// trip and the three stages share one launch:
 //   H1 = CELU(X W0^T + b0)      X streamed through two LDS chunk buffers
 //                               (region A), weights through the register
 //                               ring; H1 into LDS (X1) and to global memory
 //                               (the last slopes and the weight gradients)
 //   middle products             as k_mlp_mid, H2 / D2 in region A; D1 into X1
-//   G = D1 W0                   D1 resident in X1, four passes of 256
-//                               columns, staged per wave in region A for
+//   G = D1 W0                   D1 resident in X1, passes of eight k-steps,
+//                               staged per wave in region A for
 //                               whole-row-segment stores
+// Two workgroups share a CU (69 KB of LDS each), so one tile's barriers,
+// epilogues and weight-ring latency overlap the other's products.
 // Feature rows are sparse: an atom touches the blocks of the elements
 // around it only (about an eighth of the row in the 64-atom conformations,
 // the element pairs of water in a box).  With per-row masks of the k-steps
 // (32 columns) that may be nonzero, a tile runs layer 1 and dE/dG over the
 // union of its rows' k-steps only (a compacted k-step list, one entry per
-// lane: about half the steps for the conformations), each row reads its own
-// k-steps of X (the rest load as zero), and each row's dE/dG is written on
-// its own k-steps only, which are all the symmetry-function adjoint reads.
-// The skipped steps would add exact zeros, so the results do not change.
-// LDS: region A (two chunk buffers, 69,632 bytes) + X1 (128 rows of 528
-// bytes) + the rows' masks (1,024 bytes) = 138,240 bytes.
+// lane: about 60 % of the steps for the conformations), each row reads its
+// own k-steps of X (the rest load as zero), and each row's dE/dG is written
+// on its own k-steps only, which are all the symmetry-function adjoint
+// reads.  The skipped steps would add exact zeros, so the results do not
+// change.  LDS: region A (two chunk buffers, 34,816 bytes) + X1 (64 rows of
+// 528 bytes) + the rows' masks (512 bytes) = 69,120 bytes.
+constexpr int kNetBM = 64;
+constexpr int kNetThreads = 256;
 constexpr int kNetChunk = 256;                  // bytes of K per row and chunk
 constexpr int kNetChunkStride = kNetChunk + 16;
 
 template <int W1, int W2, int W3>
 constexpr size_t net_lds() {
-  return (size_t)2 * kMidBM * kNetChunkStride + (size_t)kMidBM * (W1 * 2 + 16) +
-         (size_t)kMidBM * 8;
+  return (size_t)2 * kNetBM * kNetChunkStride + (size_t)kNetBM * (W1 * 2 + 16) +
+         (size_t)kNetBM * 8;
 }
 
 // Lane l: the l-th set bit of m (0 when m has at most l set bits).
@@ -335,12 +345,15 @@ __device__ __forceinline__ int nth_set_bit(unsigned long long m, int l) {
 }
 
 template <int W1, int W2, int W3>
-__global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
+// (two workgroups per CU: at most 256 registers per lane)
+__global__ __launch_bounds__(kNetThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_net(
+    MidArgs a) {
   static_assert(W3 <= W1, "D3 is stored over H1");
-  constexpr int BM = kMidBM;
+  constexpr int BM = kNetBM, NTH = kNetThreads;
   constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;
   constexpr int RA = 2 * BM * kNetChunkStride;
   static_assert(BM * S2 + 4 * BM * 4 <= RA, "X2 and the energy partials fit region A");
+  static_assert(MidCfg<W1, BM>::WM * MidCfg<W1, BM>::WN * 64 == NTH, "the middle's waves");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned char* RAp = smem;
   unsigned char* X1 = smem + RA;
@@ -358,7 +371,9 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int rl = lane & 15, cq = (lane >> 4) * 4;
-  constexpr int WM = 2, WN = 4, TM = 4, TN = W1 / 64, P = 4;
+  // layer 1 and dE/dG: each wave takes all 64 rows and a quarter of the
+  // columns (A fragments from LDS, weight fragments once per workgroup)
+  constexpr int WM = 1, WN = 4, TM = 4, TN = W1 / 64, P = 4;
   static_assert(WM * TM * 16 == BM && WN * TN * 16 == W1, "one pass covers layer 1");
   const int wm = wv / WN, wn = wv % WN;
   const int K = a.ldx;
@@ -373,9 +388,10 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
   };
   unsigned long long U;
   {
-    const unsigned long long m0 = row_mask(lane), m1 = row_mask(lane + 64);
-    if (tid < BM) rmask[tid] = wv == 0 ? m0 : m1;
-    unsigned lo = (unsigned)(m0 | m1), hi = (unsigned)((m0 | m1) >> 32);
+    static_assert(BM == 64, "one row per lane");
+    const unsigned long long m = row_mask(lane);
+    if (tid < BM) rmask[tid] = m;
+    unsigned lo = (unsigned)m, hi = (unsigned)(m >> 32);
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       lo |= __shfl_xor(lo, d, 64);
@@ -387,15 +403,17 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
   const int nact = __popcll(U);
   const int qlist = nth_set_bit(U, lane);
 
+  MidRing<W2, BM> br1;  // the middle's first product (started at layer 1's last step)
   // ---- layer 1: H1 = CELU(X W0^T + b0), over the active k-steps, four per
   // chunk; thread t loads 16-byte piece t % 4 of chunk slot (t / 4) % 4 of
-  // rows t / 16 + 32 v
+  // rows t / 16 + 16 v
   {
     constexpr int KC = kNetChunk / 2;           // bf16 per chunk row
     constexpr int SPC = KC / Frag<bf16_t>::KS;  // k-steps per chunk
     static_assert(SPC == P, "one ring cycle per chunk");
     constexpr int VPR = kNetChunk / 16;
-    constexpr int NVA = BM * VPR / 512;
+    constexpr int NVA = BM * VPR / NTH;
+    constexpr int RPV = NTH / VPR;              // rows per round of loads
     static_assert(VPR == 16 && NVA == 4, "four rows per thread, a fixed piece of each");
     const __amdgpu_buffer_rsrc_t arsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<bf16_t*>(a.X + (size_t)row0 * K), (short)0, (row_end - row0) * K * 2,
@@ -403,13 +421,13 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
     const int slot = (tid >> 2) & 3, piece = tid & 3;
     unsigned long long rm[NVA];
 #pragma unroll
-    for (int v = 0; v < NVA; ++v) rm[v] = row_mask((tid >> 4) + 32 * v);
+    for (int v = 0; v < NVA; ++v) rm[v] = row_mask((tid >> 4) + RPV * v);
     auto aload = [&](int c, uint4 (&ra)[NVA]) __attribute__((always_inline)) {
       const int pos = c * SPC + slot;
       const int q = __shfl(qlist, pos & 63, 64);
 #pragma unroll
       for (int v = 0; v < NVA; ++v) {
-        const int r = (tid >> 4) + 32 * v;
+        const int r = (tid >> 4) + RPV * v;
         const bool on = pos < nact && ((rm[v] >> q) & 1ull);
         const unsigned off = on ? (unsigned)((r * K + q * 32 + piece * 8) * 2) : kOutOfRange;
         const u32x4_t val = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
@@ -420,7 +438,7 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
       unsigned char* base = RAp + buf * BM * kNetChunkStride;
 #pragma unroll
       for (int v = 0; v < NVA; ++v) {
-        const int idx = tid + v * 512;
+        const int idx = tid + v * NTH;
         *reinterpret_cast<uint4*>(base + (idx / VPR) * kNetChunkStride + (idx % VPR) * 16) = ra[v];
       }
     };
@@ -448,6 +466,7 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
       unit(u, ra0, ra1);
       if (u + 1 < nu) unit(u + 1, ra1, ra0);
     }
+    mid_ring<W2, W1, BM>(br1, a.W1 + (size_t)s * W2 * W1, lane, wv);
     const float alpha = a.alpha, ial2e = a.inv_alpha_l2e;
     const float* b0 = a.b0 + (size_t)s * W1;
 #pragma unroll
@@ -470,32 +489,35 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
   }
   __syncthreads();  // H1 in X1 (and in global memory); region A free
 
+  // dE/dG (below): G = D1 W0 over the tile's active k-steps, eight per
+  // pass: wave w takes positions 8 p + 2 w and 8 p + 2 w + 1 (column tiles
+  // 2 q0, 2 q0 + 1, 2 q1, 2 q1 + 1) for all rows; its weight ring starts at
+  // the middle's last product
+  static_assert(TN == 4 && WN == 4, "two k-steps of 32 columns per wave and pass");
+  const int npw = a.G && nact > 2 * wn ? (nact - 2 * wn + 7) / 8 : 0;  // this wave's passes
+  auto qat = [&](int pos) -> int {
+    return __builtin_amdgcn_readlane(qlist, pos < nact ? pos : (nact > 0 ? nact - 1 : 0));
+  };
+  const bf16_t* B = a.W0T + (size_t)s * K * W1;
+  BRingPair<bf16_t, P> br;
+  br.init(B, W1, lane, qat(2 * wn), qat(2 * wn + 1), qat(8 + 2 * wn), qat(8 + 2 * wn + 1));
+
   // ---- the middle: H2, energies, D3, D2, D1 (into X1)
   {
-    MidRing<W2> br1;
-    mid_ring<W2, W1>(br1, a.W1 + (size_t)s * W2 * W1, lane, wv);
     MidArgs am = a;
     am.H1 = a.H1out;
-    mid_products<W1, W2, W3>(am, br1, X1, X2, epart, row0, row_end, s, X1);
+    mid_products<W1, W2, W3, BM>(am, br1, X1, X2, epart, row0, row_end, s, X1, [&] {
+      if (npw > 0) br.prologue();
+    });
   }
   if (!a.G) return;  // block-uniform: no forces asked for
   __syncthreads();   // D1 in X1; region A free
 
-  // ---- dE/dG: G = D1 W0 over the tile's active k-steps, eight per pass:
-  // wave (wm, wn) takes positions 8 p + 2 wn and 8 p + 2 wn + 1 (column
-  // tiles 2 q0, 2 q0 + 1, 2 q1, 2 q1 + 1) for rows wm * 64 .. + 63
+  // ---- dE/dG
   {
-    static_assert(TN == 4, "two k-steps of 32 columns per wave and pass");
     constexpr int SS = TN * 16 * 2 + 16;        // staging row stride (bytes)
-    constexpr int VR = TN * 16 * 2 / 16;        // 16-byte vectors of a wave's tile row
-    const int npw = nact > 2 * wn ? (nact - 2 * wn + 7) / 8 : 0;  // this wave's passes
-    auto qat = [&](int pos) -> int {
-      return __builtin_amdgcn_readlane(qlist, pos < nact ? pos : (nact > 0 ? nact - 1 : 0));
-    };
-    const bf16_t* B = a.W0T + (size_t)s * K * W1;
-    BRingPair<bf16_t, P> br;
-    br.init(B, W1, lane, qat(2 * wn), qat(2 * wn + 1), qat(8 + 2 * wn), qat(8 + 2 * wn + 1));
-    if (npw > 0) br.prologue();
+    constexpr int VR = TN * 16 * 2 / 16;        // 16-byte vectors of a staged row
+    static_assert(16 * VR % 64 == 0, "whole store rounds");
     const int arow = (wm * TM * 16 + (lane & 15)) * S1 + (lane >> 4) * 16;
     unsigned char* stg = RAp + wv * 16 * SS;
     f32x4_t acc[TM][TN];
@@ -516,7 +538,6 @@ __global__ __launch_bounds__(512) void k_mlp_net(MidArgs a) {
           lds_put4(stg + rl * SS + (j * 16 + cq) * 2,
                    make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]));
         wave_lds_sync();
-        static_assert(16 * VR % 64 == 0, "whole store rounds");
 #pragma unroll
         for (int u = 0; u < 16 * VR / 64; ++u) {
           const int idx = lane + u * 64;
@@ -555,7 +576,8 @@ bool launch_mlp_net(const int* width, const MidArgs& a, int rows_cap, hipStream_
   constexpr size_t lds = net_lds<256, 192, 160>();
   static const bool attr = (ensure_lds(k_mlp_net<256, 192, 160>), true);
   (void)attr;
-  hipLaunchKernelGGL((k_mlp_net<256, 192, 160>), dim3(rows_cap / kMidBM), dim3(512), lds, st, a);
+  hipLaunchKernelGGL((k_mlp_net<256, 192, 160>), dim3(rows_cap / kNetBM), dim3(kNetThreads), lds,
+                     st, a);
   return true;
 }
 
