@@ -305,9 +305,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
           bm |= (unsigned long long)row << (x * S - x * (x - 1) / 2);
         }
         const unsigned r2 = rp | (rp >> 1);  // k-step j holds elements 2j and 2j + 1
+        const int k0 = C.A0 >> 5;  // block p spans k-step k0 + p (and k0 + p + 1 unaligned)
         kbits = (unsigned long long)((r2 & 1u) | ((r2 >> 1) & 2u) | ((r2 >> 2) & 4u) |
                                      ((r2 >> 3) & 8u)) |
-                (bm << (S >> 1)) | ((S & 1) ? bm << ((S >> 1) + 1) : 0ull);
+                (bm << k0) | ((C.A0 & 31) ? bm << (k0 + 1) : 0ull);
         if (lane == 0) kmask[orow_i] = kbits;
         if (sparse) {
           // this lane's stores: bit 0 radial, bits 1 + 2 u and 2 + 2 u the
@@ -315,13 +316,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
           sput = (unsigned)(kbits >> (l16 >> 1)) & 1u;
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            const int c = S * kNR + l16 * 32 + 4 * kq + 512 * u;
+            const int c = C.A0 + l16 * 32 + 4 * kq + 512 * u;
             sput |= ((unsigned)(kbits >> (c >> 5)) & 1u) << (1 + 2 * u);
             sput |= ((unsigned)(kbits >> ((c + 16) >> 5)) & 1u) << (2 + 2 * u);
           }
         }
       }
-      if (l16 < S && (sput & 1u))
+      // (element slots from S up to the angular blocks are the gap: zero)
+      if (l16 < (C.A0 >> 4) && (sput & 1u))
         Store<OutT>::put4(orow + l16 * kNR + 4 * kq, make_float4(acc[0], acc[1], acc[2], acc[3]));
     }
 
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
       }
       // column c of c0[u] is feature c of block 16 u + l16 (a = c / 8 for the
       // low radial shifts, z = c % 8); c1[u] holds features 16 + c
-      OutT* ang = orow + S * kNR + l16 * 32 + 4 * kq;
+      OutT* ang = orow + C.A0 + l16 * 32 + 4 * kq;
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
         if (l16 + 16 * u < nblk) {
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
         }
       }
     }
-    for (int c = C.F + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
+    for (int c = C.A0 + nblk * 32 + lane; c < ld; c += kWave) Store<OutT>::put(orow + c, 0.f);
   }
 }
 
@@ -544,7 +546,7 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
     // Gaussians) is computed once; the lane walks the eight angle shifts and
     // contracts each with the pair block's dE/dG values (one vector load).
     const int T = na * (na - 1) / 2;
-    const GT* gang = grow + S * kNR;
+    const GT* gang = grow + C.A0;
     for (int t0 = 0; t0 < T; t0 += kWave) {
       // lanes past the last pair recompute it and add nothing
       const int t = t0 + lane;
@@ -632,7 +634,7 @@ __device__ __forceinline__ void adjoint_passes(int nr, int na, const AevConst& C
     const float cz = C.lane_tab[kNR + tz], sz = C.lane_tab[kNR + kNZ + tz];
     const float ra0 = C.shf_a[0], ra1 = C.shf_a[1], ra2 = C.shf_a[2], ra3 = C.shf_a[3];
     const int T = na * (na - 1) / 2;
-    const GT* gang = grow + S * kNR + tz;
+    const GT* gang = grow + C.A0 + tz;
     for (int t0 = 0; t0 < T; t0 += 8) {
       // lanes past the last pair recompute it and contribute zero: every lane
       // runs the same straight-line code, with no branch around the terms
@@ -799,7 +801,7 @@ __device__ __forceinline__ void adjoint_atoms(int i0, int n, const AevConst& C,
       const float4 vj = nd[ej], vk = nd[ek];
       const float4 cj = nf[ej], ck = nf[ek];
       const float fj = cj.y, fk = ck.y, dfj = cj.w, dfk = ck.w;
-      const GT* gb = g + (size_t)ra * ldg + S * kNR + tz + pair_block(nsp[ej], nsp[ek], S) * 32;
+      const GT* gb = g + (size_t)ra * ldg + C.A0 + tz + pair_block(nsp[ej], nsp[ek], S) * 32;
       const float g0 = Store<GT>::get(gb), g1 = Store<GT>::get(gb + 8),
                   g2 = Store<GT>::get(gb + 16), g3 = Store<GT>::get(gb + 24);
       const float rj = fast_rcp(vj.w), rk = fast_rcp(vk.w);

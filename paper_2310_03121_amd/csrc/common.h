@@ -27,7 +27,10 @@ enum : uint32_t {
 struct AevConst {
   int S;             // species
   int F;             // features per atom
-  int Fp;            // row stride of the feature matrix (F rounded up to 64)
+  int Fp;            // row stride of the feature matrix (A0 + angular columns, rounded up to 64)
+  int A0;            // first angular column: S * 16 rounded up to 32, so that every
+                     // angular block is one 32-column k-step of the network (the
+                     // gap columns are zero; S * 16 for rows in the published order)
   float rc2_r;       // fl32(rc_r * rc_r): radial predicate
   float rc2_a;       // fl32(rc_a * rc_a): angular predicate
   float inv_rc_r;    // 1 / rc_r

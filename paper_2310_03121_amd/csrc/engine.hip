@@ -607,7 +607,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     float* part = at<float>(ws, P.wpart);
     const float* up = at<float>(ws, P.uprow);
     const WgradLayer layers[kLayers] = {
-        {D1, X, w1, Fp, w1, h->F, false},
+        {D1, X, w1, Fp, w1, h->F, false, S * kNR, h->C.A0 - S * kNR},
         {D2, H1, w2, w1, w2, w1, false},
         {D3, H2, w3, w2, w3, w2, false},
         {up, H3, 1, w3, 1, w3, true},
@@ -709,13 +709,15 @@ nnp_status nnp_create_ensemble(const nnp_aev_params* aev, const nnp_mlp_params* 
   h->prec = precision;
   h->S = S;
   h->F = F;
-  h->Fp = (F + 63) / 64 * 64;
+  const int A0 = (S * kNR + 31) / 32 * 32;  // the angular blocks on k-step boundaries
+  h->Fp = (A0 + (F - S * kNR) + 63) / 64 * 64;
   for (int l = 0; l <= kLayers; ++l) h->width[l] = mlp->width[l];
   h->alpha = mlp->celu_alpha;
   AevConst& C = h->C;
   C.S = S;
   C.F = F;
   C.Fp = h->Fp;
+  C.A0 = A0;
   const float rr = aev->rc_rad, ra = aev->rc_ang;
   C.rc2_r = rr * rr;
   C.rc2_a = ra * ra;
@@ -858,6 +860,8 @@ nnp_status nnp_set_params_device(nnp_handle* h, const float* params_dev, void* s
   for (int l = 0; l <= kLayers; ++l) p.width[l] = h->width[l];
   p.width[0] = h->F;
   p.Fp = h->Fp;
+  p.r0 = h->S * kNR;
+  p.a0 = h->C.A0;
   for (int l = 0; l < kLayers; ++l) {
     p.Wf[l] = h->Wf[l];
     p.Wb[l] = h->Wb[l];
@@ -1100,7 +1104,9 @@ nnp_status nnp_debug_aev(nnp_handle* h, int32_t n, int32_t nmol, const float* po
   else
     launch_pairs_mol(dims, P.n, h->C, xyzs, mrange, P.cap, at<int>(ws, P.nbr),
                      at<float4>(ws, P.rec), at<int2>(ws, P.counts), status, st);
-  launch_aev_fwd<float>(dims, P.n, h->C, at<float4>(ws, P.rec), at<int2>(ws, P.counts), P.cap,
+  AevConst Cp = h->C;  // rows in the published order: no gap before the angular blocks
+  Cp.A0 = h->S * kNR;
+  launch_aev_fwd<float>(dims, P.n, Cp, at<float4>(ws, P.rec), at<int2>(ws, P.counts), P.cap,
                         nullptr, aev, h->F, h->deterministic, nullptr, false, st);
   return launches_ok() ? NNP_OK : NNP_E_HIP;
 }

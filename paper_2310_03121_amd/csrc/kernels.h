@@ -86,6 +86,7 @@ struct PackArgs {
   bf16_t* WT0cq;          // the same in MFMA fragment order (N = F_pad, K = M * width1)
   int width[kLayers + 1];
   int Fp;
+  int r0, a0;             // layer 1: inputs from r0 on sit at columns from a0 on
   float* Wf[kLayers];     // W [slots][out][in_pad], row-major
   bf16_t* Wb[kLayers];
   float* WTf[kLayers];    // W^T [S][in_pad][out], row-major
@@ -193,6 +194,9 @@ struct WgradLayer {
   const void* H;  // [rows][ldh] the layer's input
   int ldd, ldh, Nout, Nin;
   bool d_fp32;    // D is FP32 (the output layer's), else the operand type
+  // input i (of Nin, in the parameters' order) is column i of H, or
+  // i + hgap from hgap0 on (the feature rows' gap before the angular blocks)
+  int hgap0 = 1 << 30, hgap = 0;
 };
 template <typename T>
 void launch_wgrad_net(const GroupTable* gt, int S, int n_chunks_cap, int chunk,

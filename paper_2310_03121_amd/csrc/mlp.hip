@@ -592,6 +592,7 @@ struct WgLayerArgs {
   const void* D;
   const void* H;
   int ldd, ldh, Nout, Nin;
+  int hgap0, hgap;  // input i >= hgap0 is column i + hgap of H
   int n_o, n_i;   // 128-wide output and input tiles
   int block0;     // first block of the layer after the output layer's
   long part_off;  // the layer's W inside a chunk's partial vector
@@ -621,7 +622,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const GroupTable* __restrict__ gt
                                                const TD* __restrict__ D, int ldd, int Nout,
                                                const TH* __restrict__ H, int ldh, int Nin,
                                                int chunk, float* __restrict__ partial, long part_len,
-                                               long part_off) {
+                                               long part_off, int hgap0, int hgap) {
   __shared__ float sd[32][65];
   __shared__ float sh[32][65];
   const int c = blockIdx.x;
@@ -643,7 +644,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const GroupTable* __restrict__ gt
       const int row = r + rr;
       const bool ok = row < r1;
       sd[rr][cc] = (ok && o0 + cc < Nout) ? Store<TD>::get(D + (size_t)row * ldd + o0 + cc) : 0.f;
-      sh[rr][cc] = (ok && i0 + cc < Nin) ? Store<TH>::get(H + (size_t)row * ldh + i0 + cc) : 0.f;
+      const int hc = i0 + cc + (i0 + cc >= hgap0 ? hgap : 0);
+      sh[rr][cc] = (ok && i0 + cc < Nin) ? Store<TH>::get(H + (size_t)row * ldh + hc) : 0.f;
     }
     __syncthreads();
 #pragma unroll 4
@@ -727,8 +729,8 @@ constexpr size_t wgrad_lds_bytes() {
 // consecutive i of one o, stored as one vector.
 template <typename T>
 __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int Nout,
-                                           const T* __restrict__ H, int ldh, int Nin, int r0,
-                                           int r1, int o0, int i0, bool bias,
+                                           const T* __restrict__ H, int ldh, int Nin, int hgap0,
+                                           int hgap, int r0, int r1, int o0, int i0, bool bias,
                                            float* __restrict__ out, float* __restrict__ bout,
                                            T* lds) {
   using L = WgLayout<T>;
@@ -750,16 +752,18 @@ __device__ __forceinline__ void wgrad_tile(const T* __restrict__ D, int ldd, int
   for (int e = 0; e < NB; ++e) bsum[e] = 0.f;
   if constexpr (BF) {
     const int ld = op ? ldh : ldd, N = op ? Nin : Nout, c = (op ? i0 : o0) + 8 * bg;
+    const int cm = c + (op && c >= hgap0 ? hgap : 0);  // (8-column groups: the gap is too)
 #pragma unroll
     for (int e = 0; e < NL; ++e)
-      offs[e] = c < N ? (unsigned)(((8 * blk + e) * ld + c) * 2) : kOutOfRange;
+      offs[e] = c < N ? (unsigned)(((8 * blk + e) * ld + cm) * 2) : kOutOfRange;
   } else {
     const int g = tid & 31, oc = o0 + 4 * g, ic = i0 + 4 * g;
 #pragma unroll
     for (int k = 0; k < NL / 2; ++k) {
       const int r = (tid >> 5) + 8 * k;
       offs[k] = oc < Nout ? (unsigned)((r * ldd + oc) * 4) : kOutOfRange;
-      offs[NL / 2 + k] = ic < Nin ? (unsigned)((r * ldh + ic) * 4) : kOutOfRange;
+      offs[NL / 2 + k] =
+          ic < Nin ? (unsigned)((r * ldh + ic + (ic >= hgap0 ? hgap : 0)) * 4) : kOutOfRange;
     }
   }
   uint4 ra0[NL], ra1[NL];
@@ -1042,7 +1046,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (!wgrad_chunk(a.gt, a.S, a.chunk, c, r0, r1)) return;
   float* out = a.partial + (size_t)c * a.part_len + Ly.part_off;
   wgrad_tile<T>(static_cast<const T*>(Ly.D), Ly.ldd, Ly.Nout, static_cast<const T*>(Ly.H), Ly.ldh,
-                Ly.Nin, r0, r1, ot * kWgBO, it * kWgBI, it == 0, out,
+                Ly.Nin, Ly.hgap0, Ly.hgap, r0, r1, ot * kWgBO, it * kWgBI, it == 0, out,
                 out + (size_t)Ly.Nout * Ly.Nin, reinterpret_cast<T*>(smem));
 }
 
@@ -1098,6 +1102,7 @@ void launch_wgrad_net(const GroupTable* gt, int S, int n_chunks_cap, int chunk,
     if (tiled && a.n_tiled < kLayers) {
       WgLayerArgs& t = a.L[a.n_tiled++];
       t.D = y.D; t.H = y.H; t.ldd = y.ldd; t.ldh = y.ldh; t.Nout = y.Nout; t.Nin = y.Nin;
+      t.hgap0 = y.hgap0; t.hgap = y.hgap;
       t.n_o = (y.Nout + kWgBO - 1) / kWgBO;
       t.n_i = (y.Nin + kWgBI - 1) / kWgBI;
       t.block0 = blocks;
@@ -1108,12 +1113,12 @@ void launch_wgrad_net(const GroupTable* gt, int S, int n_chunks_cap, int chunk,
       hipLaunchKernelGGL((k_wgrad<float, T>), grid, dim3(256), 0, st, gt, S,
                          static_cast<const float*>(y.D), y.ldd, y.Nout,
                          static_cast<const T*>(y.H), y.ldh, y.Nin, chunk, partial, part_len,
-                         off[l]);
+                         off[l], y.hgap0, y.hgap);
     } else {
       dim3 grid(n_chunks_cap, (y.Nout + 63) / 64, (y.Nin + 63) / 64);
       hipLaunchKernelGGL((k_wgrad<T, T>), grid, dim3(256), 0, st, gt, S,
                          static_cast<const T*>(y.D), y.ldd, y.Nout, static_cast<const T*>(y.H),
-                         y.ldh, y.Nin, chunk, partial, part_len, off[l]);
+                         y.ldh, y.Nin, chunk, partial, part_len, off[l], y.hgap0, y.hgap);
     }
   }
   a.tiled_blocks = blocks;
@@ -1158,7 +1163,10 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs p) {
   if (l < kLayers - 1) {
     if (t >= (long)out * inp) return;
     const int o = (int)(t / inp), i = (int)(t % inp);
-    const float v = i < in ? src[(size_t)o * in + i] : 0.f;
+    // layer 1: inputs from r0 on sit at columns from a0 on (zero between)
+    const int pi = l == 0 && i >= p.r0 ? i - (p.a0 - p.r0) : i;
+    const bool on = pi < in && (l != 0 || i < p.r0 || i >= p.a0);
+    const float v = on ? src[(size_t)o * in + pi] : 0.f;
     const size_t ws = (size_t)s * out * inp;
     p.Wf[l][ws + (size_t)o * inp + i] = v;
     p.Wb[l][ws + (size_t)o * inp + i] = f2bf(v);
