@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
         }
         acc = mfma4(term, hot, acc);
         // (neighbors + 4096 x angular neighbors: exact, lists hold <= 512)
-        if (kmask) cnt += (e < na ? 4097.f : 1.f) * hot;
+        cnt += (e < na ? 4097.f : 1.f) * hot;
       }
       if (kmask) {
         // the four entry groups' counts: lane l16 < S then holds element l16's
@@ -312,13 +312,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Q > 1 ? 7 :
         if (lane == 0) kmask[orow_i] = kbits;
         if (sparse) {
           // this lane's stores: bit 0 radial, bits 1 + 2 u and 2 + 2 u the
-          // two halves of angular tile u
+          // two halves of angular tile u (one k-step when A0 is aligned)
           sput = (unsigned)(kbits >> (l16 >> 1)) & 1u;
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
             const int c = C.A0 + l16 * 32 + 4 * kq + 512 * u;
-            sput |= ((unsigned)(kbits >> (c >> 5)) & 1u) << (1 + 2 * u);
-            sput |= ((unsigned)(kbits >> ((c + 16) >> 5)) & 1u) << (2 + 2 * u);
+            const unsigned lo = (unsigned)(kbits >> (c >> 5)) & 1u;
+            const unsigned hi =
+                (C.A0 & 31) ? (unsigned)(kbits >> ((c + 16) >> 5)) & 1u : lo;
+            sput |= (lo << (1 + 2 * u)) | (hi << (2 + 2 * u));
           }
         }
       }
