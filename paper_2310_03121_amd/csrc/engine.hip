@@ -490,10 +490,12 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     // layer 1: H1 = CELU(X W0^T + b0)
     g.A = X; g.lda = Fp; g.B = Wk[0]; g.Bq = Wqk[0]; g.sB = (long)w1 * Fp; g.ldb = Fp;
     g.bias = bias_k[0]; g.sBias = w1; g.N = w1; g.K = Fp; g.C = H1; g.ldc = w1;
+    g.kmask_k = kmask;  // (whole rows here: skipped stages are all zero)
     {
       StageTimer t(h, io.timed, ST_L1, st);
       ok &= launch_gemm<T>(EPI_CELU, g, P.rows_cap, st);
     }
+    g.kmask_k = nullptr;
     // BF16 with gradients: one fused launch for layer 2, the energy head and the
     // adjoint of layers 3 and 2 (intermediates stay in LDS)
     bool fused = false;
@@ -590,6 +592,7 @@ nnp_status run_path(nnp_handle* h, const Plan& P, void* ws, const EvalIO& io, hi
     g.Bq = cat ? (bf ? (const void*)h->WT0cq : nullptr) : WTq[0];
     g.sB = (long)Fp * ldd1; g.ldb = ldd1;
     g.N = Fp; g.K = ldd1; g.C = G; g.ldc = Fp; g.H = nullptr;
+    g.kmask_n = kmask;  // the adjoint reads a row's own k-steps of dE/dG only
     if (!net_fused) {
       StageTimer t(h, io.timed, ST_GRADG, st);
       ok &= launch_gemm<T>(EPI_OUT, g, P.rows_cap, st);

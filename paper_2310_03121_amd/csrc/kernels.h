@@ -35,6 +35,13 @@ struct GemmArgs {
   float alpha;
   float inv_alpha_l2e; // log2(e) / alpha
   float escale = 1.f;  // EPI_HEAD: factor on the upstream gradient (1 / ensemble size)
+  // optional per-row k-step masks of the feature rows (launch_aev_fwd's
+  // kmask; FP32 LDS-staged kernel): kmask_k skips the K stages (32 columns)
+  // that every row of the tile has zero (layer 1, K = the feature columns);
+  // kmask_n skips the column blocks no row of the tile needs (dE/dG: the
+  // adjoint reads only a row's own k-steps)
+  const unsigned long long* kmask_k = nullptr;
+  const unsigned long long* kmask_n = nullptr;
 };
 
 struct MidArgs {

@@ -322,11 +322,54 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
   const T* A = reinterpret_cast<const T*>(a.A);
   const T* B = reinterpret_cast<const T*>(a.B) + (size_t)s * a.sB;
   const int K = a.K;
-  const int nk = (K + BK - 1) / BK;
+  int nk = (K + BK - 1) / BK;
+
+  // feature-row masks: the union over the tile's rows of their k-steps
+  __shared__ unsigned long long kunion[4];
+  __shared__ int klist[64];
+  // (tiles whose stages or column blocks are not whole 32-column groups
+  // ignore the masks and run every stage and block)
+  constexpr bool kMaskable = BK == 32 && BN % 32 == 0;
+  const unsigned long long* km = a.kmask_k ? a.kmask_k : a.kmask_n;
+  const bool kskip = kMaskable && a.kmask_k && nk <= 64;
+  unsigned jact = ~0u;  // dE/dG: this wave's 16-column tiles that some row reads
+  if (kMaskable && km && (a.kmask_n || kskip)) {  // block-uniform
+    static_assert(BM <= 256, "one row per thread");
+    unsigned long long m = tid < BM && row0 + tid < row_end ? km[row0 + tid] : 0ull;
+    unsigned lo = (unsigned)m, hi = (unsigned)(m >> 32);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      lo |= __shfl_xor(lo, d, 64);
+      hi |= __shfl_xor(hi, d, 64);
+    }
+    if (lane == 0) kunion[wv] = ((unsigned long long)hi << 32) | lo;
+    __syncthreads();
+    const unsigned long long U = kunion[0] | kunion[1] | kunion[2] | kunion[3];
+    if (a.kmask_n) {
+      // this block's columns [n0, n0 + BN) in 32-column groups
+      if (n0 / 32 + BN / 32 <= 64) {
+        const unsigned long long gm = ((1ull << (BN / 32)) - 1ull) << (n0 / 32);
+        if ((U & gm) == 0ull) return;  // no row of the tile reads these columns
+        unsigned ja = 0;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          if ((U >> ((n0 + wn * WTN + j * 16) >> 5)) & 1ull) ja |= 1u << j;
+        jact = __builtin_amdgcn_readfirstlane(ja);
+      }
+    } else {
+      const unsigned long long all = nk >= 64 ? ~0ull : (1ull << nk) - 1ull;
+      const unsigned long long Uk = U & all;
+      if (tid < 64 && ((Uk >> tid) & 1ull)) klist[__popcll(Uk & ((1ull << tid) - 1ull))] = tid;
+      nk = __popcll(Uk);
+      __syncthreads();
+    }
+  }
+  // K stage kt covers columns [kcol(kt) * BK, + BK)
+  auto kcol = [&](int kt) { return kskip ? klist[kt] : kt; };
 
   uint4 ra[NVA], rb[NVB];
   auto gload = [&](int kt) {
-    const int k0 = kt * BK;
+    const int k0 = kcol(kt) * BK;
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * 256;
@@ -369,8 +412,10 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  gload(0);
-  lstore(0);
+  if (nk > 0) {
+    gload(0);
+    lstore(0);
+  }
   __syncthreads();
   const int rl = lane & 15;
   for (int kt = 0; kt < nk; ++kt) {
@@ -387,9 +432,12 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
 #pragma unroll
       for (int j = 0; j < TN; ++j) fb[j] = *reinterpret_cast<const uint4*>(bs + j * 16 * RS + ko);
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int j = 0; j < TN; ++j) {
+        // (dE/dG: columns no row of the tile reads are left at zero)
+        if (EPI == EPI_OUT && !((jact >> j) & 1u)) continue;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) Mfma<T>::mma(fa[i], fb[j], acc[i][j]);
+        for (int i = 0; i < TM; ++i) Mfma<T>::mma(fa[i], fb[j], acc[i][j]);
+      }
     }
     if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
