@@ -87,6 +87,17 @@ struct BRing {
   }
 };
 
+// Lane l: the l-th set bit of m (0 when m has at most l set bits).
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int l) {
+  int q = 0;
+#pragma unroll
+  for (int w = 32; w; w >>= 1) {
+    const int t = q + w;
+    if (__popcll(m & ((1ull << t) - 1ull)) <= l) q = t;
+  }
+  return l < __popcll(m) ? q : 0;
+}
+
 // A ring over a compacted list of k-steps: position s of the product is
 // k-step `qlist` of lane s (qlist holds the tile's active k-steps in order,
 // one per lane), so steps whose A columns are zero for the whole tile are
@@ -122,6 +133,7 @@ struct BRingQ {
       prologue<U + 1>();
     }
   }
+  __device__ __forceinline__ void next_pass(const T*, int, int) {}  // one pass only
 };
 
 // A ring for a product whose four 16-column tiles come in two pairs at

@@ -38,7 +38,10 @@ constexpr int kMaxResident = 3;
 template <typename T, int TN>
 constexpr int stage_stride() { return TN * 16 * (int)sizeof(T) + 16; }
 
-template <typename T, int WM, int WN, int TM, int TN, int EPI, bool RESIDENT>
+// KS (layer 1 with the feature rows' k-step masks, one pass over N): the
+// K loop runs over the tile's compacted list of k-steps that some row has
+// nonzero (the rows are whole, so the skipped steps are zero).
+template <typename T, int WM, int WN, int TM, int TN, int EPI, bool RESIDENT, bool KS = false>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
   constexpr int NT = 64 * WM * WN;
   constexpr int BM = WM * TM * 16;
@@ -69,6 +72,30 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
   const T* A = reinterpret_cast<const T*>(a.A);
   const T* B = reinterpret_cast<const T*>(a.Bq) + (size_t)s * a.sB;
 
+  // KS: the union of the tile's rows' k-step masks, compacted into qlist
+  // (lane l: the l-th active k-step)
+  int nact = 0, qlist = 0;
+  if constexpr (KS) {
+    static_assert(sizeof(T) == 2 && BM <= NT, "BF16, one row per thread");
+    __shared__ unsigned long long kun[NT / 64];
+    const int nks = K / Frag<T>::KS;
+    const unsigned long long all = nks >= 64 ? ~0ull : (1ull << nks) - 1ull;
+    const unsigned long long m = tid < BM && row0 + tid < row_end ? a.kmask_k[row0 + tid] & all : 0ull;
+    unsigned lo = (unsigned)m, hi = (unsigned)(m >> 32);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      lo |= __shfl_xor(lo, d, 64);
+      hi |= __shfl_xor(hi, d, 64);
+    }
+    if (lane == 0) kun[wv] = ((unsigned long long)hi << 32) | lo;
+    __syncthreads();
+    unsigned long long U = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) U |= kun[w];
+    nact = __popcll(U);
+    qlist = nth_set_bit(U, lane);
+  }
+
   // A is read through a buffer resource that spans exactly the tile's valid
   // rows: loads of pad rows, and of columns past K (sent past the range),
   // return zeros in hardware.  So no load sits behind a branch, which would
@@ -81,8 +108,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
 #pragma unroll
     for (int v = 0; v < NVA; ++v) {
       const int idx = tid + v * NT;
-      const int r = idx / VPR, k = c * KC + (idx % VPR) * (16 / (int)sizeof(T));
-      const unsigned off = k < K ? (unsigned)((r * a.lda + k) * (int)sizeof(T)) : kOutOfRange;
+      int r = idx / VPR, k = c * KC + (idx % VPR) * (16 / (int)sizeof(T));
+      bool in = k < K;
+      if constexpr (KS) {  // chunk slot (idx % VPR) / 4 holds position c * SPC + slot
+        const int pos = c * SPC + (idx % VPR) / 4;
+        k = __shfl(qlist, pos & 63, 64) * Frag<T>::KS + (idx % 4) * 8;
+        in = pos < nact;
+      }
+      const unsigned off = in ? (unsigned)((r * a.lda + k) * (int)sizeof(T)) : kOutOfRange;
       const u32x4_t val = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
       ra[v] = make_uint4(val[0], val[1], val[2], val[3]);
     }
@@ -96,8 +129,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
     }
   };
 
-  const int ns = K / Frag<T>::KS;
-  const int nchunks = (ns + SPC - 1) / SPC;  // RESIDENT: nchunks <= kMaxResident
+  const int ns = KS ? nact : K / Frag<T>::KS;
+  const int nchunks = ns > SPC ? (ns + SPC - 1) / SPC : 1;  // RESIDENT: <= kMaxResident
   const int npass = a.N / NP;
   const int arow = (wm * TM * 16 + (lane & 15)) * kChunkStride + (lane >> 4) * 16;
   const int rl = lane & 15, cq = (lane >> 4) * 4;
@@ -108,8 +141,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_rb(GemmArgs a) {
 
   f32x4_t acc[TM][TN];
   zero_acc(acc);
-  BRing<T, TN, P> br;
-  br.init(B, col_w, npass > 1 ? NP + col_w : -1, lane, K);
+  using Ring = std::conditional_t<KS, BRingQ<T, TN, P>, BRing<T, TN, P>>;
+  Ring br;
+  if constexpr (KS)
+    br.init(B, col_w, lane, K, nact, qlist);
+  else
+    br.init(B, col_w, npass > 1 ? NP + col_w : -1, lane, K);
   br.prologue();
 
   // Epilogue of pass p: finish each 16x16 tile in registers (lane holds row
@@ -215,6 +252,16 @@ template <typename T, int WM, int WN, int TM, int TN, int EPI, bool RES>
 static void launch_rb_t(const GemmArgs& a, int nchunks, int rows_cap, hipStream_t st) {
   const size_t lds = (size_t)(RES ? nchunks : 2) * kPad * kChunkStride +
                      (size_t)WM * WN * 16 * stage_stride<T, TN>();
+  // layer 1 over the tile's nonzero k-steps: one pass over N, at most 64 steps
+  if constexpr (EPI == EPI_CELU && sizeof(T) == 2) {
+    if (a.kmask_k && a.N == WN * TN * 16 && a.K / Frag<T>::KS <= 64) {
+      static const bool attr_ks = (ensure_lds(k_gemm_rb<T, WM, WN, TM, TN, EPI, RES, true>), true);
+      (void)attr_ks;
+      hipLaunchKernelGGL((k_gemm_rb<T, WM, WN, TM, TN, EPI, RES, true>), dim3(rows_cap / kPad),
+                         dim3(64 * WM * WN), lds, st, a);
+      return;
+    }
+  }
   static const bool attr = (ensure_lds(k_gemm_rb<T, WM, WN, TM, TN, EPI, RES>), true);
   (void)attr;
   hipLaunchKernelGGL((k_gemm_rb<T, WM, WN, TM, TN, EPI, RES>), dim3(rows_cap / kPad),

@@ -333,17 +333,6 @@ constexpr size_t net_lds() {
          (size_t)kNetBM * 8;
 }
 
-// Lane l: the l-th set bit of m (0 when m has at most l set bits).
-__device__ __forceinline__ int nth_set_bit(unsigned long long m, int l) {
-  int q = 0;
-#pragma unroll
-  for (int w = 32; w; w >>= 1) {
-    const int t = q + w;
-    if (__popcll(m & ((1ull << t) - 1ull)) <= l) q = t;
-  }
-  return l < __popcll(m) ? q : 0;
-}
-
 template <int W1, int W2, int W3>
 // (two workgroups per CU: at most 256 registers per lane)
 __global__ __launch_bounds__(kNetThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_net(
