@@ -73,18 +73,20 @@ __device__ __forceinline__ float4 lds_get4(const unsigned char* p) {
                      __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
 }
 
-// The four products of the fused middle, from H1 in X1 (LDS, row stride S1;
-// also in global a.H1 for the slopes of the last product) with the first
-// product's weight ring already started: H2 into X2, energies, D3 over H1,
+// The four products of the fused middle, from H1 in X1 (LDS, row stride S1)
+// with the first product's weight ring already started: H2 into X2,
+// energies, D3 into D3s (row stride S3; X1 itself when H1 need not stay),
 // D2 over H2, and D1 to global a.D1 (if set) and to LDS d1_lds (if set, row
-// stride S1, which may be X1: D3 is consumed by then).  after_last() runs
-// right after the last product's steps (a following product can start its
-// weight ring there).
+// stride S1, which may be X1: D3 is consumed by then).  The last product's
+// slopes come from H1 in X1 when it is still there (D3s elsewhere), else
+// from global a.H1.  after_last() runs right after the last product's steps
+// (a following product can start its weight ring there).
 template <int W1, int W2, int W3, int BM, typename AfterLast>
 __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2, BM>& br1,
                                              unsigned char* X1, unsigned char* X2, float* epart,
                                              int row0, int row_end, int s,
-                                             unsigned char* d1_lds, AfterLast&& after_last) {
+                                             unsigned char* d1_lds, unsigned char* D3s, int S3,
+                                             AfterLast&& after_last) {
   constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;
   (void)S2;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -156,7 +158,7 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2, BM>& 
           ep += ww[e] * h[e];
         }
         const float4 d4 = make_float4(d[0], d[1], d[2], d[3]);
-        lds_put4(X1 + r * S1 + c * 2, d4);
+        lds_put4(D3s + r * S3 + c * 2, d4);
         if (a.H3) Store<bf16_t>::put4(a.H3 + (size_t)row * W3 + c, make_float4(h[0], h[1], h[2], h[3]));
         if (a.D3) Store<bf16_t>::put4(a.D3 + (size_t)row * W3 + c, d4);
       }
@@ -184,7 +186,7 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2, BM>& 
   {
     using C = MidCfg<W2, BM>;
     f32x4_t acc[C::TM][C::TN];
-    mid_steps<W2, W3, BM>(X1, S1, br3, lane, wv, acc);
+    mid_steps<W2, W3, BM>(D3s, S3, br3, lane, wv, acc);
     mid_ring<W1, W2, BM>(br4, a.W1T + (size_t)s * W1 * W2, lane, wv);
     const int wm = wv / C::WN, wn = wv % C::WN;
 #pragma unroll
@@ -218,8 +220,12 @@ __device__ __forceinline__ void mid_products(const MidArgs& a, MidRing<W2, BM>& 
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
         const int c = wn * C::TN * 16 + j * 16 + cq;
-        h1[i][j] = row < row_end ? *reinterpret_cast<const uint2*>(a.H1 + (size_t)row * W1 + c)
-                                 : make_uint2(0, 0);
+        if (D3s != X1)  // H1 still in X1 (zero past the group)
+          h1[i][j] = *reinterpret_cast<const uint2*>(X1 + (row - row0) * S1 + c * 2);
+        else
+          h1[i][j] = row < row_end
+                         ? *reinterpret_cast<const uint2*>(a.H1 + (size_t)row * W1 + c)
+                         : make_uint2(0, 0);
       }
     }
     f32x4_t acc[C::TM][C::TN];
@@ -293,7 +299,8 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
   }
   __syncthreads();
 
-  mid_products<W1, W2, W3, kMidBM>(a, br1, X1, X2, epart, row0, row_end, s, nullptr, [] {});
+  mid_products<W1, W2, W3, kMidBM>(a, br1, X1, X2, epart, row0, row_end, s, nullptr, X1, S1,
+                                   [] {});
 }
 
 // ------------------------------------------------------------ whole network
@@ -303,14 +310,16 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
 // trip and the three stages share one launch:
 //   H1 = CELU(X W0^T + b0)      X streamed through two LDS chunk buffers
 //                               (region A), weights through the register
-//                               ring; H1 into LDS (X1) and to global memory
-//                               (the last slopes and the weight gradients)
-//   middle products             as k_mlp_mid, H2 / D2 in region A; D1 into X1
+//                               ring; H1 into LDS (X1), and to global
+//                               memory only for the weight gradients
+//   middle products             as k_mlp_mid, H2 / D2 and D3 in region A
+//                               (H1 stays in X1 for the last slopes); D1
+//                               into X1
 //   G = D1 W0                   D1 resident in X1, passes of eight k-steps,
 //                               staged per wave in region A for
 //                               whole-row-segment stores
-// Two workgroups share a CU (69 KB of LDS each), so one tile's barriers,
-// epilogues and weight-ring latency overlap the other's products.
+// Two workgroups share a CU (80 KB of LDS each, half of it), so one tile's
+// barriers, epilogues and weight-ring latency overlap the other's products.
 // Feature rows are sparse: an atom touches the blocks of the elements
 // around it only (about an eighth of the row in the 64-atom conformations,
 // the element pairs of water in a box).  With per-row masks of the k-steps
@@ -320,35 +329,50 @@ __global__ __launch_bounds__(512) void k_mlp_mid(MidArgs a) {
 // own k-steps of X (the rest load as zero), and each row's dE/dG is written
 // on its own k-steps only, which are all the symmetry-function adjoint
 // reads.  The skipped steps would add exact zeros, so the results do not
-// change.  LDS: region A (two chunk buffers, 34,816 bytes) + X1 (64 rows of
-// 528 bytes) + the rows' masks (512 bytes) = 69,120 bytes.
+// change.  LDS: region A (X2: 64 rows of 400 bytes, the energy partials
+// (512 bytes) and D3: 64 rows of 336 bytes; during layer 1 the two chunk
+// buffers, 34,816 bytes) + X1 (64 rows of 528 bytes) + the rows' masks (512
+// bytes) = 81,920 bytes.
 constexpr int kNetBM = 64;
 constexpr int kNetThreads = 256;
 constexpr int kNetChunk = 256;                  // bytes of K per row and chunk
 constexpr int kNetChunkStride = kNetChunk + 16;
 
 template <int W1, int W2, int W3>
+struct NetLds {
+  static constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16, S3 = W3 * 2 + 16;
+  static constexpr int EP = MidCfg<W3, kNetBM>::WN * kNetBM * 4;  // energy partials
+  static constexpr int D3 = kNetBM * S2 + EP;                     // D3's offset
+  static constexpr int RA_MID = D3 + kNetBM * S3;                 // region A in the middle
+  static constexpr int RA_L1 = 2 * kNetBM * kNetChunkStride;      // ... during layer 1
+  static constexpr int RA = RA_MID > RA_L1 ? RA_MID : RA_L1;
+  static constexpr int X1 = RA;
+  static constexpr int MASKS = X1 + kNetBM * S1;
+  static constexpr size_t bytes = (size_t)MASKS + kNetBM * 8;
+  static_assert(RA % 16 == 0 && D3 % 16 == 0, "aligned regions");
+};
+
+template <int W1, int W2, int W3>
 constexpr size_t net_lds() {
-  return (size_t)2 * kNetBM * kNetChunkStride + (size_t)kNetBM * (W1 * 2 + 16) +
-         (size_t)kNetBM * 8;
+  return NetLds<W1, W2, W3>::bytes;
 }
 
 template <int W1, int W2, int W3>
 // (two workgroups per CU: at most 256 registers per lane)
 __global__ __launch_bounds__(kNetThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_net(
     MidArgs a) {
-  static_assert(W3 <= W1, "D3 is stored over H1");
+  using LL = NetLds<W1, W2, W3>;
   constexpr int BM = kNetBM, NTH = kNetThreads;
-  constexpr int S1 = W1 * 2 + 16, S2 = W2 * 2 + 16;
-  constexpr int RA = 2 * BM * kNetChunkStride;
-  static_assert(BM * S2 + 4 * BM * 4 <= RA, "X2 and the energy partials fit region A");
+  constexpr int S1 = LL::S1;
+  static_assert(LL::bytes * 2 <= 160 * 1024, "two workgroups per CU");
   static_assert(MidCfg<W1, BM>::WM * MidCfg<W1, BM>::WN * 64 == NTH, "the middle's waves");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   unsigned char* RAp = smem;
-  unsigned char* X1 = smem + RA;
-  unsigned long long* rmask = reinterpret_cast<unsigned long long*>(X1 + BM * S1);
+  unsigned char* X1 = smem + LL::X1;
+  unsigned long long* rmask = reinterpret_cast<unsigned long long*>(smem + LL::MASKS);
   unsigned char* X2 = RAp;
-  float* epart = reinterpret_cast<float*>(X2 + BM * S2);
+  float* epart = reinterpret_cast<float*>(X2 + BM * LL::S2);
+  unsigned char* D3s = smem + LL::D3;
 
   const GroupTable* gt = a.gt;
   const int nt = gt->total_rows / BM;
@@ -472,7 +496,7 @@ __global__ __launch_bounds__(kNetThreads) __attribute__((amdgpu_waves_per_eu(2, 
                                celu_fwd(acc[i][j][3] + b.w, alpha, ial2e));
         if (!rv) h = make_float4(0.f, 0.f, 0.f, 0.f);
         lds_put4(X1 + r * S1 + c * 2, h);
-        if (rv) Store<bf16_t>::put4(a.H1out + (size_t)(row0 + r) * W1 + c, h);
+        if (rv && a.D1) Store<bf16_t>::put4(a.H1out + (size_t)(row0 + r) * W1 + c, h);
       }
     }
   }
@@ -495,7 +519,7 @@ __global__ __launch_bounds__(kNetThreads) __attribute__((amdgpu_waves_per_eu(2, 
   {
     MidArgs am = a;
     am.H1 = a.H1out;
-    mid_products<W1, W2, W3, BM>(am, br1, X1, X2, epart, row0, row_end, s, X1, [&] {
+    mid_products<W1, W2, W3, BM>(am, br1, X1, X2, epart, row0, row_end, s, X1, D3s, LL::S3, [&] {
       if (npw > 0) br.prologue();
     });
   }
