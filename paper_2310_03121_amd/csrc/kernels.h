@@ -74,7 +74,7 @@ struct MidArgs {
   int ldx = 0;                    // row stride of X and G, layer 1's K (a multiple of 256)
   const bf16_t* W0 = nullptr;     // [S][W1][ldx], fragment order
   const float* b0 = nullptr;      // [S][W1]
-  bf16_t* H1out = nullptr;        // [rows][W1]: H1, also read back for the last slopes
+  bf16_t* H1out = nullptr;        // [rows][W1]: H1, stored when D1 is (the weight gradients)
   const bf16_t* W0T = nullptr;    // [S][ldx][W1], fragment order
   bf16_t* G = nullptr;            // [rows][ldx] dE/dG, or null (no forces)
   // optional [rows]: per row, the k-steps (32 columns of X) that may be
