@@ -49,3 +49,54 @@ def test_sparse_rows_equal_whole_rows(name):
     E3, F3 = pot.energy_forces(pos, sp, off, s.box)
     pot.check()
     assert torch.equal(E3, E) and torch.equal(F3, F)
+
+
+def _check_against_oracle(pot, at, mt, s, prec, label):
+    import oracle as o
+    from gpu_util import check_forces
+    pos, sp, off = to_dev(s)
+    E, F = pot.energy_forces(pos, sp, off, s.box)
+    pot.check()
+    r = o.energy_forces(s, aev_table=at, mlp_table=mt)
+    check_forces(F.cpu().numpy(), r.F, prec, label)
+    # a molecule's energy error against the sum of its atomic energies, or
+    # the mean atomic energy when that is larger: a one-atom molecule's
+    # energy can be a small difference of its network's terms, and its BF16
+    # error is then that of one network evaluation (up to 2e-2 of it here)
+    mean_atom = np.abs(r.E_atom).mean()
+    scale = np.array([max(np.abs(r.E_atom[s.mol_offsets[m]:s.mol_offsets[m + 1]]).sum(),
+                          mean_atom) for m in range(s.n_mol)])
+    de = np.abs(E.cpu().numpy() - r.E) / scale
+    print(f"{label} {prec}: max |dE| / scale {de.max():.3e}")
+    assert de.max() <= (1e-5 if prec == "fp32" else 1e-2), de.max()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("S", [1, 3])
+def test_few_elements(S, prec):
+    # one element (feature rows of 48 columns, 64 with the gap: the layer
+    # kernels) and three (240 columns, 256 with the gap: the whole-network
+    # kernel on the BF16 path), against the oracle
+    mols = []
+    for n in (5, 17, 33, 64, 90):
+        m = w.single_molecule(n, seed=20 + n, n_species=4)
+        sp = np.random.default_rng(60 + n).integers(0, S, n).astype(np.int32)
+        mols.append(w.System(m.pos, sp, m.mol_offsets, None, S, f"mol{n}"))
+    s = w.pack_molecules(mols, S)
+    announce(f"{S} element(s) {prec} N={s.n_atoms}")
+    pot, at, mt = potential(S, prec)
+    _check_against_oracle(pot, at, mt, s, prec, f"S={S}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_isolated_atoms_have_empty_rows(prec):
+    # one-atom molecules have no neighbors: their rows touch no k-step, and
+    # tiles made only of them run no k-step at all; beside them two-atom and
+    # larger molecules of seven elements
+    mols = [w.single_molecule(1, seed=40 + k, n_species=7) for k in range(300)]
+    mols += [w.single_molecule(2, seed=400 + k, n_species=7) for k in range(40)]
+    mols += [w.single_molecule(24, seed=500 + k, n_species=7) for k in range(6)]
+    s = w.pack_molecules(mols, 7)
+    announce(f"isolated atoms {prec} N={s.n_atoms}")
+    pot, at, mt = potential(7, prec)
+    _check_against_oracle(pot, at, mt, s, prec, "isolated")
